@@ -1,0 +1,230 @@
+"""Compact full multigrid — oracle (test infrastructure only).
+
+Follows the paper's algorithms step by step on whole-level numpy arrays:
+
+* compact representation: ``u_L = u'_L + P_L (u'_{L-1} + ... + P_1 u'_0)``
+  (Sec. 2, eq. compact-to-standard); sections in regressive precision
+  ``k (L - l) + b`` bits on level ``l`` (Sec. 2.1, eq. regressive);
+* residual: decode the standard representation level by level, form
+  ``t = f - A u_L`` and round it to the residual precision (Alg. 2);
+* V-cycle: the compact FAS cycle relaxes, on every level, eq. cfas
+  ``A_l y'_l = r_l - s_l - A_l z_l`` (Sec. 3.2, Alg. 1).  With the initial
+  guess ``y' = 0`` that IR guarantees (Sec. 4, nu = 1) and ``nu1`` pre- and
+  ``nu2`` post-smoothing sweeps:
+
+  - fine to coarse, ``g_l := r_l - s_l`` obeys
+    ``g_{l-1} = R_l (g_l - A_l y'_l)`` where ``y'_l`` is the pre-smoothed
+    (and stored, i.e. rounded) section: this is the recursion for ``s`` in
+    Alg. 1 written for ``r - s``;
+  - on the coarsest level the equation is solved exactly;
+  - coarse to fine, ``z_l = P_l (y'_{l-1} + z_{l-1})`` (Alg. 1) and the
+    post-smoother relaxes ``A_l y'_l = g_l - A_l z_l``;
+  - the correction is added section by section, ``u'_l <- u'_l + y'_l``
+    (Alg. 3, "apply correction"; Sec. 2.2 linear combinations);
+
+* FMG: coarsest solve, then per level append a zero section and widen the
+  others by ``k`` bits (Sec. 2.2, Alg. 3) and run ``N`` IR iterations.
+
+Precision reading (Table 1 mapped to IEEE types): sections of ``u'`` carry
+``b_u + k_u (L - l)`` bits (``k_u = p + 1 = 2``), residual and correction
+``b + (L - l)`` bits (``k = m = 1``); the residual, decode chain, correction
+and coarsest solve run in float64; the V-cycle arithmetic runs in
+``vcycle_dtype`` (float32 by default), which caps residual/correction widths
+at 24 bits (53 in float64).  The paper leaves the precision of ``s`` open
+(Sec. 4); here ``g = r - s`` is stored at the residual's width.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import bfp
+from .grid import (coarse_solve, hierarchy, inject, prolong, restrict, smooth,
+                   to_full)
+
+
+@dataclass
+class Config:
+    dim: int
+    L: int
+    coarsest: int = 1
+    op: str = "poisson"            # "poisson" | "diffusion"
+    smoother: str = "rbgs"         # "rbgs" | "wjacobi"
+    omega: float = 1.0
+    nu_pre: int = 2
+    nu_post: int = 2
+    ir_iters: int = 2              # N, IR iterations per FMG level
+    final_iters: int = 0           # extra IR iterations on the finest level
+    block: int = 64
+    bits_u: int = 16
+    bits_r: int = 16
+    bits_y: int = 16
+    inc_u: int = 2
+    inc_ry: int = 1
+    vcycle_dtype: type = np.float32
+    quantize: bool = True
+
+    def cap_ry(self) -> int:
+        return 24 if self.vcycle_dtype == np.float32 else 53
+
+    def w_u(self, level: int, Lp: int) -> int:
+        return min(bfp.MAX_BITS, self.bits_u + self.inc_u * (Lp - level))
+
+    def w_r(self, level: int, Lp: int) -> int:
+        return min(self.cap_ry(), self.bits_r + self.inc_ry * (Lp - level))
+
+    def w_y(self, level: int, Lp: int) -> int:
+        return min(self.cap_ry(), self.bits_y + self.inc_ry * (Lp - level))
+
+
+class Section:
+    """One level of a compact vector: BFP codes, or raw float64 values when
+    quantisation is switched off (used to check the cycle's algebra)."""
+
+    def __init__(self, dim, level, block, w, m=None, e=None, raw=None):
+        self.dim, self.level, self.block, self.w = dim, level, block, w
+        self.n = 1 << level
+        self.m, self.e, self.raw = m, e, raw
+
+    @classmethod
+    def quantize(cls, x: np.ndarray, block: int, w: int, on: bool = True):
+        d, n = x.ndim, x.shape[0]
+        level = n.bit_length() - 1
+        if not on:
+            return cls(d, level, block, w, raw=np.array(x, dtype=np.float64))
+        m, e = bfp.encode(x.reshape(-1), block, w)
+        return cls(d, level, block, w, m=m, e=e)
+
+    @classmethod
+    def zeros(cls, dim, level, block, w, on=True):
+        return cls.quantize(np.zeros(((1 << level),) * dim), block, w, on)
+
+    def value(self, T=np.float64) -> np.ndarray:
+        shape = (self.n,) * self.dim
+        if self.raw is not None:
+            return self.raw.astype(T)
+        size = self.n ** self.dim
+        return bfp.decode(self.m, self.e, self.block, self.w, size, T).reshape(shape)
+
+    def widen(self, w_new: int) -> "Section":
+        k = w_new - self.w
+        if k < 0:
+            raise ValueError("widening cannot lower the width")
+        if self.raw is not None:
+            return Section(self.dim, self.level, self.block, w_new, raw=self.raw)
+        return Section(self.dim, self.level, self.block, w_new, m=bfp.widen(self.m, k), e=self.e)
+
+
+def decode_chain(U: dict, lc: int, Lp: int) -> np.ndarray:
+    """Standard representation of the compact vector ``U`` on level ``Lp``
+    (eq. compact-to-standard evaluated from the coarsest level up, Alg. 2)."""
+    uh = U[lc].value(np.float64)
+    for level in range(lc + 1, Lp + 1):
+        uh = U[level].value(np.float64) + prolong(uh, np.float64)
+    return uh
+
+
+def ir_residual(U, f_level, ops, cfg: Config, Lp: int) -> Section:
+    """Alg. 2 on FMG level ``Lp``: ``g_Lp = round(f - A u_Lp)`` in float64."""
+    uh = decode_chain(U, cfg.coarsest, Lp)
+    t = f_level - ops[Lp].apply(uh, np.float64)
+    return Section.quantize(t, cfg.block, cfg.w_r(Lp, Lp), cfg.quantize)
+
+
+def vcycle_correct(U, g_top: Section, ops, cfg: Config, Lp: int, trace=None):
+    """One compact V(nu1, nu2) cycle from a zero correction, then ``u' += y'``.
+
+    Returns the correction sections ``Y`` (after post-smoothing).  If
+    ``trace`` is a dict it receives the intermediate sections (``G``, the
+    pre-smoothed ``Y``) for inspection.
+    """
+    T = cfg.vcycle_dtype
+    lc, B, on = cfg.coarsest, cfg.block, cfg.quantize
+    G = {Lp: g_top}
+    Y = {}
+    for level in range(Lp, lc, -1):                       # fine to coarse
+        lv = ops[level]
+        g = G[level].value(T)
+        y = smooth(lv, np.zeros_like(g), g, cfg.nu_pre, cfg.smoother, cfg.omega, T)
+        Y[level] = Section.quantize(y, B, cfg.w_y(level, Lp), on)
+        rc = restrict(g - lv.apply(Y[level].value(T), T), T)
+        G[level - 1] = Section.quantize(rc, B, cfg.w_r(level - 1, Lp), on)
+    if trace is not None:
+        trace["G"] = dict(G)
+        trace["Ypre"] = dict(Y)
+    yc = coarse_solve(ops[lc], G[lc].value(np.float64))   # coarsest, float64
+    Y[lc] = Section.quantize(yc, B, cfg.w_y(lc, Lp), on)
+    U[lc] = Section.quantize(U[lc].value(np.float64) + Y[lc].value(np.float64),
+                             B, cfg.w_u(lc, Lp), on)
+    E = Y[lc].value(T)                                    # y'_lc + z_lc, z_lc = 0
+    for level in range(lc + 1, Lp + 1):                   # coarse to fine
+        lv = ops[level]
+        z = prolong(E, T)
+        rhs = G[level].value(T) - lv.apply(z, T)
+        y = smooth(lv, Y[level].value(T), rhs, cfg.nu_post, cfg.smoother, cfg.omega, T)
+        Y[level] = Section.quantize(y, B, cfg.w_y(level, Lp), on)
+        U[level] = Section.quantize(U[level].value(np.float64) + Y[level].value(np.float64),
+                                    B, cfg.w_u(level, Lp), on)
+        if level < Lp:
+            E = Y[level].value(T) + z
+    return Y
+
+
+def fmg_solve(f_full: np.ndarray, cfg: Config, kappa=None, history=None):
+    """Compact FMG with IR (Alg. 3).  Returns ``(u_full, U)``.
+
+    ``f_full`` is the ``(2**L + 1)**dim`` right-hand side (boundary ignored);
+    ``u_full`` the decoded FP64 solution on the same node grid (boundary 0);
+    ``U`` the final compact sections.  ``history``, if a list, receives the
+    float64 2-norm of each IR residual ``t`` before rounding.
+    """
+    lc, L = cfg.coarsest, cfg.L
+    if not 1 <= lc < L:
+        raise ValueError("need 1 <= coarsest < L")
+    ops = hierarchy(cfg.dim, L, lc, cfg.op, kappa)
+    U = {}
+    yc = coarse_solve(ops[lc], inject(f_full, L, lc))
+    U[lc] = Section.quantize(yc, cfg.block, cfg.w_u(lc, lc), cfg.quantize)
+    for Lp in range(lc + 1, L + 1):
+        for level in range(lc, Lp):
+            U[level] = U[level].widen(cfg.w_u(level, Lp))
+        U[Lp] = Section.zeros(cfg.dim, Lp, cfg.block, cfg.w_u(Lp, Lp), cfg.quantize)
+        f_level = inject(f_full, L, Lp)
+        iters = cfg.ir_iters + (cfg.final_iters if Lp == L else 0)
+        for _ in range(iters):
+            g = ir_residual(U, f_level, ops, cfg, Lp)
+            if history is not None:
+                uh = decode_chain(U, lc, Lp)
+                history.append(float(np.linalg.norm(f_level - ops[Lp].apply(uh, np.float64))))
+            vcycle_correct(U, g, ops, cfg, Lp)
+    return to_full(decode_chain(U, lc, L)), U
+
+
+def vcycle_standard(r_full: np.ndarray, cfg: Config, kappa=None):
+    """One compact V-cycle on a standard FP64 fine residual (the ``cmg_vcycle``
+    entry): round ``r`` to the finest residual width, run the cycle from zero
+    on a zero solution, and return the decoded correction on the node grid."""
+    lc, L = cfg.coarsest, cfg.L
+    ops = hierarchy(cfg.dim, L, lc, cfg.op, kappa)
+    r = inject(r_full, L, L)
+    g = Section.quantize(r, cfg.block, cfg.w_r(L, L), cfg.quantize)
+    U = {level: Section.zeros(cfg.dim, level, cfg.block, cfg.w_u(level, L), cfg.quantize)
+         for level in range(lc, L + 1)}
+    vcycle_correct(U, g, ops, cfg, L)
+    return to_full(decode_chain(U, lc, L))
+
+
+def storage_bits(cfg: Config) -> dict:
+    """Stored bits of the sections ``u'``, ``g`` and ``y'`` on the finest FMG
+    level (mantissas at their logical widths, plus 16-bit block exponents),
+    the quantity of Sec. 6.1.1 and 6.1.3."""
+    out = {"u": 0, "r": 0, "y": 0, "exp": 0}
+    L, lc, B = cfg.L, cfg.coarsest, cfg.block
+    for level in range(lc, L + 1):
+        n = (1 << level) ** cfg.dim
+        out["u"] += n * cfg.w_u(level, L)
+        out["r"] += n * cfg.w_r(level, L)
+        out["y"] += n * cfg.w_y(level, L)
+        out["exp"] += 3 * 16 * bfp.n_blocks(n, B)
+    return out
