@@ -1,0 +1,240 @@
+/*
+ * cmg.h — C ABI of the compact (linear-storage) multigrid library for AMD
+ * MI355X (gfx950).
+ *
+ * The method is the one of "Multigrid with Linear Storage Complexity"
+ * (Bauer, Kohl, McCormick, Tamstorf, arXiv 2511.19036): a full-multigrid
+ * (FMG) solver whose solution, residual and correction are stored as
+ * per-level "sections" (Sec. 2, eq. compact-to-standard) in block floating
+ * point (Sec. 6.1.3) with regressive precision (Sec. 2.1, eq. regressive).
+ *
+ * Problem class: -div(kappa grad u) = f (kappa = 1: Poisson) on the unit
+ * square/cube, zero Dirichlet boundary, finite differences on the node grid
+ * with N = 2^L + 1 points per axis (h = 2^-L), rediscretised on every level.
+ *
+ * Conventions shared by every entry point
+ *  - Node arrays (f, u, r, y, lambda, dJdu) are float64, N^dim values, C order
+ *    with x fastest (index [z][y][x]); batched arrays are [batch][N^dim].
+ *    Boundary entries of inputs are ignored; boundary entries of outputs are
+ *    written as 0.
+ *  - Cell arrays (kappa, grad_kappa) are float64, (2^L)^dim values, C order;
+ *    cell c spans nodes c..c+1 on every axis.
+ *  - Pointers named "device" must be device memory of the current HIP device;
+ *    "host" pointers are ordinary host memory.  The caller owns every array it
+ *    passes; the library never frees or retains them past the call (kappa is
+ *    copied at setup).  The context owns all its internal buffers.
+ *  - All GPU work is enqueued on the stream given to cmg_setup (or to the
+ *    codec calls).  Calls return after enqueueing, except those that fill
+ *    host memory (exports, stats with recording, memory stats), which
+ *    synchronise the stream first.
+ *  - Every call returns a cmg_status; cmg_last_error gives the message of the
+ *    last failure on that context (or on the calling thread for ctx = NULL).
+ *    After CMG_ERR_INVALID_ARG / CMG_ERR_UNSUPPORTED / CMG_ERR_NONFINITE the
+ *    context stays usable; after CMG_ERR_HIP / CMG_ERR_OUT_OF_MEMORY only
+ *    cmg_destroy is valid.  No C++ exception crosses this interface.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef CMG_H
+#define CMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cmg_ctx_s* cmg_ctx;
+
+typedef enum {
+  CMG_OK = 0,
+  CMG_ERR_INVALID_ARG = 1,   /* bad pointer, size, option or state           */
+  CMG_ERR_UNSUPPORTED = 2,   /* valid in principle, not implemented           */
+  CMG_ERR_OUT_OF_MEMORY = 3, /* device allocation failed                      */
+  CMG_ERR_HIP = 4,           /* a HIP runtime call or kernel launch failed    */
+  CMG_ERR_NONFINITE = 5,     /* NaN/Inf in an input (f, kappa, codec input)   */
+  CMG_ERR_NOT_CONVERGED = 6  /* residual grew during iterative refinement     */
+} cmg_status;
+
+enum { CMG_POISSON = 0, CMG_DIFFUSION = 1 };          /* cmg_problem.op           */
+enum { CMG_WJACOBI = 0, CMG_RBGS = 1 };               /* cmg_opts.smoother        */
+enum { CMG_PLAIN_FP64 = 0, CMG_COMPACT_BFP = 1 };     /* cmg_opts.storage         */
+enum { CMG_FP32 = 0, CMG_FP64 = 1 };                  /* cmg_opts.vcycle_prec     */
+enum { CMG_SECTION_U = 0, CMG_SECTION_R = 1, CMG_SECTION_Y = 2 }; /* section kind */
+
+typedef struct {
+  int32_t dim;      /* 2 or 3                                                 */
+  int32_t L;        /* finest level; N = 2^L + 1 nodes per axis, 2 <= L <= 10 */
+  int32_t coarsest; /* coarsest level; 1 (one interior node)                  */
+  int32_t op;       /* CMG_POISSON or CMG_DIFFUSION                           */
+  int32_t batch;    /* number of right-hand sides solved per call, >= 1      */
+} cmg_problem;
+
+/*
+ * Solver options.  Alg. 3 (cFmg) with N = ir_iters IR iterations per FMG
+ * level and nu = vcycles = 1 V-cycle per IR iteration (the paper fixes
+ * nu = 1, Sec. 4); the V-cycle is Alg. 1 generalised to nu_pre/nu_post
+ * sweeps of the smoother (eq. smoother).  Widths: section u' on level l at
+ * FMG level Lp carries bits_u + inc_u (Lp - l) bits, residual and correction
+ * bits_r/bits_y + inc_ry (Lp - l) bits (Table 1 with p + 1 = inc_u,
+ * m = inc_ry), sign included (Table 2 caption); u' is capped at 53 bits,
+ * r and y' at 24 bits with an FP32 V-cycle (53 with FP64).
+ */
+typedef struct {
+  int32_t smoother;    /* CMG_WJACOBI or CMG_RBGS                              */
+  double omega;        /* weighted-Jacobi weight (ignored by RB-GS)            */
+  int32_t nu_pre;      /* pre-smoothing sweeps, >= 0                           */
+  int32_t nu_post;     /* post-smoothing sweeps, >= 0                          */
+  int32_t ir_iters;    /* N: IR iterations per FMG level, >= 1                 */
+  int32_t vcycles;     /* nu: V-cycles per IR iteration, must be 1             */
+  int32_t final_iters; /* extra IR iterations on the finest level, >= 0       */
+  int32_t storage;     /* CMG_COMPACT_BFP, or CMG_PLAIN_FP64 (Alg. SM2)        */
+  int32_t bfp_block;   /* BFP block length: 32 or 64                           */
+  int32_t bits_u;      /* width of the finest solution section, 2..53          */
+  int32_t bits_r;      /* width of the finest residual section, 2..24 (53)     */
+  int32_t bits_y;      /* width of the finest correction section, 2..24 (53)   */
+  int32_t inc_u;       /* regressive increment of u' (k = p + 1), >= 0        */
+  int32_t inc_ry;      /* regressive increment of r, y' (k = m), >= 0         */
+  int32_t vcycle_prec; /* CMG_FP32 or CMG_FP64 arithmetic inside the V-cycle   */
+} cmg_opts;
+
+/* Optional per-solve statistics (host struct). */
+typedef struct {
+  int32_t record;             /* in: 1 = record residual norms (synchronises)   */
+  int32_t count;              /* out: residual norms written                    */
+  double residual_norm[256];  /* out: FP64 2-norm of each IR residual f - A u   */
+} cmg_stats;
+
+/* Device memory held by a context, in bytes. */
+typedef struct {
+  int64_t sections;      /* BFP codes + exponents of u', r, y' on all levels  */
+  int64_t coarse_fp64;   /* float64 temporaries of levels below the finest    */
+  int64_t coarse_work;   /* V-cycle temporaries of levels below the finest    */
+  int64_t fine_work;     /* temporaries on the finest level                   */
+  int64_t kappa;         /* coefficient hierarchy (diffusion)                 */
+  int64_t total;         /* everything the context allocated                  */
+  int64_t interior_dofs; /* (2^L - 1)^dim                                      */
+  double logical_bits_per_dof; /* mantissa + exponent bits of u', r, y' at the
+                                  finest FMG level per interior DoF          */
+} cmg_mem;
+
+/* Fill *o with the defaults: RB-GS V(2,2), N = 2, nu = 1, compact BFP,
+ * B = 64, b = 16 for u', r, y', increments 2 and 1, FP32 V-cycle. */
+cmg_status cmg_default_opts(cmg_opts* o);
+
+/*
+ * Create a solver context for one problem shape.  Validates p and o, copies
+ * kappa (device, (2^L)^dim float64 cells, must be > 0 and finite; NULL for
+ * Poisson), builds the coefficient hierarchy (coarse cell = mean of its 2^d
+ * children) and allocates every buffer with hipMalloc.  hip_stream is a
+ * hipStream_t (NULL = default stream).  On success *out receives the context.
+ */
+cmg_status cmg_setup(const cmg_problem* p, const cmg_opts* o, const double* kappa_cells,
+                     void* hip_stream, cmg_ctx* out);
+
+/*
+ * Compact FMG (Alg. 3, with Alg. 2 for the residual and the generalised
+ * Alg. 1 for the V-cycle), or plain FP64 FMG (Alg. SM2) when storage is
+ * CMG_PLAIN_FP64.  f: device [batch][N^dim]; u: device [batch][N^dim], the
+ * decoded standard representation (eq. compact-to-standard).  st: host,
+ * nullable.  Right-hand sides are injected to coarser FMG levels.
+ */
+cmg_status cmg_fmg_solve(cmg_ctx ctx, const double* f, double* u, cmg_stats* st);
+
+/*
+ * One compact V-cycle from a zero correction (generalised Alg. 1) on a
+ * given fine residual: r (device, [batch][N^dim]) is rounded to the finest
+ * residual width, the cycle runs on a zero solution, and y (device,
+ * [batch][N^dim]) receives the decoded correction.  Overwrites the
+ * context's sections.
+ */
+cmg_status cmg_vcycle(cmg_ctx ctx, const double* r, double* y);
+
+/*
+ * Adjoint solve and coefficient gradient for a loss J(u) (diffusion only).
+ * Solves A lambda_b = dJdu_b for every batch item with the same FMG as
+ * cmg_fmg_solve (A is symmetric), then forms
+ *   dJ/dkappa_c = -h^-2 2^-(d-1) sum_b sum_{edges (p,q) of cell c}
+ *                 (lambda_q - lambda_p)(u_q - u_p).
+ * u: device forward solution [batch][N^dim]; dJdu: device [batch][N^dim];
+ * lambda: device out [batch][N^dim]; grad_kappa: device out (2^L)^dim cells
+ * (summed over the batch), nullable.
+ */
+cmg_status cmg_adjoint_solve(cmg_ctx ctx, const double* u, const double* dJdu, double* lambda,
+                             double* grad_kappa);
+
+/* Release the context and everything it allocated (synchronises). */
+cmg_status cmg_destroy(cmg_ctx ctx);
+
+/* Message of the last failure (never NULL; empty if none). */
+const char* cmg_last_error(cmg_ctx ctx);
+
+/* ---------------------------------------------------------------------------
+ * Block floating point codec (Sec. 6.1.3 format; Sec. 4 rounding: round to
+ * nearest, ties to even; the width includes the sign, Table 2 caption).
+ * Blocks are `block` consecutive values (32 or 64), the last one zero-padded.
+ * Block exponent e: frexp exponent of the block's largest magnitude, raised
+ * by one if that magnitude rounds up to 2^(bits-1); value = m * 2^(e-bits+1);
+ * all-zero blocks store e = -32768.  Codes are stored in a container of 8,
+ * 12 (two values per three bytes, value t at bit 12t, little endian), 16, 32
+ * or 64 bits (the smallest that holds `bits`), sign-extended.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of the code buffer for n values (padding to whole blocks included). */
+int64_t cmg_bfp_code_bytes(int64_t n, int32_t block, int32_t bits);
+
+/* Encode n values x (device, float64 if x_is_f64 else float32) into codes
+ * (device, cmg_bfp_code_bytes) and exps (device, ceil(n/block) int16).
+ * Returns CMG_ERR_NONFINITE (after synchronising) if x holds NaN/Inf. */
+cmg_status cmg_bfp_encode(const void* x, int32_t x_is_f64, int64_t n, int32_t block, int32_t bits,
+                          void* codes, int16_t* exps, void* hip_stream);
+
+/* Decode n values into x (device float64); exact for bits <= 53. */
+cmg_status cmg_bfp_decode(const void* codes, const int16_t* exps, int64_t n, int32_t block,
+                          int32_t bits, double* x, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Section inspection and stepwise driving (tests, checkpoint/resume).
+ * Sections use the padded level layout: level l holds (2^l)^dim values, C
+ * order; index 0 on each axis is the boundary node (always 0), the node at
+ * 2^l is implicit.  `which` is CMG_SECTION_U / _R / _Y.
+ * ------------------------------------------------------------------------- */
+
+/* Shape of a stored section: values, current width, container bits, bytes of
+ * the code buffer and number of blocks.  Any output pointer may be NULL. */
+cmg_status cmg_section_info(cmg_ctx ctx, int32_t which, int32_t level, int64_t* n_values,
+                            int32_t* bits, int32_t* container_bits, int64_t* code_bytes,
+                            int64_t* n_blocks);
+
+/* Copy a section to host memory (codes: code_bytes; exps: n_blocks). */
+cmg_status cmg_export_section(cmg_ctx ctx, int32_t which, int32_t level, void* codes_host,
+                              int16_t* exps_host);
+
+/* Overwrite a section from host memory; `bits` sets its current width and
+ * must fit the section's container. */
+cmg_status cmg_import_section(cmg_ctx ctx, int32_t which, int32_t level, int32_t bits,
+                              const void* codes_host, const int16_t* exps_host);
+
+/* Enter FMG level `level` (Alg. 3): at the coarsest level, the exact coarse
+ * solve of the injected f (device [N^dim]) into u'; above it, widen every
+ * coarser u' section by inc_u bits and append a zero section. */
+cmg_status cmg_fmg_enter_level(cmg_ctx ctx, int32_t level, const double* f);
+
+/* IR residual at the current FMG level (Alg. 2): decode u', form f - A u in
+ * float64, round it into the residual section of that level. */
+cmg_status cmg_ir_residual(cmg_ctx ctx, const double* f);
+
+/* One V-cycle from zero on the current residual section, followed by the
+ * section-wise correction u' += y' (Alg. 1 generalised; Alg. 3). */
+cmg_status cmg_vcycle_correct(cmg_ctx ctx);
+
+/* Decode u' at the current FMG level Lp into u (device, (2^Lp + 1)^dim). */
+cmg_status cmg_decode_solution(cmg_ctx ctx, double* u);
+
+/* Device memory of the context by category. */
+cmg_status cmg_memory_stats(cmg_ctx ctx, cmg_mem* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMG_H */

@@ -1,0 +1,200 @@
+// Device-side building blocks: BFP code access, level indexing, stencils.
+//
+// Every floating-point expression here follows a fixed evaluation order so
+// that results are reproducible bit for bit (the library is compiled with
+// -ffp-contract=off, i.e. no fused multiply-add):
+//   * stencil neighbour terms are taken in the order -x, +x, -y, +y, -z, +z;
+//   * Poisson:   (A u)_p = (2d*u_p - u_-x - u_+x - ...) * 4^l;
+//   * diffusion: (A u)_p = (k_-x (u_p - u_-x) + k_+x (u_p - u_+x) + ...) * 4^l,
+//     k_dir the mean of the 2^(d-1) cells sharing the edge, summed in C order
+//     of the cells and then scaled by 2^-(d-1);
+//   * interpolation: sum of the weighted coarse neighbours in C order;
+//   * full weighting: sum over offsets -1, 0, +1 in C order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmg {
+
+constexpr int16_t kZeroExp = -32768;
+
+// One BFP section as a kernel argument.
+struct SecRef {
+  void* codes;      // container storage
+  int16_t* exps;    // one exponent per block
+  int64_t n;        // values (padded level size)
+  int32_t B;        // block length, 32 or 64
+  int32_t w;        // current logical width (bits, sign included)
+  int32_t cbits;    // container: 8, 12, 16, 32 or 64
+};
+
+// ------------------------------------------------------------------ codes
+__device__ __forceinline__ int64_t load_code(const SecRef& s, int64_t i) {
+  switch (s.cbits) {
+    case 8: return static_cast<const int8_t*>(s.codes)[i];
+    case 16: return static_cast<const int16_t*>(s.codes)[i];
+    case 32: return static_cast<const int32_t*>(s.codes)[i];
+    case 64: return static_cast<const int64_t*>(s.codes)[i];
+    default: {  // 12-bit: value i at bit 12 i
+      const uint8_t* b = static_cast<const uint8_t*>(s.codes);
+      int64_t byte = (i * 3) >> 1;
+      uint32_t lo = b[byte], hi = b[byte + 1];
+      uint32_t v = (i & 1) ? ((lo >> 4) | (hi << 4)) : (lo | ((hi & 0xFu) << 8));
+      return (v & 0x800u) ? static_cast<int64_t>(v) - 4096 : static_cast<int64_t>(v);
+    }
+  }
+}
+
+__device__ __forceinline__ void store_code(const SecRef& s, int64_t i, int64_t m) {
+  switch (s.cbits) {
+    case 8: static_cast<int8_t*>(s.codes)[i] = static_cast<int8_t>(m); break;
+    case 16: static_cast<int16_t*>(s.codes)[i] = static_cast<int16_t>(m); break;
+    case 32: static_cast<int32_t*>(s.codes)[i] = static_cast<int32_t>(m); break;
+    case 64: static_cast<int64_t*>(s.codes)[i] = m; break;
+    default: break;  // 12-bit codes are written a wave at a time (store_codes_wave)
+  }
+}
+
+// Exact value m * 2^(e - (w - 1)) of code i (0 for an all-zero block).
+__device__ __forceinline__ double decode_value(const SecRef& s, int64_t i) {
+  const int e = s.exps[i / s.B];
+  if (e == kZeroExp) return 0.0;
+  return ldexp(static_cast<double>(load_code(s, i)), e - (s.w - 1));
+}
+
+// Wave-wide max over groups of `width` lanes (width 32 or 64).
+__device__ __forceinline__ double group_max(double a, int width) {
+  for (int off = width >> 1; off > 0; off >>= 1) a = fmax(a, __shfl_xor(a, off, 64));
+  return a;
+}
+
+// Quantise the value v held by this lane into its block (the lanes of one
+// group of B lanes form one block).  Returns the code; *e_out the exponent.
+__device__ __forceinline__ int64_t quantise_lane(double v, int B, int w, int* e_out) {
+  const double a = group_max(fabs(v), B);
+  if (a == 0.0) {
+    *e_out = kZeroExp;
+    return 0;
+  }
+  int e;
+  (void)frexp(a, &e);                  // 2^(e-1) <= a < 2^e
+  int q = e - (w - 1);
+  if (rint(ldexp(a, -q)) == ldexp(1.0, w - 1)) {  // the max rounds up to 2^(w-1)
+    ++e;
+    ++q;
+  }
+  *e_out = e;
+  return static_cast<int64_t>(rint(ldexp(v, -q)));
+}
+
+// Store the 64 codes held by the 64 lanes of a wave at values base..base+63.
+// For the 12-bit container lanes 0..23 each assemble one 32-bit word;
+// `limit` is the number of values that may be written (whole blocks).
+__device__ __forceinline__ void store_codes_wave(const SecRef& s, int64_t base, int lane,
+                                                 int64_t m, int64_t limit) {
+  if (s.cbits != 12) {
+    if (base + lane < limit) store_code(s, base + lane, m);
+    return;
+  }
+  const uint32_t c = static_cast<uint32_t>(m) & 0xFFFu;
+  const int bit0 = 32 * lane;
+  const int v0 = bit0 / 12;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int v = v0 + j;
+    const uint32_t cv = __shfl(c, v & 63, 64);
+    const int sh = 12 * v - bit0;
+    if (v < 64 && sh < 32) acc |= (sh >= 0) ? (static_cast<uint64_t>(cv) << sh) : (cv >> (-sh));
+  }
+  // words of this wave: 24; word t covers values [8t/3, ...), write only if
+  // every value it covers lies below `limit` (limit is a multiple of 32)
+  if (lane < 24 && base + (lane * 32 + 31) / 12 < limit)
+    static_cast<uint32_t*>(s.codes)[(base / 64) * 24 + lane] = static_cast<uint32_t>(acc);
+}
+
+// ------------------------------------------------------------------ levels
+struct Geom {
+  int32_t dim;    // 2 or 3
+  int32_t level;  // n = 2^level intervals per axis
+  int32_t n;
+  int64_t size;   // n^dim
+};
+
+__device__ __forceinline__ void unflatten(const Geom& g, int64_t idx, int& i, int& j, int& k) {
+  i = static_cast<int>(idx & (g.n - 1));
+  j = static_cast<int>((idx >> g.level) & (g.n - 1));
+  k = g.dim == 3 ? static_cast<int>(idx >> (2 * g.level)) : 0;
+}
+
+__device__ __forceinline__ int64_t flat(const Geom& g, int i, int j, int k) {
+  return g.dim == 3 ? ((static_cast<int64_t>(k) << (2 * g.level)) | (static_cast<int64_t>(j) << g.level) | i)
+                    : ((static_cast<int64_t>(j) << g.level) | i);
+}
+
+// Value at (i, j, k); the far boundary node (index n) is an implicit 0.
+template <typename T>
+__device__ __forceinline__ T at(const T* u, const Geom& g, int i, int j, int k) {
+  if (i >= g.n || j >= g.n || k >= g.n) return T(0);
+  return u[flat(g, i, j, k)];
+}
+
+__device__ __forceinline__ bool is_interior(const Geom& g, int i, int j, int k) {
+  return i > 0 && j > 0 && (g.dim == 2 || k > 0);
+}
+
+// Edge coefficients k[0..2d-1] (order -x, +x, -y, +y, -z, +z) at interior
+// node (i, j, k) from the cell array `kap` (n^dim cells of this level).
+template <typename T>
+__device__ __forceinline__ void edge_coeffs(const T* kap, const Geom& g, int i, int j, int k, T* ke) {
+  auto K3 = [&](int kc, int jc, int ic) { return kap[flat(g, ic, jc, kc)]; };
+  if (g.dim == 3) {
+    const T q = T(0.25);
+    ke[0] = (((K3(k - 1, j - 1, i - 1) + K3(k - 1, j, i - 1)) + K3(k, j - 1, i - 1)) + K3(k, j, i - 1)) * q;
+    ke[1] = (((K3(k - 1, j - 1, i) + K3(k - 1, j, i)) + K3(k, j - 1, i)) + K3(k, j, i)) * q;
+    ke[2] = (((K3(k - 1, j - 1, i - 1) + K3(k - 1, j - 1, i)) + K3(k, j - 1, i - 1)) + K3(k, j - 1, i)) * q;
+    ke[3] = (((K3(k - 1, j, i - 1) + K3(k - 1, j, i)) + K3(k, j, i - 1)) + K3(k, j, i)) * q;
+    ke[4] = (((K3(k - 1, j - 1, i - 1) + K3(k - 1, j - 1, i)) + K3(k - 1, j, i - 1)) + K3(k - 1, j, i)) * q;
+    ke[5] = (((K3(k, j - 1, i - 1) + K3(k, j - 1, i)) + K3(k, j, i - 1)) + K3(k, j, i)) * q;
+  } else {
+    const T q = T(0.5);
+    ke[0] = (K3(0, j - 1, i - 1) + K3(0, j, i - 1)) * q;
+    ke[1] = (K3(0, j - 1, i) + K3(0, j, i)) * q;
+    ke[2] = (K3(0, j - 1, i - 1) + K3(0, j - 1, i)) * q;
+    ke[3] = (K3(0, j, i - 1) + K3(0, j, i)) * q;
+  }
+}
+
+// (A u)_p at an interior node; kap == nullptr selects Poisson.
+template <typename T>
+__device__ __forceinline__ T apply_A(const T* u, const T* kap, const Geom& g, int i, int j, int k, T inv_h2) {
+  const T up = u[flat(g, i, j, k)];
+  const T nb[6] = {at(u, g, i - 1, j, k), at(u, g, i + 1, j, k), at(u, g, i, j - 1, k),
+                   at(u, g, i, j + 1, k), g.dim == 3 ? at(u, g, i, j, k - 1) : T(0),
+                   g.dim == 3 ? at(u, g, i, j, k + 1) : T(0)};
+  const int nd = 2 * g.dim;
+  T s;
+  if (kap == nullptr) {
+    s = T(nd) * up;
+    for (int t = 0; t < nd; ++t) s = s - nb[t];
+  } else {
+    T ke[6];
+    edge_coeffs(kap, g, i, j, k, ke);
+    s = ke[0] * (up - nb[0]);
+    for (int t = 1; t < nd; ++t) s = s + ke[t] * (up - nb[t]);
+  }
+  return s * inv_h2;
+}
+
+// Diagonal of A at an interior node (diffusion).
+template <typename T>
+__device__ __forceinline__ T diag_A(const T* kap, const Geom& g, int i, int j, int k, T inv_h2) {
+  T ke[6];
+  edge_coeffs(kap, g, i, j, k, ke);
+  T s = ke[0];
+  for (int t = 1; t < 2 * g.dim; ++t) s = s + ke[t];
+  return s * inv_h2;
+}
+
+}  // namespace cmg

@@ -1,0 +1,477 @@
+// Level kernels of the compact multigrid path (gfx950, wave64).
+//
+// One kernel per operation on one level: BFP encode / decode / widen /
+// correction, operator application, d-linear interpolation, full weighting,
+// weighted-Jacobi and red-black Gauss-Seidel sweeps, right-hand-side
+// injection, coefficient coarsening and the coefficient gradient.  Each
+// thread owns one node of the padded level layout; BFP kernels give one
+// wave to 64 consecutive values (one block of 64 or two of 32) so that the
+// shared exponent is a wave-level max reduction.
+#include "device.h"
+#include "launch.h"
+
+namespace cmg {
+
+constexpr int kThreads = 256;
+
+static inline dim3 grid_for(int64_t n) { return dim3(static_cast<unsigned>((n + kThreads - 1) / kThreads)); }
+
+// ===================================================================== BFP
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_encode(const T* __restrict__ x, int64_t n, SecRef s,
+                                                     int* nonfinite) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
+  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  if (base >= limit) return;  // whole wave
+  const int64_t i = base + lane;
+  const double v = (i < n) ? static_cast<double>(x[i]) : 0.0;
+  if (nonfinite != nullptr && !isfinite(v)) atomicOr(nonfinite, 1);
+  int e;
+  const int64_t m = quantise_lane(v, s.B, s.w, &e);
+  store_codes_wave(s, base, lane, m, limit);
+  if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[i / s.B] = static_cast<int16_t>(e);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_decode(SecRef s, int64_t n, T* __restrict__ x) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n) x[i] = static_cast<T>(decode_value(s, i));
+}
+
+// Append k zero bits to every code (exponents unchanged).
+__global__ void __launch_bounds__(kThreads) k_widen(SecRef s, int k) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  if (s.cbits == 12) {  // one thread per pair of values (three bytes)
+    if (2 * t >= limit) return;
+    uint8_t* b = static_cast<uint8_t*>(s.codes) + 3 * t;
+    uint32_t word = b[0] | (b[1] << 8) | (b[2] << 16);
+    int32_t v0 = static_cast<int32_t>(word & 0xFFFu), v1 = static_cast<int32_t>((word >> 12) & 0xFFFu);
+    v0 = (v0 ^ 0x800) - 0x800;
+    v1 = (v1 ^ 0x800) - 0x800;
+    v0 *= (1 << k);
+    v1 *= (1 << k);
+    word = (static_cast<uint32_t>(v0) & 0xFFFu) | ((static_cast<uint32_t>(v1) & 0xFFFu) << 12);
+    b[0] = word & 0xFF;
+    b[1] = (word >> 8) & 0xFF;
+    b[2] = (word >> 16) & 0xFF;
+    return;
+  }
+  if (t >= limit) return;
+  store_code(s, t, load_code(s, t) * (static_cast<int64_t>(1) << k));
+}
+
+__global__ void __launch_bounds__(kThreads) k_zero_section(SecRef s) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  const int64_t nb = (s.n + s.B - 1) / s.B;
+  const int64_t bytes = nb * s.B * s.cbits / 8;
+  if (t < (bytes + 3) / 4) {
+    const int64_t off = 4 * t;
+    uint8_t* b = static_cast<uint8_t*>(s.codes);
+    if (off + 4 <= bytes) {
+      *reinterpret_cast<uint32_t*>(b + off) = 0u;
+    } else {
+      for (int64_t q = off; q < bytes; ++q) b[q] = 0;
+    }
+  }
+  if (t < nb) s.exps[t] = kZeroExp;
+}
+
+// Section-wise correction u' <- round(dec u' + dec y') in float64 (Alg. 3).
+__global__ void __launch_bounds__(kThreads) k_correct(SecRef u, SecRef y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
+  const int64_t limit = ((u.n + u.B - 1) / u.B) * u.B;
+  if (base >= limit) return;
+  const int64_t i = base + lane;
+  const double v = (i < limit) ? decode_value(u, i) + decode_value(y, i) : 0.0;
+  int e;
+  const int64_t m = quantise_lane(v, u.B, u.w, &e);
+  store_codes_wave(u, base, lane, m, limit);
+  if ((lane & (u.B - 1)) == 0 && i < limit) u.exps[i / u.B] = static_cast<int16_t>(e);
+}
+
+// ============================================================ level kernels
+// out = rhs - A u on interior nodes, 0 on the boundary.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rhs_minus_A(const T* __restrict__ rhs, const T* __restrict__ u,
+                                                          const T* __restrict__ kap, Geom g, T inv_h2,
+                                                          T* __restrict__ out) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= g.size) return;
+  int i, j, k;
+  unflatten(g, idx, i, j, k);
+  out[idx] = is_interior(g, i, j, k) ? rhs[idx] - apply_A(u, kap, g, i, j, k, inv_h2) : T(0);
+}
+
+// fine = P coarse (d-linear interpolation); gf is the fine level.
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T* coarse, const Geom& gc, int i, int j, int k) {
+  const int ti = i >> 1, tj = j >> 1, tk = k >> 1;
+  const int pi = i & 1, pj = j & 1, pk = k & 1;
+  T s = T(0);
+  bool first = true;
+  const int nk = (gc.dim == 3) ? 1 + pk : 1;
+  for (int oz = 0; oz < nk; ++oz) {
+    const double wz = (gc.dim == 3 && pk) ? 0.5 : 1.0;
+    for (int oy = 0; oy <= pj; ++oy) {
+      const double wy = pj ? 0.5 : 1.0;
+      for (int ox = 0; ox <= pi; ++ox) {
+        const double wx = pi ? 0.5 : 1.0;
+        const T t = static_cast<T>(wz * wy * wx) * at(coarse, gc, ti + ox, tj + oy, tk + oz);
+        s = first ? t : s + t;
+        first = false;
+      }
+    }
+  }
+  return s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_prolong(const T* __restrict__ coarse, Geom gf, Geom gc,
+                                                      T* __restrict__ fine) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= gf.size) return;
+  int i, j, k;
+  unflatten(gf, idx, i, j, k);
+  fine[idx] = prolong_at(coarse, gc, i, j, k);
+}
+
+// out = dec(section) + P coarse, float64 (one step of the decode chain).
+__global__ void __launch_bounds__(kThreads) k_prolong_add_dec(SecRef sec, const double* __restrict__ coarse,
+                                                              Geom gf, Geom gc, double* __restrict__ out) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= gf.size) return;
+  int i, j, k;
+  unflatten(gf, idx, i, j, k);
+  out[idx] = decode_value(sec, idx) + prolong_at(coarse, gc, i, j, k);
+}
+
+// coarse = R fine (full weighting); gc is the coarse level.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_restrict(const T* __restrict__ fine, Geom gc, Geom gf,
+                                                       T* __restrict__ coarse) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= gc.size) return;
+  int I, J, K;
+  unflatten(gc, idx, I, J, K);
+  if (!is_interior(gc, I, J, K)) {
+    coarse[idx] = T(0);
+    return;
+  }
+  T s = T(0);
+  bool first = true;
+  const int z0 = gc.dim == 3 ? -1 : 0, z1 = gc.dim == 3 ? 1 : 0;
+  for (int oz = z0; oz <= z1; ++oz) {
+    const double wz = gc.dim == 3 ? (oz == 0 ? 0.5 : 0.25) : 1.0;
+    for (int oy = -1; oy <= 1; ++oy) {
+      const double wy = oy == 0 ? 0.5 : 0.25;
+      for (int ox = -1; ox <= 1; ++ox) {
+        const double wx = ox == 0 ? 0.5 : 0.25;
+        const int kf = gc.dim == 3 ? 2 * K + oz : 0;
+        const T t = static_cast<T>(wz * wy * wx) * fine[flat(gf, 2 * I + ox, 2 * J + oy, kf)];
+        s = first ? t : s + t;
+        first = false;
+      }
+    }
+  }
+  coarse[idx] = s;
+}
+
+// Smoothing coefficient c of y <- y + c (rhs - A y): `cpois` for Poisson,
+// omega / diag_p for diffusion.
+template <typename T>
+__device__ __forceinline__ T smooth_coeff(const T* kap, const Geom& g, int i, int j, int k, T inv_h2, T cpois,
+                                          T omega) {
+  return kap == nullptr ? cpois : omega / diag_A(kap, g, i, j, k, inv_h2);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_jacobi(const T* __restrict__ y, const T* __restrict__ rhs,
+                                                     const T* __restrict__ kap, Geom g, T inv_h2, T cpois,
+                                                     T omega, T* __restrict__ ynew) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= g.size) return;
+  int i, j, k;
+  unflatten(g, idx, i, j, k);
+  if (!is_interior(g, i, j, k)) {
+    ynew[idx] = T(0);
+    return;
+  }
+  const T r = rhs[idx] - apply_A(y, kap, g, i, j, k, inv_h2);
+  const T c = smooth_coeff(kap, g, i, j, k, inv_h2, cpois, omega);
+  ynew[idx] = y[idx] + c * r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rbgs(T* __restrict__ y, const T* __restrict__ rhs,
+                                                   const T* __restrict__ kap, Geom g, T inv_h2, T cpois,
+                                                   int colour) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= g.size) return;
+  int i, j, k;
+  unflatten(g, idx, i, j, k);
+  if (!is_interior(g, i, j, k) || ((i + j + k) & 1) != colour) return;
+  const T r = rhs[idx] - apply_A(y, kap, g, i, j, k, inv_h2);
+  const T c = smooth_coeff(kap, g, i, j, k, inv_h2, cpois, T(1));
+  y[idx] = y[idx] + c * r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_add(const T* __restrict__ a, const T* __restrict__ b,
+                                                  T* __restrict__ out, int64_t n) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx < n) out[idx] = a[idx] + b[idx];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fill(T* __restrict__ x, T v, int64_t n) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx < n) x[idx] = v;
+}
+
+template <typename S, typename D>
+__global__ void __launch_bounds__(kThreads) k_convert(const S* __restrict__ a, D* __restrict__ b, int64_t n) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx < n) b[idx] = static_cast<D>(a[idx]);
+}
+
+// Padded level array <- full node array of level L sampled with stride
+// 2^(L - level); boundary set to 0.
+__global__ void __launch_bounds__(kThreads) k_inject(const double* __restrict__ full, int L, Geom g,
+                                                     double* __restrict__ out) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= g.size) return;
+  int i, j, k;
+  unflatten(g, idx, i, j, k);
+  if (!is_interior(g, i, j, k)) {
+    out[idx] = 0.0;
+    return;
+  }
+  const int64_t N = (static_cast<int64_t>(1) << L) + 1;
+  const int s = 1 << (L - g.level);
+  const int64_t src = g.dim == 3 ? ((static_cast<int64_t>(k) * s * N + static_cast<int64_t>(j) * s) * N + i * s)
+                                 : (static_cast<int64_t>(j) * s * N + i * s);
+  out[idx] = full[src];
+}
+
+// Full node array ((n+1)^dim) <- padded level array; far boundary 0.
+__global__ void __launch_bounds__(kThreads) k_to_full(const double* __restrict__ pad, Geom g,
+                                                      double* __restrict__ full) {
+  const int64_t N = g.n + 1;
+  const int64_t total = g.dim == 3 ? N * N * N : N * N;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= total) return;
+  const int i = static_cast<int>(idx % N);
+  const int j = static_cast<int>((idx / N) % N);
+  const int k = g.dim == 3 ? static_cast<int>(idx / (N * N)) : 0;
+  full[idx] = (i < g.n && j < g.n && k < g.n) ? pad[flat(g, i, j, k)] : 0.0;
+}
+
+// Exact solve on a level with a single interior node: y = g / diag (float64).
+__global__ void k_coarse_single(const double* __restrict__ gin, const double* __restrict__ kap, Geom g,
+                                double inv_h2, double* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int64_t t = 0; t < g.size; ++t) y[t] = 0.0;
+  const int64_t c = flat(g, 1, 1, g.dim == 3 ? 1 : 0);
+  const double diag = kap == nullptr ? static_cast<double>(2 * g.dim) * inv_h2 : diag_A(kap, g, 1, 1, g.dim == 3 ? 1 : 0, inv_h2);
+  y[c] = gin[c] / diag;
+}
+
+// ================================================================ kappa
+// Coarse cell = mean of its 2^d children (C order), float64.
+__global__ void __launch_bounds__(kThreads) k_coarsen_kappa(const double* __restrict__ fine, Geom gc, Geom gf,
+                                                            double* __restrict__ coarse) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= gc.size) return;
+  int I, J, K;
+  unflatten(gc, idx, I, J, K);
+  double s = 0.0;
+  bool first = true;
+  const int nz = gc.dim == 3 ? 2 : 1;
+  for (int oz = 0; oz < nz; ++oz)
+    for (int oy = 0; oy < 2; ++oy)
+      for (int ox = 0; ox < 2; ++ox) {
+        const double t = fine[flat(gf, 2 * I + ox, 2 * J + oy, gc.dim == 3 ? 2 * K + oz : 0)];
+        s = first ? t : s + t;
+        first = false;
+      }
+  coarse[idx] = s * (gc.dim == 3 ? 0.125 : 0.25);
+}
+
+// flags[0] |= 1 if any value <= 0, flags[1] |= 1 if any value is not finite.
+__global__ void __launch_bounds__(kThreads) k_check_positive(const double* __restrict__ x, int64_t n, int* flags) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= n) return;
+  const double v = x[idx];
+  if (!isfinite(v)) atomicOr(flags + 1, 1);
+  else if (!(v > 0.0)) atomicOr(flags, 1);
+}
+
+__global__ void __launch_bounds__(kThreads) k_check_finite(const double* __restrict__ x, int64_t n, int* flags) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx < n && !isfinite(x[idx])) atomicOr(flags + 1, 1);
+}
+
+// dJ/dkappa per cell from full node arrays u, lambda ((n+1)^dim).
+__global__ void __launch_bounds__(kThreads) k_grad_kappa(const double* __restrict__ u, const double* __restrict__ lam,
+                                                         Geom gcell, int accumulate, double* __restrict__ grad) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= gcell.size) return;
+  int ic, jc, kc;
+  unflatten(gcell, idx, ic, jc, kc);
+  const int64_t N = gcell.n + 1;
+  auto node = [&](int k, int j, int i) { return (static_cast<int64_t>(k) * N + j) * N + i; };
+  double s = 0.0;
+  bool first = true;
+  auto add = [&](int64_t lo, int64_t hi) {
+    const double t = (lam[hi] - lam[lo]) * (u[hi] - u[lo]);
+    s = first ? t : s + t;
+    first = false;
+  };
+  if (gcell.dim == 3) {
+    for (int oz = 0; oz < 2; ++oz)  // edges along x
+      for (int oy = 0; oy < 2; ++oy) add(node(kc + oz, jc + oy, ic), node(kc + oz, jc + oy, ic + 1));
+    for (int oz = 0; oz < 2; ++oz)  // edges along y
+      for (int ox = 0; ox < 2; ++ox) add(node(kc + oz, jc, ic + ox), node(kc + oz, jc + 1, ic + ox));
+    for (int oy = 0; oy < 2; ++oy)  // edges along z
+      for (int ox = 0; ox < 2; ++ox) add(node(kc, jc + oy, ic + ox), node(kc + 1, jc + oy, ic + ox));
+  } else {
+    for (int oy = 0; oy < 2; ++oy) add(node(0, jc + oy, ic), node(0, jc + oy, ic + 1));
+    for (int ox = 0; ox < 2; ++ox) add(node(0, jc, ic + ox), node(0, jc + 1, ic + ox));
+  }
+  const double fac = -(static_cast<double>(gcell.n) * static_cast<double>(gcell.n)) * (gcell.dim == 3 ? 0.25 : 0.5);
+  const double v = s * fac;
+  grad[idx] = accumulate ? grad[idx] + v : v;
+}
+
+// out[0] += sum x^2 (for residual-norm statistics; summation order is
+// unspecified).
+__global__ void __launch_bounds__(kThreads) k_sumsq(const double* __restrict__ x, int64_t n, double* out) {
+  __shared__ double part[kThreads / 64];
+  double a = 0.0;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; idx < n;
+       idx += static_cast<int64_t>(gridDim.x) * kThreads)
+    a += x[idx] * x[idx];
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) t += part[w];
+    atomicAdd(out, t);
+  }
+}
+
+// ============================================================== launchers
+#define CMG_LAUNCH(kernel, n, stream, ...) \
+  hipLaunchKernelGGL(kernel, grid_for(n), dim3(kThreads), 0, stream, __VA_ARGS__)
+
+template <typename T>
+void launch_encode(const T* x, int64_t n, const SecRef& s, int* nonfinite, hipStream_t st) {
+  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  CMG_LAUNCH(k_encode<T>, limit, st, x, n, s, nonfinite);
+}
+template <typename T>
+void launch_decode(const SecRef& s, int64_t n, T* x, hipStream_t st) {
+  CMG_LAUNCH(k_decode<T>, n, st, s, n, x);
+}
+void launch_widen(const SecRef& s, int k, hipStream_t st) {
+  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  CMG_LAUNCH(k_widen, s.cbits == 12 ? limit / 2 : limit, st, s, k);
+}
+void launch_zero_section(const SecRef& s, hipStream_t st) {
+  const int64_t nb = (s.n + s.B - 1) / s.B;
+  const int64_t words = (nb * s.B * s.cbits / 8 + 3) / 4;
+  CMG_LAUNCH(k_zero_section, words > nb ? words : nb, st, s);
+}
+void launch_correct(const SecRef& u, const SecRef& y, hipStream_t st) {
+  const int64_t limit = ((u.n + u.B - 1) / u.B) * u.B;
+  CMG_LAUNCH(k_correct, limit, st, u, y);
+}
+template <typename T>
+void launch_rhs_minus_A(const T* rhs, const T* u, const T* kap, const Geom& g, T inv_h2, T* out, hipStream_t st) {
+  CMG_LAUNCH(k_rhs_minus_A<T>, g.size, st, rhs, u, kap, g, inv_h2, out);
+}
+template <typename T>
+void launch_prolong(const T* coarse, const Geom& gf, const Geom& gc, T* fine, hipStream_t st) {
+  CMG_LAUNCH(k_prolong<T>, gf.size, st, coarse, gf, gc, fine);
+}
+void launch_prolong_add_dec(const SecRef& s, const double* coarse, const Geom& gf, const Geom& gc, double* out,
+                            hipStream_t st) {
+  CMG_LAUNCH(k_prolong_add_dec, gf.size, st, s, coarse, gf, gc, out);
+}
+template <typename T>
+void launch_restrict(const T* fine, const Geom& gc, const Geom& gf, T* coarse, hipStream_t st) {
+  CMG_LAUNCH(k_restrict<T>, gc.size, st, fine, gc, gf, coarse);
+}
+template <typename T>
+void launch_jacobi(const T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, T omega, T* ynew,
+                   hipStream_t st) {
+  CMG_LAUNCH(k_jacobi<T>, g.size, st, y, rhs, kap, g, inv_h2, cpois, omega, ynew);
+}
+template <typename T>
+void launch_rbgs(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, int colour, hipStream_t st) {
+  CMG_LAUNCH(k_rbgs<T>, g.size, st, y, rhs, kap, g, inv_h2, cpois, colour);
+}
+template <typename T>
+void launch_add(const T* a, const T* b, T* out, int64_t n, hipStream_t st) {
+  CMG_LAUNCH(k_add<T>, n, st, a, b, out, n);
+}
+template <typename T>
+void launch_fill(T* x, T v, int64_t n, hipStream_t st) {
+  CMG_LAUNCH(k_fill<T>, n, st, x, v, n);
+}
+template <typename S, typename D>
+void launch_convert(const S* a, D* b, int64_t n, hipStream_t st) {
+  CMG_LAUNCH((k_convert<S, D>), n, st, a, b, n);
+}
+void launch_inject(const double* full, int L, const Geom& g, double* out, hipStream_t st) {
+  CMG_LAUNCH(k_inject, g.size, st, full, L, g, out);
+}
+void launch_to_full(const double* pad, const Geom& g, double* full, hipStream_t st) {
+  const int64_t N = g.n + 1;
+  CMG_LAUNCH(k_to_full, g.dim == 3 ? N * N * N : N * N, st, pad, g, full);
+}
+void launch_coarse_single(const double* gin, const double* kap, const Geom& g, double inv_h2, double* y,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_single, dim3(1), dim3(64), 0, st, gin, kap, g, inv_h2, y);
+}
+void launch_coarsen_kappa(const double* fine, const Geom& gc, const Geom& gf, double* coarse, hipStream_t st) {
+  CMG_LAUNCH(k_coarsen_kappa, gc.size, st, fine, gc, gf, coarse);
+}
+void launch_check_positive(const double* x, int64_t n, int* flags, hipStream_t st) {
+  CMG_LAUNCH(k_check_positive, n, st, x, n, flags);
+}
+void launch_check_finite(const double* x, int64_t n, int* flags, hipStream_t st) {
+  CMG_LAUNCH(k_check_finite, n, st, x, n, flags);
+}
+void launch_grad_kappa(const double* u, const double* lam, const Geom& gcell, int accumulate, double* grad,
+                       hipStream_t st) {
+  CMG_LAUNCH(k_grad_kappa, gcell.size, st, u, lam, gcell, accumulate, grad);
+}
+void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
+  int64_t blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_sumsq, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, st, x, n, out);
+}
+
+#define CMG_INST_T(T)                                                                                   \
+  template void launch_encode<T>(const T*, int64_t, const SecRef&, int*, hipStream_t);                  \
+  template void launch_decode<T>(const SecRef&, int64_t, T*, hipStream_t);                              \
+  template void launch_rhs_minus_A<T>(const T*, const T*, const T*, const Geom&, T, T*, hipStream_t);   \
+  template void launch_prolong<T>(const T*, const Geom&, const Geom&, T*, hipStream_t);                 \
+  template void launch_restrict<T>(const T*, const Geom&, const Geom&, T*, hipStream_t);                \
+  template void launch_jacobi<T>(const T*, const T*, const T*, const Geom&, T, T, T, T*, hipStream_t);  \
+  template void launch_rbgs<T>(T*, const T*, const T*, const Geom&, T, T, int, hipStream_t);            \
+  template void launch_add<T>(const T*, const T*, T*, int64_t, hipStream_t);                            \
+  template void launch_fill<T>(T*, T, int64_t, hipStream_t);
+CMG_INST_T(float)
+CMG_INST_T(double)
+template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+template void launch_convert<double, double>(const double*, double*, int64_t, hipStream_t);
+
+}  // namespace cmg

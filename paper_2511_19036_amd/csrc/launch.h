@@ -1,0 +1,43 @@
+// Host-side launchers of the level kernels (all asynchronous on `st`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace cmg {
+
+template <typename T> void launch_encode(const T* x, int64_t n, const SecRef& s, int* nonfinite, hipStream_t st);
+template <typename T> void launch_decode(const SecRef& s, int64_t n, T* x, hipStream_t st);
+void launch_widen(const SecRef& s, int k, hipStream_t st);
+void launch_zero_section(const SecRef& s, hipStream_t st);
+void launch_correct(const SecRef& u, const SecRef& y, hipStream_t st);
+
+template <typename T>
+void launch_rhs_minus_A(const T* rhs, const T* u, const T* kap, const Geom& g, T inv_h2, T* out, hipStream_t st);
+template <typename T> void launch_prolong(const T* coarse, const Geom& gf, const Geom& gc, T* fine, hipStream_t st);
+void launch_prolong_add_dec(const SecRef& s, const double* coarse, const Geom& gf, const Geom& gc, double* out,
+                            hipStream_t st);
+template <typename T> void launch_restrict(const T* fine, const Geom& gc, const Geom& gf, T* coarse, hipStream_t st);
+template <typename T>
+void launch_jacobi(const T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, T omega, T* ynew,
+                   hipStream_t st);
+template <typename T>
+void launch_rbgs(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, int colour, hipStream_t st);
+template <typename T> void launch_add(const T* a, const T* b, T* out, int64_t n, hipStream_t st);
+template <typename T> void launch_fill(T* x, T v, int64_t n, hipStream_t st);
+template <typename S, typename D> void launch_convert(const S* a, D* b, int64_t n, hipStream_t st);
+
+void launch_inject(const double* full, int L, const Geom& g, double* out, hipStream_t st);
+void launch_to_full(const double* pad, const Geom& g, double* full, hipStream_t st);
+void launch_coarse_single(const double* gin, const double* kap, const Geom& g, double inv_h2, double* y,
+                          hipStream_t st);
+void launch_coarsen_kappa(const double* fine, const Geom& gc, const Geom& gf, double* coarse, hipStream_t st);
+void launch_check_positive(const double* x, int64_t n, int* flags, hipStream_t st);
+void launch_check_finite(const double* x, int64_t n, int* flags, hipStream_t st);
+void launch_grad_kappa(const double* u, const double* lam, const Geom& gcell, int accumulate, double* grad,
+                       hipStream_t st);
+void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st);
+
+}  // namespace cmg

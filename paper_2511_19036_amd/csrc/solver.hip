@@ -1,0 +1,821 @@
+// Solver context, FMG / V-cycle orchestration and the C ABI of cmg.h.
+//
+// Compact FMG (Alg. 3): coarsest solve; per FMG level widen the coarser
+// solution sections and append a zero section; N times: IR residual from the
+// decoded solution (Alg. 2, float64), one compact V-cycle from a zero
+// correction (Alg. 1 with nu_pre / nu_post sweeps, arithmetic type T), and
+// the section-wise correction u' += y' (float64).  Plain FMG (Alg. SM2)
+// keeps float64 standard vectors and a correction-scheme V-cycle.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "cmg.h"
+#include "launch.h"
+
+using namespace cmg;
+
+namespace {
+
+struct CmgError {
+  cmg_status code;
+  std::string msg;
+};
+
+thread_local std::string g_thread_error;
+
+[[noreturn]] void fail(cmg_status code, const std::string& msg) { throw CmgError{code, msg}; }
+
+#define HIPCK(call)                                                                                \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      fail(e_ == hipErrorOutOfMemory ? CMG_ERR_OUT_OF_MEMORY : CMG_ERR_HIP,                        \
+           std::string(#call) + ": " + hipGetErrorString(e_));                                     \
+  } while (0)
+#define KCK() HIPCK(hipGetLastError())
+
+int container_bits(int w) {
+  if (w <= 8) return 8;
+  if (w <= 12) return 12;
+  if (w <= 16) return 16;
+  if (w <= 32) return 32;
+  return 64;
+}
+
+int64_t n_blocks(int64_t n, int B) { return (n + B - 1) / B; }
+int64_t code_bytes(int64_t n, int B, int w) { return n_blocks(n, B) * B * container_bits(w) / 8; }
+
+enum MemCat { kSections = 0, kCoarse64, kCoarseWork, kFineWork, kKappa, kOther, kNumCat };
+
+struct Section {
+  void* codes = nullptr;
+  int16_t* exps = nullptr;
+  int64_t n = 0, nblk = 0, bytes = 0;
+  int B = 64, w = 2, cbits = 8;
+  SecRef ref() const { return SecRef{codes, exps, n, B, w, cbits}; }
+};
+
+struct LevelData {
+  Geom g{};
+  Section U, G, Y;                    // compact sections u', g = r - s, y'
+  void *gf = nullptr, *yf = nullptr;  // V-cycle arrays in the arithmetic type T
+  void *zf = nullptr, *rf = nullptr, *ef = nullptr;
+  double* uh = nullptr;   // decoded solution (compact) / solution (plain)
+  double* t64 = nullptr;  // float64 residual
+  double* f64 = nullptr;  // injected right-hand side
+  double* s64 = nullptr;  // float64 scratch (coarse solve)
+  double* kap64 = nullptr;
+  void* kapT = nullptr;
+};
+
+double inv_h2(int level) { return std::ldexp(1.0, 2 * level); }
+
+}  // namespace
+
+struct cmg_ctx_s {
+  cmg_problem p{};
+  cmg_opts o{};
+  hipStream_t st = nullptr;
+  std::vector<LevelData> lv;
+  std::vector<void*> allocs;
+  int64_t mem[kNumCat] = {};
+  int Lp = -1;
+  int* flags = nullptr;   // [0] non-positive kappa, [1] non-finite value
+  double* red = nullptr;  // reduction scratch
+  bool dead = false;
+  std::string err;
+
+  void* alloc(size_t bytes, MemCat cat) {
+    void* ptr = nullptr;
+    if (bytes == 0) return nullptr;
+    HIPCK(hipMalloc(&ptr, bytes));
+    allocs.push_back(ptr);
+    mem[cat] += static_cast<int64_t>(bytes);
+    return ptr;
+  }
+  int lc() const { return p.coarsest; }
+  int cap_ry() const { return o.vcycle_prec == CMG_FP32 ? 24 : 53; }
+  int wu(int l, int Lp_) const { return std::min(53, o.bits_u + o.inc_u * (Lp_ - l)); }
+  int wr(int l, int Lp_) const { return std::min(cap_ry(), o.bits_r + o.inc_ry * (Lp_ - l)); }
+  int wy(int l, int Lp_) const { return std::min(cap_ry(), o.bits_y + o.inc_ry * (Lp_ - l)); }
+  int64_t full_size(int level) const {
+    int64_t N = (int64_t{1} << level) + 1;
+    return p.dim == 3 ? N * N * N : N * N;
+  }
+  bool compact() const { return o.storage == CMG_COMPACT_BFP; }
+};
+
+namespace {
+
+Geom make_geom(int dim, int level) {
+  Geom g;
+  g.dim = dim;
+  g.level = level;
+  g.n = 1 << level;
+  g.size = int64_t{1} << (dim * level);
+  return g;
+}
+
+// ------------------------------------------------------------ validation
+void validate(const cmg_problem* p, const cmg_opts* o) {
+  if (p == nullptr || o == nullptr) fail(CMG_ERR_INVALID_ARG, "problem and options must not be NULL");
+  if (p->dim != 2 && p->dim != 3) fail(CMG_ERR_INVALID_ARG, "dim must be 2 or 3");
+  const int maxL = p->dim == 3 ? 10 : 14;
+  if (p->L < 2 || p->L > maxL) fail(CMG_ERR_INVALID_ARG, "L out of range");
+  if (p->coarsest < 1 || p->coarsest >= p->L) fail(CMG_ERR_INVALID_ARG, "need 1 <= coarsest < L");
+  if (p->coarsest != 1) fail(CMG_ERR_UNSUPPORTED, "only coarsest = 1 (one interior node) is implemented");
+  if (p->op != CMG_POISSON && p->op != CMG_DIFFUSION) fail(CMG_ERR_INVALID_ARG, "unknown operator");
+  if (p->batch < 1) fail(CMG_ERR_INVALID_ARG, "batch must be >= 1");
+  if (o->smoother != CMG_WJACOBI && o->smoother != CMG_RBGS) fail(CMG_ERR_INVALID_ARG, "unknown smoother");
+  if (o->smoother == CMG_WJACOBI && !(o->omega > 0.0 && o->omega < 2.0))
+    fail(CMG_ERR_INVALID_ARG, "omega must lie in (0, 2)");
+  if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre > 16 || o->nu_post > 16)
+    fail(CMG_ERR_INVALID_ARG, "smoothing sweeps must lie in [0, 16]");
+  if (o->ir_iters < 1 || o->ir_iters > 64) fail(CMG_ERR_INVALID_ARG, "ir_iters must lie in [1, 64]");
+  if (o->final_iters < 0 || o->final_iters > 200) fail(CMG_ERR_INVALID_ARG, "final_iters must lie in [0, 200]");
+  if (o->vcycles != 1) fail(CMG_ERR_UNSUPPORTED, "vcycles (nu) must be 1: the V-cycle starts from zero");
+  if (o->storage != CMG_PLAIN_FP64 && o->storage != CMG_COMPACT_BFP) fail(CMG_ERR_INVALID_ARG, "unknown storage");
+  if (o->vcycle_prec != CMG_FP32 && o->vcycle_prec != CMG_FP64) fail(CMG_ERR_INVALID_ARG, "unknown vcycle_prec");
+  if (o->storage == CMG_COMPACT_BFP) {
+    const int cap = o->vcycle_prec == CMG_FP32 ? 24 : 53;
+    if (o->bfp_block != 32 && o->bfp_block != 64) fail(CMG_ERR_INVALID_ARG, "bfp_block must be 32 or 64");
+    if (o->bits_u < 2 || o->bits_u > 53) fail(CMG_ERR_INVALID_ARG, "bits_u must lie in [2, 53]");
+    if (o->bits_r < 2 || o->bits_r > cap || o->bits_y < 2 || o->bits_y > cap)
+      fail(CMG_ERR_INVALID_ARG, "bits_r / bits_y must lie in [2, 24] (FP32 V-cycle) or [2, 53]");
+    if (o->inc_u < 0 || o->inc_ry < 0 || o->inc_u > 8 || o->inc_ry > 8)
+      fail(CMG_ERR_INVALID_ARG, "increments must lie in [0, 8]");
+  }
+}
+
+// ------------------------------------------------------------ setup
+void alloc_section(cmg_ctx c, Section& s, const Geom& g, int wmax) {
+  s.n = g.size;
+  s.B = c->o.bfp_block;
+  s.nblk = n_blocks(s.n, s.B);
+  s.cbits = container_bits(wmax);
+  s.w = wmax;
+  s.bytes = code_bytes(s.n, s.B, wmax);
+  s.codes = c->alloc(static_cast<size_t>(s.bytes), kSections);
+  s.exps = static_cast<int16_t*>(c->alloc(static_cast<size_t>(s.nblk) * 2, kSections));
+}
+
+void setup_levels(cmg_ctx c, const double* kappa) {
+  const int L = c->p.L, lc = c->lc(), d = c->p.dim;
+  const size_t tsz = c->o.vcycle_prec == CMG_FP32 ? 4 : 8;
+  c->lv.resize(L + 1);
+  for (int l = lc; l <= L; ++l) {
+    LevelData& D = c->lv[l];
+    D.g = make_geom(d, l);
+    const size_t n = static_cast<size_t>(D.g.size);
+    const MemCat work = l == L ? kFineWork : kCoarseWork;
+    const MemCat f64c = l == L ? kFineWork : kCoarse64;
+    if (c->compact()) {
+      alloc_section(c, D.U, D.g, c->wu(l, L));
+      alloc_section(c, D.G, D.g, c->wr(l, L));
+      alloc_section(c, D.Y, D.g, c->wy(l, L));
+      D.gf = c->alloc(n * tsz, work);
+      D.ef = c->alloc(n * tsz, work);
+    }
+    D.yf = c->alloc(n * tsz, work);
+    D.zf = c->alloc(n * tsz, work);
+    D.rf = c->alloc(n * tsz, work);
+    D.uh = static_cast<double*>(c->alloc(n * 8, f64c));
+    D.t64 = static_cast<double*>(c->alloc(n * 8, f64c));
+    D.f64 = static_cast<double*>(c->alloc(n * 8, f64c));
+    if (l == lc) D.s64 = static_cast<double*>(c->alloc(n * 8, kCoarse64));
+  }
+  c->flags = static_cast<int*>(c->alloc(64, kOther));
+  c->red = static_cast<double*>(c->alloc(64, kOther));
+  HIPCK(hipMemsetAsync(c->flags, 0, 64, c->st));
+  if (c->p.op == CMG_DIFFUSION) {
+    for (int l = lc; l <= L; ++l) {
+      LevelData& D = c->lv[l];
+      const size_t n = static_cast<size_t>(D.g.size);
+      D.kap64 = static_cast<double*>(c->alloc(n * 8, kKappa));
+      D.kapT = tsz == 4 ? c->alloc(n * 4, kKappa) : D.kap64;
+    }
+    LevelData& F = c->lv[L];
+    HIPCK(hipMemcpyAsync(F.kap64, kappa, static_cast<size_t>(F.g.size) * 8, hipMemcpyDeviceToDevice, c->st));
+    launch_check_positive(F.kap64, F.g.size, c->flags, c->st);
+    KCK();
+    int h[2] = {0, 0};
+    HIPCK(hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->st));
+    HIPCK(hipStreamSynchronize(c->st));
+    if (h[1]) fail(CMG_ERR_NONFINITE, "kappa holds NaN or Inf");
+    if (h[0]) fail(CMG_ERR_INVALID_ARG, "kappa must be positive");
+    for (int l = L - 1; l >= lc; --l) {
+      launch_coarsen_kappa(c->lv[l + 1].kap64, c->lv[l].g, c->lv[l + 1].g, c->lv[l].kap64, c->st);
+      KCK();
+    }
+    if (tsz == 4)
+      for (int l = lc; l <= L; ++l) {
+        launch_convert<double, float>(c->lv[l].kap64, static_cast<float*>(c->lv[l].kapT), c->lv[l].g.size, c->st);
+        KCK();
+      }
+  }
+  HIPCK(hipStreamSynchronize(c->st));
+}
+
+// ------------------------------------------------------------ V-cycle pieces
+template <typename T>
+const T* kapT(cmg_ctx c, int l) {
+  return c->p.op == CMG_DIFFUSION ? static_cast<const T*>(c->lv[l].kapT) : nullptr;
+}
+const double* kap64(cmg_ctx c, int l) { return c->p.op == CMG_DIFFUSION ? c->lv[l].kap64 : nullptr; }
+
+// nu sweeps of the smoother on A y = rhs (level l), in place on y.
+template <typename T>
+void smooth(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) {
+  LevelData& D = c->lv[l];
+  const double ih2 = inv_h2(l);
+  const T* kap = kapT<T>(c, l);
+  const int d = c->p.dim;
+  if (c->o.smoother == CMG_RBGS) {
+    const T cp = static_cast<T>(1.0 / (2.0 * d * ih2));
+    for (int s = 0; s < nu; ++s)
+      for (int colour = 0; colour < 2; ++colour) {
+        launch_rbgs<T>(y, rhs, kap, D.g, static_cast<T>(ih2), cp, colour, c->st);
+        KCK();
+      }
+    return;
+  }
+  const T cp = static_cast<T>(c->o.omega / (2.0 * d * ih2));
+  const T om = static_cast<T>(c->o.omega);
+  T* a = y;
+  T* b = scratch;
+  for (int s = 0; s < nu; ++s) {
+    launch_jacobi<T>(a, rhs, kap, D.g, static_cast<T>(ih2), cp, om, b, c->st);
+    KCK();
+    std::swap(a, b);
+  }
+  if (a != y)  // odd number of sweeps: the result sits in the scratch array
+    HIPCK(hipMemcpyAsync(y, a, static_cast<size_t>(D.g.size) * sizeof(T), hipMemcpyDeviceToDevice, c->st));
+}
+
+// One compact V-cycle from zero on G[Lp], then u' += y' (Alg. 1, Alg. 3).
+template <typename T>
+void vcycle_correct(cmg_ctx c, int Lp) {
+  const int lc = c->lc();
+  hipStream_t st = c->st;
+  int* nf = c->flags + 1;
+  for (int l = Lp; l > lc; --l) {  // fine to coarse
+    LevelData& F = c->lv[l];
+    LevelData& C = c->lv[l - 1];
+    T* gf = static_cast<T*>(F.gf);
+    T* yf = static_cast<T*>(F.yf);
+    T* rf = static_cast<T*>(F.rf);
+    launch_decode<T>(F.G.ref(), F.g.size, gf, st);
+    launch_fill<T>(yf, T(0), F.g.size, st);
+    KCK();
+    smooth<T>(c, l, yf, gf, static_cast<T*>(F.ef), c->o.nu_pre);
+    F.Y.w = c->wy(l, Lp);
+    launch_encode<T>(yf, F.g.size, F.Y.ref(), nf, st);
+    launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
+    launch_rhs_minus_A<T>(gf, yf, kapT<T>(c, l), F.g, static_cast<T>(inv_h2(l)), rf, st);
+    launch_restrict<T>(rf, C.g, F.g, static_cast<T*>(C.rf), st);
+    C.G.w = c->wr(l - 1, Lp);
+    launch_encode<T>(static_cast<T*>(C.rf), C.g.size, C.G.ref(), nf, st);
+    KCK();
+  }
+  LevelData& B = c->lv[lc];  // coarsest, float64
+  launch_decode<double>(B.G.ref(), B.g.size, B.t64, st);
+  launch_coarse_single(B.t64, kap64(c, lc), B.g, inv_h2(lc), B.s64, st);
+  B.Y.w = c->wy(lc, Lp);
+  launch_encode<double>(B.s64, B.g.size, B.Y.ref(), nf, st);
+  B.U.w = c->wu(lc, Lp);
+  launch_correct(B.U.ref(), B.Y.ref(), st);
+  launch_decode<T>(B.Y.ref(), B.g.size, static_cast<T*>(B.ef), st);
+  KCK();
+  for (int l = lc + 1; l <= Lp; ++l) {  // coarse to fine
+    LevelData& F = c->lv[l];
+    LevelData& C = c->lv[l - 1];
+    T* gf = static_cast<T*>(F.gf);
+    T* yf = static_cast<T*>(F.yf);
+    T* zf = static_cast<T*>(F.zf);
+    T* rf = static_cast<T*>(F.rf);
+    launch_prolong<T>(static_cast<T*>(C.ef), F.g, C.g, zf, st);
+    launch_decode<T>(F.G.ref(), F.g.size, gf, st);
+    launch_rhs_minus_A<T>(gf, zf, kapT<T>(c, l), F.g, static_cast<T>(inv_h2(l)), rf, st);
+    launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
+    KCK();
+    smooth<T>(c, l, yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
+    F.Y.w = c->wy(l, Lp);
+    launch_encode<T>(yf, F.g.size, F.Y.ref(), nf, st);
+    F.U.w = c->wu(l, Lp);
+    launch_correct(F.U.ref(), F.Y.ref(), st);
+    if (l < Lp) {
+      launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
+      launch_add<T>(yf, zf, static_cast<T*>(F.ef), F.g.size, st);
+    }
+    KCK();
+  }
+}
+
+void decode_chain(cmg_ctx c, int Lp) {
+  const int lc = c->lc();
+  launch_decode<double>(c->lv[lc].U.ref(), c->lv[lc].g.size, c->lv[lc].uh, c->st);
+  for (int l = lc + 1; l <= Lp; ++l)
+    launch_prolong_add_dec(c->lv[l].U.ref(), c->lv[l - 1].uh, c->lv[l].g, c->lv[l - 1].g, c->lv[l].uh, c->st);
+  KCK();
+}
+
+// IR residual (Alg. 2) into G[Lp]; f64[Lp] must hold the injected rhs.
+void ir_residual(cmg_ctx c, int Lp, cmg_stats* st) {
+  LevelData& F = c->lv[Lp];
+  decode_chain(c, Lp);
+  launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.t64, c->st);
+  F.G.w = c->wr(Lp, Lp);
+  launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
+  KCK();
+  if (st != nullptr && st->record && st->count < 256) {
+    HIPCK(hipMemsetAsync(c->red, 0, 8, c->st));
+    launch_sumsq(F.t64, F.g.size, c->red, c->st);
+    KCK();
+    double h = 0.0;
+    HIPCK(hipMemcpyAsync(&h, c->red, 8, hipMemcpyDeviceToHost, c->st));
+    HIPCK(hipStreamSynchronize(c->st));
+    st->residual_norm[st->count++] = std::sqrt(h);
+  }
+}
+
+void enter_level(cmg_ctx c, int level, const double* f) {
+  const int lc = c->lc();
+  LevelData& D = c->lv[level];
+  if (level == lc) {
+    launch_inject(f, c->p.L, D.g, D.f64, c->st);
+    launch_coarse_single(D.f64, kap64(c, lc), D.g, inv_h2(lc), D.s64, c->st);
+    D.U.w = c->wu(lc, lc);
+    launch_encode<double>(D.s64, D.g.size, D.U.ref(), c->flags + 1, c->st);
+    KCK();
+  } else {
+    for (int l = lc; l < level; ++l) {
+      Section& U = c->lv[l].U;
+      const int wnew = c->wu(l, level);
+      if (wnew > U.w) launch_widen(U.ref(), wnew - U.w, c->st);
+      U.w = wnew;
+    }
+    D.U.w = c->wu(level, level);
+    launch_zero_section(D.U.ref(), c->st);
+    launch_inject(f, c->p.L, D.g, D.f64, c->st);
+    KCK();
+  }
+  c->Lp = level;
+}
+
+template <typename T>
+void compact_fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
+  const int L = c->p.L;
+  for (int level = c->lc(); level <= L; ++level) {
+    enter_level(c, level, f);
+    if (level == c->lc()) continue;
+    const int iters = c->o.ir_iters + (level == L ? c->o.final_iters : 0);
+    for (int it = 0; it < iters; ++it) {
+      ir_residual(c, level, st);
+      vcycle_correct<T>(c, level);
+    }
+  }
+  decode_chain(c, L);
+  launch_to_full(c->lv[L].uh, c->lv[L].g, u, c->st);
+  KCK();
+}
+
+// Correction-scheme V(nu1, nu2) cycle (supplement Sec. SM1.1.1) on rf[Lp];
+// result in yf[Lp].
+template <typename T>
+void cs_vcycle(cmg_ctx c, int Lp) {
+  const int lc = c->lc();
+  hipStream_t st = c->st;
+  for (int l = Lp; l > lc; --l) {
+    LevelData& F = c->lv[l];
+    LevelData& C = c->lv[l - 1];
+    T* yf = static_cast<T*>(F.yf);
+    T* rf = static_cast<T*>(F.rf);
+    T* zf = static_cast<T*>(F.zf);
+    launch_fill<T>(yf, T(0), F.g.size, st);
+    smooth<T>(c, l, yf, rf, zf, c->o.nu_pre);
+    launch_rhs_minus_A<T>(rf, yf, kapT<T>(c, l), F.g, static_cast<T>(inv_h2(l)), zf, st);
+    launch_restrict<T>(zf, C.g, F.g, static_cast<T*>(C.rf), st);
+    KCK();
+  }
+  LevelData& B = c->lv[lc];
+  launch_convert<T, double>(static_cast<T*>(B.rf), B.t64, B.g.size, st);
+  launch_coarse_single(B.t64, kap64(c, lc), B.g, inv_h2(lc), B.s64, st);
+  launch_convert<double, T>(B.s64, static_cast<T*>(B.yf), B.g.size, st);
+  KCK();
+  for (int l = lc + 1; l <= Lp; ++l) {
+    LevelData& F = c->lv[l];
+    LevelData& C = c->lv[l - 1];
+    T* yf = static_cast<T*>(F.yf);
+    T* zf = static_cast<T*>(F.zf);
+    launch_prolong<T>(static_cast<T*>(C.yf), F.g, C.g, zf, st);
+    launch_add<T>(yf, zf, yf, F.g.size, st);
+    KCK();
+    smooth<T>(c, l, yf, static_cast<T*>(F.rf), zf, c->o.nu_post);
+  }
+}
+
+template <typename T>
+void plain_fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
+  const int L = c->p.L, lc = c->lc();
+  hipStream_t s = c->st;
+  LevelData& B = c->lv[lc];
+  launch_inject(f, L, B.g, B.f64, s);
+  launch_coarse_single(B.f64, kap64(c, lc), B.g, inv_h2(lc), B.uh, s);
+  KCK();
+  for (int level = lc + 1; level <= L; ++level) {
+    LevelData& F = c->lv[level];
+    launch_prolong<double>(c->lv[level - 1].uh, F.g, c->lv[level - 1].g, F.uh, s);
+    launch_inject(f, L, F.g, F.f64, s);
+    KCK();
+    const int iters = c->o.ir_iters + (level == L ? c->o.final_iters : 0);
+    for (int it = 0; it < iters; ++it) {
+      launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, level), F.g, inv_h2(level), F.t64, s);
+      launch_check_finite(F.t64, F.g.size, c->flags, s);
+      KCK();
+      if (st != nullptr && st->record && st->count < 256) {
+        HIPCK(hipMemsetAsync(c->red, 0, 8, s));
+        launch_sumsq(F.t64, F.g.size, c->red, s);
+        double h = 0.0;
+        HIPCK(hipMemcpyAsync(&h, c->red, 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        st->residual_norm[st->count++] = std::sqrt(h);
+      }
+      launch_convert<double, T>(F.t64, static_cast<T*>(F.rf), F.g.size, s);
+      cs_vcycle<T>(c, level);
+      launch_convert<T, double>(static_cast<T*>(F.yf), F.t64, F.g.size, s);
+      launch_add<double>(F.uh, F.t64, F.uh, F.g.size, s);
+      KCK();
+    }
+  }
+  launch_to_full(c->lv[L].uh, c->lv[L].g, u, s);
+  KCK();
+}
+
+void fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
+  const bool f32 = c->o.vcycle_prec == CMG_FP32;
+  if (c->compact()) {
+    if (f32) compact_fmg_one<float>(c, f, u, st);
+    else compact_fmg_one<double>(c, f, u, st);
+  } else {
+    if (f32) plain_fmg_one<float>(c, f, u, st);
+    else plain_fmg_one<double>(c, f, u, st);
+  }
+}
+
+void check_flags(cmg_ctx c) {
+  int h[2] = {0, 0};
+  HIPCK(hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->st));
+  HIPCK(hipStreamSynchronize(c->st));
+  if (h[1]) {
+    HIPCK(hipMemsetAsync(c->flags, 0, 8, c->st));
+    fail(CMG_ERR_NONFINITE, "non-finite value met during the solve (NaN/Inf in the input?)");
+  }
+}
+
+template <typename Fn>
+cmg_status guard(cmg_ctx c, Fn&& fn) {
+  try {
+    if (c != nullptr && c->dead) fail(CMG_ERR_INVALID_ARG, "context unusable after an earlier HIP failure");
+    fn();
+    return CMG_OK;
+  } catch (const CmgError& e) {
+    if (c != nullptr) {
+      c->err = e.msg;
+      if (e.code == CMG_ERR_HIP || e.code == CMG_ERR_OUT_OF_MEMORY) c->dead = true;
+    } else {
+      g_thread_error = e.msg;
+    }
+    return e.code;
+  } catch (const std::exception& e) {
+    if (c != nullptr) c->err = e.what(); else g_thread_error = e.what();
+    return CMG_ERR_HIP;
+  } catch (...) {
+    if (c != nullptr) c->err = "unknown error"; else g_thread_error = "unknown error";
+    return CMG_ERR_HIP;
+  }
+}
+
+void need(bool ok, const char* msg) {
+  if (!ok) fail(CMG_ERR_INVALID_ARG, msg);
+}
+
+Section& section_of(cmg_ctx c, int which, int level) {
+  if (!c->compact()) fail(CMG_ERR_UNSUPPORTED, "plain storage has no compact sections");
+  need(level >= c->lc() && level <= c->p.L, "level out of range");
+  LevelData& D = c->lv[level];
+  if (which == CMG_SECTION_U) return D.U;
+  if (which == CMG_SECTION_R) return D.G;
+  if (which == CMG_SECTION_Y) return D.Y;
+  fail(CMG_ERR_INVALID_ARG, "unknown section kind");
+}
+
+void release(cmg_ctx c) {
+  (void)hipStreamSynchronize(c->st);
+  for (void* ptr : c->allocs) (void)hipFree(ptr);
+  c->allocs.clear();
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+cmg_status cmg_default_opts(cmg_opts* o) {
+  if (o == nullptr) {
+    g_thread_error = "options must not be NULL";
+    return CMG_ERR_INVALID_ARG;
+  }
+  std::memset(o, 0, sizeof(*o));
+  o->smoother = CMG_RBGS;
+  o->omega = 0.8;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->ir_iters = 2;
+  o->vcycles = 1;
+  o->final_iters = 0;
+  o->storage = CMG_COMPACT_BFP;
+  o->bfp_block = 64;
+  o->bits_u = o->bits_r = o->bits_y = 16;
+  o->inc_u = 2;
+  o->inc_ry = 1;
+  o->vcycle_prec = CMG_FP32;
+  return CMG_OK;
+}
+
+cmg_status cmg_setup(const cmg_problem* p, const cmg_opts* o, const double* kappa_cells, void* hip_stream,
+                     cmg_ctx* out) {
+  if (out == nullptr) {
+    g_thread_error = "out must not be NULL";
+    return CMG_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  cmg_status s = guard(nullptr, [&] {
+    validate(p, o);
+    if (p->op == CMG_DIFFUSION && kappa_cells == nullptr) fail(CMG_ERR_INVALID_ARG, "diffusion needs kappa");
+  });
+  if (s != CMG_OK) return s;
+  cmg_ctx c = new (std::nothrow) cmg_ctx_s();
+  if (c == nullptr) {
+    g_thread_error = "host allocation failed";
+    return CMG_ERR_OUT_OF_MEMORY;
+  }
+  c->p = *p;
+  c->o = *o;
+  c->st = static_cast<hipStream_t>(hip_stream);
+  s = guard(c, [&] { setup_levels(c, kappa_cells); });
+  if (s != CMG_OK) {
+    g_thread_error = c->err;
+    try {
+      release(c);
+    } catch (...) {
+    }
+    delete c;
+    return s;
+  }
+  *out = c;
+  return CMG_OK;
+}
+
+cmg_status cmg_fmg_solve(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    need(f != nullptr && u != nullptr, "f and u must not be NULL");
+    if (st != nullptr) st->count = 0;
+    const int64_t M = c->full_size(c->p.L);
+    for (int b = 0; b < c->p.batch; ++b) fmg_one(c, f + b * M, u + b * M, st);
+    check_flags(c);
+  });
+}
+
+cmg_status cmg_vcycle(cmg_ctx c, const double* r, double* y) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    need(r != nullptr && y != nullptr, "r and y must not be NULL");
+    const int L = c->p.L, lc = c->lc();
+    const int64_t M = c->full_size(L);
+    const bool f32 = c->o.vcycle_prec == CMG_FP32;
+    for (int b = 0; b < c->p.batch; ++b) {
+      LevelData& F = c->lv[L];
+      launch_inject(r + b * M, L, F.g, F.t64, c->st);
+      KCK();
+      if (c->compact()) {
+        F.G.w = c->wr(L, L);
+        launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
+        for (int l = lc; l <= L; ++l) {
+          c->lv[l].U.w = c->wu(l, L);
+          launch_zero_section(c->lv[l].U.ref(), c->st);
+        }
+        KCK();
+        c->Lp = L;
+        if (f32) vcycle_correct<float>(c, L); else vcycle_correct<double>(c, L);
+        decode_chain(c, L);
+        launch_to_full(F.uh, F.g, y + b * M, c->st);
+      } else {
+        if (f32) {
+          launch_convert<double, float>(F.t64, static_cast<float*>(F.rf), F.g.size, c->st);
+          cs_vcycle<float>(c, L);
+          launch_convert<float, double>(static_cast<float*>(F.yf), F.uh, F.g.size, c->st);
+        } else {
+          launch_convert<double, double>(F.t64, static_cast<double*>(F.rf), F.g.size, c->st);
+          cs_vcycle<double>(c, L);
+          launch_convert<double, double>(static_cast<double*>(F.yf), F.uh, F.g.size, c->st);
+        }
+        launch_to_full(F.uh, F.g, y + b * M, c->st);
+      }
+      KCK();
+    }
+    check_flags(c);
+  });
+}
+
+cmg_status cmg_adjoint_solve(cmg_ctx c, const double* u, const double* dJdu, double* lambda, double* grad_kappa) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    need(u != nullptr && dJdu != nullptr && lambda != nullptr, "u, dJdu and lambda must not be NULL");
+    if (grad_kappa != nullptr && c->p.op != CMG_DIFFUSION)
+      fail(CMG_ERR_INVALID_ARG, "grad_kappa needs the diffusion operator");
+    const int64_t M = c->full_size(c->p.L);
+    const Geom gcell = make_geom(c->p.dim, c->p.L);
+    for (int b = 0; b < c->p.batch; ++b) {
+      fmg_one(c, dJdu + b * M, lambda + b * M, nullptr);
+      if (grad_kappa != nullptr) {
+        launch_grad_kappa(u + b * M, lambda + b * M, gcell, b > 0 ? 1 : 0, grad_kappa, c->st);
+        KCK();
+      }
+    }
+    check_flags(c);
+  });
+}
+
+cmg_status cmg_destroy(cmg_ctx c) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  try {
+    release(c);
+  } catch (...) {
+  }
+  delete c;
+  return CMG_OK;
+}
+
+const char* cmg_last_error(cmg_ctx c) { return c != nullptr ? c->err.c_str() : g_thread_error.c_str(); }
+
+int64_t cmg_bfp_code_bytes(int64_t n, int32_t block, int32_t bits) {
+  if (n < 0 || (block != 32 && block != 64) || bits < 2 || bits > 53) return -1;
+  return code_bytes(n, block, bits);
+}
+
+cmg_status cmg_bfp_encode(const void* x, int32_t x_is_f64, int64_t n, int32_t block, int32_t bits, void* codes,
+                          int16_t* exps, void* hip_stream) {
+  return guard(nullptr, [&] {
+    need(n >= 0 && (block == 32 || block == 64) && bits >= 2 && bits <= 53, "bad size, block or bits");
+    need(n == 0 || (x != nullptr && codes != nullptr && exps != nullptr), "NULL buffer");
+    if (n == 0) return;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    SecRef s{codes, exps, n, block, bits, container_bits(bits)};
+    int* flag = nullptr;
+    HIPCK(hipMalloc(&flag, sizeof(int)));
+    int h = 0;
+    try {
+      HIPCK(hipMemsetAsync(flag, 0, sizeof(int), st));
+      if (x_is_f64) launch_encode<double>(static_cast<const double*>(x), n, s, flag, st);
+      else launch_encode<float>(static_cast<const float*>(x), n, s, flag, st);
+      KCK();
+      HIPCK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCK(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipFree(flag);
+      throw;
+    }
+    HIPCK(hipFree(flag));
+    if (h) fail(CMG_ERR_NONFINITE, "codec input holds NaN or Inf");
+  });
+}
+
+cmg_status cmg_bfp_decode(const void* codes, const int16_t* exps, int64_t n, int32_t block, int32_t bits, double* x,
+                          void* hip_stream) {
+  return guard(nullptr, [&] {
+    need(n >= 0 && (block == 32 || block == 64) && bits >= 2 && bits <= 53, "bad size, block or bits");
+    need(n == 0 || (x != nullptr && codes != nullptr && exps != nullptr), "NULL buffer");
+    if (n == 0) return;
+    SecRef s{const_cast<void*>(codes), const_cast<int16_t*>(exps), n, block, bits, container_bits(bits)};
+    launch_decode<double>(s, n, x, static_cast<hipStream_t>(hip_stream));
+    KCK();
+  });
+}
+
+cmg_status cmg_section_info(cmg_ctx c, int32_t which, int32_t level, int64_t* n_values, int32_t* bits,
+                            int32_t* cbits, int64_t* bytes, int64_t* nblk) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    Section& s = section_of(c, which, level);
+    if (n_values) *n_values = s.n;
+    if (bits) *bits = s.w;
+    if (cbits) *cbits = s.cbits;
+    if (bytes) *bytes = s.bytes;
+    if (nblk) *nblk = s.nblk;
+  });
+}
+
+cmg_status cmg_export_section(cmg_ctx c, int32_t which, int32_t level, void* codes_host, int16_t* exps_host) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    Section& s = section_of(c, which, level);
+    need(codes_host != nullptr && exps_host != nullptr, "NULL buffer");
+    HIPCK(hipMemcpyAsync(codes_host, s.codes, static_cast<size_t>(s.bytes), hipMemcpyDeviceToHost, c->st));
+    HIPCK(hipMemcpyAsync(exps_host, s.exps, static_cast<size_t>(s.nblk) * 2, hipMemcpyDeviceToHost, c->st));
+    HIPCK(hipStreamSynchronize(c->st));
+  });
+}
+
+cmg_status cmg_import_section(cmg_ctx c, int32_t which, int32_t level, int32_t bits, const void* codes_host,
+                              const int16_t* exps_host) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    Section& s = section_of(c, which, level);
+    need(codes_host != nullptr && exps_host != nullptr, "NULL buffer");
+    need(bits >= 2 && container_bits(bits) <= s.cbits && bits <= 53, "bits do not fit the section's container");
+    need(container_bits(bits) == s.cbits || s.cbits != 12, "12-bit container needs 9..12 bits");
+    HIPCK(hipMemcpyAsync(s.codes, codes_host, static_cast<size_t>(s.bytes), hipMemcpyHostToDevice, c->st));
+    HIPCK(hipMemcpyAsync(s.exps, exps_host, static_cast<size_t>(s.nblk) * 2, hipMemcpyHostToDevice, c->st));
+    HIPCK(hipStreamSynchronize(c->st));
+    s.w = bits;
+  });
+}
+
+cmg_status cmg_fmg_enter_level(cmg_ctx c, int32_t level, const double* f) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    if (!c->compact()) fail(CMG_ERR_UNSUPPORTED, "stepwise driving needs compact storage");
+    need(f != nullptr, "f must not be NULL");
+    need(level == c->lc() || (level == c->Lp + 1 && level <= c->p.L),
+         "levels are entered in order, starting at the coarsest");
+    enter_level(c, level, f);
+  });
+}
+
+cmg_status cmg_ir_residual(cmg_ctx c, const double* f) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    need(f != nullptr, "f must not be NULL");
+    need(c->Lp > c->lc(), "enter an FMG level above the coarsest first");
+    launch_inject(f, c->p.L, c->lv[c->Lp].g, c->lv[c->Lp].f64, c->st);
+    KCK();
+    ir_residual(c, c->Lp, nullptr);
+  });
+}
+
+cmg_status cmg_vcycle_correct(cmg_ctx c) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    need(c->Lp > c->lc(), "enter an FMG level above the coarsest first");
+    if (c->o.vcycle_prec == CMG_FP32) vcycle_correct<float>(c, c->Lp);
+    else vcycle_correct<double>(c, c->Lp);
+  });
+}
+
+cmg_status cmg_decode_solution(cmg_ctx c, double* u) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    need(u != nullptr, "u must not be NULL");
+    need(c->Lp >= c->lc(), "no FMG level entered");
+    decode_chain(c, c->Lp);
+    launch_to_full(c->lv[c->Lp].uh, c->lv[c->Lp].g, u, c->st);
+    KCK();
+  });
+}
+
+cmg_status cmg_memory_stats(cmg_ctx c, cmg_mem* out) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    need(out != nullptr, "out must not be NULL");
+    std::memset(out, 0, sizeof(*out));
+    out->sections = c->mem[kSections];
+    out->coarse_fp64 = c->mem[kCoarse64];
+    out->coarse_work = c->mem[kCoarseWork];
+    out->fine_work = c->mem[kFineWork];
+    out->kappa = c->mem[kKappa];
+    int64_t total = 0;
+    for (int i = 0; i < kNumCat; ++i) total += c->mem[i];
+    out->total = total;
+    const int L = c->p.L;
+    int64_t m = (int64_t{1} << L) - 1;
+    out->interior_dofs = c->p.dim == 3 ? m * m * m : m * m;
+    double bits = 0.0;
+    for (int l = c->lc(); l <= L; ++l) {
+      const double n = static_cast<double>(int64_t{1} << (c->p.dim * l));
+      if (c->compact()) {
+        const double nb = static_cast<double>(n_blocks(static_cast<int64_t>(n), c->o.bfp_block));
+        bits += n * (c->wu(l, L) + c->wr(l, L) + c->wy(l, L)) + 3.0 * 16.0 * nb;
+      } else {
+        bits += 64.0 * n * (l == L ? 3.0 : 2.0);
+      }
+    }
+    out->logical_bits_per_dof = bits / static_cast<double>(out->interior_dofs);
+  });
+}
+
+}  // extern "C"

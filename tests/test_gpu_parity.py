@@ -1,0 +1,229 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+* BFP codec: bit-exact codes and exponents, exact decode, over widths,
+  block sizes, ragged lengths and both input types;
+* one IR residual (Alg. 2) on identical imported sections: bit-exact codes;
+* one compact V-cycle plus correction on identical inputs against the
+  oracle run in float32 (the GPU V-cycle precision): bit-exact sections;
+* whole compact FMG, plain FP64 FMG, the V-cycle entry and the adjoint
+  gradient against the oracle on small grids spanning many BFP blocks.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as S
+from oracle import adjoint as oa
+from oracle import bfp as ob
+from oracle import compact as oc
+from oracle import grid as og
+from oracle import plain as op
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cmg(gpu_lib):
+    import paper_2511_19036_amd
+    return paper_2511_19036_amd
+
+
+def _codes(codes_u8, w, count):
+    return ob.unpack(np.ascontiguousarray(codes_u8).tobytes(), w, count)
+
+
+# ------------------------------------------------------------------ codec
+@pytest.mark.parametrize("n", [1, 63, 1000, 4097])
+@pytest.mark.parametrize("w", [2, 3, 8, 11, 12, 16, 17, 24, 33, 53])
+@pytest.mark.parametrize("B", [32, 64])
+@pytest.mark.parametrize("f64", [True, False])
+def test_codec_bit_exact(cmg, n, w, B, f64):
+    rng = np.random.default_rng(n * 1000 + w * 10 + B)
+    x = rng.standard_normal(n) * np.exp(rng.uniform(-20, 20, n))
+    x[::7] = 0.0                                # zero entries and (for small n) zero blocks
+    if n > 200:
+        x[128:192] = 0.0                        # an all-zero block
+        x[200] = 2.5 * 2.0 ** -30               # tie cases scaled into a block
+    if not f64:
+        x = x.astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    codes, exps = cmg.bfp_encode(xt, B, w)
+    m_ref, e_ref = ob.encode(x, B, w)
+    nb = (n + B - 1) // B
+    assert np.array_equal(exps.cpu().numpy()[:nb], e_ref)
+    assert np.array_equal(_codes(codes.cpu().numpy(), w, nb * B), m_ref)
+    dec = cmg.bfp_decode(codes, exps, n, B, w).cpu().numpy()
+    assert np.array_equal(dec, ob.decode(m_ref, e_ref, B, w, n))
+
+
+def test_codec_rejects_nonfinite(cmg):
+    x = torch.zeros(100, dtype=torch.float64, device="cuda")
+    x[17] = float("nan")
+    with pytest.raises(cmg.CmgError) as ei:
+        cmg.bfp_encode(x, 64, 8)
+    assert ei.value.status == 5
+
+
+# ------------------------------------------------------------ step parity
+CFGS = {
+    "3d-rbgs-b16": dict(dim=3, L=5, smoother="rbgs", omega=1.0, block=64, bits=16),
+    "3d-rbgs-b8": dict(dim=3, L=5, smoother="rbgs", omega=1.0, block=64, bits=8),
+    "3d-rbgs-b12": dict(dim=3, L=5, smoother="rbgs", omega=1.0, block=64, bits=12),
+    "2d-wjacobi-b16": dict(dim=2, L=7, smoother="wjacobi", omega=0.8, block=32, bits=16),
+    "2d-wjacobi-b11": dict(dim=2, L=6, smoother="wjacobi", omega=0.8, block=32, bits=11),
+}
+
+
+def _oracle_cfg(c, **kw):
+    return oc.Config(dim=c["dim"], L=c["L"], smoother=c["smoother"], omega=c["omega"], block=c["block"],
+                     bits_u=c["bits"], bits_r=c["bits"], bits_y=c["bits"], **kw)
+
+
+def _solver(cmg, c, **kw):
+    return cmg.Solver(c["dim"], c["L"], smoother=c["smoother"], omega=c["omega"], bfp_block=c["block"],
+                      bits=c["bits"], **kw)
+
+
+def _random_sections(cfg, Lp, seed):
+    rng = np.random.default_rng(seed)
+    U = {}
+    for level in range(cfg.coarsest, Lp + 1):
+        n = 1 << level
+        x = np.zeros((n,) * cfg.dim)
+        x[(slice(1, None),) * cfg.dim] = rng.standard_normal((n - 1,) * cfg.dim) * 2.0 ** (-2 * level)
+        U[level] = oc.Section.quantize(x, cfg.block, cfg.w_u(level, Lp))
+    return U
+
+
+def _enter_all(s, L, f):
+    for level in range(1, L + 1):
+        s.enter_level(level, f)
+
+
+def _export(s, which, level):
+    codes, exps, bits = s.export_section(which, level)
+    nb = exps.size
+    return _codes(codes, bits, nb * s.opts.bfp_block), exps, bits
+
+
+@pytest.mark.parametrize("name", list(CFGS))
+def test_ir_residual_bit_exact(cmg, name):
+    c = CFGS[name]
+    cfg = _oracle_cfg(c)
+    L = c["L"]
+    f_np = S.gaussian_noise_rhs(c["dim"], L, sigma=0.1, seed=1)
+    f = torch.from_numpy(f_np).cuda()
+    U = _random_sections(cfg, L, 5)
+    with _solver(cmg, c) as s:
+        _enter_all(s, L, f)
+        for level, sec in U.items():
+            s.import_section("u", level, sec.w, np.frombuffer(ob.pack(sec.m, sec.w), dtype=np.uint8), sec.e)
+        s.ir_residual(f)
+        m, e, bits = _export(s, "r", L)
+    ops = og.hierarchy(c["dim"], L, 1)
+    g = oc.ir_residual(U, og.inject(f_np, L, L), ops, cfg, L)
+    assert bits == g.w
+    assert np.array_equal(e, g.e)
+    assert np.array_equal(m, g.m)
+
+
+@pytest.mark.parametrize("name", list(CFGS))
+def test_vcycle_step_bit_exact(cmg, name):
+    c = CFGS[name]
+    cfg = _oracle_cfg(c)
+    L = c["L"]
+    f_np = S.gaussian_noise_rhs(c["dim"], L, sigma=0.1, seed=2)
+    f = torch.from_numpy(f_np).cuda()
+    U = _random_sections(cfg, L, 7)
+    with _solver(cmg, c) as s:
+        _enter_all(s, L, f)
+        for level, sec in U.items():
+            s.import_section("u", level, sec.w, np.frombuffer(ob.pack(sec.m, sec.w), dtype=np.uint8), sec.e)
+        s.ir_residual(f)
+        s.vcycle_correct()
+        got = {(w, level): _export(s, w, level) for w in ("u", "y", "r") for level in range(1, L + 1)}
+    ops = og.hierarchy(c["dim"], L, 1)
+    g = oc.ir_residual(U, og.inject(f_np, L, L), ops, cfg, L)
+    trace = {}
+    Y = oc.vcycle_correct(U, g, ops, cfg, L, trace=trace)
+    for level in range(1, L + 1):
+        for which, sec in (("u", U[level]), ("y", Y[level]), ("r", trace["G"][level])):
+            m, e, bits = got[(which, level)]
+            assert bits == sec.w, (which, level)
+            assert np.array_equal(e, sec.e), (which, level)
+            assert np.array_equal(m, sec.m), (which, level)
+
+
+# ------------------------------------------------------------ whole solves
+@pytest.mark.parametrize("name", list(CFGS))
+def test_compact_fmg_matches_oracle(cmg, name):
+    c = CFGS[name]
+    cfg = _oracle_cfg(c)
+    L = c["L"]
+    f_np = S.gaussian_noise_rhs(c["dim"], L, sigma=1e-3, seed=0)
+    with _solver(cmg, c) as s:
+        u = s.solve(torch.from_numpy(f_np).cuda()[None])[0].cpu().numpy()
+        secs = {level: _export(s, "u", level) for level in range(1, L + 1)}
+    u_ref, U = oc.fmg_solve(f_np, cfg)
+    for level in range(1, L + 1):
+        m, e, bits = secs[level]
+        assert bits == U[level].w
+        assert np.array_equal(e, U[level].e) and np.array_equal(m, U[level].m), level
+    assert np.array_equal(u, u_ref)
+
+
+@pytest.mark.parametrize("dim,L,smoother,omega", [(2, 6, "wjacobi", 0.8), (3, 5, "rbgs", 1.0)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plain_fmg_matches_oracle(cmg, dim, L, smoother, omega, prec):
+    f_np = S.gaussian_noise_rhs(dim, L, sigma=1e-3, seed=3)
+    cfg = oc.Config(dim=dim, L=L, smoother=smoother, omega=omega)
+    T = np.float64 if prec == "fp64" else np.float32
+    with cmg.Solver(dim, L, smoother=smoother, omega=omega, storage="plain", vcycle_prec=prec) as s:
+        u = s.solve(torch.from_numpy(f_np).cuda()[None])[0].cpu().numpy()
+    u_ref = op.fmg_solve(f_np, cfg, vcycle_dtype=T)
+    assert np.array_equal(u, u_ref)
+
+
+@pytest.mark.parametrize("name", ["3d-rbgs-b16", "2d-wjacobi-b16"])
+def test_vcycle_entry_matches_oracle(cmg, name):
+    c = CFGS[name]
+    cfg = _oracle_cfg(c)
+    r_np = S.gaussian_noise_rhs(c["dim"], c["L"], sigma=1.0, seed=9)
+    with _solver(cmg, c) as s:
+        y = s.vcycle(torch.from_numpy(r_np).cuda()[None])[0].cpu().numpy()
+    assert np.array_equal(y, oc.vcycle_standard(r_np, cfg))
+
+
+@pytest.mark.parametrize("dim,L,smoother,omega,block", [(3, 4, "rbgs", 1.0, 64), (2, 5, "wjacobi", 0.8, 32)])
+def test_diffusion_fmg_and_gradient_match_oracle(cmg, dim, L, smoother, omega, block):
+    kappa = S.lognormal_kappa(dim, L, 0.2, 1)
+    kobs = S.lognormal_kappa(dim, L, 0.2, 2)
+    f_np = np.zeros(((1 << L) + 1,) * dim)
+    f_np[(slice(1, -1),) * dim] = 1.0
+    cfg = oc.Config(dim=dim, L=L, op="diffusion", smoother=smoother, omega=omega, block=block)
+    u_ref, _ = oc.fmg_solve(f_np, cfg, kappa)
+    uobs, _ = oc.fmg_solve(f_np, cfg, kobs)
+    dj = oa.loss_grad_u(u_ref, uobs)
+    lam_ref, _ = oc.fmg_solve(dj, cfg, kappa)
+    g_ref = oa.grad_kappa(u_ref, lam_ref)
+    kt = torch.from_numpy(kappa).cuda()
+    with cmg.Solver(dim, L, op="diffusion", kappa=kt, smoother=smoother, omega=omega, bfp_block=block) as s:
+        u = s.solve(torch.from_numpy(f_np).cuda()[None])
+        assert np.array_equal(u[0].cpu().numpy(), u_ref)
+        lam, g = s.adjoint(u, torch.from_numpy(dj).cuda()[None])
+    assert np.array_equal(lam[0].cpu().numpy(), lam_ref)
+    assert np.array_equal(g.cpu().numpy(), g_ref)
+
+
+# ------------------------------------------------------------ accuracy
+@pytest.mark.parametrize("bits", [8, 12, 16])
+def test_gpu_fmg_discretisation_accuracy_3d(cmg, bits):
+    dim, L = 3, 7
+    h = 2.0 ** -L
+    us = S.sine_solution(dim, L)
+    uh = ((np.pi * h / 2) / np.sin(np.pi * h / 2)) ** 2 * us
+    with cmg.Solver(dim, L, smoother="rbgs", bits=bits) as s:
+        u = s.solve(torch.from_numpy(S.sine_rhs(dim, L)).cuda()[None])[0].cpu().numpy()
+    disc = og.norm_h(uh - us, h)
+    assert og.norm_h(u - us, h) <= 2.0 * disc
+    assert og.norm_h(u - uh, h) <= 0.5 * disc
