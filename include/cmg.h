@@ -233,6 +233,24 @@ cmg_status cmg_decode_solution(cmg_ctx ctx, double* u);
 /* Device memory of the context by category. */
 cmg_status cmg_memory_stats(cmg_ctx ctx, cmg_mem* out);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing for benchmarks.  While enabled, every kernel launch the
+ * context makes (or only launches of the kernel named `kernel`, if not NULL)
+ * is bracketed by two HIP events on the context stream, and its algorithmic
+ * bytes (each operand read or written once) are recorded.  Each API call
+ * that launches kernels waits for its events before returning and adds the
+ * durations to per-kernel totals.  Enabling (or disabling) clears the totals.
+ * ------------------------------------------------------------------------- */
+cmg_status cmg_timing_enable(cmg_ctx ctx, int32_t enable, const char* kernel);
+
+/* Number of distinct kernels with recorded launches. */
+cmg_status cmg_timing_count(cmg_ctx ctx, int32_t* count);
+
+/* Totals of one kernel: name (NUL-terminated, truncated to name_len), launch
+ * count, summed event time in milliseconds and summed algorithmic bytes. */
+cmg_status cmg_timing_entry(cmg_ctx ctx, int32_t index, char* name, int32_t name_len, int64_t* launches,
+                            double* total_ms, double* total_bytes);
+
 #ifdef __cplusplus
 }
 #endif

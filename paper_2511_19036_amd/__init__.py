@@ -200,6 +200,23 @@ class Solver:
                                                 codes.ctypes.data_as(C.c_void_p),
                                                 exps.ctypes.data_as(C.c_void_p)))
 
+    def timing(self, enable: bool = True, kernel: str | None = None):
+        """Start (clearing totals) or stop per-kernel event timing."""
+        self._check(self.lib.cmg_timing_enable(self.ctx, 1 if enable else 0,
+                                               kernel.encode() if kernel else None))
+
+    def timing_report(self) -> list[dict]:
+        """Per-kernel launches, total ms and total algorithmic bytes."""
+        cnt = C.c_int32()
+        self._check(self.lib.cmg_timing_count(self.ctx, C.byref(cnt)))
+        out = []
+        for i in range(cnt.value):
+            name = C.create_string_buffer(128)
+            n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+            self._check(self.lib.cmg_timing_entry(self.ctx, i, name, 128, C.byref(n), C.byref(ms), C.byref(b)))
+            out.append(dict(kernel=name.value.decode(), launches=n.value, ms=ms.value, bytes=b.value))
+        return sorted(out, key=lambda r: -r["ms"])
+
     def memory_stats(self) -> dict:
         m = _lib.cmg_mem()
         self._check(self.lib.cmg_memory_stats(self.ctx, C.byref(m)))

@@ -81,6 +81,10 @@ SIGNATURES = {
     "cmg_vcycle_correct": (_ST, [_P]),
     "cmg_decode_solution": (_ST, [_P, _P]),
     "cmg_memory_stats": (_ST, [_P, C.POINTER(cmg_mem)]),
+    "cmg_timing_enable": (_ST, [_P, _I32, C.c_char_p]),
+    "cmg_timing_count": (_ST, [_P, C.POINTER(_I32)]),
+    "cmg_timing_entry": (_ST, [_P, _I32, C.c_char_p, _I32, C.POINTER(_I64), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double)]),
 }
 
 _lib = None

@@ -7,8 +7,11 @@
 // thread owns one node of the padded level layout; BFP kernels give one
 // wave to 64 consecutive values (one block of 64 or two of 32) so that the
 // shared exponent is a wave-level max reduction.
+#include <string>
+
 #include "device.h"
 #include "launch.h"
+#include "timing.h"
 
 namespace cmg {
 
@@ -365,97 +368,135 @@ __global__ void __launch_bounds__(kThreads) k_sumsq(const double* __restrict__ x
 }
 
 // ============================================================== launchers
-#define CMG_LAUNCH(kernel, n, stream, ...) \
-  hipLaunchKernelGGL(kernel, grid_for(n), dim3(kThreads), 0, stream, __VA_ARGS__)
+thread_local KernelTiming* g_timing = nullptr;
+
+template <typename T> struct TName;
+template <> struct TName<float> { static constexpr const char* s = "float"; };
+template <> struct TName<double> { static constexpr const char* s = "double"; };
+
+// Launch `kernel` over n threads, timed when a timing sink is active.
+#define CMG_TLAUNCH(name, nbytes, kernel, n, stream, ...)                                 \
+  do {                                                                                    \
+    if (g_timing != nullptr) g_timing->begin((name), static_cast<double>(nbytes), stream); \
+    hipLaunchKernelGGL(kernel, grid_for(n), dim3(kThreads), 0, stream, __VA_ARGS__);       \
+    if (g_timing != nullptr) g_timing->end(stream);                                       \
+  } while (0)
+
+static inline std::string tname(const char* base, const char* t) { return std::string(base) + "<" + t + ">"; }
+static inline double sec_bytes(const SecRef& s) {
+  const double nb = static_cast<double>((s.n + s.B - 1) / s.B);
+  return nb * s.B * s.cbits / 8.0 + 2.0 * nb;
+}
 
 template <typename T>
 void launch_encode(const T* x, int64_t n, const SecRef& s, int* nonfinite, hipStream_t st) {
   const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
-  CMG_LAUNCH(k_encode<T>, limit, st, x, n, s, nonfinite);
+  CMG_TLAUNCH(tname("k_encode", TName<T>::s).c_str(), n * sizeof(T) + sec_bytes(s), k_encode<T>, limit, st, x, n,
+              s, nonfinite);
 }
 template <typename T>
 void launch_decode(const SecRef& s, int64_t n, T* x, hipStream_t st) {
-  CMG_LAUNCH(k_decode<T>, n, st, s, n, x);
+  CMG_TLAUNCH(tname("k_decode", TName<T>::s).c_str(), n * sizeof(T) + sec_bytes(s), k_decode<T>, n, st, s, n, x);
 }
 void launch_widen(const SecRef& s, int k, hipStream_t st) {
   const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
-  CMG_LAUNCH(k_widen, s.cbits == 12 ? limit / 2 : limit, st, s, k);
+  CMG_TLAUNCH("k_widen", 2.0 * (sec_bytes(s) - 2.0 * (limit / s.B)), k_widen, s.cbits == 12 ? limit / 2 : limit,
+              st, s, k);
 }
 void launch_zero_section(const SecRef& s, hipStream_t st) {
   const int64_t nb = (s.n + s.B - 1) / s.B;
   const int64_t words = (nb * s.B * s.cbits / 8 + 3) / 4;
-  CMG_LAUNCH(k_zero_section, words > nb ? words : nb, st, s);
+  CMG_TLAUNCH("k_zero_section", sec_bytes(s), k_zero_section, words > nb ? words : nb, st, s);
 }
 void launch_correct(const SecRef& u, const SecRef& y, hipStream_t st) {
   const int64_t limit = ((u.n + u.B - 1) / u.B) * u.B;
-  CMG_LAUNCH(k_correct, limit, st, u, y);
+  CMG_TLAUNCH("k_correct", 2.0 * sec_bytes(u) + sec_bytes(y), k_correct, limit, st, u, y);
 }
 template <typename T>
 void launch_rhs_minus_A(const T* rhs, const T* u, const T* kap, const Geom& g, T inv_h2, T* out, hipStream_t st) {
-  CMG_LAUNCH(k_rhs_minus_A<T>, g.size, st, rhs, u, kap, g, inv_h2, out);
+  const double b = (3.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
+  CMG_TLAUNCH(tname("k_rhs_minus_A", TName<T>::s).c_str(), b, k_rhs_minus_A<T>, g.size, st, rhs, u, kap, g, inv_h2,
+              out);
 }
 template <typename T>
 void launch_prolong(const T* coarse, const Geom& gf, const Geom& gc, T* fine, hipStream_t st) {
-  CMG_LAUNCH(k_prolong<T>, gf.size, st, coarse, gf, gc, fine);
+  CMG_TLAUNCH(tname("k_prolong", TName<T>::s).c_str(), (gf.size + gc.size) * sizeof(T), k_prolong<T>, gf.size, st,
+              coarse, gf, gc, fine);
 }
 void launch_prolong_add_dec(const SecRef& s, const double* coarse, const Geom& gf, const Geom& gc, double* out,
                             hipStream_t st) {
-  CMG_LAUNCH(k_prolong_add_dec, gf.size, st, s, coarse, gf, gc, out);
+  CMG_TLAUNCH("k_prolong_add_dec", sec_bytes(s) + 8.0 * (gf.size + gc.size), k_prolong_add_dec, gf.size, st, s,
+              coarse, gf, gc, out);
 }
 template <typename T>
 void launch_restrict(const T* fine, const Geom& gc, const Geom& gf, T* coarse, hipStream_t st) {
-  CMG_LAUNCH(k_restrict<T>, gc.size, st, fine, gc, gf, coarse);
+  CMG_TLAUNCH(tname("k_restrict", TName<T>::s).c_str(), (gf.size + gc.size) * sizeof(T), k_restrict<T>, gc.size,
+              st, fine, gc, gf, coarse);
 }
 template <typename T>
 void launch_jacobi(const T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, T omega, T* ynew,
                    hipStream_t st) {
-  CMG_LAUNCH(k_jacobi<T>, g.size, st, y, rhs, kap, g, inv_h2, cpois, omega, ynew);
+  const double b = (3.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
+  CMG_TLAUNCH(tname("k_jacobi", TName<T>::s).c_str(), b, k_jacobi<T>, g.size, st, y, rhs, kap, g, inv_h2, cpois,
+              omega, ynew);
 }
 template <typename T>
 void launch_rbgs(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, int colour, hipStream_t st) {
-  CMG_LAUNCH(k_rbgs<T>, g.size, st, y, rhs, kap, g, inv_h2, cpois, colour);
+  // reads y everywhere and rhs on one colour, writes y on one colour
+  const double b = (2.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
+  CMG_TLAUNCH(tname("k_rbgs", TName<T>::s).c_str(), b, k_rbgs<T>, g.size, st, y, rhs, kap, g, inv_h2, cpois,
+              colour);
 }
 template <typename T>
 void launch_add(const T* a, const T* b, T* out, int64_t n, hipStream_t st) {
-  CMG_LAUNCH(k_add<T>, n, st, a, b, out, n);
+  CMG_TLAUNCH(tname("k_add", TName<T>::s).c_str(), 3.0 * n * sizeof(T), k_add<T>, n, st, a, b, out, n);
 }
 template <typename T>
 void launch_fill(T* x, T v, int64_t n, hipStream_t st) {
-  CMG_LAUNCH(k_fill<T>, n, st, x, v, n);
+  CMG_TLAUNCH(tname("k_fill", TName<T>::s).c_str(), 1.0 * n * sizeof(T), k_fill<T>, n, st, x, v, n);
 }
 template <typename S, typename D>
 void launch_convert(const S* a, D* b, int64_t n, hipStream_t st) {
-  CMG_LAUNCH((k_convert<S, D>), n, st, a, b, n);
+  CMG_TLAUNCH((std::string("k_convert<") + TName<S>::s + "," + TName<D>::s + ">").c_str(),
+              1.0 * n * (sizeof(S) + sizeof(D)), (k_convert<S, D>), n, st, a, b, n);
 }
 void launch_inject(const double* full, int L, const Geom& g, double* out, hipStream_t st) {
-  CMG_LAUNCH(k_inject, g.size, st, full, L, g, out);
+  CMG_TLAUNCH("k_inject", 16.0 * g.size, k_inject, g.size, st, full, L, g, out);
 }
 void launch_to_full(const double* pad, const Geom& g, double* full, hipStream_t st) {
   const int64_t N = g.n + 1;
-  CMG_LAUNCH(k_to_full, g.dim == 3 ? N * N * N : N * N, st, pad, g, full);
+  const int64_t tot = g.dim == 3 ? N * N * N : N * N;
+  CMG_TLAUNCH("k_to_full", 8.0 * (g.size + tot), k_to_full, tot, st, pad, g, full);
 }
 void launch_coarse_single(const double* gin, const double* kap, const Geom& g, double inv_h2, double* y,
                           hipStream_t st) {
+  if (g_timing != nullptr) g_timing->begin("k_coarse_single", 16.0 * g.size, st);
   hipLaunchKernelGGL(k_coarse_single, dim3(1), dim3(64), 0, st, gin, kap, g, inv_h2, y);
+  if (g_timing != nullptr) g_timing->end(st);
 }
 void launch_coarsen_kappa(const double* fine, const Geom& gc, const Geom& gf, double* coarse, hipStream_t st) {
-  CMG_LAUNCH(k_coarsen_kappa, gc.size, st, fine, gc, gf, coarse);
+  CMG_TLAUNCH("k_coarsen_kappa", 8.0 * (gf.size + gc.size), k_coarsen_kappa, gc.size, st, fine, gc, gf, coarse);
 }
 void launch_check_positive(const double* x, int64_t n, int* flags, hipStream_t st) {
-  CMG_LAUNCH(k_check_positive, n, st, x, n, flags);
+  CMG_TLAUNCH("k_check_positive", 8.0 * n, k_check_positive, n, st, x, n, flags);
 }
 void launch_check_finite(const double* x, int64_t n, int* flags, hipStream_t st) {
-  CMG_LAUNCH(k_check_finite, n, st, x, n, flags);
+  CMG_TLAUNCH("k_check_finite", 8.0 * n, k_check_finite, n, st, x, n, flags);
 }
 void launch_grad_kappa(const double* u, const double* lam, const Geom& gcell, int accumulate, double* grad,
                        hipStream_t st) {
-  CMG_LAUNCH(k_grad_kappa, gcell.size, st, u, lam, gcell, accumulate, grad);
+  const double N = gcell.n + 1.0;
+  const double nodes = gcell.dim == 3 ? N * N * N : N * N;
+  CMG_TLAUNCH("k_grad_kappa", 16.0 * nodes + 8.0 * gcell.size * (accumulate ? 2 : 1), k_grad_kappa, gcell.size, st,
+              u, lam, gcell, accumulate, grad);
 }
 void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
   int64_t blocks = (n + kThreads - 1) / kThreads;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
+  if (g_timing != nullptr) g_timing->begin("k_sumsq", 8.0 * n, st);
   hipLaunchKernelGGL(k_sumsq, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, st, x, n, out);
+  if (g_timing != nullptr) g_timing->end(st);
 }
 
 #define CMG_INST_T(T)                                                                                   \

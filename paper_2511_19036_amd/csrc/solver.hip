@@ -15,6 +15,7 @@
 
 #include "cmg.h"
 #include "launch.h"
+#include "timing.h"
 
 using namespace cmg;
 
@@ -87,6 +88,8 @@ struct cmg_ctx_s {
   int* flags = nullptr;   // [0] non-positive kappa, [1] non-finite value
   double* red = nullptr;  // reduction scratch
   bool dead = false;
+  bool timing_on = false;
+  KernelTiming timing;
   std::string err;
 
   void* alloc(size_t bytes, MemCat cat) {
@@ -476,10 +479,22 @@ void check_flags(cmg_ctx c) {
   }
 }
 
+// Installs the context's timing sink for the duration of one API call and
+// folds the recorded events into the totals when the call ends.
+struct TimingScope {
+  cmg_ctx c;
+  explicit TimingScope(cmg_ctx ctx) : c(ctx) { g_timing = (c != nullptr && c->timing_on) ? &c->timing : nullptr; }
+  ~TimingScope() {
+    if (g_timing != nullptr) g_timing->flush();
+    g_timing = nullptr;
+  }
+};
+
 template <typename Fn>
 cmg_status guard(cmg_ctx c, Fn&& fn) {
   try {
     if (c != nullptr && c->dead) fail(CMG_ERR_INVALID_ARG, "context unusable after an earlier HIP failure");
+    TimingScope ts(c);
     fn();
     return CMG_OK;
   } catch (const CmgError& e) {
@@ -785,6 +800,36 @@ cmg_status cmg_decode_solution(cmg_ctx c, double* u) {
     decode_chain(c, c->Lp);
     launch_to_full(c->lv[c->Lp].uh, c->lv[c->Lp].g, u, c->st);
     KCK();
+  });
+}
+
+cmg_status cmg_timing_enable(cmg_ctx c, int32_t enable, const char* kernel) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    c->timing.reset();
+    c->timing_on = enable != 0;
+    c->timing.filter = (kernel != nullptr) ? kernel : "";
+  });
+}
+
+cmg_status cmg_timing_count(cmg_ctx c, int32_t* count) {
+  if (c == nullptr || count == nullptr) return CMG_ERR_INVALID_ARG;
+  *count = static_cast<int32_t>(c->timing.names.size());
+  return CMG_OK;
+}
+
+cmg_status cmg_timing_entry(cmg_ctx c, int32_t index, char* name, int32_t name_len, int64_t* launches,
+                            double* total_ms, double* total_bytes) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    need(index >= 0 && index < static_cast<int32_t>(c->timing.names.size()), "timing index out of range");
+    if (name != nullptr && name_len > 0) {
+      std::strncpy(name, c->timing.names[index].c_str(), static_cast<size_t>(name_len - 1));
+      name[name_len - 1] = 0;
+    }
+    if (launches) *launches = c->timing.launches[index];
+    if (total_ms) *total_ms = c->timing.ms[index];
+    if (total_bytes) *total_bytes = c->timing.bytes[index];
   });
 }
 
