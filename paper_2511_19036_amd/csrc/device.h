@@ -30,6 +30,14 @@ struct SecRef {
 };
 
 // ------------------------------------------------------------------ codes
+// Block index of value i (B is 32 or 64: a shift, never a division).
+__device__ __forceinline__ int64_t blk(const SecRef& s, int64_t i) { return i >> (s.B == 64 ? 6 : 5); }
+// Values in the section's whole blocks.
+__device__ __forceinline__ int64_t limit_of(const SecRef& s) {
+  const int sh = s.B == 64 ? 6 : 5;
+  return ((s.n + s.B - 1) >> sh) << sh;
+}
+
 __device__ __forceinline__ int64_t load_code(const SecRef& s, int64_t i) {
   switch (s.cbits) {
     case 8: return static_cast<const int8_t*>(s.codes)[i];
@@ -58,9 +66,58 @@ __device__ __forceinline__ void store_code(const SecRef& s, int64_t i, int64_t m
 
 // Exact value m * 2^(e - (w - 1)) of code i (0 for an all-zero block).
 __device__ __forceinline__ double decode_value(const SecRef& s, int64_t i) {
-  const int e = s.exps[i / s.B];
+  const int e = s.exps[blk(s, i)];
   if (e == kZeroExp) return 0.0;
   return ldexp(static_cast<double>(load_code(s, i)), e - (s.w - 1));
+}
+
+// Raw code and exponent of one value, loaded without arithmetic on the
+// loaded registers (the narrow loads sign-extend in hardware), so that the
+// loads can stay in flight across barriers until raw_value() consumes them.
+struct RawCode {
+  int lo, hi, e;
+};
+
+__device__ __forceinline__ RawCode raw_none() { return RawCode{0, 0, kZeroExp}; }
+
+__device__ __forceinline__ RawCode raw_load(const SecRef& s, int64_t i) {
+  RawCode r;
+  r.e = s.exps[blk(s, i)];
+  r.hi = 0;
+  switch (s.cbits) {
+    case 8: r.lo = static_cast<const int8_t*>(s.codes)[i]; break;
+    case 16: r.lo = static_cast<const int16_t*>(s.codes)[i]; break;
+    case 32: r.lo = static_cast<const int32_t*>(s.codes)[i]; break;
+    case 64: {
+      const int2 v = static_cast<const int2*>(s.codes)[i];
+      r.lo = v.x;
+      r.hi = v.y;
+      break;
+    }
+    default: {  // 12-bit: the two bytes holding value i
+      const uint8_t* b = static_cast<const uint8_t*>(s.codes);
+      const int64_t byte = (i * 3) >> 1;
+      r.lo = b[byte];
+      r.hi = b[byte + 1];
+    }
+  }
+  return r;
+}
+
+// Value of a raw code (same result as decode_value).
+__device__ __forceinline__ double raw_value(const SecRef& s, int64_t i, const RawCode& r) {
+  int64_t m;
+  if (s.cbits == 64) {
+    m = static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(r.hi)) << 32) | static_cast<uint32_t>(r.lo));
+  } else if (s.cbits == 12) {
+    const uint32_t lo = static_cast<uint32_t>(r.lo), hi = static_cast<uint32_t>(r.hi);
+    const uint32_t v = (i & 1) ? ((lo >> 4) | (hi << 4)) : (lo | ((hi & 0xFu) << 8));
+    m = (v & 0x800u) ? static_cast<int64_t>(v) - 4096 : static_cast<int64_t>(v);
+  } else {
+    m = r.lo;
+  }
+  const double v = ldexp(static_cast<double>(m), r.e - (s.w - 1));
+  return r.e == kZeroExp ? 0.0 : v;
 }
 
 // Wave-wide max over groups of `width` lanes (width 32 or 64).

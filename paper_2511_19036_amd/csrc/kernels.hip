@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(kThreads) k_encode(const T* __restrict__ x, in
                                                      int* nonfinite) {
   const int lane = threadIdx.x & 63;
   const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
-  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  const int64_t limit = limit_of(s);
   if (base >= limit) return;  // whole wave
   const int64_t i = base + lane;
   const double v = (i < n) ? static_cast<double>(x[i]) : 0.0;
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(kThreads) k_encode(const T* __restrict__ x, in
   int e;
   const int64_t m = quantise_lane(v, s.B, s.w, &e);
   store_codes_wave(s, base, lane, m, limit);
-  if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[i / s.B] = static_cast<int16_t>(e);
+  if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
 }
 
 template <typename T>
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(kThreads) k_decode(SecRef s, int64_t n, T* __r
 // Append k zero bits to every code (exponents unchanged).
 __global__ void __launch_bounds__(kThreads) k_widen(SecRef s, int k) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  const int64_t limit = limit_of(s);
   if (s.cbits == 12) {  // one thread per pair of values (three bytes)
     if (2 * t >= limit) return;
     uint8_t* b = static_cast<uint8_t*>(s.codes) + 3 * t;
@@ -81,18 +81,42 @@ __global__ void __launch_bounds__(kThreads) k_zero_section(SecRef s) {
   if (t < nb) s.exps[t] = kZeroExp;
 }
 
+// Encode the interior of a full node array of level g (boundary 0).
+__global__ void __launch_bounds__(kThreads) k_encode_full(const double* __restrict__ full, Geom g, SecRef s,
+                                                          int* nonfinite) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
+  const int64_t limit = limit_of(s);
+  if (base >= limit) return;
+  const int64_t i = base + lane;
+  double v = 0.0;
+  if (i < g.size) {
+    int x, y, z;
+    unflatten(g, i, x, y, z);
+    if (is_interior(g, x, y, z)) {
+      const int64_t N = g.n + 1;
+      v = full[g.dim == 3 ? (static_cast<int64_t>(z) * N + y) * N + x : static_cast<int64_t>(y) * N + x];
+    }
+  }
+  if (nonfinite != nullptr && !isfinite(v)) atomicOr(nonfinite, 1);
+  int e;
+  const int64_t m = quantise_lane(v, s.B, s.w, &e);
+  store_codes_wave(s, base, lane, m, limit);
+  if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
+}
+
 // Section-wise correction u' <- round(dec u' + dec y') in float64 (Alg. 3).
 __global__ void __launch_bounds__(kThreads) k_correct(SecRef u, SecRef y) {
   const int lane = threadIdx.x & 63;
   const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
-  const int64_t limit = ((u.n + u.B - 1) / u.B) * u.B;
+  const int64_t limit = limit_of(u);
   if (base >= limit) return;
   const int64_t i = base + lane;
   const double v = (i < limit) ? decode_value(u, i) + decode_value(y, i) : 0.0;
   int e;
   const int64_t m = quantise_lane(v, u.B, u.w, &e);
   store_codes_wave(u, base, lane, m, limit);
-  if ((lane & (u.B - 1)) == 0 && i < limit) u.exps[i / u.B] = static_cast<int16_t>(e);
+  if ((lane & (u.B - 1)) == 0 && i < limit) u.exps[blk(u, i)] = static_cast<int16_t>(e);
 }
 
 // ============================================================ level kernels
@@ -397,6 +421,11 @@ void launch_encode(const T* x, int64_t n, const SecRef& s, int* nonfinite, hipSt
 template <typename T>
 void launch_decode(const SecRef& s, int64_t n, T* x, hipStream_t st) {
   CMG_TLAUNCH(tname("k_decode", TName<T>::s).c_str(), n * sizeof(T) + sec_bytes(s), k_decode<T>, n, st, s, n, x);
+}
+void launch_encode_full(const double* full, int L, const Geom& g, const SecRef& s, int* nonfinite, hipStream_t st) {
+  (void)L;
+  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  CMG_TLAUNCH("k_encode_full", 8.0 * g.size + sec_bytes(s), k_encode_full, limit, st, full, g, s, nonfinite);
 }
 void launch_widen(const SecRef& s, int k, hipStream_t st) {
   const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;

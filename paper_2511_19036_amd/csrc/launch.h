@@ -11,6 +11,8 @@ namespace cmg {
 template <typename T> void launch_encode(const T* x, int64_t n, const SecRef& s, int* nonfinite, hipStream_t st);
 template <typename T> void launch_decode(const SecRef& s, int64_t n, T* x, hipStream_t st);
 void launch_widen(const SecRef& s, int k, hipStream_t st);
+// Encode the interior of a full node array (boundary and far nodes 0).
+void launch_encode_full(const double* full, int L, const Geom& g, const SecRef& s, int* nonfinite, hipStream_t st);
 void launch_zero_section(const SecRef& s, hipStream_t st);
 void launch_correct(const SecRef& u, const SecRef& y, hipStream_t st);
 

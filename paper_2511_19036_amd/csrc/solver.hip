@@ -11,9 +11,11 @@
 #include <cstring>
 #include <exception>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "cmg.h"
+#include "fused.h"
 #include "launch.h"
 #include "timing.h"
 
@@ -62,7 +64,8 @@ struct Section {
 
 struct LevelData {
   Geom g{};
-  Section U, G, Y;                    // compact sections u', g = r - s, y'
+  Section U, G, Y;                    // compact sections u', g = r - s, pre-smoothed y'
+  Section Yp;                         // post-smoothed y' (the correction added to u')
   void *gf = nullptr, *yf = nullptr;  // V-cycle arrays in the arithmetic type T
   void *zf = nullptr, *rf = nullptr, *ef = nullptr;
   double* uh = nullptr;   // decoded solution (compact) / solution (plain)
@@ -110,6 +113,14 @@ struct cmg_ctx_s {
     return p.dim == 3 ? N * N * N : N * N;
   }
   bool compact() const { return o.storage == CMG_COMPACT_BFP; }
+  // Levels handled by the fused 3-D kernels (rows of at least 64 nodes).
+  bool fused3d() const {
+    return compact() && p.dim == 3 && p.op == CMG_POISSON && o.smoother == CMG_RBGS &&
+           o.vcycle_prec == CMG_FP32 && o.nu_pre >= 1 && o.nu_pre <= 2 && o.nu_post >= 1 && o.nu_post <= 2;
+  }
+  bool smooth_fused(int l) const { return fused3d() && l >= 6; }
+  bool rr_fused(int l) const { return fused3d() && l >= 7; }
+  bool res_fused(int l) const { return compact() && p.dim == 3 && p.op == CMG_POISSON && l >= 6; }
 };
 
 namespace {
@@ -180,15 +191,31 @@ void setup_levels(cmg_ctx c, const double* kappa) {
       alloc_section(c, D.U, D.g, c->wu(l, L));
       alloc_section(c, D.G, D.g, c->wr(l, L));
       alloc_section(c, D.Y, D.g, c->wy(l, L));
-      D.gf = c->alloc(n * tsz, work);
-      D.ef = c->alloc(n * tsz, work);
+      alloc_section(c, D.Yp, D.g, c->wy(l, L));
+      // per-operation scratch only where a per-operation kernel runs
+      const bool v1s = !c->smooth_fused(l), v1rr = !c->rr_fused(l);
+      const bool target = l < L && !c->rr_fused(l + 1);  // restriction target of level l + 1
+      if (v1s || v1rr) {
+        D.gf = c->alloc(n * tsz, work);
+        D.yf = c->alloc(n * tsz, work);
+      }
+      if (v1s || v1rr || target) D.rf = c->alloc(n * tsz, work);
+      if (v1s) D.zf = c->alloc(n * tsz, work);
+      if (l < L || v1s) D.ef = c->alloc(n * tsz, work);
+      const bool v1res = !c->res_fused(l);
+      if (l < L || d == 2 || v1res) D.uh = static_cast<double*>(c->alloc(n * 8, f64c));
+      if (v1res || l == lc) {
+        D.t64 = static_cast<double*>(c->alloc(n * 8, f64c));
+        D.f64 = static_cast<double*>(c->alloc(n * 8, f64c));
+      }
+    } else {
+      D.yf = c->alloc(n * tsz, work);
+      D.zf = c->alloc(n * tsz, work);
+      D.rf = c->alloc(n * tsz, work);
+      D.uh = static_cast<double*>(c->alloc(n * 8, f64c));
+      D.t64 = static_cast<double*>(c->alloc(n * 8, f64c));
+      D.f64 = static_cast<double*>(c->alloc(n * 8, f64c));
     }
-    D.yf = c->alloc(n * tsz, work);
-    D.zf = c->alloc(n * tsz, work);
-    D.rf = c->alloc(n * tsz, work);
-    D.uh = static_cast<double*>(c->alloc(n * 8, f64c));
-    D.t64 = static_cast<double*>(c->alloc(n * 8, f64c));
-    D.f64 = static_cast<double*>(c->alloc(n * 8, f64c));
     if (l == lc) D.s64 = static_cast<double*>(c->alloc(n * 8, kCoarse64));
   }
   c->flags = static_cast<int*>(c->alloc(64, kOther));
@@ -260,84 +287,137 @@ void smooth(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) {
 }
 
 // One compact V-cycle from zero on G[Lp], then u' += y' (Alg. 1, Alg. 3).
+// Levels with rows of >= 64 nodes run the fused 3-D kernels; the others (and
+// every 2-D, Jacobi or diffusion level) run one kernel per operation.
 template <typename T>
 void vcycle_correct(cmg_ctx c, int Lp) {
   const int lc = c->lc();
   hipStream_t st = c->st;
   int* nf = c->flags + 1;
+  constexpr bool f32 = std::is_same<T, float>::value;
   for (int l = Lp; l > lc; --l) {  // fine to coarse
     LevelData& F = c->lv[l];
     LevelData& C = c->lv[l - 1];
+    const double ih2 = inv_h2(l);
+    F.Y.w = c->wy(l, Lp);
+    C.G.w = c->wr(l - 1, Lp);
+    const bool fs = f32 && c->smooth_fused(l);
+    if (fs) {
+      const float cp = static_cast<float>(1.0 / (2.0 * c->p.dim * ih2));
+      if (!fused_down_smooth(F.G.ref(), F.Y.ref(), F.g, c->o.nu_pre, cp, static_cast<float>(ih2), st))
+        fail(CMG_ERR_HIP, "fused down-smoothing rejected a level it was selected for");
+      KCK();
+    }
+    if (f32 && c->rr_fused(l)) {
+      fused_resid_restrict(F.G.ref(), F.Y.ref(), C.G.ref(), F.g, C.g, static_cast<float>(ih2), st);
+      KCK();
+      continue;
+    }
     T* gf = static_cast<T*>(F.gf);
     T* yf = static_cast<T*>(F.yf);
     T* rf = static_cast<T*>(F.rf);
     launch_decode<T>(F.G.ref(), F.g.size, gf, st);
-    launch_fill<T>(yf, T(0), F.g.size, st);
-    KCK();
-    smooth<T>(c, l, yf, gf, static_cast<T*>(F.ef), c->o.nu_pre);
-    F.Y.w = c->wy(l, Lp);
-    launch_encode<T>(yf, F.g.size, F.Y.ref(), nf, st);
+    if (!fs) {
+      launch_fill<T>(yf, T(0), F.g.size, st);
+      KCK();
+      smooth<T>(c, l, yf, gf, static_cast<T*>(F.ef), c->o.nu_pre);
+      launch_encode<T>(yf, F.g.size, F.Y.ref(), nf, st);
+    }
     launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
-    launch_rhs_minus_A<T>(gf, yf, kapT<T>(c, l), F.g, static_cast<T>(inv_h2(l)), rf, st);
+    launch_rhs_minus_A<T>(gf, yf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);
     launch_restrict<T>(rf, C.g, F.g, static_cast<T*>(C.rf), st);
-    C.G.w = c->wr(l - 1, Lp);
     launch_encode<T>(static_cast<T*>(C.rf), C.g.size, C.G.ref(), nf, st);
     KCK();
   }
   LevelData& B = c->lv[lc];  // coarsest, float64
   launch_decode<double>(B.G.ref(), B.g.size, B.t64, st);
   launch_coarse_single(B.t64, kap64(c, lc), B.g, inv_h2(lc), B.s64, st);
-  B.Y.w = c->wy(lc, Lp);
-  launch_encode<double>(B.s64, B.g.size, B.Y.ref(), nf, st);
+  B.Yp.w = c->wy(lc, Lp);
+  launch_encode<double>(B.s64, B.g.size, B.Yp.ref(), nf, st);
   B.U.w = c->wu(lc, Lp);
-  launch_correct(B.U.ref(), B.Y.ref(), st);
-  launch_decode<T>(B.Y.ref(), B.g.size, static_cast<T*>(B.ef), st);
+  launch_correct(B.U.ref(), B.Yp.ref(), st);
+  launch_decode<T>(B.Yp.ref(), B.g.size, static_cast<T*>(B.ef), st);
   KCK();
   for (int l = lc + 1; l <= Lp; ++l) {  // coarse to fine
     LevelData& F = c->lv[l];
     LevelData& C = c->lv[l - 1];
+    const double ih2 = inv_h2(l);
+    F.Y.w = c->wy(l, Lp);
+    F.Yp.w = c->wy(l, Lp);
+    F.U.w = c->wu(l, Lp);
+    if (f32 && c->smooth_fused(l)) {
+      const float cp = static_cast<float>(1.0 / (2.0 * c->p.dim * ih2));
+      fused_up_smooth(static_cast<const float*>(C.ef), F.G.ref(), F.Y.ref(), F.Yp.ref(), F.U.ref(),
+                      l < Lp ? static_cast<float*>(F.ef) : nullptr, F.g, C.g, c->o.nu_post, cp,
+                      static_cast<float>(ih2), st);
+      KCK();
+      continue;
+    }
     T* gf = static_cast<T*>(F.gf);
     T* yf = static_cast<T*>(F.yf);
     T* zf = static_cast<T*>(F.zf);
     T* rf = static_cast<T*>(F.rf);
     launch_prolong<T>(static_cast<T*>(C.ef), F.g, C.g, zf, st);
     launch_decode<T>(F.G.ref(), F.g.size, gf, st);
-    launch_rhs_minus_A<T>(gf, zf, kapT<T>(c, l), F.g, static_cast<T>(inv_h2(l)), rf, st);
+    launch_rhs_minus_A<T>(gf, zf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);
     launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
     KCK();
     smooth<T>(c, l, yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
-    F.Y.w = c->wy(l, Lp);
-    launch_encode<T>(yf, F.g.size, F.Y.ref(), nf, st);
-    F.U.w = c->wu(l, Lp);
-    launch_correct(F.U.ref(), F.Y.ref(), st);
+    launch_encode<T>(yf, F.g.size, F.Yp.ref(), nf, st);
+    launch_correct(F.U.ref(), F.Yp.ref(), st);
     if (l < Lp) {
-      launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
+      launch_decode<T>(F.Yp.ref(), F.g.size, yf, st);
       launch_add<T>(yf, zf, static_cast<T*>(F.ef), F.g.size, st);
     }
     KCK();
   }
 }
 
-void decode_chain(cmg_ctx c, int Lp) {
+// Decoded solution u_l = dec u'_l + P u_{l-1} for levels lc .. top (float64).
+void decode_chain(cmg_ctx c, int top) {
   const int lc = c->lc();
   launch_decode<double>(c->lv[lc].U.ref(), c->lv[lc].g.size, c->lv[lc].uh, c->st);
-  for (int l = lc + 1; l <= Lp; ++l)
+  for (int l = lc + 1; l <= top; ++l)
     launch_prolong_add_dec(c->lv[l].U.ref(), c->lv[l - 1].uh, c->lv[l].g, c->lv[l - 1].g, c->lv[l].uh, c->st);
   KCK();
 }
 
-// IR residual (Alg. 2) into G[Lp]; f64[Lp] must hold the injected rhs.
-void ir_residual(cmg_ctx c, int Lp, cmg_stats* st) {
-  LevelData& F = c->lv[Lp];
-  decode_chain(c, Lp);
-  launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.t64, c->st);
-  F.G.w = c->wr(Lp, Lp);
-  launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
+// Decoded solution of FMG level Lp into a full node array (Lp + 1)^dim.
+void decode_to_full(cmg_ctx c, int Lp, double* u) {
+  if (c->p.dim == 3 && Lp > c->lc()) {
+    decode_chain(c, Lp - 1);
+    launch_decode_full(c->lv[Lp].U.ref(), c->lv[Lp - 1].uh, c->lv[Lp].g, c->lv[Lp - 1].g, u, c->st);
+  } else {
+    decode_chain(c, Lp);
+    launch_to_full(c->lv[Lp].uh, c->lv[Lp].g, u, c->st);
+  }
   KCK();
-  if (st != nullptr && st->record && st->count < 256) {
-    HIPCK(hipMemsetAsync(c->red, 0, 8, c->st));
-    launch_sumsq(F.t64, F.g.size, c->red, c->st);
+}
+
+// IR residual (Alg. 2) into G[Lp].  f is the caller's finest node array; the
+// per-operation path uses the injected copy in f64[Lp].
+void ir_residual(cmg_ctx c, int Lp, const double* f, cmg_stats* st) {
+  LevelData& F = c->lv[Lp];
+  F.G.w = c->wr(Lp, Lp);
+  const bool rec = st != nullptr && st->record && st->count < 256;
+  if (c->res_fused(Lp)) {
+    decode_chain(c, Lp - 1);
+    if (rec) HIPCK(hipMemsetAsync(c->red, 0, 8, c->st));
+    fused_ir_residual(F.U.ref(), c->lv[Lp - 1].uh, f, c->p.L, F.g, c->lv[Lp - 1].g, inv_h2(Lp), F.G.ref(),
+                      c->flags + 1, rec ? c->red : nullptr, c->st);
     KCK();
+  } else {
+    decode_chain(c, Lp);
+    launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.t64, c->st);
+    launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
+    KCK();
+    if (rec) {
+      HIPCK(hipMemsetAsync(c->red, 0, 8, c->st));
+      launch_sumsq(F.t64, F.g.size, c->red, c->st);
+      KCK();
+    }
+  }
+  if (rec) {
     double h = 0.0;
     HIPCK(hipMemcpyAsync(&h, c->red, 8, hipMemcpyDeviceToHost, c->st));
     HIPCK(hipStreamSynchronize(c->st));
@@ -363,7 +443,7 @@ void enter_level(cmg_ctx c, int level, const double* f) {
     }
     D.U.w = c->wu(level, level);
     launch_zero_section(D.U.ref(), c->st);
-    launch_inject(f, c->p.L, D.g, D.f64, c->st);
+    if (D.f64 != nullptr) launch_inject(f, c->p.L, D.g, D.f64, c->st);
     KCK();
   }
   c->Lp = level;
@@ -377,13 +457,11 @@ void compact_fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
     if (level == c->lc()) continue;
     const int iters = c->o.ir_iters + (level == L ? c->o.final_iters : 0);
     for (int it = 0; it < iters; ++it) {
-      ir_residual(c, level, st);
+      ir_residual(c, level, f, st);
       vcycle_correct<T>(c, level);
     }
   }
-  decode_chain(c, L);
-  launch_to_full(c->lv[L].uh, c->lv[L].g, u, c->st);
-  KCK();
+  decode_to_full(c, L, u);
 }
 
 // Correction-scheme V(nu1, nu2) cycle (supplement Sec. SM1.1.1) on rf[Lp];
@@ -524,7 +602,7 @@ Section& section_of(cmg_ctx c, int which, int level) {
   LevelData& D = c->lv[level];
   if (which == CMG_SECTION_U) return D.U;
   if (which == CMG_SECTION_R) return D.G;
-  if (which == CMG_SECTION_Y) return D.Y;
+  if (which == CMG_SECTION_Y) return D.Yp;
   fail(CMG_ERR_INVALID_ARG, "unknown section kind");
 }
 
@@ -615,11 +693,9 @@ cmg_status cmg_vcycle(cmg_ctx c, const double* r, double* y) {
     const bool f32 = c->o.vcycle_prec == CMG_FP32;
     for (int b = 0; b < c->p.batch; ++b) {
       LevelData& F = c->lv[L];
-      launch_inject(r + b * M, L, F.g, F.t64, c->st);
-      KCK();
       if (c->compact()) {
-        F.G.w = c->wr(L, L);
-        launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
+        F.G.w = c->wr(L, L);  // r rounded to the finest residual width
+        launch_encode_full(r + b * M, L, F.g, F.G.ref(), c->flags + 1, c->st);
         for (int l = lc; l <= L; ++l) {
           c->lv[l].U.w = c->wu(l, L);
           launch_zero_section(c->lv[l].U.ref(), c->st);
@@ -627,9 +703,9 @@ cmg_status cmg_vcycle(cmg_ctx c, const double* r, double* y) {
         KCK();
         c->Lp = L;
         if (f32) vcycle_correct<float>(c, L); else vcycle_correct<double>(c, L);
-        decode_chain(c, L);
-        launch_to_full(F.uh, F.g, y + b * M, c->st);
+        decode_to_full(c, L, y + b * M);
       } else {
+        launch_inject(r + b * M, L, F.g, F.t64, c->st);
         if (f32) {
           launch_convert<double, float>(F.t64, static_cast<float*>(F.rf), F.g.size, c->st);
           cs_vcycle<float>(c, L);
@@ -777,9 +853,9 @@ cmg_status cmg_ir_residual(cmg_ctx c, const double* f) {
   return guard(c, [&] {
     need(f != nullptr, "f must not be NULL");
     need(c->Lp > c->lc(), "enter an FMG level above the coarsest first");
-    launch_inject(f, c->p.L, c->lv[c->Lp].g, c->lv[c->Lp].f64, c->st);
+    if (c->lv[c->Lp].f64 != nullptr) launch_inject(f, c->p.L, c->lv[c->Lp].g, c->lv[c->Lp].f64, c->st);
     KCK();
-    ir_residual(c, c->Lp, nullptr);
+    ir_residual(c, c->Lp, f, nullptr);
   });
 }
 
@@ -797,9 +873,7 @@ cmg_status cmg_decode_solution(cmg_ctx c, double* u) {
   return guard(c, [&] {
     need(u != nullptr, "u must not be NULL");
     need(c->Lp >= c->lc(), "no FMG level entered");
-    decode_chain(c, c->Lp);
-    launch_to_full(c->lv[c->Lp].uh, c->lv[c->Lp].g, u, c->st);
-    KCK();
+    decode_to_full(c, c->Lp, u);
   });
 }
 

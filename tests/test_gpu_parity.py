@@ -66,6 +66,11 @@ def test_codec_rejects_nonfinite(cmg):
 
 # ------------------------------------------------------------ step parity
 CFGS = {
+    # L >= 6 runs the fused 3-D kernels on the fine levels, per-operation below
+    "3d-L7-b16": dict(dim=3, L=7, smoother="rbgs", omega=1.0, block=64, bits=16),
+    "3d-L7-b12-B32": dict(dim=3, L=7, smoother="rbgs", omega=1.0, block=32, bits=12),
+    "3d-L7-b8-nu1": dict(dim=3, L=7, smoother="rbgs", omega=1.0, block=64, bits=8, nu=1),
+    "3d-L6-b10": dict(dim=3, L=6, smoother="rbgs", omega=1.0, block=64, bits=10),
     "3d-rbgs-b16": dict(dim=3, L=5, smoother="rbgs", omega=1.0, block=64, bits=16),
     "3d-rbgs-b8": dict(dim=3, L=5, smoother="rbgs", omega=1.0, block=64, bits=8),
     "3d-rbgs-b12": dict(dim=3, L=5, smoother="rbgs", omega=1.0, block=64, bits=12),
@@ -75,13 +80,15 @@ CFGS = {
 
 
 def _oracle_cfg(c, **kw):
+    nu = c.get("nu", 2)
     return oc.Config(dim=c["dim"], L=c["L"], smoother=c["smoother"], omega=c["omega"], block=c["block"],
-                     bits_u=c["bits"], bits_r=c["bits"], bits_y=c["bits"], **kw)
+                     bits_u=c["bits"], bits_r=c["bits"], bits_y=c["bits"], nu_pre=nu, nu_post=nu, **kw)
 
 
 def _solver(cmg, c, **kw):
+    nu = c.get("nu", 2)
     return cmg.Solver(c["dim"], c["L"], smoother=c["smoother"], omega=c["omega"], bfp_block=c["block"],
-                      bits=c["bits"], **kw)
+                      bits=c["bits"], nu_pre=nu, nu_post=nu, **kw)
 
 
 def _random_sections(cfg, Lp, seed):
@@ -172,7 +179,7 @@ def test_compact_fmg_matches_oracle(cmg, name):
     assert np.array_equal(u, u_ref)
 
 
-@pytest.mark.parametrize("dim,L,smoother,omega", [(2, 6, "wjacobi", 0.8), (3, 5, "rbgs", 1.0)])
+@pytest.mark.parametrize("dim,L,smoother,omega", [(2, 6, "wjacobi", 0.8), (3, 5, "rbgs", 1.0), (3, 7, "rbgs", 1.0)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_plain_fmg_matches_oracle(cmg, dim, L, smoother, omega, prec):
     f_np = S.gaussian_noise_rhs(dim, L, sigma=1e-3, seed=3)
@@ -184,7 +191,7 @@ def test_plain_fmg_matches_oracle(cmg, dim, L, smoother, omega, prec):
     assert np.array_equal(u, u_ref)
 
 
-@pytest.mark.parametrize("name", ["3d-rbgs-b16", "2d-wjacobi-b16"])
+@pytest.mark.parametrize("name", ["3d-rbgs-b16", "2d-wjacobi-b16", "3d-L7-b16"])
 def test_vcycle_entry_matches_oracle(cmg, name):
     c = CFGS[name]
     cfg = _oracle_cfg(c)
@@ -213,6 +220,29 @@ def test_diffusion_fmg_and_gradient_match_oracle(cmg, dim, L, smoother, omega, b
         lam, g = s.adjoint(u, torch.from_numpy(dj).cuda()[None])
     assert np.array_equal(lam[0].cpu().numpy(), lam_ref)
     assert np.array_equal(g.cpu().numpy(), g_ref)
+
+
+def test_residual_norms_recorded(cmg):
+    dim, L = 3, 7
+    f_np = S.sine_rhs(dim, L)
+    hist = []
+    cfg = oc.Config(dim=dim, L=L, bits_u=16, bits_r=16, bits_y=16)
+    oc.fmg_solve(f_np, cfg, history=hist)
+    with cmg.Solver(dim, L, bits=16) as s:
+        _, norms = s.solve(torch.from_numpy(f_np).cuda()[None], record=True)
+    assert len(norms) == len(hist) == 2 * (L - 1)
+    assert np.allclose(norms, hist, rtol=1e-10)
+
+
+def test_nonfinite_rhs_reported(cmg):
+    f = torch.zeros((1, 65, 65, 65), dtype=torch.float64, device="cuda")
+    f[0, 30, 30, 30] = float("inf")
+    with cmg.Solver(3, 6, bits=16) as s:
+        with pytest.raises(cmg.CmgError) as ei:
+            s.solve(f)
+        assert ei.value.status == 5
+        ok = s.solve(torch.zeros_like(f))          # the context stays usable
+        assert float(ok.abs().max()) == 0.0
 
 
 # ------------------------------------------------------------ accuracy
