@@ -71,51 +71,30 @@ __device__ __forceinline__ double decode_value(const SecRef& s, int64_t i) {
   return ldexp(static_cast<double>(load_code(s, i)), e - (s.w - 1));
 }
 
-// Raw code and exponent of one value, loaded without arithmetic on the
-// loaded registers (the narrow loads sign-extend in hardware), so that the
-// loads can stay in flight across barriers until raw_value() consumes them.
+// Raw code and exponent of one value of a library-owned section: the two
+// 32-bit words holding the code's bits (value i occupies bits
+// [i*cbits, (i+1)*cbits) of the little-endian code stream for every
+// container) and the block exponent.  No arithmetic touches the loaded
+// registers here, so the loads can stay in flight across barriers until
+// raw_value() consumes them; the field extraction is branch-free.  Reads up
+// to 8 bytes past the value: section buffers carry 16 bytes of padding.
 struct RawCode {
-  int lo, hi, e;
+  uint32_t lo, hi;
+  int e;
 };
 
-__device__ __forceinline__ RawCode raw_none() { return RawCode{0, 0, kZeroExp}; }
+__device__ __forceinline__ RawCode raw_none() { return RawCode{0u, 0u, kZeroExp}; }
 
 __device__ __forceinline__ RawCode raw_load(const SecRef& s, int64_t i) {
-  RawCode r;
-  r.e = s.exps[blk(s, i)];
-  r.hi = 0;
-  switch (s.cbits) {
-    case 8: r.lo = static_cast<const int8_t*>(s.codes)[i]; break;
-    case 16: r.lo = static_cast<const int16_t*>(s.codes)[i]; break;
-    case 32: r.lo = static_cast<const int32_t*>(s.codes)[i]; break;
-    case 64: {
-      const int2 v = static_cast<const int2*>(s.codes)[i];
-      r.lo = v.x;
-      r.hi = v.y;
-      break;
-    }
-    default: {  // 12-bit: the two bytes holding value i
-      const uint8_t* b = static_cast<const uint8_t*>(s.codes);
-      const int64_t byte = (i * 3) >> 1;
-      r.lo = b[byte];
-      r.hi = b[byte + 1];
-    }
-  }
-  return r;
+  const uint32_t* w = static_cast<const uint32_t*>(s.codes) + ((i * s.cbits) >> 5);
+  return RawCode{w[0], w[1], s.exps[blk(s, i)]};
 }
 
 // Value of a raw code (same result as decode_value).
 __device__ __forceinline__ double raw_value(const SecRef& s, int64_t i, const RawCode& r) {
-  int64_t m;
-  if (s.cbits == 64) {
-    m = static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(r.hi)) << 32) | static_cast<uint32_t>(r.lo));
-  } else if (s.cbits == 12) {
-    const uint32_t lo = static_cast<uint32_t>(r.lo), hi = static_cast<uint32_t>(r.hi);
-    const uint32_t v = (i & 1) ? ((lo >> 4) | (hi << 4)) : (lo | ((hi & 0xFu) << 8));
-    m = (v & 0x800u) ? static_cast<int64_t>(v) - 4096 : static_cast<int64_t>(v);
-  } else {
-    m = r.lo;
-  }
+  const int sh = static_cast<int>((i * s.cbits) & 31);
+  const uint64_t cat = (static_cast<uint64_t>(r.hi) << 32) | r.lo;
+  const int64_t m = static_cast<int64_t>(cat << (64 - sh - s.cbits)) >> (64 - s.cbits);
   const double v = ldexp(static_cast<double>(m), r.e - (s.w - 1));
   return r.e == kZeroExp ? 0.0 : v;
 }
@@ -143,6 +122,51 @@ __device__ __forceinline__ int64_t quantise_lane(double v, int B, int w, int* e_
   }
   *e_out = e;
   return static_cast<int64_t>(rint(ldexp(v, -q)));
+}
+
+// --------------------------------------------------- wave reductions (DPP)
+// Max over each 16-lane row by quad permutes and row mirrors, then over the
+// rows of one block (B = 64: all four rows; B = 32: rows 0-1 and 2-3) with
+// readlane.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float dpp_maxf(float a) {
+  a = fmaxf(a, __int_as_float(dpp_i<0xB1>(__float_as_int(a))));   // quad_perm 1,0,3,2
+  a = fmaxf(a, __int_as_float(dpp_i<0x4E>(__float_as_int(a))));   // quad_perm 2,3,0,1
+  a = fmaxf(a, __int_as_float(dpp_i<0x141>(__float_as_int(a))));  // row_half_mirror
+  a = fmaxf(a, __int_as_float(dpp_i<0x140>(__float_as_int(a))));  // row_mirror
+  return a;
+}
+__device__ __forceinline__ float block_maxf(float a, int B, int lane) {
+  a = dpp_maxf(a);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 48));
+  if (B == 64) return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
+  return lane < 32 ? fmaxf(r0, r1) : fmaxf(r2, r3);
+}
+
+// Quantise a float32 value; identical codes to quantise_lane for w <= 24:
+// a float scaled by a power of two stays exact, and results in the float
+// subnormal range lie far below 1/2 and round to zero either way.
+__device__ __forceinline__ int32_t quantise_lane_f32(float v, int B, int w, int lane, int* e_out) {
+  const float a = block_maxf(fabsf(v), B, lane);
+  if (a == 0.0f) {
+    *e_out = kZeroExp;
+    return 0;
+  }
+  int e;
+  (void)frexpf(a, &e);
+  int q = e - (w - 1);
+  if (rintf(ldexpf(a, -q)) == ldexpf(1.0f, w - 1)) {
+    ++e;
+    ++q;
+  }
+  *e_out = e;
+  return static_cast<int32_t>(rintf(ldexpf(v, -q)));
 }
 
 // Store the 64 codes held by the 64 lanes of a wave at values base..base+63.

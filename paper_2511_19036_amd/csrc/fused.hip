@@ -129,222 +129,406 @@ __device__ __forceinline__ void rb_stage(float* yp, const float* ym, const float
 
 // =========================================================== down-smoothing
 // y'_l = Q(S^nu1(0; g_l)): S = 2 nu1 half-sweeps from zero (red first).
+//
+// Register columns: each thread owns K pairs of adjacent x-columns of the
+// tile (with halo H = S - 1: the first half-sweep is pointwise) and keeps,
+// per column, the y values of planes j-S-1 .. j and the right-hand side of
+// planes j-S .. j in registers.  At step j stage s updates plane j - s;
+// within a pair exactly one column has the stage's colour on that plane,
+// and which one alternates with j.  The z-neighbours come from the
+// column's own registers; the four in-plane neighbours come from LDS,
+// where stage s publishes its updated values (double-buffered by step
+// parity) for stage s + 1 to read at the next step.  One barrier per step.
 template <int S, int TY, int NT>
 __global__ void __launch_bounds__(NT) k_down_smooth(SecRef G, SecRef Y, Geom g, float cp, float ih2, int TZ) {
-  constexpr int H = S - 1;  // the first half-sweep is pointwise
+  constexpr int H = S - 1;
   constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H;
-  using PL = Plane<EXW, EXH>;
-  constexpr int NY = S + 2, NR = S + 1;
-  constexpr int PPT = (PL::SIZE + NT - 1) / NT;
-  __shared__ float ys[NY * PL::SIZE];
-  __shared__ float rs[NR * PL::SIZE];
-  const int tid = threadIdx.x;
+  constexpr int PW = EXW / 2, NPAIR = PW * EXH, K = (NPAIR + NT - 1) / NT;
+  constexpr int LW = EXW + 2, LPL = LW * (EXH + 2);  // LDS plane with a margin of one
+  constexpr int NB = S > 1 ? S - 1 : 1;
+  __shared__ float pub[2][NB][LPL];
+  __shared__ float outb[2][TY * kTX];
+  const int tid = threadIdx.x, lane = tid & 63;
   const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY, Z0 = blockIdx.z * TZ;
   const int n = g.n;
-  RawCode pre[PPT];
+  const int64_t zstride = static_cast<int64_t>(1) << (2 * g.level);
+
+  // per-pair constants
+  int pos[K];        // LDS position of column 0 of the pair
+  int par[K];        // column active at step j: (par + j) & 1
+  int64_t xy[K][2];  // flat x-y index of each column (or -1 outside the level)
+  unsigned upd[K];   // bit (2 (s-1) + c): stage s updates column c
+  unsigned outm[K];  // bit c: column c lies in the output interior; bit 2: pair exists
+  int oidx[K];       // output buffer index of column 0
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int q = tid + k * NT;
+    const bool valid = q < NPAIR;
+    const int ly = valid ? q / PW : 0, lx0 = valid ? 2 * (q - ly * PW) : 0;
+    const int gx0 = X0 - H + lx0, gy = Y0 - H + ly;
+    pos[k] = (ly + 1) * LW + lx0 + 1;
+    par[k] = (gx0 + gy - 1) & 1;
+    upd[k] = 0u;
+    outm[k] = 0u;
+    oidx[k] = (ly - H) * kTX + (lx0 - H);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int lx = lx0 + c, gx = gx0 + c;
+      const bool dom = valid && gx >= 0 && gx < n && gy >= 0 && gy < n;
+      xy[k][c] = dom ? ((static_cast<int64_t>(gy) << g.level) | gx) : -1;
+      const int dx = max(max(H - lx, lx - (H + kTX - 1)), 0);
+      const int dy = max(max(H - ly, ly - (H + TY - 1)), 0);
+      const int d = max(dx, dy);
+      const bool inner = valid && gx >= 1 && gx < n && gy >= 1 && gy < n;
+#pragma unroll
+      for (int s = 1; s <= S; ++s)
+        if (inner && d <= S - s) upd[k] |= 1u << (2 * (s - 1) + c);
+      if (valid && d == 0) outm[k] |= 1u << c;
+    }
+    if (valid) outm[k] |= 4u;
+  }
+  // pairs k whose whole wave lies beyond the tile do no work
+  auto wave_has = [&](int k) { return k * NT + (tid & ~63) < NPAIR; };
+  float y[K][2][S + 2];
+  float r[K][2][S + 1];
+  RawCode pre[K][2];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll
+      for (int i = 0; i < S + 2; ++i) y[k][c][i] = 0.0f;
+#pragma unroll
+      for (int i = 0; i < S + 1; ++i) r[k][c][i] = 0.0f;
+    }
   auto fetch = [&](int jj) {
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int t = tid + k * NT;
-      const int ly = t / EXW, lx = t - ly * EXW;
-      const int gx = X0 - H + lx, gy = Y0 - H + ly;
-      pre[k] = raw_none();
-      if (t < PL::SIZE && jj >= 0 && jj < n && gx >= 0 && gx < n && gy >= 0 && gy < n)
-        pre[k] = raw_load(G, flat(g, gx, gy, jj));
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        pre[k][c] = raw_none();
+        if (xy[k][c] >= 0 && jj >= 0 && jj < n) pre[k][c] = raw_load(G, jj * zstride + xy[k][c]);
+      }
+  };
+  auto quantise_out = [&](int po, int slot) {
+    if (po < Z0 || po >= Z0 + TZ) return;
+    for (int rr = tid >> 6; rr < TY; rr += NT / 64) {
+      const float v = outb[slot][rr * kTX + lane];
+      const int64_t base = flat(g, X0, Y0 + rr, po);
+      int e;
+      const int32_t m = quantise_lane_f32(v, Y.B, Y.w, lane, &e);
+      store_codes_wave(Y, base, lane, m, Y.n);
+      if ((lane & (Y.B - 1)) == 0) Y.exps[blk(Y, base + lane)] = static_cast<int16_t>(e);
     }
   };
-  const int jend = Z0 + TZ + S;
-  fetch(Z0 - S);
-  for (int j = Z0 - S; j < jend; ++j) {
-    {  // plane j: decoded g (prefetched last step), zero y
-      float* yp = ys + ring(j, NY) * PL::SIZE;
-      float* rp = rs + ring(j, NR) * PL::SIZE;
+
+  const int jbeg = Z0 - S, jend = Z0 + TZ + S;
+  fetch(jbeg);
+  for (int j = jbeg; j < jend; ++j) {
+    quantise_out(j - 1 - S, (j - 1) & 1);  // plane finished at the previous step
+    // new plane j: y = 0, rhs from the prefetch
 #pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        const int t = tid + k * NT;
-        if (t < PL::SIZE) {
-          const int ly = t / EXW, lx = t - ly * EXW;
-          const int gx = X0 - H + lx, gy = Y0 - H + ly;
-          const int64_t idx = (gx >= 0 && gy >= 0 && j >= 0) ? flat(g, gx, gy, j) : 0;
-          const int c = PL::at(lx, ly);
-          rp[c] = static_cast<float>(raw_value(G, idx, pre[k]));
-          yp[c] = 0.0f;
-        }
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int i = 0; i < S + 1; ++i) y[k][c][i] = y[k][c][i + 1];
+        y[k][c][S + 1] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < S; ++i) r[k][c][i] = r[k][c][i + 1];
+        const int64_t idx = xy[k][c] >= 0 ? j * zstride + xy[k][c] : 0;
+        r[k][c][S] = static_cast<float>(raw_value(G, idx, pre[k][c]));
       }
-    }
     if (j + 1 < jend) fetch(j + 1);
-    __syncthreads();
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
       const int p = j - s;
-      if (p >= Z0 - (S - s) && p < Z0 + TZ + (S - s) && p >= 1 && p <= n - 1)
-        rb_stage<H, TY, EXW, EXH>(ys + ring(p, NY) * PL::SIZE, ys + ring(p - 1, NY) * PL::SIZE,
-                                  ys + ring(p + 1, NY) * PL::SIZE, rs + ring(p, NR) * PL::SIZE, S - s, (s - 1) & 1,
-                                  p, X0, Y0, n, cp, ih2, s == 1, tid, NT);
-      __syncthreads();
-    }
-    const int po = j - S;
-    if (po >= Z0 && po < Z0 + TZ) {
-      const float* yp = ys + ring(po, NY) * PL::SIZE;
-      const int lane = tid & 63;
-      for (int r = tid >> 6; r < TY; r += NT / 64) {
-        const float v = yp[PL::at(H + lane, H + r)];
-        const int64_t base = flat(g, X0, Y0 + r, po);
-        int e;
-        const int64_t m = quantise_lane(static_cast<double>(v), Y.B, Y.w, &e);
-        store_codes_wave(Y, base, lane, m, Y.n);
-        if ((lane & (Y.B - 1)) == 0) Y.exps[blk(Y, base + lane)] = static_cast<int16_t>(e);
+      if (p < max(1, Z0 - (S - s)) || p > min(n - 1, Z0 + TZ + (S - s) - 1)) continue;
+      const int iy = S + 1 - s;
+      const float* src = pub[(j - 1) & 1][s >= 2 ? s - 2 : 0];
+      float* dst = pub[j & 1][s - 1 < NB ? s - 1 : 0];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (!wave_has(k)) continue;
+        const int ca = (par[k] + j) & 1;
+        const float yc = ca ? y[k][1][iy] : y[k][0][iy];
+        const float rhs = ca ? r[k][1][S - s] : r[k][0][S - s];
+        const int pa = pos[k] + ca;
+        float v;
+        if (s == 1) {
+          v = cp * rhs;
+        } else {
+          const float zm = ca ? y[k][1][iy - 1] : y[k][0][iy - 1];
+          const float zp = ca ? y[k][1][iy + 1] : y[k][0][iy + 1];
+          float a = 6.0f * yc;
+          a = a - src[pa - 1];
+          a = a - src[pa + 1];
+          a = a - src[pa - LW];
+          a = a - src[pa + LW];
+          a = a - zm;
+          a = a - zp;
+          a = a * ih2;
+          const float rr = rhs - a;
+          v = yc + cp * rr;
+        }
+        const bool u = (upd[k] >> (2 * (s - 1) + ca)) & 1u;
+        const float yv = u ? v : yc;
+        y[k][0][iy] = ca == 0 ? yv : y[k][0][iy];
+        y[k][1][iy] = ca == 1 ? yv : y[k][1][iy];
+        if (s < S && (outm[k] & 4u)) dst[pa] = yv;
       }
     }
+    const int po = j - S;  // plane complete: both colours have their last update
+    if (po >= Z0 && po < Z0 + TZ) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (outm[k] & 1u) outb[j & 1][oidx[k]] = y[k][0][1];
+        if (outm[k] & 2u) outb[j & 1][oidx[k] + 1] = y[k][1][1];
+      }
+    }
+    __syncthreads();
   }
+  quantise_out(jend - 1 - S, (jend - 1) & 1);
 }
 
 // ============================================================= up-smoothing
 // z = P e_{l-1}; rhs = g - A z; y = S^nu2(y'_pre; rhs); Yp = Q(y);
 // u'_l = Q(dec u'_l + dec Yp) (float64); e_l = dec Yp + z when eout != null.
+//
+// Same register-column scheme as the down-smoothing kernel, with two more
+// pipeline stages in front: z of plane j is prolongated per column from a
+// coarse ring in LDS and published, and at the next step the right-hand side
+// of plane j - 1 needs the published in-plane z neighbours.  The
+// pre-smoothed y' of a plane enters as stage 0 and is published too.
 template <int S, int TY, int NT>
 __global__ void __launch_bounds__(NT) k_up_smooth(const float* __restrict__ ec, SecRef G, SecRef Y, SecRef Yp,
                                                   SecRef U, float* __restrict__ eout, Geom g, Geom gc, float cp,
                                                   float ih2, int TZ) {
   constexpr int H = S + 1;
   constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H;
-  using PL = Plane<EXW, EXH>;
-  constexpr int NZ = 3, NY = S + 2, NR = S + 1;
+  constexpr int PW = EXW / 2, NPAIR = PW * EXH, K = (NPAIR + NT - 1) / NT;
+  constexpr int LW = EXW + 2, LPL = LW * (EXH + 2);
   constexpr int NC = 6, CW = EXW / 2 + 3, CH = EXH / 2 + 3, CPL = CW * CH;
-  constexpr int RW = kTX + 2 * S, RH = TY + 2 * S, RPT = (RW * RH + NT - 1) / NT;
-  constexpr int OPT = (TY * 64 + NT - 1) / NT;
-  __shared__ float zs[NZ * PL::SIZE];
-  __shared__ float ys[NY * PL::SIZE];
-  __shared__ float rs[NR * PL::SIZE];
+  constexpr int OPT = (TY * kTX + NT - 1) / NT;
   __shared__ float cs[NC * CPL];
+  __shared__ float zpub[2][LPL];
+  __shared__ float pub[2][S][LPL];
+  __shared__ float outb[2][TY * kTX];
   const int tid = threadIdx.x, lane = tid & 63;
   const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY, Z0 = blockIdx.z * TZ;
   const int n = g.n;
   const int CX0 = (X0 - H) >> 1, CY0 = (Y0 - H) >> 1;
-  const int jbeg = Z0 - S - 1, jend = Z0 + TZ + S + 1;
-  CoarseFetch<float, CW, CH, NT> cpf;
-  RawCode gpre[RPT], ypre[RPT], upre[OPT];
-  auto fetch_gy = [&](int p) {
+  const int64_t zstride = static_cast<int64_t>(1) << (2 * g.level);
+
+  int pos[K], par[K], gxy[K][2];
+  int64_t xy[K][2];   // flat x-y index of a column inside the level, else -1
+  unsigned upd[K];    // bit 2 (s-1) + c: stage s updates column c; bits 2S + c: rhs/y0 of column c
+  unsigned outm[K];   // bit c: column c in the output interior; bit 2: pair exists
+  int oidx[K];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int t = tid + k * NT;
-      const int ry = t / RW, rx = t - ry * RW;
-      const int gx = X0 - H + rx + 1, gy = Y0 - H + ry + 1;
-      gpre[k] = raw_none();
-      ypre[k] = raw_none();
-      if (t < RW * RH && p >= 1 && p < n && gx >= 1 && gx < n && gy >= 1 && gy < n) {
-        const int64_t idx = flat(g, gx, gy, p);
-        gpre[k] = raw_load(G, idx);
-        ypre[k] = raw_load(Y, idx);
-      }
+  for (int k = 0; k < K; ++k) {
+    const int q = tid + k * NT;
+    const bool valid = q < NPAIR;
+    const int ly = valid ? q / PW : 0, lx0 = valid ? 2 * (q - ly * PW) : 0;
+    const int gx0 = X0 - H + lx0, gy = Y0 - H + ly;
+    pos[k] = (ly + 1) * LW + lx0 + 1;
+    par[k] = (gx0 + gy - 1) & 1;
+    upd[k] = 0u;
+    outm[k] = valid ? 4u : 0u;
+    oidx[k] = (ly - H) * kTX + (lx0 - H);
+    gxy[k][0] = gx0;
+    gxy[k][1] = gy;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int lx = lx0 + c, gx = gx0 + c;
+      const bool dom = valid && gx >= 0 && gx < n && gy >= 0 && gy < n;
+      xy[k][c] = dom ? ((static_cast<int64_t>(gy) << g.level) | gx) : -1;
+      const int d = max(max(max(H - lx, lx - (H + kTX - 1)), 0), max(max(H - ly, ly - (H + TY - 1)), 0));
+      const bool inner = valid && gx >= 1 && gx < n && gy >= 1 && gy < n;
+#pragma unroll
+      for (int s = 1; s <= S; ++s)
+        if (inner && d <= S - s) upd[k] |= 1u << (2 * (s - 1) + c);
+      if (inner && d <= S) upd[k] |= 1u << (2 * S + c);
+      if (valid && d == 0) outm[k] |= 1u << c;
     }
+  }
+  auto wave_has = [&](int k) { return k * NT + (tid & ~63) < NPAIR; };
+
+  float z[K][2][3];      // z of planes j-2, j-1, j
+  float r[K][2][S + 1];  // rhs of planes j-1-S .. j-1
+  float y[K][2][S + 2];  // y of planes j-2-S .. j-1
+  RawCode gpre[K][2], ypre[K][2], upre[OPT];
+  CoarseFetch<float, CW, CH, NT> cpf;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) z[k][c][i] = 0.0f;
+#pragma unroll
+      for (int i = 0; i < S + 1; ++i) r[k][c][i] = 0.0f;
+#pragma unroll
+      for (int i = 0; i < S + 2; ++i) y[k][c][i] = 0.0f;
+    }
+  auto fetch_gy = [&](int p) {  // g and y' of plane p for the own columns
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        gpre[k][c] = raw_none();
+        ypre[k][c] = raw_none();
+        if (xy[k][c] >= 0 && p >= 1 && p < n && ((upd[k] >> (2 * S + c)) & 1u)) {
+          const int64_t idx = p * zstride + xy[k][c];
+          gpre[k][c] = raw_load(G, idx);
+          ypre[k][c] = raw_load(Y, idx);
+        }
+      }
   };
   auto fetch_u = [&](int po) {
 #pragma unroll
-    for (int k = 0; k < OPT; ++k) {
-      const int r = (tid >> 6) + k * (NT / 64);
-      upre[k] = raw_none();
-      if (r < TY && po >= Z0 && po < Z0 + TZ) upre[k] = raw_load(U, flat(g, X0 + lane, Y0 + r, po));
+    for (int t = 0; t < OPT; ++t) {
+      const int rr = (tid >> 6) + t * (NT / 64);
+      upre[t] = raw_none();
+      if (rr < TY && po >= Z0 && po < Z0 + TZ) upre[t] = raw_load(U, flat(g, X0 + lane, Y0 + rr, po));
     }
   };
-  // prologue: the two coarse planes of z(jbeg), g and y' of plane jbeg - 1
+  auto finish_out = [&](int po, int slot) {  // quantise y', correct u', write e
+    if (po < Z0 || po >= Z0 + TZ) return;
+#pragma unroll
+    for (int t = 0; t < OPT; ++t) {
+      const int rr = (tid >> 6) + t * (NT / 64);
+      if (rr >= TY) continue;
+      const float v = outb[slot][rr * kTX + lane];
+      const int64_t base = flat(g, X0, Y0 + rr, po);
+      const int64_t i = base + lane;
+      int ey;
+      const int32_t my = quantise_lane_f32(v, Yp.B, Yp.w, lane, &ey);
+      store_codes_wave(Yp, base, lane, my, Yp.n);
+      if ((lane & (Yp.B - 1)) == 0) Yp.exps[blk(Yp, i)] = static_cast<int16_t>(ey);
+      const double dy = ey == kZeroExp ? 0.0 : ldexp(static_cast<double>(my), ey - (Yp.w - 1));
+      const double vu = raw_value(U, i, upre[t]) + dy;
+      int eu;
+      const int64_t mu = quantise_lane(vu, U.B, U.w, &eu);
+      store_codes_wave(U, base, lane, mu, U.n);
+      if ((lane & (U.B - 1)) == 0) U.exps[blk(U, i)] = static_cast<int16_t>(eu);
+      if (eout != nullptr) {
+        const float zz = prolong_lds<float, NC, CW, CPL>(cs, CX0, CY0, X0 + lane, Y0 + rr, po);
+        eout[i] = static_cast<float>(dy) + zz;
+      }
+    }
+  };
+
+  const int jbeg = Z0 - S - 1, jend = Z0 + TZ + S + 1;
   cpf.fetch(ec, gc, CX0, CY0, jbeg >> 1, tid);
   cpf.store(cs + ring(jbeg >> 1, NC) * CPL, tid);
   cpf.fetch(ec, gc, CX0, CY0, (jbeg >> 1) + 1, tid);
   cpf.store(cs + ring((jbeg >> 1) + 1, NC) * CPL, tid);
   fetch_gy(jbeg - 1);
-  fetch_u(jbeg - 1 - S);
+  fetch_u(jbeg - 2 - S);
+  __syncthreads();
   for (int j = jbeg; j < jend; ++j) {
-    // (a) the coarse plane (j + 1) / 2 that z(j) needs for odd j
-    if (j != jbeg && (j & 1)) cpf.store(cs + ring((j + 1) >> 1, NC) * CPL, tid);
-    __syncthreads();
-    {  // (b) z on plane j over the whole tile
-      float* zp = zs + ring(j, NZ) * PL::SIZE;
-      for (int t = tid; t < PL::SIZE; t += NT) {
-        const int ly = t / EXW, lx = t - ly * EXW;
-        const int gx = X0 - H + lx, gy = Y0 - H + ly;
-        float z = 0.0f;
-        if (j >= 0 && gx >= 0 && gy >= 0) z = prolong_lds<float, NC, CW, CPL>(cs, CX0, CY0, gx, gy, j);
-        zp[PL::at(lx, ly)] = z;
+    finish_out(j - 2 - S, (j - 1) & 1);  // plane completed at the previous step
+    fetch_u(j - 1 - S);
+    const bool need_c = ((j + 1) & 1) && j + 1 < jend;  // z(j+1) needs coarse plane (j+2)/2
+    if (need_c) cpf.fetch(ec, gc, CX0, CY0, (j + 2) >> 1, tid);
+    // (b) z of plane j for the own columns, published
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!wave_has(k)) continue;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        z[k][c][0] = z[k][c][1];
+        z[k][c][1] = z[k][c][2];
+        const int gx = gxy[k][0] + c, gy = gxy[k][1];
+        float zz = 0.0f;
+        if ((outm[k] & 4u) && j >= 0 && gx >= 0 && gy >= 0)
+          zz = prolong_lds<float, NC, CW, CPL>(cs, CX0, CY0, gx, gy, j);
+        z[k][c][2] = zz;
+        if (outm[k] & 4u) zpub[j & 1][pos[k] + c] = zz;
       }
     }
-    __syncthreads();
-    {  // (c) plane j-1: rhs = g - A z and the pre-smoothed y, on halo S
+    // (c) plane j - 1: rhs = g - A z and y0 for both columns; y0 published as stage 0
+    {
       const int p = j - 1;
-      float* rp = rs + ring(p, NR) * PL::SIZE;
-      float* yp = ys + ring(p, NY) * PL::SIZE;
-      const float* zc = zs + ring(p, NZ) * PL::SIZE;
-      const float* zm = zs + ring(p - 1, NZ) * PL::SIZE;
-      const float* zpl = zs + ring(p + 1, NZ) * PL::SIZE;
+      const float* zs = zpub[(j - 1) & 1];
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int t = tid + k * NT;
-        if (t >= RW * RH) continue;
-        const int ry = t / RW, rx = t - ry * RW;
-        const int lx = rx + 1, ly = ry + 1;
-        const int gx = X0 - H + lx, gy = Y0 - H + ly;
-        const int c = PL::at(lx, ly);
-        float r = 0.0f, y0 = 0.0f;
-        if (p >= 1 && p < n && gx >= 1 && gx < n && gy >= 1 && gy < n) {
-          const int64_t idx = flat(g, gx, gy, p);
-          float a = 6.0f * zc[c];
-          a = a - zc[PL::at(lx - 1, ly)];
-          a = a - zc[PL::at(lx + 1, ly)];
-          a = a - zc[PL::at(lx, ly - 1)];
-          a = a - zc[PL::at(lx, ly + 1)];
-          a = a - zm[c];
-          a = a - zpl[c];
-          a = a * ih2;
-          r = static_cast<float>(raw_value(G, idx, gpre[k])) - a;
-          y0 = static_cast<float>(raw_value(Y, idx, ypre[k]));
+      for (int k = 0; k < K; ++k) {
+        if (!wave_has(k)) continue;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+          for (int i = 0; i < S; ++i) r[k][c][i] = r[k][c][i + 1];
+#pragma unroll
+          for (int i = 0; i < S + 1; ++i) y[k][c][i] = y[k][c][i + 1];
+          float rv = 0.0f, yv = 0.0f;
+          if (((upd[k] >> (2 * S + c)) & 1u) && p >= 1 && p < n) {
+            const int pc = pos[k] + c;
+            float a = 6.0f * z[k][c][1];
+            a = a - zs[pc - 1];
+            a = a - zs[pc + 1];
+            a = a - zs[pc - LW];
+            a = a - zs[pc + LW];
+            a = a - z[k][c][0];
+            a = a - z[k][c][2];
+            a = a * ih2;
+            const int64_t idx = p * zstride + xy[k][c];
+            rv = static_cast<float>(raw_value(G, idx, gpre[k][c])) - a;
+            yv = static_cast<float>(raw_value(Y, idx, ypre[k][c]));
+          }
+          r[k][c][S] = rv;
+          y[k][c][S + 1] = yv;
+          if (outm[k] & 4u) pub[j & 1][0][pos[k] + c] = yv;
         }
-        rp[c] = r;
-        yp[c] = y0;
       }
-      // prefetch for the next step: g and y' of plane j, coarse plane of z(j+1)
-      if (j + 1 < jend) {
-        fetch_gy(j);
-        if ((j + 1) & 1) cpf.fetch(ec, gc, CX0, CY0, (j + 2) >> 1, tid);
-      }
+      if (j + 1 < jend) fetch_gy(j);
     }
-    __syncthreads();
+    // (d) post-smoothing: stage s on plane j - 1 - s
 #pragma unroll
-    for (int s = 1; s <= S; ++s) {  // (d) post-smoothing pipeline
+    for (int s = 1; s <= S; ++s) {
       const int p = j - 1 - s;
-      if (p >= Z0 - (S - s) && p < Z0 + TZ + (S - s) && p >= 1 && p <= n - 1)
-        rb_stage<H, TY, EXW, EXH>(ys + ring(p, NY) * PL::SIZE, ys + ring(p - 1, NY) * PL::SIZE,
-                                  ys + ring(p + 1, NY) * PL::SIZE, rs + ring(p, NR) * PL::SIZE, S - s, (s - 1) & 1,
-                                  p, X0, Y0, n, cp, ih2, false, tid, NT);
-      __syncthreads();
-    }
-    const int po = j - 1 - S;  // (e) output
-    if (po >= Z0 && po < Z0 + TZ) {
-      const float* yp = ys + ring(po, NY) * PL::SIZE;
+      if (p < max(1, Z0 - (S - s)) || p > min(n - 1, Z0 + TZ + (S - s) - 1)) continue;
+      const int iy = S + 1 - s;
+      const float* src = pub[(j - 1) & 1][s - 1];
+      float* dst = pub[j & 1][s < S ? s : 0];
 #pragma unroll
-      for (int k = 0; k < OPT; ++k) {
-        const int r = (tid >> 6) + k * (NT / 64);
-        if (r >= TY) continue;
-        const float v = yp[PL::at(H + lane, H + r)];
-        const int64_t base = flat(g, X0, Y0 + r, po);
-        const int64_t i = base + lane;
-        int ey;
-        const int64_t my = quantise_lane(static_cast<double>(v), Yp.B, Yp.w, &ey);
-        store_codes_wave(Yp, base, lane, my, Yp.n);
-        if ((lane & (Yp.B - 1)) == 0) Yp.exps[blk(Yp, i)] = static_cast<int16_t>(ey);
-        const double dy = ey == kZeroExp ? 0.0 : ldexp(static_cast<double>(my), ey - (Yp.w - 1));
-        const double vu = raw_value(U, i, upre[k]) + dy;
-        int eu;
-        const int64_t mu = quantise_lane(vu, U.B, U.w, &eu);
-        store_codes_wave(U, base, lane, mu, U.n);
-        if ((lane & (U.B - 1)) == 0) U.exps[blk(U, i)] = static_cast<int16_t>(eu);
-        if (eout != nullptr) {
-          const float z = prolong_lds<float, NC, CW, CPL>(cs, CX0, CY0, X0 + lane, Y0 + r, po);
-          eout[i] = static_cast<float>(dy) + z;
-        }
+      for (int k = 0; k < K; ++k) {
+        if (!wave_has(k)) continue;
+        const int ca = (par[k] + j - 1) & 1;
+        const float yc = ca ? y[k][1][iy] : y[k][0][iy];
+        const float zm = ca ? y[k][1][iy - 1] : y[k][0][iy - 1];
+        const float zp = ca ? y[k][1][iy + 1] : y[k][0][iy + 1];
+        const float rhs = ca ? r[k][1][S - s] : r[k][0][S - s];
+        const int pa = pos[k] + ca;
+        float a = 6.0f * yc;
+        a = a - src[pa - 1];
+        a = a - src[pa + 1];
+        a = a - src[pa - LW];
+        a = a - src[pa + LW];
+        a = a - zm;
+        a = a - zp;
+        a = a * ih2;
+        const float rr = rhs - a;
+        const float v = yc + cp * rr;
+        const bool u = (upd[k] >> (2 * (s - 1) + ca)) & 1u;
+        const float yv = u ? v : yc;
+        y[k][0][iy] = ca == 0 ? yv : y[k][0][iy];
+        y[k][1][iy] = ca == 1 ? yv : y[k][1][iy];
+        if (s < S && (outm[k] & 4u)) dst[pa] = yv;
       }
     }
-    fetch_u(j - S);
+    // (e) plane j - 1 - S is complete
+    const int po = j - 1 - S;
+    if (po >= Z0 && po < Z0 + TZ) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (outm[k] & 1u) outb[j & 1][oidx[k]] = y[k][0][1];
+        if (outm[k] & 2u) outb[j & 1][oidx[k] + 1] = y[k][1][1];
+      }
+    }
+    if (need_c) cpf.store(cs + ring((j + 2) >> 1, NC) * CPL, tid);
+    __syncthreads();
   }
+  finish_out(jend - 2 - S, (jend - 1) & 1);
 }
 
 // ======================================================== residual-restrict
@@ -464,7 +648,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(SecRef G, SecRef Y, SecRe
           }
           const int64_t base = flat(gc, CX0, J, K);
           int e;
-          const int64_t m = quantise_lane(static_cast<double>(s), Gc.B, Gc.w, &e);
+          const int32_t m = quantise_lane_f32(s, Gc.B, Gc.w, lane, &e);
           store_codes_wave(Gc, base, lane, m, Gc.n);
           if ((lane & (Gc.B - 1)) == 0) Gc.exps[blk(Gc, base + lane)] = static_cast<int16_t>(e);
         }

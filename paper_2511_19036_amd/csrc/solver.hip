@@ -173,7 +173,8 @@ void alloc_section(cmg_ctx c, Section& s, const Geom& g, int wmax) {
   s.cbits = container_bits(wmax);
   s.w = wmax;
   s.bytes = code_bytes(s.n, s.B, wmax);
-  s.codes = c->alloc(static_cast<size_t>(s.bytes), kSections);
+  // 16 bytes of padding: the fused kernels read codes as 8-byte windows
+  s.codes = c->alloc(static_cast<size_t>(s.bytes) + 16, kSections);
   s.exps = static_cast<int16_t*>(c->alloc(static_cast<size_t>(s.nblk) * 2, kSections));
 }
 
