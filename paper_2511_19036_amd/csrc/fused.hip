@@ -1,25 +1,24 @@
 // Fused level-sweep kernels for 3-D Poisson with red-black Gauss-Seidel.
 //
 // Each workgroup owns an x-y tile (64 x TY nodes: one BFP block of 64 per
-// row, or two of 32) and marches along z through a chunk of TZ planes,
-// keeping a ring of planes in LDS.  The smoothing stages (half-sweeps) form
-// a pipeline with a lag of one plane per stage: at step j the plane j is
-// loaded and stage s updates plane j - s.  A red-black half-sweep updates
-// one colour and reads only the other, and the z-neighbours of a colour are
-// of the other colour, so every plane is updated in place.  The x-y halo
-// shrinks by one node per stage (redundant work at the tile edges); the z
-// halo costs S extra planes at both ends of a chunk.  Sections are read and
-// written only as BFP codes: the finest-level temporaries (the prolongated
-// coarse correction z, the decoded solution, the residual) live in LDS.
-//
-// LDS planes are split by the parity of the tile-local x index (even and
-// odd halves), so that lanes updating one colour touch consecutive words.
+// row, or two of 32) and marches along z through a chunk of TZ planes.  The
+// smoothing stages (half-sweeps) form a pipeline with a lag of one plane per
+// stage.  A red-black half-sweep updates one colour and reads only the
+// other, and the z-neighbours of a node have the other colour, so every
+// plane is updated in place.  The x-y halo covers the dependence cone of the
+// stages (redundant work at the tile edges); the z halo costs a few extra
+// planes at both ends of a chunk.  Sections are read and written only as BFP
+// codes: the finest-level temporaries (the prolongated coarse correction z,
+// the decoded solution, the residual) live in registers and LDS.
 //
 // The per-node arithmetic is exactly that of the per-operation kernels in
 // kernels.hip (same operand order, no contraction), so both paths give
 // bit-identical results.
+#include <type_traits>
+
 #include "device.h"
 #include "fused.h"
+#include "plane.h"
 #include "timing.h"
 
 namespace cmg {
@@ -27,14 +26,6 @@ namespace cmg {
 constexpr int kTX = 64;
 
 __device__ __forceinline__ int ring(int j, int n) { return (j % n + n) % n; }
-
-// Tile-local plane addressing with the x-parity split.
-template <int EXW, int EXH>
-struct Plane {
-  static constexpr int W2 = EXW / 2;
-  static constexpr int SIZE = EXW * EXH;
-  __device__ static __forceinline__ int at(int lx, int ly) { return ((lx & 1) * EXH + ly) * W2 + (lx >> 1); }
-};
 
 // d-linear interpolation at fine node (gx, gy, gz) from a coarse ring in LDS
 // holding coarse planes cz -> slot ring(cz, NC), tile origin (CX0, CY0),
@@ -89,109 +80,127 @@ struct CoarseFetch {
   }
 };
 
-// One red-black half-sweep (colour col) on plane p over the tile region of
-// halo h around the interior, in place on `yp`; ym / ypl are planes p -/+ 1.
-// `zero_start`: the plane still holds the zero initial guess (first
-// half-sweep of a pre-smoother), so y = c * rhs.
-template <int H, int TY, int EXW, int EXH>
-__device__ __forceinline__ void rb_stage(float* yp, const float* ym, const float* ypl, const float* rp, int h, int col,
-                                         int p, int X0, int Y0, int n, float cp, float ih2, bool zero_start,
-                                         int tid, int nt) {
-  using PL = Plane<EXW, EXH>;
-  const int rw = kTX + 2 * h, rh = TY + 2 * h, half = rw / 2;
-  for (int t = tid; t < half * rh; t += nt) {
-    const int r = t / half, q = t - r * half;
-    const int ly = H - h + r, gy = Y0 - H + ly;
-    const int lx0 = H - h + 2 * q, gx0 = X0 - H + lx0;
-    const int par = ((gx0 + gy + p) ^ col) & 1;
-    const int lx = lx0 + par, gx = gx0 + par;
-    if (gx < 1 || gx >= n || gy < 1 || gy >= n) continue;
-    const int c = PL::at(lx, ly);
-    float v;
-    if (zero_start) {
-      v = cp * rp[c];
-    } else {
-      const float yc = yp[c];
-      float a = 6.0f * yc;
-      a = a - yp[PL::at(lx - 1, ly)];
-      a = a - yp[PL::at(lx + 1, ly)];
-      a = a - yp[PL::at(lx, ly - 1)];
-      a = a - yp[PL::at(lx, ly + 1)];
-      a = a - ym[c];
-      a = a - ypl[c];
-      a = a * ih2;
-      const float rr = rp[c] - a;
-      v = yc + cp * rr;
+// ======================================================= register columns
+// Scheme shared by the two smoothing kernels.  A workgroup owns an x-y tile
+// of 64 x TY output nodes plus a halo of H nodes and marches along z through
+// a chunk of TZ planes.  Each thread owns K pairs of adjacent x-columns of
+// the extended tile and keeps, per column, a ring of y and right-hand-side
+// values of consecutive planes in registers.  The half-sweeps are pipeline
+// stages with a lag of one plane.  Stage s updates colour (s + 1) & 1 of its
+// plane (red first), so at any one step all stages update the columns of a
+// single class (x + y) & 1: the rings are indexed by that class (the slot)
+// rather than by the x offset, and with the step loop unrolled by two the
+// slot is a compile-time constant.  z-neighbours come from the column's own
+// ring; the four in-plane neighbours come from LDS, where every plane under
+// way has one buffer: a stage reads the colour that its predecessor wrote at
+// the previous step and writes the other colour, so one barrier per step
+// suffices.  Nodes near the tile edge outside the dependence cone of the
+// output nodes may take inexact values (their LDS reads wrap into the
+// neighbouring row or plane) but no node inside the cone reads them.
+// Dirichlet boundary nodes and nodes outside the level stay zero.
+
+// Pair geometry of a register-column tile.
+template <int H, int TY, int NT>
+struct ColTile {
+  static constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H;
+  static constexpr int PW = EXW / 2, NPAIR = PW * EXH, K = (NPAIR + NT - 1) / NT;
+  static constexpr int LPL = EXW * EXH, PS = LPL + 2, PAD = EXW + 2;  // plane, its stride, margin
+  static constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;          // output rows per wave
+};
+
+// Per-pair flags.
+constexpr unsigned kInnerSlot = 0u;   // bits 0, 1: the node of slot s is inside the level's interior
+constexpr unsigned kOutSlot = 2u;     // bits 2, 3: the node of slot s is an output node
+constexpr unsigned kSwap = 4u;        // bit 4: column 0 holds slot 1
+constexpr unsigned kOddY = 5u;        // bit 5: odd y
+constexpr unsigned kInnerCol = 6u;    // bits 6, 7: column c is inside the level's interior
+
+template <int H, int TY, int NT>
+__device__ __forceinline__ void col_setup(int tid, int X0, int Y0, int level, int* pos, uint32_t (*xy)[2],
+                                          unsigned* fl, int* oidx) {
+  using T = ColTile<H, TY, NT>;
+  const int n = 1 << level;
+#pragma unroll
+  for (int k = 0; k < T::K; ++k) {
+    const int q = tid + k * NT;
+    const bool valid = q < T::NPAIR;
+    const int ly = valid ? q / T::PW : 0, lx0 = valid ? 2 * (q - ly * T::PW) : 0;
+    const int gx0 = X0 - H + lx0, gy = Y0 - H + ly;
+    pos[k] = valid ? ly * T::EXW + lx0 : T::LPL;  // a missing pair writes the spare words
+    oidx[k] = (ly - H) * kTX + (lx0 - H);
+    const unsigned sw = static_cast<unsigned>(gx0 + gy) & 1u;
+    unsigned f = (sw << kSwap) | ((static_cast<unsigned>(gy) & 1u) << kOddY);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int gx = gx0 + c, lx = lx0 + c;
+      const unsigned slot = sw ^ static_cast<unsigned>(c);
+      const bool dom = valid && gx >= 0 && gx < n && gy >= 0 && gy < n;
+      const bool inner = valid && gx >= 1 && gx < n && gy >= 1 && gy < n;
+      const bool out = valid && lx >= H && lx < H + kTX && ly >= H && ly < H + TY;
+      xy[k][c] = dom ? ((static_cast<uint32_t>(gy) << level) | static_cast<uint32_t>(gx)) : 0u;
+      f |= (inner ? 1u : 0u) << (kInnerSlot + slot);
+      f |= (out ? 1u : 0u) << (kOutSlot + slot);
+      f |= (inner ? 1u : 0u) << (kInnerCol + c);
     }
-    yp[c] = v;
+    fl[k] = f;
+  }
+}
+
+// Quantise the output rows of plane po (tile values in `ob`) into section S.
+template <int LB, int TY, int NT>
+__device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, int po, int X0, int Y0, int level,
+                                              int tid) {
+  constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;
+  const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const PlanePtr pq = plane_of(S, po);
+#pragma unroll
+  for (int t = 0; t < RPW; ++t) {
+    const int rr = wv + t * NW;
+    if (rr >= TY) break;
+    const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
+    int e;
+    const int m = quant_f32<LB>(ob[rr * kTX + lane], S.w, lane, &e);
+    store_row(pq.c, xyr, lane, m, S.cbits);
+    if ((lane & ((1 << LB) - 1)) == 0) pq.e[(xyr + lane) >> LB] = static_cast<int16_t>(e);
   }
 }
 
 // =========================================================== down-smoothing
-// y'_l = Q(S^nu1(0; g_l)): S = 2 nu1 half-sweeps from zero (red first).
-//
-// Register columns: each thread owns K pairs of adjacent x-columns of the
-// tile (with halo H = S - 1: the first half-sweep is pointwise) and keeps,
-// per column, the y values of planes j-S-1 .. j and the right-hand side of
-// planes j-S .. j in registers.  At step j stage s updates plane j - s;
-// within a pair exactly one column has the stage's colour on that plane,
-// and which one alternates with j.  The z-neighbours come from the
-// column's own registers; the four in-plane neighbours come from LDS,
-// where stage s publishes its updated values (double-buffered by step
-// parity) for stage s + 1 to read at the next step.  One barrier per step.
-template <int S, int TY, int NT>
-__global__ void __launch_bounds__(NT) k_down_smooth(SecRef G, SecRef Y, Geom g, float cp, float ih2, int TZ) {
+// y'_l = Q(S^nu1(0; g_l)): S = 2 nu1 half-sweeps from zero.  At step j the
+// right-hand side of plane j enters and stage s updates plane j - s; the
+// first half-sweep is pointwise (y = c g), hence a halo of S - 1.
+template <int S, int TY, int NT, int LB>
+__global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level, float cp, float ih2, int TZ) {
   constexpr int H = S - 1;
-  constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H;
-  constexpr int PW = EXW / 2, NPAIR = PW * EXH, K = (NPAIR + NT - 1) / NT;
-  constexpr int LW = EXW + 2, LPL = LW * (EXH + 2);  // LDS plane with a margin of one
-  constexpr int NB = S > 1 ? S - 1 : 1;
-  __shared__ float pub[2][NB][LPL];
+  using T = ColTile<H, TY, NT>;
+  constexpr int K = T::K, EXW = T::EXW, PS = T::PS, PAD = T::PAD;
+  constexpr int NB = S;  // plane j - s is in flight from step j - s + 1 to j - s + S
+  __shared__ float lds[2 * PAD + NB * PS];
   __shared__ float outb[2][TY * kTX];
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x;
   const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY, Z0 = blockIdx.z * TZ;
-  const int n = g.n;
-  const int64_t zstride = static_cast<int64_t>(1) << (2 * g.level);
+  const int n = 1 << level;
 
-  // per-pair constants
-  int pos[K];        // LDS position of column 0 of the pair
-  int par[K];        // column active at step j: (par + j) & 1
-  int64_t xy[K][2];  // flat x-y index of each column (or -1 outside the level)
-  unsigned upd[K];   // bit (2 (s-1) + c): stage s updates column c
-  unsigned outm[K];  // bit c: column c lies in the output interior; bit 2: pair exists
-  int oidx[K];       // output buffer index of column 0
+  int pos[K], oidx[K];
+  uint32_t xy[K][2];
+  unsigned fl[K];
+  col_setup<H, TY, NT>(tid, X0, Y0, level, pos, xy, fl, oidx);
+  const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+  auto wave_has = [&](int k) { return k * NT + wbase < T::NPAIR; };
+  auto launder = [&]() {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int q = tid + k * NT;
-    const bool valid = q < NPAIR;
-    const int ly = valid ? q / PW : 0, lx0 = valid ? 2 * (q - ly * PW) : 0;
-    const int gx0 = X0 - H + lx0, gy = Y0 - H + ly;
-    pos[k] = (ly + 1) * LW + lx0 + 1;
-    par[k] = (gx0 + gy - 1) & 1;
-    upd[k] = 0u;
-    outm[k] = 0u;
-    oidx[k] = (ly - H) * kTX + (lx0 - H);
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int lx = lx0 + c, gx = gx0 + c;
-      const bool dom = valid && gx >= 0 && gx < n && gy >= 0 && gy < n;
-      xy[k][c] = dom ? ((static_cast<int64_t>(gy) << g.level) | gx) : -1;
-      const int dx = max(max(H - lx, lx - (H + kTX - 1)), 0);
-      const int dy = max(max(H - ly, ly - (H + TY - 1)), 0);
-      const int d = max(dx, dy);
-      const bool inner = valid && gx >= 1 && gx < n && gy >= 1 && gy < n;
-#pragma unroll
-      for (int s = 1; s <= S; ++s)
-        if (inner && d <= S - s) upd[k] |= 1u << (2 * (s - 1) + c);
-      if (valid && d == 0) outm[k] |= 1u << c;
+    for (int k = 0; k < K; ++k) {
+      opaque(pos[k]);
+      opaque(oidx[k]);
+      opaque(fl[k]);
+      opaque(xy[k][0]);
+      opaque(xy[k][1]);
     }
-    if (valid) outm[k] |= 4u;
-  }
-  // pairs k whose whole wave lies beyond the tile do no work
-  auto wave_has = [&](int k) { return k * NT + (tid & ~63) < NPAIR; };
-  float y[K][2][S + 2];
-  float r[K][2][S + 1];
-  RawCode pre[K][2];
+  };
+
+  float y[K][2][S + 2];  // slot-indexed, planes j-S-1 .. j
+  float r[K][2][S + 1];  // slot-indexed, planes j-S .. j
+  RawCode gpre[K][2];    // column-indexed codes of the next plane
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -201,34 +210,37 @@ __global__ void __launch_bounds__(NT) k_down_smooth(SecRef G, SecRef Y, Geom g, 
 #pragma unroll
       for (int i = 0; i < S + 1; ++i) r[k][c][i] = 0.0f;
     }
-  auto fetch = [&](int jj) {
+  auto fetch = [&](int p) {
+    if (p >= 1 && p < n) {
+      const PlanePtr gq = plane_of(G, p);
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+      for (int k = 0; k < K; ++k)
+        if (wave_has(k))
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        pre[k][c] = raw_none();
-        if (xy[k][c] >= 0 && jj >= 0 && jj < n) pre[k][c] = raw_load(G, jj * zstride + xy[k][c]);
-      }
-  };
-  auto quantise_out = [&](int po, int slot) {
-    if (po < Z0 || po >= Z0 + TZ) return;
-    for (int rr = tid >> 6; rr < TY; rr += NT / 64) {
-      const float v = outb[slot][rr * kTX + lane];
-      const int64_t base = flat(g, X0, Y0 + rr, po);
-      int e;
-      const int32_t m = quantise_lane_f32(v, Y.B, Y.w, lane, &e);
-      store_codes_wave(Y, base, lane, m, Y.n);
-      if ((lane & (Y.B - 1)) == 0) Y.exps[blk(Y, base + lane)] = static_cast<int16_t>(e);
+          for (int c = 0; c < 2; ++c) gpre[k][c] = raw_at<LB>(gq, xy[k][c], G.cbits);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) gpre[k][c] = raw_none();
     }
   };
 
-  const int jbeg = Z0 - S, jend = Z0 + TZ + S;
-  fetch(jbeg);
-  for (int j = jbeg; j < jend; ++j) {
-    quantise_out(j - 1 - S, (j - 1) & 1);  // plane finished at the previous step
-    // new plane j: y = 0, rhs from the prefetch
+  auto step = [&](auto jpc, const int j) {
+    constexpr int JP = decltype(jpc)::value;
+    constexpr int SG = 1 - JP;  // slot updated by every stage at this step
+    launder();
+    {
+      const int po = j - 1 - S;  // completed at the previous step
+      if (po >= Z0 && po < Z0 + TZ) quantise_rows<LB, TY, NT>(outb[1 - JP], Y, po, X0, Y0, level, tid);
+    }
+    // plane j enters: y = 0, rhs from the prefetched codes
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) {
+      if (!wave_has(k)) continue;
+      const bool sw = (fl[k] >> kSwap) & 1u;
+      const float g0 = raw_f32(gpre[k][0], xy[k][0], G.cbits, G.w);
+      const float g1 = raw_f32(gpre[k][1], xy[k][1], G.cbits, G.w);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
 #pragma unroll
@@ -236,129 +248,175 @@ __global__ void __launch_bounds__(NT) k_down_smooth(SecRef G, SecRef Y, Geom g, 
         y[k][c][S + 1] = 0.0f;
 #pragma unroll
         for (int i = 0; i < S; ++i) r[k][c][i] = r[k][c][i + 1];
-        const int64_t idx = xy[k][c] >= 0 ? j * zstride + xy[k][c] : 0;
-        r[k][c][S] = static_cast<float>(raw_value(G, idx, pre[k][c]));
       }
-    if (j + 1 < jend) fetch(j + 1);
+      r[k][0][S] = sw ? g1 : g0;
+      r[k][1][S] = sw ? g0 : g1;
+    }
+    fetch(j + 1);
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
       const int p = j - s;
       if (p < max(1, Z0 - (S - s)) || p > min(n - 1, Z0 + TZ + (S - s) - 1)) continue;
       const int iy = S + 1 - s;
-      const float* src = pub[(j - 1) & 1][s >= 2 ? s - 2 : 0];
-      float* dst = pub[j & 1][s - 1 < NB ? s - 1 : 0];
+      float* yb = lds + PAD + (p % NB) * PS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (!wave_has(k)) continue;
-        const int ca = (par[k] + j) & 1;
-        const float yc = ca ? y[k][1][iy] : y[k][0][iy];
-        const float rhs = ca ? r[k][1][S - s] : r[k][0][S - s];
-        const int pa = pos[k] + ca;
+        const unsigned sw = (fl[k] >> kSwap) & 1u;
+        const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
+        const float yc = y[k][SG][iy];
+        const float rhs = r[k][SG][S - s];
         float v;
         if (s == 1) {
           v = cp * rhs;
         } else {
-          const float zm = ca ? y[k][1][iy - 1] : y[k][0][iy - 1];
-          const float zp = ca ? y[k][1][iy + 1] : y[k][0][iy + 1];
           float a = 6.0f * yc;
-          a = a - src[pa - 1];
-          a = a - src[pa + 1];
-          a = a - src[pa - LW];
-          a = a - src[pa + LW];
-          a = a - zm;
-          a = a - zp;
+          a = a - yb[pa - 1];
+          a = a - yb[pa + 1];
+          a = a - yb[pa - EXW];
+          a = a - yb[pa + EXW];
+          a = a - y[k][SG][iy - 1];
+          a = a - y[k][SG][iy + 1];
           a = a * ih2;
           const float rr = rhs - a;
           v = yc + cp * rr;
         }
-        const bool u = (upd[k] >> (2 * (s - 1) + ca)) & 1u;
-        const float yv = u ? v : yc;
-        y[k][0][iy] = ca == 0 ? yv : y[k][0][iy];
-        y[k][1][iy] = ca == 1 ? yv : y[k][1][iy];
-        if (s < S && (outm[k] & 4u)) dst[pa] = yv;
+        const float yv = ((fl[k] >> (kInnerSlot + SG)) & 1u) ? v : yc;
+        y[k][SG][iy] = yv;
+        if (s < S) yb[pa] = yv;
       }
     }
-    const int po = j - S;  // plane complete: both colours have their last update
-    if (po >= Z0 && po < Z0 + TZ) {
+    {
+      const int po = j - S;  // both colours have their last update
+      if (po >= Z0 && po < Z0 + TZ) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (outm[k] & 1u) outb[j & 1][oidx[k]] = y[k][0][1];
-        if (outm[k] & 2u) outb[j & 1][oidx[k] + 1] = y[k][1][1];
+        for (int k = 0; k < K; ++k) {
+          const unsigned sw = (fl[k] >> kSwap) & 1u;
+#pragma unroll
+          for (int sg = 0; sg < 2; ++sg)
+            if ((fl[k] >> (kOutSlot + sg)) & 1u) outb[JP][oidx[k] + static_cast<int>(sg ^ sw)] = y[k][sg][1];
+        }
       }
     }
     __syncthreads();
+  };
+
+  const int jbeg = Z0 - S, jend = Z0 + TZ + S + 2;  // an even number of steps
+  fetch(jbeg);
+#pragma unroll 1
+  for (int j = jbeg; j < jend; j += 2) {
+    step(std::integral_constant<int, 0>(), j);
+    step(std::integral_constant<int, 1>(), j + 1);
   }
-  quantise_out(jend - 1 - S, (jend - 1) & 1);
 }
 
 // ============================================================= up-smoothing
 // z = P e_{l-1}; rhs = g - A z; y = S^nu2(y'_pre; rhs); Yp = Q(y);
 // u'_l = Q(dec u'_l + dec Yp) (float64); e_l = dec Yp + z when eout != null.
 //
-// Same register-column scheme as the down-smoothing kernel, with two more
-// pipeline stages in front: z of plane j is prolongated per column from a
-// coarse ring in LDS and published, and at the next step the right-hand side
-// of plane j - 1 needs the published in-plane z neighbours.  The
-// pre-smoothed y' of a plane enters as stage 0 and is published too.
-template <int S, int TY, int NT>
-__global__ void __launch_bounds__(NT) k_up_smooth(const float* __restrict__ ec, SecRef G, SecRef Y, SecRef Yp,
-                                                  SecRef U, float* __restrict__ eout, Geom g, Geom gc, float cp,
-                                                  float ih2, int TZ) {
-  constexpr int H = S + 1;
-  constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H;
-  constexpr int PW = EXW / 2, NPAIR = PW * EXH, K = (NPAIR + NT - 1) / NT;
-  constexpr int LW = EXW + 2, LPL = LW * (EXH + 2);
-  constexpr int NC = 6, CW = EXW / 2 + 3, CH = EXH / 2 + 3, CPL = CW * CH;
-  constexpr int OPT = (TY * kTX + NT - 1) / NT;
-  __shared__ float cs[NC * CPL];
-  __shared__ float zpub[2][LPL];
-  __shared__ float pub[2][S][LPL];
-  __shared__ float outb[2][TY * kTX];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY, Z0 = blockIdx.z * TZ;
-  const int n = g.n;
-  const int CX0 = (X0 - H) >> 1, CY0 = (Y0 - H) >> 1;
-  const int64_t zstride = static_cast<int64_t>(1) << (2 * g.level);
+// Two stages run ahead of the smoother: at step j the columns interpolate z
+// of plane j from a ring of coarse planes in LDS and publish it; the
+// right-hand side of plane j - 1 then needs the published in-plane z
+// neighbours, and the pre-smoothed y' of plane j - 1 is published as stage
+// 0.  Stage s updates plane j - 1 - s.  The right-hand side of a node at
+// distance d from the output tile needs z at d + 1, and the first half-sweep
+// needs y' at d + 1 for d <= S - 1, so the halo is S.
+//
+// Interpolation weights are powers of two: 2^-(number of odd coordinates);
+// the weighted coarse neighbours are summed in C order (z, y, x).
+template <int PK, int CW>
+__device__ __forceinline__ float prolong_node(const float* c0, const float* c1, int ci, bool px, bool py) {
+  const float w = (px ? 0.5f : 1.0f) * (py ? 0.5f : 1.0f) * (PK ? 0.5f : 1.0f);
+  float s = w * c0[ci];
+  {
+    const float t = w * c0[ci + 1];
+    s = px ? s + t : s;
+  }
+  {
+    const float t = w * c0[ci + CW];
+    s = py ? s + t : s;
+  }
+  {
+    const float t = w * c0[ci + CW + 1];
+    s = (px && py) ? s + t : s;
+  }
+  if (PK) {
+    s = s + w * c1[ci];
+    {
+      const float t = w * c1[ci + 1];
+      s = px ? s + t : s;
+    }
+    {
+      const float t = w * c1[ci + CW];
+      s = py ? s + t : s;
+    }
+    {
+      const float t = w * c1[ci + CW + 1];
+      s = (px && py) ? s + t : s;
+    }
+  }
+  return s;
+}
 
-  int pos[K], par[K], gxy[K][2];
-  int64_t xy[K][2];   // flat x-y index of a column inside the level, else -1
-  unsigned upd[K];    // bit 2 (s-1) + c: stage s updates column c; bits 2S + c: rhs/y0 of column c
-  unsigned outm[K];   // bit c: column c in the output interior; bit 2: pair exists
-  int oidx[K];
+template <int S, int TY, int NT, int LB>
+__global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ ec, PSec G, PSec Y, PSec Yp, PSec U,
+                                                     float* __restrict__ eout, int level, int levelc, float cp,
+                                                     float ih2, int TZ) {
+  constexpr int H = S;
+  static_assert(H % 2 == 0, "even halo: column 0 of a pair has even x");
+  using T = ColTile<H, TY, NT>;
+  constexpr int K = T::K, EXW = T::EXW, PS = T::PS, PAD = T::PAD, NW = T::NW, RPW = T::RPW;
+  constexpr int NB = S + 1;  // y buffers: plane j - 1 - s in flight from step j - s to j - s + S
+  constexpr int NC = 8, CW = EXW / 2 + 2, CH = T::EXH / 2 + 1, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
+  __shared__ float cs[NC * CPL];
+  __shared__ float lds[2 * PAD + (2 + NB) * PS];  // z of planes j, j - 1; then y buffers
+  __shared__ float outb[2][TY * kTX];
+  const int tid = threadIdx.x;
+  int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int lane = tid & 63;
+  int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY;
+  const int Z0 = blockIdx.z * TZ;
+  const int n = 1 << level, nc = 1 << levelc;
+  const int CX0 = (X0 - H) >> 1, CY0 = (Y0 - H) >> 1;
+
+  int pos[K], oidx[K], cb[K];
+  uint32_t xy[K][2];
+  unsigned fl[K];
+  col_setup<H, TY, NT>(tid, X0, Y0, level, pos, xy, fl, oidx);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int q = tid + k * NT;
-    const bool valid = q < NPAIR;
-    const int ly = valid ? q / PW : 0, lx0 = valid ? 2 * (q - ly * PW) : 0;
-    const int gx0 = X0 - H + lx0, gy = Y0 - H + ly;
-    pos[k] = (ly + 1) * LW + lx0 + 1;
-    par[k] = (gx0 + gy - 1) & 1;
-    upd[k] = 0u;
-    outm[k] = valid ? 4u : 0u;
-    oidx[k] = (ly - H) * kTX + (lx0 - H);
-    gxy[k][0] = gx0;
-    gxy[k][1] = gy;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int lx = lx0 + c, gx = gx0 + c;
-      const bool dom = valid && gx >= 0 && gx < n && gy >= 0 && gy < n;
-      xy[k][c] = dom ? ((static_cast<int64_t>(gy) << g.level) | gx) : -1;
-      const int d = max(max(max(H - lx, lx - (H + kTX - 1)), 0), max(max(H - ly, ly - (H + TY - 1)), 0));
-      const bool inner = valid && gx >= 1 && gx < n && gy >= 1 && gy < n;
-#pragma unroll
-      for (int s = 1; s <= S; ++s)
-        if (inner && d <= S - s) upd[k] |= 1u << (2 * (s - 1) + c);
-      if (inner && d <= S) upd[k] |= 1u << (2 * S + c);
-      if (valid && d == 0) outm[k] |= 1u << c;
-    }
+    const int ly = q < T::NPAIR ? q / T::PW : 0, lx0 = q < T::NPAIR ? 2 * (q - ly * T::PW) : 0;
+    cb[k] = (((Y0 - H + ly) >> 1) - CY0) * CW + (((X0 - H + lx0) >> 1) - CX0);
   }
-  auto wave_has = [&](int k) { return k * NT + (tid & ~63) < NPAIR; };
+  const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+  auto wave_has = [&](int k) { return k * NT + wbase < T::NPAIR; };
+  auto launder = [&]() {
+    opaque(lane);
+    opaque_s(wv);
+    opaque_s(X0);
+    opaque_s(Y0);
+    opaque_s(level);
+    opaque_s(G);
+    opaque_s(Y);
+    opaque_s(Yp);
+    opaque_s(U);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      opaque(pos[k]);
+      opaque(oidx[k]);
+      opaque(cb[k]);
+      opaque(fl[k]);
+      opaque(xy[k][0]);
+      opaque(xy[k][1]);
+    }
+  };
 
-  float z[K][2][3];      // z of planes j-2, j-1, j
-  float r[K][2][S + 1];  // rhs of planes j-1-S .. j-1
-  float y[K][2][S + 2];  // y of planes j-2-S .. j-1
-  RawCode gpre[K][2], ypre[K][2], upre[OPT];
-  CoarseFetch<float, CW, CH, NT> cpf;
+  float z[K][2][3];      // column-indexed, planes j-2 .. j
+  float r[K][2][S + 1];  // slot-indexed, planes j-1-S .. j-1
+  float y[K][2][S + 2];  // slot-indexed, planes j-2-S .. j-1
+  RawCode gpre[K][2], ypre[K][2], upre[RPW];
+  float cpf[CPT];
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -370,165 +428,206 @@ __global__ void __launch_bounds__(NT) k_up_smooth(const float* __restrict__ ec, 
 #pragma unroll
       for (int i = 0; i < S + 2; ++i) y[k][c][i] = 0.0f;
     }
-  auto fetch_gy = [&](int p) {  // g and y' of plane p for the own columns
+  auto cfetch = [&](int cz) {  // coarse tile of plane cz into registers (0 outside the level)
+    const bool zin = cz >= 0 && cz < nc;
+    const float* src = ec + (static_cast<uint64_t>(zin ? cz : 0) << (2 * levelc));
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        gpre[k][c] = raw_none();
-        ypre[k][c] = raw_none();
-        if (xy[k][c] >= 0 && p >= 1 && p < n && ((upd[k] >> (2 * S + c)) & 1u)) {
-          const int64_t idx = p * zstride + xy[k][c];
-          gpre[k][c] = raw_load(G, idx);
-          ypre[k][c] = raw_load(Y, idx);
-        }
-      }
-  };
-  auto fetch_u = [&](int po) {
-#pragma unroll
-    for (int t = 0; t < OPT; ++t) {
-      const int rr = (tid >> 6) + t * (NT / 64);
-      upre[t] = raw_none();
-      if (rr < TY && po >= Z0 && po < Z0 + TZ) upre[t] = raw_load(U, flat(g, X0 + lane, Y0 + rr, po));
+    for (int k = 0; k < CPT; ++k) {
+      const int t = tid + k * NT;
+      const int cy = t / CW, cx = t - cy * CW;
+      const int gx = CX0 + cx, gy = CY0 + cy;
+      cpf[k] = 0.0f;
+      if (zin && t < CPL && gx >= 0 && gx < nc && gy >= 0 && gy < nc)
+        cpf[k] = src[(static_cast<uint32_t>(gy) << levelc) | static_cast<uint32_t>(gx)];
     }
   };
-  auto finish_out = [&](int po, int slot) {  // quantise y', correct u', write e
-    if (po < Z0 || po >= Z0 + TZ) return;
+  auto cstore = [&](int cz) {
+    float* dst = cs + (cz & (NC - 1)) * CPL;
 #pragma unroll
-    for (int t = 0; t < OPT; ++t) {
-      const int rr = (tid >> 6) + t * (NT / 64);
-      if (rr >= TY) continue;
-      const float v = outb[slot][rr * kTX + lane];
-      const int64_t base = flat(g, X0, Y0 + rr, po);
-      const int64_t i = base + lane;
+    for (int k = 0; k < CPT; ++k) {
+      const int t = tid + k * NT;
+      if (t < CPL) dst[t] = cpf[k];
+    }
+  };
+  auto fetch_gy = [&](int p) {  // codes of plane p for the own columns
+    if (p >= 1 && p < n) {
+      const PlanePtr gq = plane_of(G, p), yq = plane_of(Y, p);
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (wave_has(k))
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            gpre[k][c] = raw_at<LB>(gq, xy[k][c], G.cbits);
+            ypre[k][c] = raw_at<LB>(yq, xy[k][c], Y.cbits);
+          }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          gpre[k][c] = raw_none();
+          ypre[k][c] = raw_none();
+        }
+    }
+  };
+  auto fetch_u = [&](int po) {  // codes of the output rows of plane po
+    if (po < Z0 || po >= Z0 + TZ) return;
+    const PlanePtr uq = plane_of(U, po);
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+      const int rr = wv + t * NW;
+      if (rr < TY) upre[t] = raw_at<LB>(uq, ((static_cast<uint32_t>(Y0 + rr) << level) | X0) + lane, U.cbits);
+    }
+  };
+  auto finish = [&](auto pkc, int po, const float* ob) {  // quantise y', correct u', write e
+    constexpr int PK = decltype(pkc)::value;
+    if (po < Z0 || po >= Z0 + TZ) return;
+    const PlanePtr yq = plane_of(Yp, po), uq = plane_of(U, po);
+    const float* c0 = cs + ((po >> 1) & (NC - 1)) * CPL;
+    const float* c1 = cs + (((po >> 1) + 1) & (NC - 1)) * CPL;
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+      const int rr = wv + t * NW;
+      if (rr >= TY) break;
+      const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
+      const uint32_t xyl = xyr + lane;
       int ey;
-      const int32_t my = quantise_lane_f32(v, Yp.B, Yp.w, lane, &ey);
-      store_codes_wave(Yp, base, lane, my, Yp.n);
-      if ((lane & (Yp.B - 1)) == 0) Yp.exps[blk(Yp, i)] = static_cast<int16_t>(ey);
+      const int my = quant_f32<LB>(ob[rr * kTX + lane], Yp.w, lane, &ey);
+      store_row(yq.c, xyr, lane, my, Yp.cbits);
+      if ((lane & ((1 << LB) - 1)) == 0) yq.e[xyl >> LB] = static_cast<int16_t>(ey);
       const double dy = ey == kZeroExp ? 0.0 : ldexp(static_cast<double>(my), ey - (Yp.w - 1));
-      const double vu = raw_value(U, i, upre[t]) + dy;
+      const double vu = raw_f64(upre[t], xyl, U.cbits, U.w) + dy;
       int eu;
-      const int64_t mu = quantise_lane(vu, U.B, U.w, &eu);
-      store_codes_wave(U, base, lane, mu, U.n);
-      if ((lane & (U.B - 1)) == 0) U.exps[blk(U, i)] = static_cast<int16_t>(eu);
+      const int64_t mu = quant_f64<LB>(vu, U.w, lane, &eu);
+      store_row(uq.c, xyr, lane, mu, U.cbits);
+      if ((lane & ((1 << LB) - 1)) == 0) uq.e[xyl >> LB] = static_cast<int16_t>(eu);
       if (eout != nullptr) {
-        const float zz = prolong_lds<float, NC, CW, CPL>(cs, CX0, CY0, X0 + lane, Y0 + rr, po);
-        eout[i] = static_cast<float>(dy) + zz;
+        const int ci = ((rr >> 1) + H / 2) * CW + (lane >> 1) + H / 2;
+        const float zz = prolong_node<PK, CW>(c0, c1, ci, lane & 1, rr & 1);
+        eout[(static_cast<uint64_t>(po) << (2 * level)) + xyl] = static_cast<float>(dy) + zz;
       }
     }
   };
 
-  const int jbeg = Z0 - S - 1, jend = Z0 + TZ + S + 1;
-  cpf.fetch(ec, gc, CX0, CY0, jbeg >> 1, tid);
-  cpf.store(cs + ring(jbeg >> 1, NC) * CPL, tid);
-  cpf.fetch(ec, gc, CX0, CY0, (jbeg >> 1) + 1, tid);
-  cpf.store(cs + ring((jbeg >> 1) + 1, NC) * CPL, tid);
-  fetch_gy(jbeg - 1);
-  fetch_u(jbeg - 2 - S);
-  __syncthreads();
-  for (int j = jbeg; j < jend; ++j) {
-    finish_out(j - 2 - S, (j - 1) & 1);  // plane completed at the previous step
+  auto step = [&](auto jpc, const int j) {
+    constexpr int JP = decltype(jpc)::value;
+    constexpr int SG = JP;  // slot updated by every stage at this step
+    launder();
+    finish(jpc, j - 2 - S, outb[1 - JP]);
     fetch_u(j - 1 - S);
-    const bool need_c = ((j + 1) & 1) && j + 1 < jend;  // z(j+1) needs coarse plane (j+2)/2
-    if (need_c) cpf.fetch(ec, gc, CX0, CY0, (j + 2) >> 1, tid);
-    // (b) z of plane j for the own columns, published
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (!wave_has(k)) continue;
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        z[k][c][0] = z[k][c][1];
-        z[k][c][1] = z[k][c][2];
-        const int gx = gxy[k][0] + c, gy = gxy[k][1];
-        float zz = 0.0f;
-        if ((outm[k] & 4u) && j >= 0 && gx >= 0 && gy >= 0)
-          zz = prolong_lds<float, NC, CW, CPL>(cs, CX0, CY0, gx, gy, j);
-        z[k][c][2] = zz;
-        if (outm[k] & 4u) zpub[j & 1][pos[k] + c] = zz;
-      }
-    }
-    // (c) plane j - 1: rhs = g - A z and y0 for both columns; y0 published as stage 0
-    {
-      const int p = j - 1;
-      const float* zs = zpub[(j - 1) & 1];
+    if (JP == 0) cfetch((j + 2) >> 1);  // z(j + 1) needs coarse plane (j + 2) / 2
+    {  // z of plane j
+      const float* c0 = cs + ((j >> 1) & (NC - 1)) * CPL;
+      const float* c1 = cs + (((j >> 1) + 1) & (NC - 1)) * CPL;
+      float* zb = lds + PAD + JP * PS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (!wave_has(k)) continue;
+        const bool py = (fl[k] >> kOddY) & 1u;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          z[k][c][0] = z[k][c][1];
+          z[k][c][1] = z[k][c][2];
+          z[k][c][2] = prolong_node<JP, CW>(c0, c1, cb[k], c == 1, py);
+          zb[pos[k] + c] = z[k][c][2];
+        }
+      }
+    }
+    {  // plane j - 1: rhs = g - A z, and y' as stage 0
+      const int p = j - 1;
+      const bool pin = p >= 1 && p < n;
+      const float* zs = lds + PAD + (1 - JP) * PS;
+      float* yb = lds + PAD + (2 + (p + 4 * NB) % NB) * PS;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (!wave_has(k)) continue;
+        float rv[2], yv[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int pc = pos[k] + c;
+          float a = 6.0f * z[k][c][1];
+          a = a - zs[pc - 1];
+          a = a - zs[pc + 1];
+          a = a - zs[pc - EXW];
+          a = a - zs[pc + EXW];
+          a = a - z[k][c][0];
+          a = a - z[k][c][2];
+          a = a * ih2;
+          const bool keep = pin && ((fl[k] >> (kInnerCol + c)) & 1u);
+          const float gv = raw_f32(gpre[k][c], xy[k][c], G.cbits, G.w) - a;
+          const float y0 = raw_f32(ypre[k][c], xy[k][c], Y.cbits, Y.w);
+          rv[c] = keep ? gv : 0.0f;
+          yv[c] = keep ? y0 : 0.0f;
+          yb[pc] = yv[c];
+        }
+        const bool sw = (fl[k] >> kSwap) & 1u;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
 #pragma unroll
           for (int i = 0; i < S; ++i) r[k][c][i] = r[k][c][i + 1];
 #pragma unroll
           for (int i = 0; i < S + 1; ++i) y[k][c][i] = y[k][c][i + 1];
-          float rv = 0.0f, yv = 0.0f;
-          if (((upd[k] >> (2 * S + c)) & 1u) && p >= 1 && p < n) {
-            const int pc = pos[k] + c;
-            float a = 6.0f * z[k][c][1];
-            a = a - zs[pc - 1];
-            a = a - zs[pc + 1];
-            a = a - zs[pc - LW];
-            a = a - zs[pc + LW];
-            a = a - z[k][c][0];
-            a = a - z[k][c][2];
-            a = a * ih2;
-            const int64_t idx = p * zstride + xy[k][c];
-            rv = static_cast<float>(raw_value(G, idx, gpre[k][c])) - a;
-            yv = static_cast<float>(raw_value(Y, idx, ypre[k][c]));
-          }
-          r[k][c][S] = rv;
-          y[k][c][S + 1] = yv;
-          if (outm[k] & 4u) pub[j & 1][0][pos[k] + c] = yv;
         }
+        r[k][0][S] = sw ? rv[1] : rv[0];
+        r[k][1][S] = sw ? rv[0] : rv[1];
+        y[k][0][S + 1] = sw ? yv[1] : yv[0];
+        y[k][1][S + 1] = sw ? yv[0] : yv[1];
       }
-      if (j + 1 < jend) fetch_gy(j);
+      fetch_gy(j);
     }
-    // (d) post-smoothing: stage s on plane j - 1 - s
 #pragma unroll
-    for (int s = 1; s <= S; ++s) {
+    for (int s = 1; s <= S; ++s) {  // post-smoothing: stage s on plane j - 1 - s
       const int p = j - 1 - s;
       if (p < max(1, Z0 - (S - s)) || p > min(n - 1, Z0 + TZ + (S - s) - 1)) continue;
       const int iy = S + 1 - s;
-      const float* src = pub[(j - 1) & 1][s - 1];
-      float* dst = pub[j & 1][s < S ? s : 0];
+      float* yb = lds + PAD + (2 + p % NB) * PS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (!wave_has(k)) continue;
-        const int ca = (par[k] + j - 1) & 1;
-        const float yc = ca ? y[k][1][iy] : y[k][0][iy];
-        const float zm = ca ? y[k][1][iy - 1] : y[k][0][iy - 1];
-        const float zp = ca ? y[k][1][iy + 1] : y[k][0][iy + 1];
-        const float rhs = ca ? r[k][1][S - s] : r[k][0][S - s];
-        const int pa = pos[k] + ca;
+        const unsigned sw = (fl[k] >> kSwap) & 1u;
+        const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
+        const float yc = y[k][SG][iy];
         float a = 6.0f * yc;
-        a = a - src[pa - 1];
-        a = a - src[pa + 1];
-        a = a - src[pa - LW];
-        a = a - src[pa + LW];
-        a = a - zm;
-        a = a - zp;
+        a = a - yb[pa - 1];
+        a = a - yb[pa + 1];
+        a = a - yb[pa - EXW];
+        a = a - yb[pa + EXW];
+        a = a - y[k][SG][iy - 1];
+        a = a - y[k][SG][iy + 1];
         a = a * ih2;
-        const float rr = rhs - a;
+        const float rr = r[k][SG][S - s] - a;
         const float v = yc + cp * rr;
-        const bool u = (upd[k] >> (2 * (s - 1) + ca)) & 1u;
-        const float yv = u ? v : yc;
-        y[k][0][iy] = ca == 0 ? yv : y[k][0][iy];
-        y[k][1][iy] = ca == 1 ? yv : y[k][1][iy];
-        if (s < S && (outm[k] & 4u)) dst[pa] = yv;
+        const float yv = ((fl[k] >> (kInnerSlot + SG)) & 1u) ? v : yc;
+        y[k][SG][iy] = yv;
+        if (s < S) yb[pa] = yv;
       }
     }
-    // (e) plane j - 1 - S is complete
-    const int po = j - 1 - S;
-    if (po >= Z0 && po < Z0 + TZ) {
+    {
+      const int po = j - 1 - S;  // complete
+      if (po >= Z0 && po < Z0 + TZ) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (outm[k] & 1u) outb[j & 1][oidx[k]] = y[k][0][1];
-        if (outm[k] & 2u) outb[j & 1][oidx[k] + 1] = y[k][1][1];
+        for (int k = 0; k < K; ++k) {
+          const unsigned sw = (fl[k] >> kSwap) & 1u;
+#pragma unroll
+          for (int sg = 0; sg < 2; ++sg)
+            if ((fl[k] >> (kOutSlot + sg)) & 1u) outb[JP][oidx[k] + static_cast<int>(sg ^ sw)] = y[k][sg][1];
+        }
       }
     }
-    if (need_c) cpf.store(cs + ring((j + 2) >> 1, NC) * CPL, tid);
+    if (JP == 0) cstore((j + 2) >> 1);
     __syncthreads();
+  };
+
+  const int jbeg = Z0 - S, jend = Z0 + TZ + S + 2;  // an even number of steps
+  cfetch(jbeg >> 1);
+  cstore(jbeg >> 1);
+  fetch_gy(jbeg - 1);
+  __syncthreads();
+#pragma unroll 1
+  for (int j = jbeg; j < jend; j += 2) {
+    step(std::integral_constant<int, 0>(), j);
+    step(std::integral_constant<int, 1>(), j + 1);
   }
-  finish_out(jend - 2 - S, (jend - 1) & 1);
 }
 
 // ======================================================== residual-restrict
@@ -820,41 +919,63 @@ static double sec_b(const SecRef& s) {
     if (g_timing != nullptr) g_timing->end(stream);                                       \
   } while (0)
 
-constexpr int kDownTY = 16, kUpTY = 16, kResTY = 16, kRRCTY = 4, kUpNT = 512;
+constexpr int kDownTY = 16, kUpTY = 16, kResTY = 16, kRRCTY = 4, kDownNT = 448, kUpNT = 896;
+
+static PSec psec(const SecRef& s, const Geom& g) {
+  const uint64_t pv = static_cast<uint64_t>(1) << (2 * g.level);  // values per plane
+  PSec p;
+  p.codes = static_cast<char*>(s.codes);
+  p.exps = s.exps;
+  p.plane_bytes = static_cast<uint32_t>(pv * s.cbits / 8);
+  p.plane_blks = static_cast<uint32_t>(pv / s.B);
+  p.cbits = s.cbits;
+  p.w = s.w;
+  return p;
+}
 
 bool fused_down_smooth(const SecRef& G, const SecRef& Y, const Geom& g, int nu, float cp, float ih2,
                        hipStream_t st) {
-  if (g.dim != 3 || g.n < kTX) return false;
-  const int ty = kDownTY;
-  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / ty), 16);
-  const dim3 grid(g.n / kTX, g.n / ty, g.n / tz);
+  if (g.dim != 3 || g.n < kTX || (nu != 1 && nu != 2) || (G.B != 32 && G.B != 64) || Y.B != G.B) return false;
+  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDownTY), 16);
+  const dim3 grid(g.n / kTX, g.n / kDownTY, g.n / tz), block(kDownNT);
   const double bytes = sec_b(G) + sec_b(Y);
-  if (nu == 2)
-    CMG_FLAUNCH("k_down_smooth<4>", bytes, (k_down_smooth<4, kDownTY, 256>), grid, dim3(256), st, G, Y, g, cp, ih2,
-                tz);
-  else if (nu == 1)
-    CMG_FLAUNCH("k_down_smooth<2>", bytes, (k_down_smooth<2, kDownTY, 256>), grid, dim3(256), st, G, Y, g, cp, ih2,
-                tz);
+  const PSec pg = psec(G, g), py = psec(Y, g);
+  if (nu == 2 && G.B == 64)
+    CMG_FLAUNCH("k_down_smooth<4>", bytes, (k_down_smooth<4, kDownTY, kDownNT, 6>), grid, block, st, pg, py, g.level,
+                cp, ih2, tz);
+  else if (nu == 2)
+    CMG_FLAUNCH("k_down_smooth<4>", bytes, (k_down_smooth<4, kDownTY, kDownNT, 5>), grid, block, st, pg, py, g.level,
+                cp, ih2, tz);
+  else if (G.B == 64)
+    CMG_FLAUNCH("k_down_smooth<2>", bytes, (k_down_smooth<2, kDownTY, kDownNT, 6>), grid, block, st, pg, py, g.level,
+                cp, ih2, tz);
   else
-    return false;
+    CMG_FLAUNCH("k_down_smooth<2>", bytes, (k_down_smooth<2, kDownTY, kDownNT, 5>), grid, block, st, pg, py, g.level,
+                cp, ih2, tz);
   return true;
 }
 
 bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const SecRef& Yp, const SecRef& U,
                      float* eout, const Geom& g, const Geom& gc, int nu, float cp, float ih2, hipStream_t st) {
-  if (g.dim != 3 || g.n < kTX) return false;
-  const int ty = kUpTY;
-  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / ty), 16);
-  const dim3 grid(g.n / kTX, g.n / ty, g.n / tz);
-  const double bytes = sec_b(G) + sec_b(Y) + sec_b(Yp) + 2.0 * sec_b(U) + 4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
-  if (nu == 2)
-    CMG_FLAUNCH("k_up_smooth<4>", bytes, (k_up_smooth<4, kUpTY, kUpNT>), grid, dim3(kUpNT), st, ec, G, Y, Yp, U, eout, g,
-                gc, cp, ih2, tz);
-  else if (nu == 1)
-    CMG_FLAUNCH("k_up_smooth<2>", bytes, (k_up_smooth<2, kUpTY, kUpNT>), grid, dim3(kUpNT), st, ec, G, Y, Yp, U, eout, g,
-                gc, cp, ih2, tz);
-  else
+  if (g.dim != 3 || g.n < kTX || (nu != 1 && nu != 2) || (G.B != 32 && G.B != 64) || Y.B != G.B || Yp.B != G.B ||
+      U.B != G.B)
     return false;
+  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kUpTY), 16);
+  const dim3 grid(g.n / kTX, g.n / kUpTY, g.n / tz), block(kUpNT);
+  const double bytes = sec_b(G) + sec_b(Y) + sec_b(Yp) + 2.0 * sec_b(U) + 4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
+  const PSec pg = psec(G, g), py = psec(Y, g), pp = psec(Yp, g), pu = psec(U, g);
+  if (nu == 2 && G.B == 64)
+    CMG_FLAUNCH("k_up_smooth<4>", bytes, (k_up_smooth<4, kUpTY, kUpNT, 6>), grid, block, st, ec, pg, py, pp, pu, eout,
+                g.level, gc.level, cp, ih2, tz);
+  else if (nu == 2)
+    CMG_FLAUNCH("k_up_smooth<4>", bytes, (k_up_smooth<4, kUpTY, kUpNT, 5>), grid, block, st, ec, pg, py, pp, pu, eout,
+                g.level, gc.level, cp, ih2, tz);
+  else if (G.B == 64)
+    CMG_FLAUNCH("k_up_smooth<2>", bytes, (k_up_smooth<2, kUpTY, kUpNT, 6>), grid, block, st, ec, pg, py, pp, pu, eout,
+                g.level, gc.level, cp, ih2, tz);
+  else
+    CMG_FLAUNCH("k_up_smooth<2>", bytes, (k_up_smooth<2, kUpTY, kUpNT, 5>), grid, block, st, ec, pg, py, pp, pu, eout,
+                g.level, gc.level, cp, ih2, tz);
   return true;
 }
 

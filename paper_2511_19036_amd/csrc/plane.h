@@ -1,0 +1,183 @@
+// Plane-addressed section access and block quantisation for the fused 3-D
+// level kernels.
+//
+// On a 3-D level with at least 64^3 nodes one z-plane holds 4^l values: a
+// whole number of blocks and of 32-bit code words for every container.  A
+// value is then addressed by a wave-uniform plane pointer plus a 32-bit
+// in-plane offset, which keeps 64-bit index arithmetic out of the kernels.
+//
+// Block quantisation uses the following fact: with E(a) the exponent that a
+// block whose maximum magnitude is a receives (the frexp exponent of a, plus
+// one when a rounds up to 2^(w-1) at w bits), E is non-decreasing in a, so
+// the block exponent equals the largest E over the block's values.  Each lane
+// computes its own E and the block takes an integer maximum over its lanes
+// (DPP row reductions plus readlane), which gives the same exponent and codes
+// as rounding the block maximum itself.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace cmg {
+
+struct PSec {
+  char* codes;           // code stream (values at bit cbits * i)
+  int16_t* exps;         // block exponents
+  uint32_t plane_bytes;  // 4^l * cbits / 8
+  uint32_t plane_blks;   // 4^l / B
+  int32_t cbits;         // 8, 12, 16, 32 or 64
+  int32_t w;             // logical width, sign included
+};
+
+struct PlanePtr {
+  char* c;
+  int16_t* e;
+};
+
+// Plane p >= 0 of a section.
+__device__ __forceinline__ PlanePtr plane_of(const PSec& s, int p) {
+  const uint32_t up = static_cast<uint32_t>(p);
+  return PlanePtr{s.codes + static_cast<uint64_t>(up) * s.plane_bytes, s.exps + static_cast<uint64_t>(up) * s.plane_blks};
+}
+
+// Raw words and block exponent of in-plane value xy (see RawCode).  Sections
+// carry 16 bytes of padding, so the second word is always readable.
+template <int LB>
+__device__ __forceinline__ RawCode raw_at(const PlanePtr& pp, uint32_t xy, int cbits) {
+  const uint32_t bit = xy * static_cast<uint32_t>(cbits);
+  const uint32_t* wp = reinterpret_cast<const uint32_t*>(pp.c + ((bit >> 5) << 2));
+  RawCode r;
+  r.lo = wp[0];
+  r.hi = (cbits == 12 || cbits == 64) ? wp[1] : 0u;
+  r.e = pp.e[xy >> LB];
+  return r;
+}
+
+// Value of a raw code of width w <= 24 (container at most 32 bits) as float:
+// the code converts exactly and the scaling rounds once, as the conversion
+// of the exact double value to float does.
+__device__ __forceinline__ float raw_f32(const RawCode& r, uint32_t xy, int cbits, int w) {
+  const uint32_t sh = (xy * static_cast<uint32_t>(cbits)) & 31u;
+  const uint32_t x = __builtin_amdgcn_alignbit(r.hi, r.lo, sh);
+  const int m = static_cast<int>(x << (32 - cbits)) >> (32 - cbits);
+  const float v = ldexpf(static_cast<float>(m), r.e - (w - 1));
+  return r.e == kZeroExp ? 0.0f : v;
+}
+
+// Exact value of a raw code of any container as double.
+__device__ __forceinline__ double raw_f64(const RawCode& r, uint32_t xy, int cbits, int w) {
+  double d;
+  if (cbits == 64) {
+    d = static_cast<double>(static_cast<int64_t>((static_cast<uint64_t>(r.hi) << 32) | r.lo));
+  } else {
+    const uint32_t sh = (xy * static_cast<uint32_t>(cbits)) & 31u;
+    const uint32_t x = __builtin_amdgcn_alignbit(r.hi, r.lo, sh);
+    d = static_cast<double>(static_cast<int>(x << (32 - cbits)) >> (32 - cbits));
+  }
+  const double v = ldexp(d, r.e - (w - 1));
+  return r.e == kZeroExp ? 0.0 : v;
+}
+
+// Hide a per-lane value from loop-invariant code motion, so that values
+// derived from it are recomputed where they are used instead of occupying
+// registers for the whole z-march.
+template <typename T>
+__device__ __forceinline__ void opaque(T& v) {
+  asm volatile("" : "+v"(v));
+}
+// The same for a wave-uniform value (kept in scalar registers).
+template <typename T>
+__device__ __forceinline__ void opaque_s(T& v) {
+  asm volatile("" : "+s"(v));
+}
+__device__ __forceinline__ void opaque_s(PSec& s) {
+  opaque_s(s.plane_bytes);
+  opaque_s(s.plane_blks);
+  opaque_s(s.cbits);
+  opaque_s(s.w);
+}
+
+// ------------------------------------------------------- block exponents
+constexpr int kNoExp = INT32_MIN;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+// Max over the lanes of each block of B = 2^LB lanes.  All 64 lanes active.
+template <int LB>
+__device__ __forceinline__ int block_max_int(int a, int lane) {
+  a = max(a, dpp_int<0xB1>(a));   // quad_perm 1,0,3,2
+  a = max(a, dpp_int<0x4E>(a));   // quad_perm 2,3,0,1
+  a = max(a, dpp_int<0x141>(a));  // row_half_mirror
+  a = max(a, dpp_int<0x140>(a));  // row_mirror
+  const int r0 = __builtin_amdgcn_readlane(a, 0), r1 = __builtin_amdgcn_readlane(a, 16);
+  const int r2 = __builtin_amdgcn_readlane(a, 32), r3 = __builtin_amdgcn_readlane(a, 48);
+  if (LB == 6) return max(max(r0, r1), max(r2, r3));
+  return lane < 32 ? max(r0, r1) : max(r2, r3);
+}
+
+// Per-lane exponent E(|v|) at width w (kNoExp for 0); top = 2^(w-1).
+__device__ __forceinline__ int lane_exp(float v, int w, float top) {
+  const float a = fabsf(v);
+  int e;
+  (void)frexpf(a, &e);
+  const int up = rintf(ldexpf(a, w - 1 - e)) == top ? 1 : 0;
+  return a == 0.0f ? kNoExp : e + up;
+}
+__device__ __forceinline__ int lane_exp(double v, int w, double top) {
+  const double a = fabs(v);
+  int e;
+  (void)frexp(a, &e);
+  const int up = rint(ldexp(a, w - 1 - e)) == top ? 1 : 0;
+  return a == 0.0 ? kNoExp : e + up;
+}
+
+// Quantise the value of each lane into its block (w <= 24): returns the code,
+// *e_out the block exponent (kZeroExp for an all-zero block).
+template <int LB>
+__device__ __forceinline__ int quant_f32(float v, int w, int lane, int* e_out) {
+  const int E = block_max_int<LB>(lane_exp(v, w, ldexpf(1.0f, w - 1)), lane);
+  const int Eq = E == kNoExp ? 0 : E;
+  *e_out = E == kNoExp ? kZeroExp : E;
+  return static_cast<int>(rintf(ldexpf(v, w - 1 - Eq)));
+}
+
+template <int LB>
+__device__ __forceinline__ int64_t quant_f64(double v, int w, int lane, int* e_out) {
+  const int E = block_max_int<LB>(lane_exp(v, w, ldexp(1.0, w - 1)), lane);
+  const int Eq = E == kNoExp ? 0 : E;
+  *e_out = E == kNoExp ? kZeroExp : E;
+  const double q = rint(ldexp(v, w - 1 - Eq));
+  return w <= 32 ? static_cast<int64_t>(static_cast<int>(q)) : static_cast<int64_t>(q);
+}
+
+// Store the codes of one row of 64 values (in-plane offset xy0, a multiple
+// of 64) held by the 64 lanes; the 12-bit container is packed by lanes 0..23.
+__device__ __forceinline__ void store_row(char* pc, uint32_t xy0, int lane, int64_t m, int cbits) {
+  switch (cbits) {
+    case 8: reinterpret_cast<int8_t*>(pc)[xy0 + lane] = static_cast<int8_t>(m); break;
+    case 16: reinterpret_cast<int16_t*>(pc)[xy0 + lane] = static_cast<int16_t>(m); break;
+    case 32: reinterpret_cast<int32_t*>(pc)[xy0 + lane] = static_cast<int32_t>(m); break;
+    case 64: reinterpret_cast<int64_t*>(pc)[xy0 + lane] = m; break;
+    default: {
+      const uint32_t c = static_cast<uint32_t>(m) & 0xFFFu;
+      const int bit0 = 32 * lane;
+      const int v0 = bit0 / 12;
+      uint32_t acc = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int v = v0 + k;
+        const uint32_t cv = __shfl(c, v & 63, 64);
+        const int sh = 12 * v - bit0;
+        if (v < 64 && sh < 32) acc |= sh >= 0 ? (cv << sh) : (cv >> (-sh));
+      }
+      if (lane < 24) reinterpret_cast<uint32_t*>(pc)[(xy0 >> 6) * 24 + lane] = acc;
+    }
+  }
+}
+
+}  // namespace cmg
