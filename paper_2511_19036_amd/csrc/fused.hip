@@ -324,34 +324,34 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
 //
 // Interpolation weights are powers of two: 2^-(number of odd coordinates);
 // the weighted coarse neighbours are summed in C order (z, y, x).
-template <int PK, int CW>
-__device__ __forceinline__ float prolong_node(const float* c0, const float* c1, int ci, bool px, bool py) {
-  const float w = (px ? 0.5f : 1.0f) * (py ? 0.5f : 1.0f) * (PK ? 0.5f : 1.0f);
-  float s = w * c0[ci];
+template <typename T, int PK, int CW>
+__device__ __forceinline__ T prolong_node(const T* c0, const T* c1, int ci, bool px, bool py) {
+  const T w = (px ? T(0.5) : T(1)) * (py ? T(0.5) : T(1)) * (PK ? T(0.5) : T(1));
+  T s = w * c0[ci];
   {
-    const float t = w * c0[ci + 1];
+    const T t = w * c0[ci + 1];
     s = px ? s + t : s;
   }
   {
-    const float t = w * c0[ci + CW];
+    const T t = w * c0[ci + CW];
     s = py ? s + t : s;
   }
   {
-    const float t = w * c0[ci + CW + 1];
+    const T t = w * c0[ci + CW + 1];
     s = (px && py) ? s + t : s;
   }
   if (PK) {
     s = s + w * c1[ci];
     {
-      const float t = w * c1[ci + 1];
+      const T t = w * c1[ci + 1];
       s = px ? s + t : s;
     }
     {
-      const float t = w * c1[ci + CW];
+      const T t = w * c1[ci + CW];
       s = py ? s + t : s;
     }
     {
-      const float t = w * c1[ci + CW + 1];
+      const T t = w * c1[ci + CW + 1];
       s = (px && py) ? s + t : s;
     }
   }
@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       if ((lane & ((1 << LB) - 1)) == 0) uq.e[xyl >> LB] = static_cast<int16_t>(eu);
       if (eout != nullptr) {
         const int ci = ((rr >> 1) + H / 2) * CW + (lane >> 1) + H / 2;
-        const float zz = prolong_node<PK, CW>(c0, c1, ci, lane & 1, rr & 1);
+        const float zz = prolong_node<float, PK, CW>(c0, c1, ci, lane & 1, rr & 1);
         eout[(static_cast<uint64_t>(po) << (2 * level)) + xyl] = static_cast<float>(dy) + zz;
       }
     }
@@ -528,7 +528,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
         for (int c = 0; c < 2; ++c) {
           z[k][c][0] = z[k][c][1];
           z[k][c][1] = z[k][c][2];
-          z[k][c][2] = prolong_node<JP, CW>(c0, c1, cb[k], c == 1, py);
+          z[k][c][2] = prolong_node<float, JP, CW>(c0, c1, cb[k], c == 1, py);
           zb[pos[k] + c] = z[k][c][2];
         }
       }
@@ -760,144 +760,228 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(SecRef G, SecRef Y, SecRe
 // g_Lp = Q(f - A(dec u'_Lp + P u_{Lp-1})) in float64 (Alg. 2 on the finest
 // level of the current FMG level); f is the caller's full node array of the
 // finest level L, sampled with stride 2^(L - Lp).
-template <int TY, int NT>
-__global__ void __launch_bounds__(NT) k_ir_residual(SecRef U, const double* __restrict__ uc,
-                                                    const double* __restrict__ f, int Lfull, Geom g, Geom gc,
-                                                    double ih2, SecRef Gout, int TZ, int* nonfinite,
-                                                    double* sumsq) {
-  constexpr int EXW = kTX + 2, EXH = TY + 2, PLS = EXW * EXH;
-  constexpr int NC = 3, CW = EXW / 2 + 3, CH = EXH / 2 + 3, CPL = CW * CH;
-  constexpr int UPT = (PLS + NT - 1) / NT, FPT = (TY * 64 + NT - 1) / NT;
-  __shared__ double us[3 * PLS];
+//
+// Each thread owns RPT output columns (x = X0 + lane, rows wv + NW t) and
+// keeps u of planes j-2 .. j of them in registers; the threads tid < NHALO
+// also decode one node of the one-node x-y halo.  Every plane of u goes
+// through a ring of three LDS planes, so that a single barrier per step
+// separates the writes of plane j from the reads of plane j - 2.
+template <int TY, int NT, int LB>
+__global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __restrict__ uc,
+                                                    const double* __restrict__ f, int Lfull, int level, int levelc,
+                                                    double ih2, PSec Gout, int TZ, int* nonfinite, double* sumsq) {
+  constexpr int NW = NT / 64, RPT = TY / NW;
+  static_assert(TY % NW == 0, "whole rows per wave");
+  constexpr int EXW = kTX + 2, LPL = EXW * (TY + 2);
+  constexpr int NHALO = 2 * EXW + 2 * TY;
+  static_assert(NHALO <= NT, "one halo node per thread");
+  constexpr int NC = 4, CW = kTX / 2 + 3, CH = TY / 2 + 3, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
+  __shared__ double us[3 * LPL];
   __shared__ double cs[NC * CPL];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY, Z0 = blockIdx.z * TZ;
-  const int n = g.n;
-  const int CX0 = (X0 - 1) >> 1, CY0 = (Y0 - 1) >> 1;
+  const int tid = threadIdx.x;
+  int lane = tid & 63;
+  int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY;
+  const int Z0 = blockIdx.z * TZ;
+  const int n = 1 << level, nc = 1 << levelc;
+  const int CX0 = (X0 >> 1) - 1, CY0 = (Y0 >> 1) - 1;
   const int64_t N = (static_cast<int64_t>(1) << Lfull) + 1;
-  const int st = 1 << (Lfull - g.level);
-  const int jbeg = Z0 - 1, jend = Z0 + TZ + 1;
-  CoarseFetch<double, CW, CH, NT> cpf;
-  RawCode upre[UPT];
-  double fpre[FPT];
-  auto fetch_u = [&](int jj) {
+  const int fst = 1 << (Lfull - level);
+
+  // halo node of this thread (tile-local hx in -1..64, hy in -1..TY)
+  int hx = 0, hy = 0;
+  if (tid < EXW) {
+    hy = -1;
+    hx = tid - 1;
+  } else if (tid < 2 * EXW) {
+    hy = TY;
+    hx = tid - EXW - 1;
+  } else if (tid < 2 * EXW + TY) {
+    hx = -1;
+    hy = tid - 2 * EXW;
+  } else {
+    hx = kTX;
+    hy = tid - 2 * EXW - TY;
+  }
+  const bool has_h = tid < NHALO;
+  int gxh = X0 + hx, gyh = Y0 + hy;
+  const bool hdom = has_h && gxh >= 0 && gxh < n && gyh >= 0 && gyh < n;
+  uint32_t xyh = hdom ? ((static_cast<uint32_t>(gyh) << level) | static_cast<uint32_t>(gxh)) : 0u;
+  int hpos = has_h ? (hy + 1) * EXW + hx + 1 : 0;
+  int hci = ((gyh >> 1) - CY0) * CW + ((gxh >> 1) - CX0);
+
+  double u[RPT][3];
+  RawCode upre[RPT], hpre;
+  double fpre[RPT];
+  double cpf[CPT];
 #pragma unroll
-    for (int k = 0; k < UPT; ++k) {
+  for (int t = 0; t < RPT; ++t) u[t][0] = u[t][1] = u[t][2] = 0.0;
+  auto xy_own = [&](int t) {
+    return (static_cast<uint32_t>(Y0 + wv + NW * t) << level) | static_cast<uint32_t>(X0 + lane);
+  };
+  auto cfetch = [&](int cz) {
+    const bool zin = cz >= 0 && cz < nc;
+    const double* src = uc + (static_cast<uint64_t>(zin ? cz : 0) << (2 * levelc));
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
       const int t = tid + k * NT;
-      const int ly = t / EXW, lx = t - ly * EXW;
-      const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
-      upre[k] = raw_none();
-      if (t < PLS && jj >= 0 && jj < n && gx >= 0 && gx < n && gy >= 0 && gy < n)
-        upre[k] = raw_load(U, flat(g, gx, gy, jj));
+      const int cy = t / CW, cx = t - cy * CW;
+      const int gx = CX0 + cx, gy = CY0 + cy;
+      cpf[k] = 0.0;
+      if (zin && t < CPL && gx >= 0 && gx < nc && gy >= 0 && gy < nc)
+        cpf[k] = src[(static_cast<uint32_t>(gy) << levelc) | static_cast<uint32_t>(gx)];
     }
   };
-  auto fetch_f = [&](int p) {  // f at the output rows of plane p
+  auto cstore = [&](int cz) {
+    double* dst = cs + (cz & (NC - 1)) * CPL;
 #pragma unroll
-    for (int k = 0; k < FPT; ++k) {
-      const int r = (tid >> 6) + k * (NT / 64);
-      const int gx = X0 + lane, gy = Y0 + r;
-      fpre[k] = 0.0;
-      if (r < TY && p >= 1 && p < n && gx >= 1 && gy >= 1)
-        fpre[k] = f[(static_cast<int64_t>(p) * st * N + static_cast<int64_t>(gy) * st) * N +
-                    static_cast<int64_t>(gx) * st];
+    for (int k = 0; k < CPT; ++k) {
+      const int t = tid + k * NT;
+      if (t < CPL) dst[t] = cpf[k];
     }
   };
-  cpf.fetch(uc, gc, CX0, CY0, jbeg >> 1, tid);
-  cpf.store(cs + ring(jbeg >> 1, NC) * CPL, tid);
-  cpf.fetch(uc, gc, CX0, CY0, (jbeg >> 1) + 1, tid);
-  cpf.store(cs + ring((jbeg >> 1) + 1, NC) * CPL, tid);
-  fetch_u(jbeg);
-  fetch_f(jbeg - 1);
-  for (int j = jbeg; j < jend; ++j) {
-    if (j != jbeg && (j & 1)) cpf.store(cs + ring((j + 1) >> 1, NC) * CPL, tid);
-    __syncthreads();
-    {  // decoded solution on plane j (tile plus a halo of one)
-      double* up = us + ring(j, 3) * PLS;
+  auto fetch_u = [&](int p) {
+    if (p >= 0 && p < n) {
+      const PlanePtr uq = plane_of(U, p);
 #pragma unroll
-      for (int k = 0; k < UPT; ++k) {
-        const int t = tid + k * NT;
-        if (t >= PLS) continue;
-        const int ly = t / EXW, lx = t - ly * EXW;
-        const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
-        double v = 0.0;
-        if (j >= 0 && j < n && gx >= 0 && gx < n && gy >= 0 && gy < n)
-          v = raw_value(U, flat(g, gx, gy, j), upre[k]) + prolong_lds<double, NC, CW, CPL>(cs, CX0, CY0, gx, gy, j);
-        up[t] = v;
+      for (int t = 0; t < RPT; ++t) upre[t] = raw_at<LB>(uq, xy_own(t), U.cbits);
+      hpre = hdom ? raw_at<LB>(uq, xyh, U.cbits) : raw_none();
+    } else {
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) upre[t] = raw_none();
+      hpre = raw_none();
+    }
+  };
+  auto fetch_f = [&](int p) {  // f at the own columns of plane p (0 on the boundary)
+    const bool pin = p >= 1 && p < n;
+    const double* fp = f + static_cast<uint64_t>(pin ? p : 0) * fst * N * N;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int gx = X0 + lane, gy = Y0 + wv + NW * t;
+      fpre[t] = 0.0;
+      if (pin && gx >= 1 && gy >= 1)
+        fpre[t] = fp[static_cast<uint32_t>(gy * fst) * static_cast<uint32_t>(N) + static_cast<uint32_t>(gx * fst)];
+    }
+  };
+
+  auto step = [&](auto jpc, const int j) {
+    constexpr int JP = decltype(jpc)::value;
+    opaque(lane);
+    opaque(xyh);
+    opaque(hpos);
+    opaque(hci);
+    opaque(gxh);
+    opaque(gyh);
+    opaque_s(wv);
+    opaque_s(X0);
+    opaque_s(Y0);
+    opaque_s(U);
+    opaque_s(Gout);
+    if (JP == 0) cfetch((j + 2) >> 1);  // u(j + 1) needs coarse plane (j + 2) / 2
+    {  // u of plane j
+      const bool pin = j >= 0 && j < n;
+      const double* c0 = cs + ((j >> 1) & (NC - 1)) * CPL;
+      const double* c1 = cs + (((j >> 1) + 1) & (NC - 1)) * CPL;
+      double* ub = us + ((j + 3) % 3) * LPL;
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int rr = wv + NW * t;
+        u[t][0] = u[t][1];
+        u[t][1] = u[t][2];
+        const int ci = ((rr >> 1) + 1) * CW + (lane >> 1) + 1;
+        const double v = raw_f64(upre[t], xy_own(t), U.cbits, U.w) +
+                         prolong_node<double, JP, CW>(c0, c1, ci, lane & 1, rr & 1);
+        u[t][2] = pin ? v : 0.0;
+        ub[(rr + 1) * EXW + lane + 1] = u[t][2];
       }
-      if (j + 1 < jend) {
-        fetch_u(j + 1);
-        if ((j + 1) & 1) cpf.fetch(uc, gc, CX0, CY0, (j + 2) >> 1, tid);
+      if (has_h) {
+        const double v = raw_f64(hpre, xyh, U.cbits, U.w) + prolong_node<double, JP, CW>(c0, c1, hci, gxh & 1, gyh & 1);
+        ub[hpos] = (pin && hdom) ? v : 0.0;
       }
     }
+    fetch_u(j + 1);
+    if (JP == 0) cstore((j + 2) >> 1);
     __syncthreads();
     const int p = j - 1;
-    if (p >= Z0 && p < Z0 + TZ) {
-      const double* uc0 = us + ring(p, 3) * PLS;
-      const double* um = us + ring(p - 1, 3) * PLS;
-      const double* upl = us + ring(p + 1, 3) * PLS;
+    if (p >= Z0 && p < Z0 + TZ) {  // residual on plane p
+      const double* ua = us + ((p + 3) % 3) * LPL;
+      const PlanePtr gq = plane_of(Gout, p);
 #pragma unroll
-      for (int k = 0; k < FPT; ++k) {
-        const int r = (tid >> 6) + k * (NT / 64);
-        if (r >= TY) continue;
-        const int gx = X0 + lane, gy = Y0 + r;
-        double t = 0.0;
-        if (p >= 1 && gx >= 1 && gy >= 1) {
-          const int c = (r + 1) * EXW + lane + 1;
-          double a = 6.0 * uc0[c];
-          a = a - uc0[c - 1];
-          a = a - uc0[c + 1];
-          a = a - uc0[c - EXW];
-          a = a - uc0[c + EXW];
-          a = a - um[c];
-          a = a - upl[c];
-          a = a * ih2;
-          t = fpre[k] - a;
-        }
-        if (nonfinite != nullptr && !isfinite(t)) atomicOr(nonfinite, 1);
+      for (int t = 0; t < RPT; ++t) {
+        const int rr = wv + NW * t;
+        const int c = (rr + 1) * EXW + lane + 1;
+        double a = 6.0 * u[t][1];
+        a = a - ua[c - 1];
+        a = a - ua[c + 1];
+        a = a - ua[c - EXW];
+        a = a - ua[c + EXW];
+        a = a - u[t][0];
+        a = a - u[t][2];
+        a = a * ih2;
+        const bool inside = p >= 1 && X0 + lane >= 1 && Y0 + rr >= 1;
+        const double tv = inside ? fpre[t] - a : 0.0;
+        if (nonfinite != nullptr && !isfinite(tv)) atomicOr(nonfinite, 1);
         if (sumsq != nullptr) {
-          double a2 = t * t;
+          double a2 = tv * tv;
           for (int off = 32; off > 0; off >>= 1) a2 += __shfl_xor(a2, off, 64);
           if (lane == 0) atomicAdd(sumsq, a2);
         }
-        const int64_t base = flat(g, X0, gy, p);
+        const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
         int e;
-        const int64_t m = quantise_lane(t, Gout.B, Gout.w, &e);
-        store_codes_wave(Gout, base, lane, m, Gout.n);
-        if ((lane & (Gout.B - 1)) == 0) Gout.exps[blk(Gout, base + lane)] = static_cast<int16_t>(e);
+        const int64_t m = quant_f64<LB>(tv, Gout.w, lane, &e);
+        store_row(gq.c, xyr, lane, m, Gout.cbits);
+        if ((lane & ((1 << LB) - 1)) == 0) gq.e[(xyr + lane) >> LB] = static_cast<int16_t>(e);
       }
     }
     fetch_f(j);
+  };
+
+  const int jbeg = Z0 - 1, jend = Z0 + TZ + 1;  // an even number of steps, jbeg odd
+  cfetch(jbeg >> 1);
+  cstore(jbeg >> 1);
+  cfetch((jbeg >> 1) + 1);
+  cstore((jbeg >> 1) + 1);
+  fetch_u(jbeg);
+  __syncthreads();
+#pragma unroll 1
+  for (int j = jbeg; j < jend; j += 2) {
+    step(std::integral_constant<int, 1>(), j);
+    step(std::integral_constant<int, 0>(), j + 1);
   }
 }
 
 // ============================================================ final decode
-// u (full node grid of level g) = dec u'_l + P u_{l-1}; far boundary 0.
-__global__ void __launch_bounds__(256) k_decode_full(SecRef U, const double* __restrict__ uc, Geom g, Geom gc,
+// u (full node grid of level g) = dec u'_l + P u_{l-1}; far boundary 0.  One
+// thread per node; block (64, 4) over x and y, grid z over the planes.
+template <int LB>
+__global__ void __launch_bounds__(256) k_decode_full(PSec U, const double* __restrict__ uc, int level, int levelc,
                                                      double* __restrict__ full) {
-  const int64_t N = g.n + 1;
-  const int64_t total = N * N * N;
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (idx >= total) return;
-  const int i = static_cast<int>(idx % N);
-  const int j = static_cast<int>((idx / N) % N);
-  const int k = static_cast<int>(idx / (N * N));
+  const int n = 1 << level, nc = 1 << levelc, N = n + 1;
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  if (i >= N || j >= N) return;
   double v = 0.0;
-  if (i < g.n && j < g.n && k < g.n) {
+  if (i < n && j < n && k < n) {
     const int ti = i >> 1, tj = j >> 1, tk = k >> 1;
     const int pi = i & 1, pj = j & 1, pk = k & 1;
+    const double w = (pk ? 0.5 : 1.0) * (pj ? 0.5 : 1.0) * (pi ? 0.5 : 1.0);
     double s = 0.0;
     bool first = true;
     for (int oz = 0; oz <= pk; ++oz)
       for (int oy = 0; oy <= pj; ++oy)
         for (int ox = 0; ox <= pi; ++ox) {
-          const double w = (pk ? 0.5 : 1.0) * (pj ? 0.5 : 1.0) * (pi ? 0.5 : 1.0);
-          const double t = w * at(uc, gc, ti + ox, tj + oy, tk + oz);
+          const int a = ti + ox, b = tj + oy, c = tk + oz;
+          const double cv = (a < nc && b < nc && c < nc)
+                                ? uc[(static_cast<uint64_t>(c) << (2 * levelc)) |
+                                     (static_cast<uint64_t>(b) << levelc) | static_cast<uint64_t>(a)]
+                                : 0.0;
+          const double t = w * cv;
           s = first ? t : s + t;
           first = false;
         }
-    v = decode_value(U, flat(g, i, j, k)) + s;
+    const uint32_t xy = (static_cast<uint32_t>(j) << level) | static_cast<uint32_t>(i);
+    v = raw_f64(raw_at<LB>(plane_of(U, k), xy, U.cbits), xy, U.cbits, U.w) + s;
   }
-  full[idx] = v;
+  full[(static_cast<uint64_t>(k) * N + j) * N + i] = v;
 }
 
 // =============================================================== launchers
@@ -919,7 +1003,7 @@ static double sec_b(const SecRef& s) {
     if (g_timing != nullptr) g_timing->end(stream);                                       \
   } while (0)
 
-constexpr int kDownTY = 16, kUpTY = 16, kResTY = 16, kRRCTY = 4, kDownNT = 448, kUpNT = 896;
+constexpr int kDownTY = 16, kUpTY = 16, kResTY = 32, kRRCTY = 4, kDownNT = 448, kUpNT = 896, kResNT = 512;
 
 static PSec psec(const SecRef& s, const Geom& g) {
   const uint64_t pv = static_cast<uint64_t>(1) << (2 * g.level);  // values per plane
@@ -992,22 +1076,30 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
 
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
                        double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st) {
-  if (g.dim != 3 || g.n < kTX) return false;
-  const int ty = kResTY;
-  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / ty), 16);
-  const dim3 grid(g.n / kTX, g.n / ty, g.n / tz);
+  if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64) || Gout.B != U.B) return false;
+  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kResTY), 16);
+  const dim3 grid(g.n / kTX, g.n / kResTY, g.n / tz), block(kResNT);
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size + sec_b(Gout);
-  CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, 256>), grid, dim3(256), st, U, uc, f, Lfull, g, gc, ih2,
-              Gout, tz, nonfinite, sumsq);
+  const PSec pu = psec(U, g), pg = psec(Gout, g);
+  if (U.B == 64)
+    CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, 6>), grid, block, st, pu, uc, f, Lfull, g.level,
+                gc.level, ih2, pg, tz, nonfinite, sumsq);
+  else
+    CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, 5>), grid, block, st, pu, uc, f, Lfull, g.level,
+                gc.level, ih2, pg, tz, nonfinite, sumsq);
   return true;
 }
 
 void launch_decode_full(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* full,
                         hipStream_t st) {
   const int64_t N = g.n + 1;
-  const int64_t total = N * N * N;
-  CMG_FLAUNCH("k_decode_full", sec_b(U) + 8.0 * gc.size + 8.0 * total, k_decode_full,
-              dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), st, U, uc, g, gc, full);
+  const dim3 grid(static_cast<unsigned>((N + 63) / 64), static_cast<unsigned>((N + 3) / 4), static_cast<unsigned>(N));
+  const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * N * N * N;
+  const PSec pu = psec(U, g);
+  if (U.B == 64)
+    CMG_FLAUNCH("k_decode_full", bytes, k_decode_full<6>, grid, dim3(64, 4), st, pu, uc, g.level, gc.level, full);
+  else
+    CMG_FLAUNCH("k_decode_full", bytes, k_decode_full<5>, grid, dim3(64, 4), st, pu, uc, g.level, gc.level, full);
 }
 
 }  // namespace cmg
