@@ -631,128 +631,193 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
 }
 
 // ======================================================== residual-restrict
-// g_{l-1} = Q(R(g_l - A y'_l)) on a coarse tile of 64 x CTY nodes; the fine
-// level is marched plane by plane.
-template <int CTY, int NT>
-__global__ void __launch_bounds__(NT) k_resid_restrict(SecRef G, SecRef Y, SecRef Gc, Geom g, Geom gc, float ih2,
-                                                       int TZc) {
-  constexpr int YW = 2 * kTX + 4, YH = 2 * CTY + 3;  // y' tile: fine x in [2CX0-2, 2CX0+130)
-  constexpr int TW = 2 * kTX + 2, TH = 2 * CTY + 1;  // t tile: fine x in [2CX0-1, 2CX0+129)
-  constexpr int YPT = (YW * YH + NT - 1) / NT, GPT = (TW * TH + NT - 1) / NT;
-  __shared__ float yv[3 * YW * YH];
-  __shared__ float gv[2 * TW * TH];
-  __shared__ float tv[3 * TW * TH];
+// g_{l-1} = Q(R(g_l - A y'_l)) on a coarse tile of 64 x CTY nodes, marching
+// along the fine planes.  Three stages with a lag of one plane each, one
+// barrier per step:
+//   A: the threads decode y' of fine plane s for their own columns of the
+//      fine tile (plus a halo of two) and publish it (ring of three planes);
+//   B: t = g - A y' on plane s - 1 for the own columns inside the t region
+//      (z-neighbours from the column's registers), published (two planes);
+//   C: each coarse node adds the nine weighted t values of plane s - 2 to
+//      its running full-weighting sum (the 27 terms in C order: z, y, x);
+//      on an odd fine plane 2K + 1 the sum of coarse plane K is complete and
+//      the sum of plane K + 1 starts with the same nine products.
+// The t planes are stored split by x parity so that the stride-two reads of
+// the coarse nodes are consecutive.
+template <int CTY, int NT, int LB>
+__global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, int level, float ih2, int TZc) {
+  constexpr int YW = 2 * kTX + 4, YH = 2 * CTY + 3;  // y' region, origin (2 CX0 - 2, 2 CY0 - 2)
+  constexpr int NCOL = YW * YH, YPS = NCOL + 1, K = (NCOL + NT - 1) / NT;
+  constexpr int TW = 2 * kTX + 2, TH = 2 * CTY + 1, TPL = TW * TH;  // t region, origin (2 CX0 - 1, 2 CY0 - 1)
+  constexpr int TPS = TPL + 1, YPAD = YW + 1;  // a spare word per plane; margins for the edge columns' reads
+  constexpr int NW = NT / 64, CRW = CTY / NW;
+  static_assert(CTY % NW == 0, "whole coarse rows per wave");
+  __shared__ float yl[2 * YPAD + 3 * YPS];
+  __shared__ float tl[2 * TPS];
   const int tid = threadIdx.x;
-  const int CX0 = blockIdx.x * kTX, CY0 = blockIdx.y * CTY, CZ0 = blockIdx.z * TZc;
-  const int n = g.n;
-  const int FX0 = 2 * CX0 - 2, FY0 = 2 * CY0 - 2;  // origin of the y' tile
-  RawCode ypre[YPT], gpre[GPT];
-  auto fetch = [&](int q) {
+  int lane = tid & 63;
+  int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int CX0 = blockIdx.x * kTX, CY0 = blockIdx.y * CTY;
+  const int CZ0 = blockIdx.z * TZc;
+  const int n = 1 << level, levelc = level - 1;
+
+  int pos[K], tpos[K];
+  uint32_t xy[K];
+  unsigned fl[K];  // bit 0: node in the level; bit 1: t column; bit 2: interior node
 #pragma unroll
-    for (int k = 0; k < YPT; ++k) {
-      const int t = tid + k * NT;
-      const int ly = t / YW, lx = t - ly * YW;
-      const int gx = FX0 + lx, gy = FY0 + ly;
-      ypre[k] = raw_none();
-      if (t < YW * YH && q >= 0 && q < n && gx >= 0 && gx < n && gy >= 0 && gy < n)
-        ypre[k] = raw_load(Y, flat(g, gx, gy, q));
-    }
+  for (int k = 0; k < K; ++k) {
+    const int q = tid + k * NT;
+    const bool valid = q < NCOL;
+    const int ly = valid ? q / YW : 0, lx = valid ? q - ly * YW : 0;
+    const int gx = 2 * CX0 - 2 + lx, gy = 2 * CY0 - 2 + ly;
+    const bool dom = valid && gx >= 0 && gx < n && gy >= 0 && gy < n;
+    const bool inner = valid && gx >= 1 && gx < n && gy >= 1 && gy < n;
+    const bool tcol = valid && lx >= 1 && lx <= TW && ly >= 1 && ly <= TH;
+    pos[k] = valid ? q : NCOL;
+    const int tx = lx - 1, ty = ly - 1;
+    tpos[k] = tcol ? ty * TW + (tx & 1) * (TW / 2) + (tx >> 1) : TPL;
+    xy[k] = dom ? ((static_cast<uint32_t>(gy) << level) | static_cast<uint32_t>(gx)) : 0u;
+    fl[k] = (dom ? 1u : 0u) | (tcol ? 2u : 0u) | (inner ? 4u : 0u);
+  }
+  const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+  auto wave_has = [&](int k) { return k * NT + wbase < NCOL; };
+
+  float yr[K][3];  // y' of planes s-2 .. s
+  RawCode ypre[K], gpre[K];
+  float sc[CRW];   // running coarse sums
 #pragma unroll
-    for (int k = 0; k < GPT; ++k) {
-      const int t = tid + k * NT;
-      const int ly = t / TW, lx = t - ly * TW;
-      const int gx = FX0 + 1 + lx, gy = FY0 + 1 + ly;
-      gpre[k] = raw_none();
-      if (t < TW * TH && q >= 0 && q < n && gx >= 0 && gx < n && gy >= 0 && gy < n)
-        gpre[k] = raw_load(G, flat(g, gx, gy, q));
+  for (int k = 0; k < K; ++k) yr[k][0] = yr[k][1] = yr[k][2] = 0.0f;
+#pragma unroll
+  for (int r = 0; r < CRW; ++r) sc[r] = 0.0f;
+  auto fetch_y = [&](int p) {
+    if (p >= 0 && p < n) {
+      const PlanePtr yq = plane_of(Y, p);
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (wave_has(k)) ypre[k] = raw_at<LB>(yq, xy[k], Y.cbits);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) ypre[k] = raw_none();
     }
   };
-  const int qend = 2 * (CZ0 + TZc);
-  fetch(2 * CZ0 - 2);
-  for (int q = 2 * CZ0 - 2; q <= qend; ++q) {
-    {  // y'(q) and g(q) from the prefetch
-      float* yp = yv + ring(q, 3) * YW * YH;
+  auto fetch_g = [&](int p) {
+    if (p >= 1 && p < n) {
+      const PlanePtr gq = plane_of(G, p);
 #pragma unroll
-      for (int k = 0; k < YPT; ++k) {
-        const int t = tid + k * NT;
-        if (t >= YW * YH) continue;
-        const int ly = t / YW, lx = t - ly * YW;
-        const int gx = FX0 + lx, gy = FY0 + ly;
-        const int64_t idx = (gx >= 0 && gy >= 0 && q >= 0) ? flat(g, gx, gy, q) : 0;
-        yp[t] = static_cast<float>(raw_value(Y, idx, ypre[k]));
-      }
-      float* gp = gv + ring(q, 2) * TW * TH;
+      for (int k = 0; k < K; ++k)
+        if (wave_has(k)) gpre[k] = raw_at<LB>(gq, xy[k], G.cbits);
+    } else {
 #pragma unroll
-      for (int k = 0; k < GPT; ++k) {
-        const int t = tid + k * NT;
-        if (t >= TW * TH) continue;
-        const int ly = t / TW, lx = t - ly * TW;
-        const int gx = FX0 + 1 + lx, gy = FY0 + 1 + ly;
-        const int64_t idx = (gx >= 0 && gy >= 0 && q >= 0) ? flat(g, gx, gy, q) : 0;
-        gp[t] = static_cast<float>(raw_value(G, idx, gpre[k]));
+      for (int k = 0; k < K; ++k) gpre[k] = raw_none();
+    }
+  };
+
+  auto step = [&](auto spc, const int s) {
+    constexpr int SP = decltype(spc)::value;  // parity of s and of the plane s - 2 of stage C
+    opaque(lane);
+    opaque_s(wv);
+    opaque_s(CX0);
+    opaque_s(CY0);
+    opaque_s(G);
+    opaque_s(Y);
+    opaque_s(Gc);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      opaque(pos[k]);
+      opaque(tpos[k]);
+      opaque(xy[k]);
+      opaque(fl[k]);
+    }
+    {  // A: y' of plane s
+      const bool pin = s >= 0 && s < n;
+      float* yb = yl + YPAD + ((s + 3) % 3) * YPS;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (!wave_has(k)) continue;
+        yr[k][0] = yr[k][1];
+        yr[k][1] = yr[k][2];
+        const float v = raw_f32(ypre[k], xy[k], Y.cbits, Y.w);
+        yr[k][2] = (pin && (fl[k] & 1u)) ? v : 0.0f;
+        yb[pos[k]] = yr[k][2];
       }
     }
-    if (q + 1 <= qend) fetch(q + 1);
-    __syncthreads();
-    const int p = q - 1;  // t on plane p
-    if (p >= 2 * CZ0 - 1) {
-      const float* yc = yv + ring(p, 3) * YW * YH;
-      const float* ym = yv + ring(p - 1, 3) * YW * YH;
-      const float* ypl = yv + ring(p + 1, 3) * YW * YH;
-      const float* gp = gv + ring(p, 2) * TW * TH;
-      float* tp = tv + ring(p, 3) * TW * TH;
-      for (int t = tid; t < TW * TH; t += NT) {
-        const int ly = t / TW, lx = t - ly * TW;
-        const int gx = FX0 + 1 + lx, gy = FY0 + 1 + ly;
-        float v = 0.0f;
-        if (p >= 1 && p < n && gx >= 1 && gx < n && gy >= 1 && gy < n) {
-          const int c = (ly + 1) * YW + (lx + 1);
-          float a = 6.0f * yc[c];
-          a = a - yc[c - 1];
-          a = a - yc[c + 1];
-          a = a - yc[c - YW];
-          a = a - yc[c + YW];
-          a = a - ym[c];
-          a = a - ypl[c];
-          a = a * ih2;
-          v = gp[t] - a;
+    {  // B: t on plane s - 1
+      const int p = s - 1;
+      const bool pin = p >= 1 && p < n;
+      const float* ya = yl + YPAD + ((p + 3) % 3) * YPS;
+      float* tb = tl + ((p + 2) & 1) * TPS;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (!wave_has(k)) continue;
+        const int c = pos[k];
+        float a = 6.0f * yr[k][1];
+        a = a - ya[c - 1];
+        a = a - ya[c + 1];
+        a = a - ya[c - YW];
+        a = a - ya[c + YW];
+        a = a - yr[k][0];
+        a = a - yr[k][2];
+        a = a * ih2;
+        const float v = raw_f32(gpre[k], xy[k], G.cbits, G.w) - a;
+        tb[tpos[k]] = (pin && (fl[k] & 4u)) ? v : 0.0f;
+      }
+    }
+    fetch_y(s + 1);
+    fetch_g(s);
+    {  // C: plane q = s - 2 into the coarse sums
+      const int q = s - 2;
+      const float* ta = tl + ((q + 2) & 1) * TPS;
+      const float wz = SP ? 0.25f : 0.5f;
+#pragma unroll
+      for (int r = 0; r < CRW; ++r) {
+        const int jr = wv + NW * r;  // coarse row within the tile
+        float prod[9];
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy) {
+          const float* trow = ta + (2 * jr + oy + 1) * TW;
+          const float wy = oy == 0 ? 0.5f : 0.25f;
+          const float t0 = trow[lane];                // x = 2I - 1
+          const float t1 = trow[TW / 2 + lane];       // x = 2I
+          const float t2 = trow[lane + 1];            // x = 2I + 1
+          prod[3 * (oy + 1) + 0] = (wz * wy * 0.25f) * t0;
+          prod[3 * (oy + 1) + 1] = (wz * wy * 0.5f) * t1;
+          prod[3 * (oy + 1) + 2] = (wz * wy * 0.25f) * t2;
         }
-        tp[t] = v;
-      }
-    }
-    __syncthreads();
-    if ((q & 1) == 0) {  // coarse plane K = q/2 - 1 has t on 2K-1 .. 2K+1
-      const int K = q / 2 - 1;
-      if (K >= CZ0 && K < CZ0 + TZc) {
-        const int lane = tid & 63;
-        for (int r = tid >> 6; r < CTY; r += NT / 64) {
-          const int I = CX0 + lane, J = CY0 + r;
-          float s = 0.0f;
-          if (I >= 1 && J >= 1 && K >= 1) {
-            bool first = true;
-            for (int oz = -1; oz <= 1; ++oz) {
-              const double wz = oz == 0 ? 0.5 : 0.25;
-              const float* tp = tv + ring(2 * K + oz, 3) * TW * TH;
-              for (int oy = -1; oy <= 1; ++oy) {
-                const double wy = oy == 0 ? 0.5 : 0.25;
-                for (int ox = -1; ox <= 1; ++ox) {
-                  const double wx = ox == 0 ? 0.5 : 0.25;
-                  const int lx = 2 * I + ox - (FX0 + 1), ly = 2 * J + oy - (FY0 + 1);
-                  const float t = static_cast<float>(wz * wy * wx) * tp[ly * TW + lx];
-                  s = first ? t : s + t;
-                  first = false;
-                }
-              }
-            }
+        if (SP == 0) {  // oz = 0 of coarse plane q / 2
+#pragma unroll
+          for (int i = 0; i < 9; ++i) sc[r] = sc[r] + prod[i];
+        } else {  // oz = +1 of plane (q - 1) / 2, then oz = -1 of plane (q + 1) / 2
+          float done = sc[r];
+#pragma unroll
+          for (int i = 0; i < 9; ++i) done = done + prod[i];
+          float next = prod[0];
+#pragma unroll
+          for (int i = 1; i < 9; ++i) next = next + prod[i];
+          sc[r] = next;
+          const int Kc = (q - 1) >> 1;
+          if (Kc >= CZ0 && Kc < CZ0 + TZc) {
+            const int J = CY0 + jr, I = CX0 + lane;
+            const float v = (I >= 1 && J >= 1 && Kc >= 1) ? done : 0.0f;
+            const PlanePtr cq = plane_of(Gc, Kc);
+            const uint32_t xyr = (static_cast<uint32_t>(J) << levelc) | static_cast<uint32_t>(CX0);
+            int e;
+            const int m = quant_f32<LB>(v, Gc.w, lane, &e);
+            store_row(cq.c, xyr, lane, m, Gc.cbits);
+            if ((lane & ((1 << LB) - 1)) == 0) cq.e[(xyr + lane) >> LB] = static_cast<int16_t>(e);
           }
-          const int64_t base = flat(gc, CX0, J, K);
-          int e;
-          const int32_t m = quantise_lane_f32(s, Gc.B, Gc.w, lane, &e);
-          store_codes_wave(Gc, base, lane, m, Gc.n);
-          if ((lane & (Gc.B - 1)) == 0) Gc.exps[blk(Gc, base + lane)] = static_cast<int16_t>(e);
         }
       }
     }
+    __syncthreads();
+  };
+
+  const int sbeg = 2 * CZ0 - 2, send = 2 * (CZ0 + TZc) + 2;  // an even number of steps, sbeg even
+  fetch_y(sbeg);
+  fetch_g(sbeg - 1);
+#pragma unroll 1
+  for (int s0 = sbeg; s0 < send; s0 += 2) {
+    step(std::integral_constant<int, 0>(), s0);
+    step(std::integral_constant<int, 1>(), s0 + 1);
   }
 }
 
@@ -1003,7 +1068,8 @@ static double sec_b(const SecRef& s) {
     if (g_timing != nullptr) g_timing->end(stream);                                       \
   } while (0)
 
-constexpr int kDownTY = 16, kUpTY = 16, kResTY = 32, kRRCTY = 4, kDownNT = 448, kUpNT = 896, kResNT = 512;
+constexpr int kDownTY = 16, kUpTY = 16, kResTY = 32, kRRCTY = 8, kDownNT = 448, kUpNT = 896, kResNT = 512,
+              kRRNT = 512;
 
 static PSec psec(const SecRef& s, const Geom& g) {
   const uint64_t pv = static_cast<uint64_t>(1) << (2 * g.level);  // values per plane
@@ -1065,12 +1131,17 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
 
 bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, const Geom& g, const Geom& gc,
                           float ih2, hipStream_t st) {
-  if (g.dim != 3 || gc.n < kTX) return false;
+  if (g.dim != 3 || gc.n < kTX || (G.B != 32 && G.B != 64) || Y.B != G.B || Gc.B != G.B) return false;
   const int tz = pick_tz(gc.n, (gc.n / kTX) * (gc.n / kRRCTY), 8);
-  const dim3 grid(gc.n / kTX, gc.n / kRRCTY, gc.n / tz);
+  const dim3 grid(gc.n / kTX, gc.n / kRRCTY, gc.n / tz), block(kRRNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Gc);
-  CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, 256>), grid, dim3(256), st, G, Y, Gc, g, gc, ih2,
-              tz);
+  const PSec pg = psec(G, g), py = psec(Y, g), pc = psec(Gc, gc);
+  if (G.B == 64)
+    CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, kRRNT, 6>), grid, block, st, pg, py, pc, g.level,
+                ih2, tz);
+  else
+    CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, kRRNT, 5>), grid, block, st, pg, py, pc, g.level,
+                ih2, tz);
   return true;
 }
 
