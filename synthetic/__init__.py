@@ -221,6 +221,73 @@ def smoothed_noise_rhs(dim: int, L: int, seed: int, passes: int = 4) -> np.ndarr
     return f
 
 
+def _smooth_torch(w, dim: int, passes: int):
+    """The filter and rescaling of :func:`smoothed_noise_rhs` on a torch
+    tensor ``w`` of interior white noise (same operation order per node)."""
+    import torch
+    N = w.shape[0] + 2
+    f = torch.zeros((N,) * dim, dtype=torch.float64, device=w.device)
+    inner = (slice(1, -1),) * dim
+    f[inner] = w
+    for _ in range(passes):
+        for ax in range(dim):
+            g = torch.zeros_like(f)
+            lo = [slice(1, -1)] * dim
+            mid = [slice(1, -1)] * dim
+            hi = [slice(1, -1)] * dim
+            lo[ax] = slice(0, -2)
+            hi[ax] = slice(2, None)
+            g[inner] = 0.25 * f[tuple(lo)] + 0.5 * f[tuple(mid)] + 0.25 * f[tuple(hi)]
+            f = g
+    f[inner] /= f[inner].std(unbiased=False)
+    return f
+
+
+def smoothed_noise_rhs_torch(dim: int, L: int, seed: int, passes: int = 4, device="cpu"):
+    """:func:`smoothed_noise_rhs` built on a torch device for large grids.
+
+    The white noise comes from ``torch.Generator(device).manual_seed(seed)``
+    (so the draws, unlike the filter, depend on the device type).
+    """
+    import torch
+    N = (1 << L) + 1
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    w = torch.randn(((N - 2),) * dim, generator=gen, dtype=torch.float64, device=device)
+    return _smooth_torch(w, dim, passes)
+
+
+def _grf_filter_torch(w, corr_len: float):
+    """The spectral filter and standardisation of
+    :func:`gaussian_random_field` applied to white noise ``w``."""
+    import torch
+    dim, ncell = w.dim(), w.shape[0]
+    wh = torch.fft.rfftn(w)
+    k_full = 2.0 * np.pi * torch.fft.fftfreq(ncell, d=1.0 / ncell, dtype=torch.float64, device=w.device)
+    k_half = 2.0 * np.pi * torch.fft.rfftfreq(ncell, d=1.0 / ncell, dtype=torch.float64, device=w.device)
+    axes = [k_full] * (dim - 1) + [k_half]
+    k2 = torch.zeros(wh.shape, dtype=torch.float64, device=w.device)
+    for ax, k in enumerate(axes):
+        shape = [1] * dim
+        shape[ax] = k.numel()
+        k2 = k2 + k.reshape(shape) ** 2
+    wh = wh * torch.exp(-0.25 * k2 * corr_len ** 2)
+    g = torch.fft.irfftn(wh, s=(ncell,) * dim)
+    g = g - g.mean()
+    return g / g.std(unbiased=False)
+
+
+def lognormal_kappa_torch(dim: int, L: int, corr_len: float, seed: int, device="cpu"):
+    """:func:`lognormal_kappa` built on a torch device for large grids (white
+    noise from ``torch.Generator(device).manual_seed(seed)``)."""
+    import torch
+    ncell = 1 << L
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    w = torch.randn((ncell,) * dim, generator=gen, dtype=torch.float64, device=device)
+    return torch.exp(_grf_filter_torch(w, corr_len))
+
+
 # The five workloads (problem shape, inputs and solver settings).
 WORKLOADS = {
     "poisson2d_129": dict(dim=2, L=7, op="poisson", smoother="wjacobi", omega=0.8,

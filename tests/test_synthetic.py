@@ -43,3 +43,27 @@ def test_smoothed_rhs_unit_std():
     f = S.smoothed_noise_rhs(3, 4, 100)
     assert np.isclose(f[1:-1, 1:-1, 1:-1].std(), 1.0)
     assert not np.any(f[0])
+
+
+def test_torch_smoothing_matches_numpy_on_the_same_noise():
+    import torch
+    dim, L, seed = 3, 4, 21
+    N = (1 << L) + 1
+    w = np.random.default_rng(seed).standard_normal(((N - 2),) * dim)
+    ref = S.smoothed_noise_rhs(dim, L, seed)
+    got = S._smooth_torch(torch.from_numpy(w), dim, 4).numpy()
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-14)
+    f = S.smoothed_noise_rhs_torch(dim, L, seed)
+    assert f.shape == (N,) * dim and float(f[0].abs().max()) == 0.0
+    assert abs(float(f[1:-1, 1:-1, 1:-1].std(unbiased=False)) - 1.0) < 1e-12
+
+
+def test_torch_random_field_matches_numpy_on_the_same_noise():
+    import torch
+    dim, ncell, corr, seed = 3, 16, 0.2, 5
+    w = np.random.default_rng(seed).standard_normal((ncell,) * dim)
+    ref = S.gaussian_random_field(dim, ncell, corr, seed)
+    got = S._grf_filter_torch(torch.from_numpy(w), corr).numpy()
+    assert np.allclose(got, ref, rtol=1e-10, atol=1e-12)
+    k = S.lognormal_kappa_torch(dim, 4, corr, seed)
+    assert k.shape == (16, 16, 16) and float(k.min()) > 0.0
