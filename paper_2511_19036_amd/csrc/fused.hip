@@ -25,6 +25,27 @@ namespace cmg {
 
 constexpr int kTX = 64;
 
+// Tile coordinates of this workgroup (1-D launch over NX * NY * NZ tiles).
+// Workgroups are handed to the eight XCDs, each with its own L2, in
+// round-robin order of their ids.  The tiles are renumbered so that every
+// XCD owns a band of NY / 8 tile rows and walks it x fastest: the x- and
+// y-neighbours of a tile, whose halos overlap it, then run on the same L2
+// at about the same time, and the halo rows and the partial cache lines at
+// the tile's x-edges are fetched from HBM once instead of once per tile.
+__device__ __forceinline__ void tile_of(int NX, int NY, int& bx, int& by, int& bz) {
+  const int id = blockIdx.x;
+  if (NY % 8 != 0) {
+    bx = id % NX;
+    by = (id / NX) % NY;
+    bz = id / (NX * NY);
+    return;
+  }
+  const int x8 = id & 7, sl = id >> 3, band = NY >> 3;
+  bx = sl % NX;
+  by = x8 * band + (sl / NX) % band;
+  bz = sl / (NX * band);
+}
+
 __device__ __forceinline__ int ring(int j, int n) { return (j % n + n) % n; }
 
 // d-linear interpolation at fine node (gx, gy, gz) from a coarse ring in LDS
@@ -178,7 +199,9 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
   __shared__ float lds[2 * PAD + NB * PS];
   __shared__ float outb[2][TY * kTX];
   const int tid = threadIdx.x;
-  const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY, Z0 = blockIdx.z * TZ;
+  int bx, by, bz;
+  tile_of((1 << level) / kTX, (1 << level) / TY, bx, by, bz);
+  const int X0 = bx * kTX, Y0 = by * TY, Z0 = bz * TZ;
   const int n = 1 << level;
 
   int pos[K], oidx[K];
@@ -374,8 +397,10 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   const int tid = threadIdx.x;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   int lane = tid & 63;
-  int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY;
-  const int Z0 = blockIdx.z * TZ;
+  int bx, by, bz;
+  tile_of((1 << level) / kTX, (1 << level) / TY, bx, by, bz);
+  int X0 = bx * kTX, Y0 = by * TY;
+  const int Z0 = bz * TZ;
   const int n = 1 << level, nc = 1 << levelc;
   const int CX0 = (X0 - H) >> 1, CY0 = (Y0 - H) >> 1;
 
@@ -657,8 +682,10 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
   const int tid = threadIdx.x;
   int lane = tid & 63;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  int CX0 = blockIdx.x * kTX, CY0 = blockIdx.y * CTY;
-  const int CZ0 = blockIdx.z * TZc;
+  int bx, by, bz;
+  tile_of((1 << (level - 1)) / kTX, (1 << (level - 1)) / CTY, bx, by, bz);
+  int CX0 = bx * kTX, CY0 = by * CTY;
+  const int CZ0 = bz * TZc;
   const int n = 1 << level, levelc = level - 1;
 
   int pos[K], tpos[K];
@@ -846,8 +873,10 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
   const int tid = threadIdx.x;
   int lane = tid & 63;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * TY;
-  const int Z0 = blockIdx.z * TZ;
+  int bx, by, bz;
+  tile_of((1 << level) / kTX, (1 << level) / TY, bx, by, bz);
+  int X0 = bx * kTX, Y0 = by * TY;
+  const int Z0 = bz * TZ;
   const int n = 1 << level, nc = 1 << levelc;
   const int CX0 = (X0 >> 1) - 1, CY0 = (Y0 >> 1) - 1;
   const int64_t N = (static_cast<int64_t>(1) << Lfull) + 1;
@@ -1087,7 +1116,7 @@ bool fused_down_smooth(const SecRef& G, const SecRef& Y, const Geom& g, int nu, 
                        hipStream_t st) {
   if (g.dim != 3 || g.n < kTX || (nu != 1 && nu != 2) || (G.B != 32 && G.B != 64) || Y.B != G.B) return false;
   const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDownTY), 16);
-  const dim3 grid(g.n / kTX, g.n / kDownTY, g.n / tz), block(kDownNT);
+  const dim3 grid((g.n / kTX) * (g.n / kDownTY) * (g.n / tz)), block(kDownNT);
   const double bytes = sec_b(G) + sec_b(Y);
   const PSec pg = psec(G, g), py = psec(Y, g);
   if (nu == 2 && G.B == 64)
@@ -1111,7 +1140,7 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
       U.B != G.B)
     return false;
   const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kUpTY), 16);
-  const dim3 grid(g.n / kTX, g.n / kUpTY, g.n / tz), block(kUpNT);
+  const dim3 grid((g.n / kTX) * (g.n / kUpTY) * (g.n / tz)), block(kUpNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Yp) + 2.0 * sec_b(U) + 4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
   const PSec pg = psec(G, g), py = psec(Y, g), pp = psec(Yp, g), pu = psec(U, g);
   if (nu == 2 && G.B == 64)
@@ -1133,7 +1162,7 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
                           float ih2, hipStream_t st) {
   if (g.dim != 3 || gc.n < kTX || (G.B != 32 && G.B != 64) || Y.B != G.B || Gc.B != G.B) return false;
   const int tz = pick_tz(gc.n, (gc.n / kTX) * (gc.n / kRRCTY), 8);
-  const dim3 grid(gc.n / kTX, gc.n / kRRCTY, gc.n / tz), block(kRRNT);
+  const dim3 grid((gc.n / kTX) * (gc.n / kRRCTY) * (gc.n / tz)), block(kRRNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Gc);
   const PSec pg = psec(G, g), py = psec(Y, g), pc = psec(Gc, gc);
   if (G.B == 64)
@@ -1149,7 +1178,7 @@ bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int L
                        double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st) {
   if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64) || Gout.B != U.B) return false;
   const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kResTY), 16);
-  const dim3 grid(g.n / kTX, g.n / kResTY, g.n / tz), block(kResNT);
+  const dim3 grid((g.n / kTX) * (g.n / kResTY) * (g.n / tz)), block(kResNT);
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size + sec_b(Gout);
   const PSec pu = psec(U, g), pg = psec(Gout, g);
   if (U.B == 64)

@@ -116,7 +116,7 @@ struct cmg_ctx_s {
   // Levels handled by the fused 3-D kernels (rows of at least 64 nodes).
   bool fused3d() const {
     return compact() && p.dim == 3 && p.op == CMG_POISSON && o.smoother == CMG_RBGS &&
-           o.vcycle_prec == CMG_FP32 && o.nu_pre >= 1 && o.nu_pre <= 2 && o.nu_post >= 1 && o.nu_post <= 2;
+           o.vcycle_prec == CMG_FP32 && o.nu_pre >= 0 && o.nu_pre <= 2 && o.nu_post >= 1 && o.nu_post <= 2;
   }
   bool smooth_fused(int l) const { return fused3d() && l >= 6; }
   bool rr_fused(int l) const { return fused3d() && l >= 7; }
@@ -303,7 +303,10 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     F.Y.w = c->wy(l, Lp);
     C.G.w = c->wr(l - 1, Lp);
     const bool fs = f32 && c->smooth_fused(l);
-    if (fs) {
+    if (fs && c->o.nu_pre == 0) {  // V(0, nu2): y' = Q(0)
+      launch_zero_section(F.Y.ref(), st);
+      KCK();
+    } else if (fs) {
       const float cp = static_cast<float>(1.0 / (2.0 * c->p.dim * ih2));
       if (!fused_down_smooth(F.G.ref(), F.Y.ref(), F.g, c->o.nu_pre, cp, static_cast<float>(ih2), st))
         fail(CMG_ERR_HIP, "fused down-smoothing rejected a level it was selected for");

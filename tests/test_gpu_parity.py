@@ -76,19 +76,27 @@ CFGS = {
     "3d-rbgs-b12": dict(dim=3, L=5, smoother="rbgs", omega=1.0, block=64, bits=12),
     "2d-wjacobi-b16": dict(dim=2, L=7, smoother="wjacobi", omega=0.8, block=32, bits=16),
     "2d-wjacobi-b11": dict(dim=2, L=6, smoother="wjacobi", omega=0.8, block=32, bits=11),
+    # the paper's own cycle, V(0,1) Gauss-Seidel (no pre-smoothing: y' = 0 on the way down)
+    "3d-L7-V01-b12": dict(dim=3, L=7, smoother="rbgs", omega=1.0, block=64, bits=12, nu_pre=0, nu_post=1),
+    "2d-L6-V01-b16": dict(dim=2, L=6, smoother="rbgs", omega=1.0, block=32, bits=16, nu_pre=0, nu_post=1),
 }
 
 
-def _oracle_cfg(c, **kw):
+def _nus(c):
     nu = c.get("nu", 2)
+    return c.get("nu_pre", nu), c.get("nu_post", nu)
+
+
+def _oracle_cfg(c, **kw):
+    n1, n2 = _nus(c)
     return oc.Config(dim=c["dim"], L=c["L"], smoother=c["smoother"], omega=c["omega"], block=c["block"],
-                     bits_u=c["bits"], bits_r=c["bits"], bits_y=c["bits"], nu_pre=nu, nu_post=nu, **kw)
+                     bits_u=c["bits"], bits_r=c["bits"], bits_y=c["bits"], nu_pre=n1, nu_post=n2, **kw)
 
 
 def _solver(cmg, c, **kw):
-    nu = c.get("nu", 2)
+    n1, n2 = _nus(c)
     return cmg.Solver(c["dim"], c["L"], smoother=c["smoother"], omega=c["omega"], bfp_block=c["block"],
-                      bits=c["bits"], nu_pre=nu, nu_post=nu, **kw)
+                      bits=c["bits"], nu_pre=n1, nu_post=n2, **kw)
 
 
 def _random_sections(cfg, Lp, seed):

@@ -145,11 +145,14 @@ def _dense_vcycle_error(dim, L, lc, smoother, omega, nu1=2, nu2=2):
     return E
 
 
-@pytest.mark.parametrize("dim,L,smoother,omega", [(2, 5, "wjacobi", 0.8), (3, 3, "rbgs", 1.0)])
-def test_vcycle_error_map_equals_dense_recursion(dim, L, smoother, omega):
-    E = _dense_vcycle_error(dim, L, 1, smoother, omega)
+@pytest.mark.parametrize("dim,L,smoother,omega,nu1,nu2", [
+    (2, 5, "wjacobi", 0.8, 2, 2), (3, 3, "rbgs", 1.0, 2, 2),
+    # the paper's own cycle: V(0,1) Gauss-Seidel (Alg. 1)
+    (2, 4, "rbgs", 1.0, 0, 1), (3, 3, "rbgs", 1.0, 0, 1)])
+def test_vcycle_error_map_equals_dense_recursion(dim, L, smoother, omega, nu1, nu2):
+    E = _dense_vcycle_error(dim, L, 1, smoother, omega, nu1, nu2)
     cfg = compact.Config(dim=dim, L=L, smoother=smoother, omega=omega, quantize=False,
-                         vcycle_dtype=np.float64)
+                         vcycle_dtype=np.float64, nu_pre=nu1, nu_post=nu2)
     n = 1 << L
     e = np.zeros((n + 1,) * dim)
     e[(slice(1, -1),) * dim] = np.random.default_rng(4).standard_normal((n - 1,) * dim)
