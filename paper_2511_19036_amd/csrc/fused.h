@@ -27,8 +27,8 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
                        double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st);
 
-// Full node grid u = dec u'_l + P uc.
-void launch_decode_full(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* full,
-                        hipStream_t st);
+// Full node grid u = dec u'_l + P uc (3-D levels of at least 64^3 nodes).
+bool fused_decode_full(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* full,
+                       hipStream_t st);
 
 }  // namespace cmg

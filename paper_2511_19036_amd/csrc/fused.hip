@@ -1045,37 +1045,97 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
 }
 
 // ============================================================ final decode
-// u (full node grid of level g) = dec u'_l + P u_{l-1}; far boundary 0.  One
-// thread per node; block (64, 4) over x and y, grid z over the planes.
-template <int LB>
-__global__ void __launch_bounds__(256) k_decode_full(PSec U, const double* __restrict__ uc, int level, int levelc,
-                                                     double* __restrict__ full) {
-  const int n = 1 << level, nc = 1 << levelc, N = n + 1;
-  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-  if (i >= N || j >= N) return;
-  double v = 0.0;
-  if (i < n && j < n && k < n) {
-    const int ti = i >> 1, tj = j >> 1, tk = k >> 1;
-    const int pi = i & 1, pj = j & 1, pk = k & 1;
-    const double w = (pk ? 0.5 : 1.0) * (pj ? 0.5 : 1.0) * (pi ? 0.5 : 1.0);
-    double s = 0.0;
-    bool first = true;
-    for (int oz = 0; oz <= pk; ++oz)
-      for (int oy = 0; oy <= pj; ++oy)
-        for (int ox = 0; ox <= pi; ++ox) {
-          const int a = ti + ox, b = tj + oy, c = tk + oz;
-          const double cv = (a < nc && b < nc && c < nc)
-                                ? uc[(static_cast<uint64_t>(c) << (2 * levelc)) |
-                                     (static_cast<uint64_t>(b) << levelc) | static_cast<uint64_t>(a)]
-                                : 0.0;
-          const double t = w * cv;
-          s = first ? t : s + t;
-          first = false;
-        }
-    const uint32_t xy = (static_cast<uint32_t>(j) << level) | static_cast<uint32_t>(i);
-    v = raw_f64(raw_at<LB>(plane_of(U, k), xy, U.cbits), xy, U.cbits, U.w) + s;
+// u (full node grid of level l) = dec u'_l + P u_{l-1}; far boundary 0.
+// A z-march like the residual: each thread owns one column of a 64 x TY
+// tile, coarse planes come through a ring in LDS, and every plane is
+// written as whole rows.  Tiles at the far x / y edges also write the
+// boundary column / row at node 2^l; the last chunk writes plane 2^l.
+template <int TY, int LB>
+__global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* __restrict__ uc, int level,
+                                                         int levelc, int TZ, double* __restrict__ full) {
+  constexpr int NT = 64 * TY;
+  constexpr int NC = 4, CW = kTX / 2 + 2, CH = TY / 2 + 2, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
+  __shared__ double cs[NC * CPL];
+  const int tid = threadIdx.x;
+  int lane = tid & 63;
+  int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int bx, by, bz;
+  tile_of((1 << level) / kTX, (1 << level) / TY, bx, by, bz);
+  int X0 = bx * kTX, Y0 = by * TY;
+  const int Z0 = bz * TZ;
+  const int n = 1 << level, nc = 1 << levelc;
+  const uint64_t N = static_cast<uint64_t>(n) + 1;
+  const int CX0 = X0 >> 1, CY0 = Y0 >> 1;
+  double cpf[CPT];
+  RawCode upre;
+  auto cfetch = [&](int cz) {
+    const bool zin = cz >= 0 && cz < nc;
+    const double* src = uc + (static_cast<uint64_t>(zin ? cz : 0) << (2 * levelc));
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int t = tid + k * NT;
+      const int cy = t / CW, cx = t - cy * CW;
+      const int gx = CX0 + cx, gy = CY0 + cy;
+      cpf[k] = 0.0;
+      if (zin && t < CPL && gx < nc && gy < nc)
+        cpf[k] = src[(static_cast<uint32_t>(gy) << levelc) | static_cast<uint32_t>(gx)];
+    }
+  };
+  auto cstore = [&](int cz) {
+    double* dst = cs + (cz & (NC - 1)) * CPL;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int t = tid + k * NT;
+      if (t < CPL) dst[t] = cpf[k];
+    }
+  };
+  auto xy_own = [&]() { return (static_cast<uint32_t>(Y0 + wv) << level) | static_cast<uint32_t>(X0 + lane); };
+  auto fetch_u = [&](int k) {
+    if (k < n) upre = raw_at<LB>(plane_of(U, k), xy_own(), U.cbits);
+  };
+  auto step = [&](auto kpc, const int k) {
+    constexpr int KP = decltype(kpc)::value;
+    opaque(lane);
+    opaque_s(wv);
+    opaque_s(X0);
+    opaque_s(Y0);
+    opaque_s(U);
+    if (KP == 0) cfetch((k >> 1) + 1);  // plane k + 1 needs coarse plane k / 2 + 1
+    const RawCode r = upre;
+    fetch_u(k + 1);
+    const double* c0 = cs + ((k >> 1) & (NC - 1)) * CPL;
+    const double* c1 = cs + (((k >> 1) + 1) & (NC - 1)) * CPL;
+    const int ci = (wv >> 1) * CW + (lane >> 1);
+    const double v = raw_f64(r, xy_own(), U.cbits, U.w) + prolong_node<double, KP, CW>(c0, c1, ci, lane & 1, wv & 1);
+    double* row = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(Y0 + wv)) * N;
+    row[X0 + lane] = v;
+    if (X0 + kTX == n && lane == 63) row[n] = 0.0;
+    if (Y0 + TY == n && wv == TY - 1) {
+      double* last = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(n)) * N;
+      last[X0 + lane] = 0.0;
+      if (X0 + kTX == n && lane == 63) last[n] = 0.0;
+    }
+    if (KP == 0) cstore((k >> 1) + 1);
+    __syncthreads();
+  };
+  cfetch(Z0 >> 1);
+  cstore(Z0 >> 1);
+  fetch_u(Z0);
+  __syncthreads();
+#pragma unroll 1
+  for (int k = Z0; k < Z0 + TZ; k += 2) {
+    step(std::integral_constant<int, 0>(), k);
+    step(std::integral_constant<int, 1>(), k + 1);
   }
-  full[(static_cast<uint64_t>(k) * N + j) * N + i] = v;
+  if (Z0 + TZ == n) {  // plane 2^l
+    double* plane = full + static_cast<uint64_t>(n) * N * N;
+    plane[static_cast<uint64_t>(Y0 + wv) * N + X0 + lane] = 0.0;
+    if (X0 + kTX == n && lane == 63) plane[static_cast<uint64_t>(Y0 + wv) * N + n] = 0.0;
+    if (Y0 + TY == n && wv == TY - 1) {
+      plane[static_cast<uint64_t>(n) * N + X0 + lane] = 0.0;
+      if (X0 + kTX == n && lane == 63) plane[static_cast<uint64_t>(n) * N + n] = 0.0;
+    }
+  }
 }
 
 // =============================================================== launchers
@@ -1098,7 +1158,7 @@ static double sec_b(const SecRef& s) {
   } while (0)
 
 constexpr int kDownTY = 16, kUpTY = 16, kResTY = 32, kRRCTY = 8, kDownNT = 448, kUpNT = 896, kResNT = 512,
-              kRRNT = 512;
+              kRRNT = 512, kDecTY = 8;
 
 static PSec psec(const SecRef& s, const Geom& g) {
   const uint64_t pv = static_cast<uint64_t>(1) << (2 * g.level);  // values per plane
@@ -1190,16 +1250,21 @@ bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int L
   return true;
 }
 
-void launch_decode_full(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* full,
-                        hipStream_t st) {
+bool fused_decode_full(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* full,
+                       hipStream_t st) {
+  if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64)) return false;
   const int64_t N = g.n + 1;
-  const dim3 grid(static_cast<unsigned>((N + 63) / 64), static_cast<unsigned>((N + 3) / 4), static_cast<unsigned>(N));
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * N * N * N;
   const PSec pu = psec(U, g);
+  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDecTY), 16);
+  const dim3 grid((g.n / kTX) * (g.n / kDecTY) * (g.n / tz)), block(64 * kDecTY);
   if (U.B == 64)
-    CMG_FLAUNCH("k_decode_full", bytes, k_decode_full<6>, grid, dim3(64, 4), st, pu, uc, g.level, gc.level, full);
+    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, 6>), grid, block, st, pu, uc, g.level, gc.level, tz,
+                full);
   else
-    CMG_FLAUNCH("k_decode_full", bytes, k_decode_full<5>, grid, dim3(64, 4), st, pu, uc, g.level, gc.level, full);
+    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, 5>), grid, block, st, pu, uc, g.level, gc.level, tz,
+                full);
+  return true;
 }
 
 }  // namespace cmg

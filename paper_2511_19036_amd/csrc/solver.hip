@@ -388,9 +388,10 @@ void decode_chain(cmg_ctx c, int top) {
 
 // Decoded solution of FMG level Lp into a full node array (Lp + 1)^dim.
 void decode_to_full(cmg_ctx c, int Lp, double* u) {
-  if (c->p.dim == 3 && Lp > c->lc()) {
+  if (c->p.dim == 3 && Lp > c->lc() && c->lv[Lp].g.n >= 64) {
     decode_chain(c, Lp - 1);
-    launch_decode_full(c->lv[Lp].U.ref(), c->lv[Lp - 1].uh, c->lv[Lp].g, c->lv[Lp - 1].g, u, c->st);
+    if (!fused_decode_full(c->lv[Lp].U.ref(), c->lv[Lp - 1].uh, c->lv[Lp].g, c->lv[Lp - 1].g, u, c->st))
+      fail(CMG_ERR_HIP, "fused decode rejected a level it was selected for");
   } else {
     decode_chain(c, Lp);
     launch_to_full(c->lv[Lp].uh, c->lv[Lp].g, u, c->st);
