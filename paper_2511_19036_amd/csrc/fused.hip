@@ -129,16 +129,28 @@ struct ColTile {
   static constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;          // output rows per wave
 };
 
+// Output row t of wave wv when TY rows are shared by NW waves.  Waves are
+// spread over the four SIMDs round-robin; with NW = 2 (mod 4) SIMDs 2 and 3
+// hold one wave fewer, so the rows beyond the first NW go to waves 2, 3, ...
+// first (measured: 7% faster up-sweep with 14 waves; no gain for 7).
+template <int NW>
+__device__ __forceinline__ int out_row(int wv, int t) {
+  constexpr int ROT = NW % 4 == 2 ? 2 : 0;
+  return t == 0 ? wv : NW * t + (wv - ROT + NW) % NW;
+}
+
 // Per-pair flags.
 constexpr unsigned kInnerSlot = 0u;   // bits 0, 1: the node of slot s is inside the level's interior
 constexpr unsigned kOutSlot = 2u;     // bits 2, 3: the node of slot s is an output node
 constexpr unsigned kSwap = 4u;        // bit 4: column 0 holds slot 1
 constexpr unsigned kOddY = 5u;        // bit 5: odd y
 constexpr unsigned kInnerCol = 6u;    // bits 6, 7: column c is inside the level's interior
+constexpr unsigned kDomCol = 8u;      // bits 8, 9: column c is a node of the level
+constexpr unsigned kValid = 10u;      // bit 10: the pair exists
 
 template <int H, int TY, int NT>
 __device__ __forceinline__ void col_setup(int tid, int X0, int Y0, int level, int* pos, uint32_t (*xy)[2],
-                                          unsigned* fl, int* oidx) {
+                                          unsigned* fl, int* oidx, uint32_t* lyx = nullptr) {
   using T = ColTile<H, TY, NT>;
   const int n = 1 << level;
 #pragma unroll
@@ -149,8 +161,9 @@ __device__ __forceinline__ void col_setup(int tid, int X0, int Y0, int level, in
     const int gx0 = X0 - H + lx0, gy = Y0 - H + ly;
     pos[k] = valid ? ly * T::EXW + lx0 : T::LPL;  // a missing pair writes the spare words
     oidx[k] = (ly - H) * kTX + (lx0 - H);
+    if (lyx != nullptr) lyx[k] = (static_cast<uint32_t>(ly) << 16) | static_cast<uint32_t>(lx0);
     const unsigned sw = static_cast<unsigned>(gx0 + gy) & 1u;
-    unsigned f = (sw << kSwap) | ((static_cast<unsigned>(gy) & 1u) << kOddY);
+    unsigned f = (sw << kSwap) | ((static_cast<unsigned>(gy) & 1u) << kOddY) | ((valid ? 1u : 0u) << kValid);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int gx = gx0 + c, lx = lx0 + c;
@@ -162,6 +175,7 @@ __device__ __forceinline__ void col_setup(int tid, int X0, int Y0, int level, in
       f |= (inner ? 1u : 0u) << (kInnerSlot + slot);
       f |= (out ? 1u : 0u) << (kOutSlot + slot);
       f |= (inner ? 1u : 0u) << (kInnerCol + c);
+      f |= (dom ? 1u : 0u) << (kDomCol + c);
     }
     fl[k] = f;
   }
@@ -176,8 +190,8 @@ __device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, in
   const PlanePtr pq = plane_of(S, po);
 #pragma unroll
   for (int t = 0; t < RPW; ++t) {
-    const int rr = wv + t * NW;
-    if (rr >= TY) break;
+    const int rr = out_row<NW>(wv, t);
+    if (rr >= TY) continue;
     const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
     int e;
     const int m = quant_f32<LB>(ob[rr * kTX + lane], S.w, lane, &e);
@@ -190,7 +204,7 @@ __device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, in
 // y'_l = Q(S^nu1(0; g_l)): S = 2 nu1 half-sweeps from zero.  At step j the
 // right-hand side of plane j enters and stage s updates plane j - s; the
 // first half-sweep is pointwise (y = c g), hence a halo of S - 1.
-template <int S, int TY, int NT, int LB>
+template <int S, int TY, int NT, int LB, bool HI>
 __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level, float cp, float ih2, int TZ) {
   constexpr int H = S - 1;
   using T = ColTile<H, TY, NT>;
@@ -240,7 +254,7 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
       for (int k = 0; k < K; ++k)
         if (wave_has(k))
 #pragma unroll
-          for (int c = 0; c < 2; ++c) gpre[k][c] = raw_at<LB>(gq, xy[k][c], G.cbits);
+          for (int c = 0; c < 2; ++c) gpre[k][c] = raw_at<LB, HI>(gq, xy[k][c], G.cbits);
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k)
@@ -381,7 +395,7 @@ __device__ __forceinline__ T prolong_node(const T* c0, const T* c1, int ci, bool
   return s;
 }
 
-template <int S, int TY, int NT, int LB>
+template <int S, int TY, int NT, int LB, bool HI>
 __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ ec, PSec G, PSec Y, PSec Yp, PSec U,
                                                      float* __restrict__ eout, int level, int levelc, float cp,
                                                      float ih2, int TZ) {
@@ -482,8 +496,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
         if (wave_has(k))
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            gpre[k][c] = raw_at<LB>(gq, xy[k][c], G.cbits);
-            ypre[k][c] = raw_at<LB>(yq, xy[k][c], Y.cbits);
+            gpre[k][c] = raw_at<LB, HI>(gq, xy[k][c], G.cbits);
+            ypre[k][c] = raw_at<LB, HI>(yq, xy[k][c], Y.cbits);
           }
     } else {
 #pragma unroll
@@ -500,7 +514,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     const PlanePtr uq = plane_of(U, po);
 #pragma unroll
     for (int t = 0; t < RPW; ++t) {
-      const int rr = wv + t * NW;
+      const int rr = out_row<NW>(wv, t);
       if (rr < TY) upre[t] = raw_at<LB>(uq, ((static_cast<uint32_t>(Y0 + rr) << level) | X0) + lane, U.cbits);
     }
   };
@@ -512,8 +526,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     const float* c1 = cs + (((po >> 1) + 1) & (NC - 1)) * CPL;
 #pragma unroll
     for (int t = 0; t < RPW; ++t) {
-      const int rr = wv + t * NW;
-      if (rr >= TY) break;
+      const int rr = out_row<NW>(wv, t);
+      if (rr >= TY) continue;
       const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
       const uint32_t xyl = xyr + lane;
       int ey;
@@ -669,7 +683,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
 //      the sum of plane K + 1 starts with the same nine products.
 // The t planes are stored split by x parity so that the stride-two reads of
 // the coarse nodes are consecutive.
-template <int CTY, int NT, int LB>
+template <int CTY, int NT, int LB, bool HI>
 __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, int level, float ih2, int TZc) {
   constexpr int YW = 2 * kTX + 4, YH = 2 * CTY + 3;  // y' region, origin (2 CX0 - 2, 2 CY0 - 2)
   constexpr int NCOL = YW * YH, YPS = NCOL + 1, K = (NCOL + NT - 1) / NT;
@@ -721,7 +735,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
       const PlanePtr yq = plane_of(Y, p);
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        if (wave_has(k)) ypre[k] = raw_at<LB>(yq, xy[k], Y.cbits);
+        if (wave_has(k)) ypre[k] = raw_at<LB, HI>(yq, xy[k], Y.cbits);
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k) ypre[k] = raw_none();
@@ -732,7 +746,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
       const PlanePtr gq = plane_of(G, p);
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        if (wave_has(k)) gpre[k] = raw_at<LB>(gq, xy[k], G.cbits);
+        if (wave_has(k)) gpre[k] = raw_at<LB, HI>(gq, xy[k], G.cbits);
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k) gpre[k] = raw_none();
@@ -1179,18 +1193,24 @@ bool fused_down_smooth(const SecRef& G, const SecRef& Y, const Geom& g, int nu, 
   const dim3 grid((g.n / kTX) * (g.n / kDownTY) * (g.n / tz)), block(kDownNT);
   const double bytes = sec_b(G) + sec_b(Y);
   const PSec pg = psec(G, g), py = psec(Y, g);
-  if (nu == 2 && G.B == 64)
-    CMG_FLAUNCH("k_down_smooth<4>", bytes, (k_down_smooth<4, kDownTY, kDownNT, 6>), grid, block, st, pg, py, g.level,
-                cp, ih2, tz);
-  else if (nu == 2)
-    CMG_FLAUNCH("k_down_smooth<4>", bytes, (k_down_smooth<4, kDownTY, kDownNT, 5>), grid, block, st, pg, py, g.level,
-                cp, ih2, tz);
-  else if (G.B == 64)
-    CMG_FLAUNCH("k_down_smooth<2>", bytes, (k_down_smooth<2, kDownTY, kDownNT, 6>), grid, block, st, pg, py, g.level,
-                cp, ih2, tz);
-  else
-    CMG_FLAUNCH("k_down_smooth<2>", bytes, (k_down_smooth<2, kDownTY, kDownNT, 5>), grid, block, st, pg, py, g.level,
-                cp, ih2, tz);
+  const bool hi = G.cbits == 12;
+#define CMG_DOWN(S_, LB_, HI_)                                                                                  \
+  CMG_FLAUNCH("k_down_smooth<" #S_ ">", bytes, (k_down_smooth<S_, kDownTY, kDownNT, LB_, HI_>), grid, block, st, pg, \
+              py, g.level, cp, ih2, tz)
+  if (nu == 2) {
+    if (G.B == 64) {
+      if (hi) CMG_DOWN(4, 6, true); else CMG_DOWN(4, 6, false);
+    } else {
+      if (hi) CMG_DOWN(4, 5, true); else CMG_DOWN(4, 5, false);
+    }
+  } else {
+    if (G.B == 64) {
+      if (hi) CMG_DOWN(2, 6, true); else CMG_DOWN(2, 6, false);
+    } else {
+      if (hi) CMG_DOWN(2, 5, true); else CMG_DOWN(2, 5, false);
+    }
+  }
+#undef CMG_DOWN
   return true;
 }
 
@@ -1203,18 +1223,24 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
   const dim3 grid((g.n / kTX) * (g.n / kUpTY) * (g.n / tz)), block(kUpNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Yp) + 2.0 * sec_b(U) + 4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
   const PSec pg = psec(G, g), py = psec(Y, g), pp = psec(Yp, g), pu = psec(U, g);
-  if (nu == 2 && G.B == 64)
-    CMG_FLAUNCH("k_up_smooth<4>", bytes, (k_up_smooth<4, kUpTY, kUpNT, 6>), grid, block, st, ec, pg, py, pp, pu, eout,
-                g.level, gc.level, cp, ih2, tz);
-  else if (nu == 2)
-    CMG_FLAUNCH("k_up_smooth<4>", bytes, (k_up_smooth<4, kUpTY, kUpNT, 5>), grid, block, st, ec, pg, py, pp, pu, eout,
-                g.level, gc.level, cp, ih2, tz);
-  else if (G.B == 64)
-    CMG_FLAUNCH("k_up_smooth<2>", bytes, (k_up_smooth<2, kUpTY, kUpNT, 6>), grid, block, st, ec, pg, py, pp, pu, eout,
-                g.level, gc.level, cp, ih2, tz);
-  else
-    CMG_FLAUNCH("k_up_smooth<2>", bytes, (k_up_smooth<2, kUpTY, kUpNT, 5>), grid, block, st, ec, pg, py, pp, pu, eout,
-                g.level, gc.level, cp, ih2, tz);
+  const bool hi = G.cbits == 12 || Y.cbits == 12;
+#define CMG_UP(S_, LB_, HI_)                                                                                     \
+  CMG_FLAUNCH("k_up_smooth<" #S_ ">", bytes, (k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_>), grid, block, st, ec, pg, py, \
+              pp, pu, eout, g.level, gc.level, cp, ih2, tz)
+  if (nu == 2) {
+    if (G.B == 64) {
+      if (hi) CMG_UP(4, 6, true); else CMG_UP(4, 6, false);
+    } else {
+      if (hi) CMG_UP(4, 5, true); else CMG_UP(4, 5, false);
+    }
+  } else {
+    if (G.B == 64) {
+      if (hi) CMG_UP(2, 6, true); else CMG_UP(2, 6, false);
+    } else {
+      if (hi) CMG_UP(2, 5, true); else CMG_UP(2, 5, false);
+    }
+  }
+#undef CMG_UP
   return true;
 }
 
@@ -1225,12 +1251,16 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
   const dim3 grid((gc.n / kTX) * (gc.n / kRRCTY) * (gc.n / tz)), block(kRRNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Gc);
   const PSec pg = psec(G, g), py = psec(Y, g), pc = psec(Gc, gc);
-  if (G.B == 64)
-    CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, kRRNT, 6>), grid, block, st, pg, py, pc, g.level,
-                ih2, tz);
-  else
-    CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, kRRNT, 5>), grid, block, st, pg, py, pc, g.level,
-                ih2, tz);
+  const bool hi = G.cbits == 12 || Y.cbits == 12;
+#define CMG_RR(LB_, HI_)                                                                                      \
+  CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, kRRNT, LB_, HI_>), grid, block, st, pg, py, pc, \
+              g.level, ih2, tz)
+  if (G.B == 64) {
+    if (hi) CMG_RR(6, true); else CMG_RR(6, false);
+  } else {
+    if (hi) CMG_RR(5, true); else CMG_RR(5, false);
+  }
+#undef CMG_RR
   return true;
 }
 

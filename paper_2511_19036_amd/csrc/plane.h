@@ -43,14 +43,17 @@ __device__ __forceinline__ PlanePtr plane_of(const PSec& s, int p) {
 }
 
 // Raw words and block exponent of in-plane value xy (see RawCode).  Sections
-// carry 16 bytes of padding, so the second word is always readable.
-template <int LB>
+// carry 16 bytes of padding, so the second word is always readable.  With
+// HI = false the caller guarantees an 8-, 16- or 32-bit container, whose
+// codes never straddle two words: the second word is not loaded and the
+// compiler knows it is zero.
+template <int LB, bool HI = true>
 __device__ __forceinline__ RawCode raw_at(const PlanePtr& pp, uint32_t xy, int cbits) {
   const uint32_t bit = xy * static_cast<uint32_t>(cbits);
   const uint32_t* wp = reinterpret_cast<const uint32_t*>(pp.c + ((bit >> 5) << 2));
   RawCode r;
   r.lo = wp[0];
-  r.hi = (cbits == 12 || cbits == 64) ? wp[1] : 0u;
+  r.hi = (HI && (cbits == 12 || cbits == 64)) ? wp[1] : 0u;
   r.e = pp.e[xy >> LB];
   return r;
 }
