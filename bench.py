@@ -114,6 +114,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 FMG comparison")
     ap.add_argument("--cpu-L", type=int, default=8)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 8/12-bit and tuned-width runs")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for counter runs: one warm-up solve, a calibration copy of 1 GiB, one solve; no JSON")
     args = ap.parse_args()
@@ -211,6 +212,40 @@ def main():
         plain = dict(dof_per_s=dofs / (pms * 1e-3), ms_per_solve=pms, err_over_disc=perr, dev_over_disc=pdev,
                      bytes_per_dof=pmem["total"] / dofs)
 
+    def solve_rate(opts, steps):
+        """DoF/s, accuracy and bytes/DoF of the same problem with other widths."""
+        q = Solver(dim, L, smoother="rbgs", bfp_block=64, vcycle_prec="fp32", **opts)
+        q.solve(f, u)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            q.solve(f, u)
+        e1.record()
+        torch.cuda.synchronize()
+        qms = e0.elapsed_time(e1) / steps
+        qerr, qdev = discretisation_check(u[0], L)
+        qmem = q.memory_stats()
+        q.close()
+        return dict(opts=opts, dof_per_s=dofs / (qms * 1e-3), ms_per_solve=qms, err_over_disc=qerr,
+                    dev_over_disc=qdev, accuracy_pass=bool(qerr <= 2.0 and qdev <= 0.5),
+                    bytes_per_dof=qmem["total"] / dofs, logical_bits_per_dof=qmem["logical_bits_per_dof"])
+
+    sweep = None
+    if not args.no_sweep:
+        sweep = {}
+        for b in (8, 12):
+            log(f"[bench] compact FMG with {b}-bit tails")
+            sweep[str(b)] = solve_rate(dict(bits=b, ir_iters=2), min(args.steps, 3))
+        from paper_2511_19036_amd.tune import tune_widths
+        log("[bench] tuning widths and N on the 33^3 .. 65^3 sine problems (Sec. 7.1 procedure)")
+        t0 = time.perf_counter()
+        tuned = tune_widths(3, 6, smoother="rbgs", omega=1.0, bfp_block=64)
+        tune_s = time.perf_counter() - t0
+        log(f"[bench] tuned: {tuned} ({tune_s:.1f} s); timing it at {N}^3")
+        sweep["tuned"] = solve_rate(tuned, min(args.steps, 3))
+        sweep["tuned"]["tuning_s"] = tune_s
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU baseline: oracle at {(1 << args.cpu_L) + 1}^3")
@@ -245,6 +280,7 @@ def main():
                          gbs=(r["bytes"] / (r["ms"] * 1e-3) / 1e9) if r["ms"] > 0 else None)
                     for r in per_kernel[:12]],
         "plain_fp64": plain,
+        "width_sweep": sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -171,13 +171,14 @@ def vcycle_correct(U, g_top: Section, ops, cfg: Config, Lp: int, trace=None):
     return Y
 
 
-def fmg_solve(f_full: np.ndarray, cfg: Config, kappa=None, history=None):
+def fmg_solve(f_full: np.ndarray, cfg: Config, kappa=None, history=None, levels=None):
     """Compact FMG with IR (Alg. 3).  Returns ``(u_full, U)``.
 
     ``f_full`` is the ``(2**L + 1)**dim`` right-hand side (boundary ignored);
     ``u_full`` the decoded FP64 solution on the same node grid (boundary 0);
     ``U`` the final compact sections.  ``history``, if a list, receives the
-    float64 2-norm of each IR residual ``t`` before rounding.
+    float64 2-norm of each IR residual ``t`` before rounding; ``levels``, if a
+    dict, receives the decoded node-grid solution after every FMG level.
     """
     lc, L = cfg.coarsest, cfg.L
     if not 1 <= lc < L:
@@ -198,6 +199,8 @@ def fmg_solve(f_full: np.ndarray, cfg: Config, kappa=None, history=None):
                 uh = decode_chain(U, lc, Lp)
                 history.append(float(np.linalg.norm(f_level - ops[Lp].apply(uh, np.float64))))
             vcycle_correct(U, g, ops, cfg, Lp)
+        if levels is not None:
+            levels[Lp] = to_full(decode_chain(U, lc, Lp))
     return to_full(decode_chain(U, lc, L)), U
 
 
