@@ -1,0 +1,238 @@
+// The V-cycle on the small levels of the hierarchy in one workgroup.
+//
+// On the smallest levels a kernel launch costs more than the work it does,
+// and a V-cycle visits every level with some twenty operations.  Here one
+// workgroup of 1024 threads runs the whole down sweep from level Lc, the
+// coarsest solve and the up sweep back to Lc, with a workgroup barrier
+// between operations.  The level arrays live in LDS (the sections stay in
+// global memory); at the end e[Lc] is copied out for the next finer level.
+// Each operation computes exactly what the corresponding per-operation
+// kernel computes (same expressions in the same order), so the results are
+// bit-identical.
+#include "coarse.h"
+#include "timing.h"
+
+namespace cmg {
+
+constexpr int kCoarseNT = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
+  constexpr int NW = kCoarseNT / 64;
+  __shared__ double pool[kCoarsePoolBytes / 8];
+  __shared__ double cpool[2 * kCoarsestMax];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  T* const base = reinterpret_cast<T*>(pool);
+  // the five arrays of level l: g, y, z, r, e (in that order)
+  auto arr = [&](int l, int which) { return base + a.off[l] + which * a.lv[l].g.size; };
+  double* const t64 = cpool;
+  double* const s64 = cpool + kCoarsestMax;
+
+  auto each = [&](int64_t n, auto&& f) {
+    for (int64_t i = tid; i < n; i += kCoarseNT) f(i);
+  };
+  auto sync = [&]() { __syncthreads(); };
+  auto decode = [&](const SecRef& s, int64_t n, T* x) {
+    each(n, [&](int64_t i) { x[i] = static_cast<T>(decode_value(s, i)); });
+  };
+  auto decode64 = [&](const SecRef& s, int64_t n, double* x) {
+    each(n, [&](int64_t i) { x[i] = decode_value(s, i); });
+  };
+  // one wave per 64 consecutive values (one block of 64 or two of 32)
+  auto encode = [&](auto* x, int64_t n, const SecRef& s) {
+    const int64_t limit = limit_of(s);
+    for (int64_t base = static_cast<int64_t>(wv) * 64; base < limit; base += NW * 64) {
+      const int64_t i = base + lane;
+      const double v = (i < n) ? static_cast<double>(x[i]) : 0.0;
+      if (a.nonfinite != nullptr && !isfinite(v)) atomicOr(a.nonfinite, 1);
+      int e;
+      const int64_t m = quantise_lane(v, s.B, s.w, &e);
+      store_codes_wave(s, base, lane, m, limit);
+      if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
+    }
+  };
+  auto correct = [&](const SecRef& u, const SecRef& y) {  // u' <- Q(dec u' + dec y')
+    const int64_t limit = limit_of(u);
+    for (int64_t base = static_cast<int64_t>(wv) * 64; base < limit; base += NW * 64) {
+      const int64_t i = base + lane;
+      const double v = (i < limit) ? decode_value(u, i) + decode_value(y, i) : 0.0;
+      int e;
+      const int64_t m = quantise_lane(v, u.B, u.w, &e);
+      store_codes_wave(u, base, lane, m, limit);
+      if ((lane & (u.B - 1)) == 0 && i < limit) u.exps[blk(u, i)] = static_cast<int16_t>(e);
+    }
+  };
+  auto rhs_minus_A = [&](const T* rhs, const T* u, const T* kap, const Geom& g, T ih2, T* out) {
+    each(g.size, [&](int64_t idx) {
+      int i, j, k;
+      unflatten(g, idx, i, j, k);
+      out[idx] = is_interior(g, i, j, k) ? rhs[idx] - apply_A(u, kap, g, i, j, k, ih2) : T(0);
+    });
+  };
+  auto restrict_to = [&](const T* fine, const Geom& gc, const Geom& gf, T* coarse) {
+    each(gc.size, [&](int64_t idx) {
+      int I, J, K;
+      unflatten(gc, idx, I, J, K);
+      if (!is_interior(gc, I, J, K)) {
+        coarse[idx] = T(0);
+        return;
+      }
+      T s = T(0);
+      bool first = true;
+      const int z0 = gc.dim == 3 ? -1 : 0, z1 = gc.dim == 3 ? 1 : 0;
+      for (int oz = z0; oz <= z1; ++oz) {
+        const double wz = gc.dim == 3 ? (oz == 0 ? 0.5 : 0.25) : 1.0;
+        for (int oy = -1; oy <= 1; ++oy) {
+          const double wy = oy == 0 ? 0.5 : 0.25;
+          for (int ox = -1; ox <= 1; ++ox) {
+            const double wx = ox == 0 ? 0.5 : 0.25;
+            const int kf = gc.dim == 3 ? 2 * K + oz : 0;
+            const T t = static_cast<T>(wz * wy * wx) * fine[flat(gf, 2 * I + ox, 2 * J + oy, kf)];
+            s = first ? t : s + t;
+            first = false;
+          }
+        }
+      }
+      coarse[idx] = s;
+    });
+  };
+  auto prolong = [&](const T* coarse, const Geom& gf, const Geom& gc, T* fine) {
+    each(gf.size, [&](int64_t idx) {
+      int i, j, k;
+      unflatten(gf, idx, i, j, k);
+      fine[idx] = prolong_at(coarse, gc, i, j, k);
+    });
+  };
+  auto smooth = [&](const CoarseLevel& L, T* y, const T* rhs, T* scratch, int nu) {
+    const T* kap = static_cast<const T*>(L.kap);
+    const T ih2 = static_cast<T>(L.ih2), cp = static_cast<T>(L.cp);
+    const Geom& g = L.g;
+    if (a.rbgs) {
+      for (int s = 0; s < nu; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+          each(g.size, [&](int64_t idx) {
+            int i, j, k;
+            unflatten(g, idx, i, j, k);
+            if (!is_interior(g, i, j, k) || ((i + j + k) & 1) != colour) return;
+            const T r = rhs[idx] - apply_A(y, kap, g, i, j, k, ih2);
+            const T c = smooth_coeff(kap, g, i, j, k, ih2, cp, T(1));
+            y[idx] = y[idx] + c * r;
+          });
+          sync();
+        }
+      return;
+    }
+    const T om = static_cast<T>(a.omega);
+    T* p = y;
+    T* q = scratch;
+    for (int s = 0; s < nu; ++s) {
+      each(g.size, [&](int64_t idx) {
+        int i, j, k;
+        unflatten(g, idx, i, j, k);
+        if (!is_interior(g, i, j, k)) {
+          q[idx] = T(0);
+          return;
+        }
+        const T r = rhs[idx] - apply_A(p, kap, g, i, j, k, ih2);
+        const T c = smooth_coeff(kap, g, i, j, k, ih2, cp, om);
+        q[idx] = p[idx] + c * r;
+      });
+      sync();
+      T* t = p;
+      p = q;
+      q = t;
+    }
+    if (p != y) {
+      each(g.size, [&](int64_t idx) { y[idx] = p[idx]; });
+      sync();
+    }
+  };
+
+  // ---------------------------------------------------------- down sweep
+  for (int l = a.Lc; l > a.lc; --l) {
+    const CoarseLevel& F = a.lv[l];
+    const CoarseLevel& C = a.lv[l - 1];
+    T* gf = arr(l, 0);
+    T* yf = arr(l, 1);
+    T* rf = arr(l, 3);
+    decode(F.G, F.g.size, gf);
+    each(F.g.size, [&](int64_t i) { yf[i] = T(0); });
+    sync();
+    smooth(F, yf, gf, arr(l, 4), a.nu_pre);
+    encode(yf, F.g.size, F.Y);
+    sync();
+    decode(F.Y, F.g.size, yf);
+    sync();
+    rhs_minus_A(gf, yf, static_cast<const T*>(F.kap), F.g, static_cast<T>(F.ih2), rf);
+    sync();
+    restrict_to(rf, C.g, F.g, arr(l - 1, 3));
+    sync();
+    encode(arr(l - 1, 3), C.g.size, C.G);
+    sync();
+  }
+  // ------------------------------------------------------ coarsest (float64)
+  {
+    const CoarseLevel& B = a.lv[a.lc];
+    decode64(B.G, B.g.size, t64);
+    each(B.g.size, [&](int64_t t) { s64[t] = 0.0; });
+    sync();
+    if (tid == 0) {
+      const Geom& g = B.g;
+      const int64_t c = flat(g, 1, 1, g.dim == 3 ? 1 : 0);
+      const double diag = a.kap64 == nullptr ? static_cast<double>(2 * g.dim) * B.ih2
+                                             : diag_A(a.kap64, g, 1, 1, g.dim == 3 ? 1 : 0, B.ih2);
+      s64[c] = t64[c] / diag;
+    }
+    sync();
+    encode(s64, B.g.size, B.Yp);
+    sync();
+    correct(B.U, B.Yp);
+    decode(B.Yp, B.g.size, arr(a.lc, 4));
+    sync();
+  }
+  // ------------------------------------------------------------ up sweep
+  for (int l = a.lc + 1; l <= a.Lc; ++l) {
+    const CoarseLevel& F = a.lv[l];
+    const CoarseLevel& C = a.lv[l - 1];
+    T* gf = arr(l, 0);
+    T* yf = arr(l, 1);
+    T* zf = arr(l, 2);
+    T* rf = arr(l, 3);
+    prolong(arr(l - 1, 4), F.g, C.g, zf);
+    decode(F.G, F.g.size, gf);
+    sync();
+    rhs_minus_A(gf, zf, static_cast<const T*>(F.kap), F.g, static_cast<T>(F.ih2), rf);
+    decode(F.Y, F.g.size, yf);
+    sync();
+    smooth(F, yf, rf, arr(l, 4), a.nu_post);
+    encode(yf, F.g.size, F.Yp);
+    sync();
+    correct(F.U, F.Yp);
+    if (l < a.Lp) {
+      decode(F.Yp, F.g.size, yf);
+      sync();
+      T* ef = arr(l, 4);
+      each(F.g.size, [&](int64_t i) { ef[i] = yf[i] + zf[i]; });
+    }
+    sync();
+  }
+  if (a.Lc < a.Lp) {  // e[Lc] for the next finer level
+    const T* e = arr(a.Lc, 4);
+    T* out = static_cast<T*>(a.lv[a.Lc].ef);
+    each(a.lv[a.Lc].g.size, [&](int64_t i) { out[i] = e[i]; });
+  }
+}
+
+template <typename T>
+void launch_coarse_vcycle(const CoarseArgs& a, hipStream_t st) {
+  double bytes = 0.0;  // the sections read and written
+  for (int l = a.lc; l <= a.Lc; ++l) bytes += 5.0 * 2.0 * static_cast<double>(a.lv[l].g.size);
+  if (g_timing != nullptr) g_timing->begin("k_coarse_vcycle", bytes, st);
+  hipLaunchKernelGGL(k_coarse_vcycle<T>, dim3(1), dim3(kCoarseNT), 0, st, a);
+  if (g_timing != nullptr) g_timing->end(st);
+}
+
+template void launch_coarse_vcycle<float>(const CoarseArgs&, hipStream_t);
+template void launch_coarse_vcycle<double>(const CoarseArgs&, hipStream_t);
+
+}  // namespace cmg

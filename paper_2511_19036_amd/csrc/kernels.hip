@@ -132,29 +132,6 @@ __global__ void __launch_bounds__(kThreads) k_rhs_minus_A(const T* __restrict__ 
   out[idx] = is_interior(g, i, j, k) ? rhs[idx] - apply_A(u, kap, g, i, j, k, inv_h2) : T(0);
 }
 
-// fine = P coarse (d-linear interpolation); gf is the fine level.
-template <typename T>
-__device__ __forceinline__ T prolong_at(const T* coarse, const Geom& gc, int i, int j, int k) {
-  const int ti = i >> 1, tj = j >> 1, tk = k >> 1;
-  const int pi = i & 1, pj = j & 1, pk = k & 1;
-  T s = T(0);
-  bool first = true;
-  const int nk = (gc.dim == 3) ? 1 + pk : 1;
-  for (int oz = 0; oz < nk; ++oz) {
-    const double wz = (gc.dim == 3 && pk) ? 0.5 : 1.0;
-    for (int oy = 0; oy <= pj; ++oy) {
-      const double wy = pj ? 0.5 : 1.0;
-      for (int ox = 0; ox <= pi; ++ox) {
-        const double wx = pi ? 0.5 : 1.0;
-        const T t = static_cast<T>(wz * wy * wx) * at(coarse, gc, ti + ox, tj + oy, tk + oz);
-        s = first ? t : s + t;
-        first = false;
-      }
-    }
-  }
-  return s;
-}
-
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_prolong(const T* __restrict__ coarse, Geom gf, Geom gc,
                                                       T* __restrict__ fine) {
@@ -204,14 +181,6 @@ __global__ void __launch_bounds__(kThreads) k_restrict(const T* __restrict__ fin
     }
   }
   coarse[idx] = s;
-}
-
-// Smoothing coefficient c of y <- y + c (rhs - A y): `cpois` for Poisson,
-// omega / diag_p for diffusion.
-template <typename T>
-__device__ __forceinline__ T smooth_coeff(const T* kap, const Geom& g, int i, int j, int k, T inv_h2, T cpois,
-                                          T omega) {
-  return kap == nullptr ? cpois : omega / diag_A(kap, g, i, j, k, inv_h2);
 }
 
 template <typename T>

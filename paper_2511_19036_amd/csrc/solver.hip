@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "cmg.h"
+#include "coarse.h"
 #include "fused.h"
 #include "launch.h"
 #include "timing.h"
@@ -296,7 +297,15 @@ void vcycle_correct(cmg_ctx c, int Lp) {
   hipStream_t st = c->st;
   int* nf = c->flags + 1;
   constexpr bool f32 = std::is_same<T, float>::value;
-  for (int l = Lp; l > lc; --l) {  // fine to coarse
+  // Lc: the top of the small levels that one workgroup cycles through
+  int Lc = lc;
+  for (int l = std::min(Lp, kCoarseMaxLevel); l > lc; --l)
+    if (coarse_pool_bytes(c->p.dim, lc, l, sizeof(T)) <= kCoarsePoolBytes && !c->smooth_fused(l) &&
+        c->lv[lc].g.size <= kCoarsestMax) {
+      Lc = l;
+      break;
+    }
+  for (int l = Lp; l > Lc; --l) {  // fine to coarse
     LevelData& F = c->lv[l];
     LevelData& C = c->lv[l - 1];
     const double ih2 = inv_h2(l);
@@ -334,15 +343,48 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     KCK();
   }
   LevelData& B = c->lv[lc];  // coarsest, float64
-  launch_decode<double>(B.G.ref(), B.g.size, B.t64, st);
-  launch_coarse_single(B.t64, kap64(c, lc), B.g, inv_h2(lc), B.s64, st);
-  B.Yp.w = c->wy(lc, Lp);
-  launch_encode<double>(B.s64, B.g.size, B.Yp.ref(), nf, st);
-  B.U.w = c->wu(lc, Lp);
-  launch_correct(B.U.ref(), B.Yp.ref(), st);
-  launch_decode<T>(B.Yp.ref(), B.g.size, static_cast<T*>(B.ef), st);
-  KCK();
-  for (int l = lc + 1; l <= Lp; ++l) {  // coarse to fine
+  if (Lc > lc) {  // levels lc .. Lc in one workgroup
+    CoarseArgs a{};
+    for (int l = lc; l <= Lc; ++l) {
+      LevelData& D = c->lv[l];
+      D.Y.w = c->wy(l, Lp);
+      D.Yp.w = c->wy(l, Lp);
+      D.U.w = c->wu(l, Lp);
+      if (l < Lc) D.G.w = c->wr(l, Lp);
+      CoarseLevel& q = a.lv[l];
+      q.G = D.G.ref();
+      q.Y = D.Y.ref();
+      q.Yp = D.Yp.ref();
+      q.U = D.U.ref();
+      q.ef = D.ef;
+      a.off[l] = l == lc ? 0 : a.off[l - 1] + 5 * static_cast<int>(c->lv[l - 1].g.size);
+      q.kap = kapT<T>(c, l);
+      q.g = D.g;
+      q.ih2 = inv_h2(l);
+      q.cp = (c->o.smoother == CMG_RBGS ? 1.0 : c->o.omega) / (2.0 * c->p.dim * q.ih2);
+    }
+    a.kap64 = kap64(c, lc);
+    a.lc = lc;
+    a.Lc = Lc;
+    a.Lp = Lp;
+    a.nu_pre = c->o.nu_pre;
+    a.nu_post = c->o.nu_post;
+    a.rbgs = c->o.smoother == CMG_RBGS ? 1 : 0;
+    a.omega = c->o.omega;
+    a.nonfinite = nf;
+    launch_coarse_vcycle<T>(a, st);
+    KCK();
+  } else {
+    launch_decode<double>(B.G.ref(), B.g.size, B.t64, st);
+    launch_coarse_single(B.t64, kap64(c, lc), B.g, inv_h2(lc), B.s64, st);
+    B.Yp.w = c->wy(lc, Lp);
+    launch_encode<double>(B.s64, B.g.size, B.Yp.ref(), nf, st);
+    B.U.w = c->wu(lc, Lp);
+    launch_correct(B.U.ref(), B.Yp.ref(), st);
+    launch_decode<T>(B.Yp.ref(), B.g.size, static_cast<T*>(B.ef), st);
+    KCK();
+  }
+  for (int l = Lc + 1; l <= Lp; ++l) {  // coarse to fine
     LevelData& F = c->lv[l];
     LevelData& C = c->lv[l - 1];
     const double ih2 = inv_h2(l);
