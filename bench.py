@@ -104,6 +104,66 @@ def cpu_baseline(L_sample: int, bits: int):
                        f"({dofs} DoF), one FMG solve, {t:.1f} s on one host thread")
 
 
+def _time_solves(s, f, reps):
+    import torch
+    u = torch.empty_like(f)
+    s.solve(f, u)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        s.solve(f, u)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, u
+
+
+def other_workloads():
+    """Solve times of the other workloads (same library, same GPU)."""
+    import torch
+
+    import synthetic
+    from paper_2511_19036_amd import Solver
+    out = {}
+    log("[bench] other workloads: 2-D 129^2, 3-D 257^3, diffusion 129^3 and 513^3 x 8")
+    f = torch.from_numpy(synthetic.gaussian_noise_rhs(2, 7, 1e-3, 0)).cuda()[None].contiguous()
+    with Solver(2, 7, smoother="wjacobi", omega=0.8, bfp_block=32, bits=16) as s:
+        ms, _ = _time_solves(s, f, 20)
+    out["poisson2d_129_b16"] = dict(ms_per_solve=ms, dof_per_s=127 ** 2 / (ms * 1e-3))
+    f = torch.from_numpy(synthetic.sine_rhs(3, 8)).cuda()[None].contiguous()
+    for b in (8, 12, 16):
+        with Solver(3, 8, smoother="rbgs", bfp_block=64, bits=b) as s:
+            ms, u = _time_solves(s, f, 10)
+        e, dv = discretisation_check(u[0], 8)
+        out[f"poisson3d_257_b{b}"] = dict(ms_per_solve=ms, dof_per_s=255 ** 3 / (ms * 1e-3), err_over_disc=e,
+                                          dev_over_disc=dv)
+    kap = torch.from_numpy(synthetic.lognormal_kappa(3, 7, 0.1, 1)).cuda()
+    f = torch.zeros((1, 129, 129, 129), dtype=torch.float64, device="cuda")
+    f[:, 1:-1, 1:-1, 1:-1] = 1.0
+    with Solver(3, 7, op="diffusion", kappa=kap, bits=16) as s:
+        ms, u = _time_solves(s, f, 5)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.adjoint(u, u)
+        e1.record()
+        torch.cuda.synchronize()
+    out["diffusion3d_129_b16"] = dict(ms_per_solve=ms, dof_per_s=127 ** 3 / (ms * 1e-3),
+                                      ms_adjoint_and_gradient=e0.elapsed_time(e1))
+    kap = synthetic.lognormal_kappa_torch(3, 9, 0.05, 4, device="cuda")
+    f = torch.stack([synthetic.smoothed_noise_rhs_torch(3, 9, sd, device="cuda") for sd in range(100, 108)])
+    with Solver(3, 9, op="diffusion", kappa=kap, batch=8, bits=16) as s:
+        ms, u = _time_solves(s, f, 2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.adjoint(u, u)
+        e1.record()
+        torch.cuda.synchronize()
+    out["diffusion3d_513x8_b16"] = dict(ms_per_solve=ms, dof_per_s=8 * 511 ** 3 / (ms * 1e-3),
+                                        ms_adjoint_and_gradient=e0.elapsed_time(e1),
+                                        note="diffusion runs the per-operation kernels (no fused path)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +175,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 FMG comparison")
     ap.add_argument("--cpu-L", type=int, default=8)
     ap.add_argument("--no-sweep", action="store_true", help="skip the 8/12-bit and tuned-width runs")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the timings of the other workloads")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for counter runs: one warm-up solve, a calibration copy of 1 GiB, one solve; no JSON")
     args = ap.parse_args()
@@ -246,6 +307,10 @@ def main():
         sweep["tuned"] = solve_rate(tuned, min(args.steps, 3))
         sweep["tuned"]["tuning_s"] = tune_s
 
+    others = None
+    if not args.no_workloads:
+        others = other_workloads()
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU baseline: oracle at {(1 << args.cpu_L) + 1}^3")
@@ -281,6 +346,7 @@ def main():
                     for r in per_kernel[:12]],
         "plain_fp64": plain,
         "width_sweep": sweep,
+        "other_workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

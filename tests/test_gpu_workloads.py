@@ -89,3 +89,34 @@ def test_diffusion3d_513x8_batch(cmg):
         ep = float(torch.linalg.vector_norm(up[b] - ref[b]) / nr)
         print(f"rhs {b}: relative L2 error vs converged: compact {ec:.3e}, plain float64 FMG {ep:.3e}", flush=True)
         assert ec <= 1.05 * ep, (b, ec, ep)
+
+
+@pytest.mark.slow
+def test_poisson3d_1025_headline_configuration(cmg):
+    """The benchmark's own configuration (1025^3, hashed 1e-4 noise, b = 16,
+    B = 64, N = 2, FP32 V-cycle): the solution meets the acceptance test
+    against the closed-form discrete solution of the sine part (the noise
+    moves it by ~1e-10 relative) and the solver state stays below 13 bytes
+    per DoF, a quarter of what plain FP64 multigrid allocates."""
+    import math
+    L = 10
+    f = S.hash_noise_rhs_torch(3, L, amp=1e-4, seed=3, device="cuda")[None].contiguous()
+    with cmg.Solver(3, L, smoother="rbgs", bfp_block=64, bits=16, ir_iters=2, vcycle_prec="fp32") as s:
+        u = s.solve(f)
+        mem = s.memory_stats()
+    h = 2.0 ** -L
+    N = (1 << L) + 1
+    x = torch.arange(N, dtype=torch.float64, device="cuda") * h
+    sn = torch.sin(math.pi * x)
+    sn[0] = 0.0
+    sn[-1] = 0.0
+    ch = ((math.pi * h / 2) / math.sin(math.pi * h / 2)) ** 2
+    err2 = dev2 = disc2 = 0.0
+    for k in range(N):
+        us = sn[k] * (sn[:, None] * sn[None, :])
+        err2 += float(((u[0, k] - us) ** 2).sum())
+        dev2 += float(((u[0, k] - ch * us) ** 2).sum())
+        disc2 += float((((ch - 1.0) * us) ** 2).sum())
+    assert math.sqrt(err2 / disc2) <= 2.0
+    assert math.sqrt(dev2 / disc2) <= 0.5
+    assert mem["total"] / 1023 ** 3 < 13.0
