@@ -1171,7 +1171,7 @@ static double sec_b(const SecRef& s) {
     if (g_timing != nullptr) g_timing->end(stream);                                       \
   } while (0)
 
-constexpr int kDownTY = 16, kUpTY = 16, kResTY = 32, kRRCTY = 8, kDownNT = 448, kUpNT = 896, kResNT = 512,
+constexpr int kDownTY = 32, kUpTY = 32, kResTY = 32, kRRCTY = 8, kDownNT = 704, kUpNT = 768, kResNT = 512,
               kRRNT = 512, kDecTY = 8;
 
 static PSec psec(const SecRef& s, const Geom& g) {
