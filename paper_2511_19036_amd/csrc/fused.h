@@ -31,4 +31,9 @@ bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int L
 bool fused_decode_full(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* full,
                        hipStream_t st);
 
+// One decode-chain step u_l = dec u'_l + P u_{l-1} in the padded layout
+// (3-D levels of at least 64^3 nodes).
+bool fused_decode_level(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* out,
+                        hipStream_t st);
+
 }  // namespace cmg

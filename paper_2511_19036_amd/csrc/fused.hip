@@ -1064,7 +1064,9 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
 // tile, coarse planes come through a ring in LDS, and every plane is
 // written as whole rows.  Tiles at the far x / y edges also write the
 // boundary column / row at node 2^l; the last chunk writes plane 2^l.
-template <int TY, int LB>
+// PAD: write the padded level layout (2^l per axis) instead, as one step of
+// the decode chain u_l = dec u'_l + P u_{l-1}.
+template <int TY, int LB, bool PAD>
 __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* __restrict__ uc, int level,
                                                          int levelc, int TZ, double* __restrict__ full) {
   constexpr int NT = 64 * TY;
@@ -1078,7 +1080,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
   int X0 = bx * kTX, Y0 = by * TY;
   const int Z0 = bz * TZ;
   const int n = 1 << level, nc = 1 << levelc;
-  const uint64_t N = static_cast<uint64_t>(n) + 1;
+  const uint64_t N = static_cast<uint64_t>(n) + (PAD ? 0 : 1);
   const int CX0 = X0 >> 1, CY0 = Y0 >> 1;
   double cpf[CPT];
   RawCode upre;
@@ -1123,8 +1125,8 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     const double v = raw_f64(r, xy_own(), U.cbits, U.w) + prolong_node<double, KP, CW>(c0, c1, ci, lane & 1, wv & 1);
     double* row = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(Y0 + wv)) * N;
     row[X0 + lane] = v;
-    if (X0 + kTX == n && lane == 63) row[n] = 0.0;
-    if (Y0 + TY == n && wv == TY - 1) {
+    if (!PAD && X0 + kTX == n && lane == 63) row[n] = 0.0;
+    if (!PAD && Y0 + TY == n && wv == TY - 1) {
       double* last = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(n)) * N;
       last[X0 + lane] = 0.0;
       if (X0 + kTX == n && lane == 63) last[n] = 0.0;
@@ -1141,7 +1143,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     step(std::integral_constant<int, 0>(), k);
     step(std::integral_constant<int, 1>(), k + 1);
   }
-  if (Z0 + TZ == n) {  // plane 2^l
+  if (!PAD && Z0 + TZ == n) {  // plane 2^l
     double* plane = full + static_cast<uint64_t>(n) * N * N;
     plane[static_cast<uint64_t>(Y0 + wv) * N + X0 + lane] = 0.0;
     if (X0 + kTX == n && lane == 63) plane[static_cast<uint64_t>(Y0 + wv) * N + n] = 0.0;
@@ -1289,11 +1291,27 @@ bool fused_decode_full(const SecRef& U, const double* uc, const Geom& g, const G
   const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDecTY), 16);
   const dim3 grid((g.n / kTX) * (g.n / kDecTY) * (g.n / tz)), block(64 * kDecTY);
   if (U.B == 64)
-    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, 6>), grid, block, st, pu, uc, g.level, gc.level, tz,
-                full);
+    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, 6, false>), grid, block, st, pu, uc, g.level, gc.level,
+                tz, full);
   else
-    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, 5>), grid, block, st, pu, uc, g.level, gc.level, tz,
-                full);
+    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, 5, false>), grid, block, st, pu, uc, g.level, gc.level,
+                tz, full);
+  return true;
+}
+
+bool fused_decode_level(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* out,
+                        hipStream_t st) {
+  if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64)) return false;
+  const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size;
+  const PSec pu = psec(U, g);
+  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDecTY), 16);
+  const dim3 grid((g.n / kTX) * (g.n / kDecTY) * (g.n / tz)), block(64 * kDecTY);
+  if (U.B == 64)
+    CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, 6, true>), grid, block, st, pu, uc, g.level,
+                gc.level, tz, out);
+  else
+    CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, 5, true>), grid, block, st, pu, uc, g.level,
+                gc.level, tz, out);
   return true;
 }
 

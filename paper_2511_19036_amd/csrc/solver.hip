@@ -424,7 +424,8 @@ void decode_chain(cmg_ctx c, int top) {
   const int lc = c->lc();
   launch_decode<double>(c->lv[lc].U.ref(), c->lv[lc].g.size, c->lv[lc].uh, c->st);
   for (int l = lc + 1; l <= top; ++l)
-    launch_prolong_add_dec(c->lv[l].U.ref(), c->lv[l - 1].uh, c->lv[l].g, c->lv[l - 1].g, c->lv[l].uh, c->st);
+    if (!fused_decode_level(c->lv[l].U.ref(), c->lv[l - 1].uh, c->lv[l].g, c->lv[l - 1].g, c->lv[l].uh, c->st))
+      launch_prolong_add_dec(c->lv[l].U.ref(), c->lv[l - 1].uh, c->lv[l].g, c->lv[l - 1].g, c->lv[l].uh, c->st);
   KCK();
 }
 
