@@ -65,19 +65,14 @@ __global__ void __launch_bounds__(kThreads) k_widen(SecRef s, int k) {
   store_code(s, t, load_code(s, t) * (static_cast<int64_t>(1) << k));
 }
 
+// Codes of a whole section set to zero with 16-byte stores (every block holds
+// a multiple of 16 bytes: B >= 32 values of >= 8 bits); exponents to the
+// all-zero sentinel.
 __global__ void __launch_bounds__(kThreads) k_zero_section(SecRef s) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   const int64_t nb = (s.n + s.B - 1) / s.B;
   const int64_t bytes = nb * s.B * s.cbits / 8;
-  if (t < (bytes + 3) / 4) {
-    const int64_t off = 4 * t;
-    uint8_t* b = static_cast<uint8_t*>(s.codes);
-    if (off + 4 <= bytes) {
-      *reinterpret_cast<uint32_t*>(b + off) = 0u;
-    } else {
-      for (int64_t q = off; q < bytes; ++q) b[q] = 0;
-    }
-  }
+  if (t < bytes / 16) reinterpret_cast<uint4*>(s.codes)[t] = make_uint4(0u, 0u, 0u, 0u);
   if (t < nb) s.exps[t] = kZeroExp;
 }
 
@@ -403,8 +398,8 @@ void launch_widen(const SecRef& s, int k, hipStream_t st) {
 }
 void launch_zero_section(const SecRef& s, hipStream_t st) {
   const int64_t nb = (s.n + s.B - 1) / s.B;
-  const int64_t words = (nb * s.B * s.cbits / 8 + 3) / 4;
-  CMG_TLAUNCH("k_zero_section", sec_bytes(s), k_zero_section, words > nb ? words : nb, st, s);
+  const int64_t quads = nb * s.B * s.cbits / 8 / 16;
+  CMG_TLAUNCH("k_zero_section", sec_bytes(s), k_zero_section, quads > nb ? quads : nb, st, s);
 }
 void launch_correct(const SecRef& u, const SecRef& y, hipStream_t st) {
   const int64_t limit = ((u.n + u.B - 1) / u.B) * u.B;
