@@ -125,7 +125,10 @@ template <int H, int TY, int NT>
 struct ColTile {
   static constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H;
   static constexpr int PW = EXW / 2, NPAIR = PW * EXH, K = (NPAIR + NT - 1) / NT;
-  static constexpr int LPL = EXW * EXH, PS = LPL + 2, PAD = EXW + 2;  // plane, its stride, margin
+  // plane, its stride (two spare words), margin: the neighbour reads of a
+  // missing pair (whose slot is past NPAIR and which works on the spare
+  // words) stay inside the LDS array
+  static constexpr int LPL = EXW * EXH, PS = LPL + 2, PAD = EXW + 2;
   static constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;          // output rows per wave
 };
 
@@ -182,21 +185,35 @@ __device__ __forceinline__ void col_setup(int tid, int X0, int Y0, int level, in
 }
 
 // Quantise the output rows of plane po (tile values in `ob`) into section S.
+// The rows of a wave are quantised in one straight-line block (a wave with
+// fewer than RPW rows repeats its first row, unstored), then stored.
 template <int LB, int TY, int NT>
 __device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, int po, int X0, int Y0, int level,
                                               int tid) {
   constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;
   const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const PlanePtr pq = plane_of(S, po);
+  int m[RPW], e[RPW];
+#pragma unroll
+  for (int t = 0; t < RPW; ++t) {
+    const int rr0 = out_row<NW>(wv, t);
+    const int rr = rr0 < TY ? rr0 : out_row<NW>(wv, 0);
+    m[t] = quant_f32<LB>(ob[rr * kTX + lane], S.w, lane, &e[t]);
+  }
 #pragma unroll
   for (int t = 0; t < RPW; ++t) {
     const int rr = out_row<NW>(wv, t);
     if (rr >= TY) continue;
-    const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
-    int e;
-    const int m = quant_f32<LB>(ob[rr * kTX + lane], S.w, lane, &e);
-    store_row(pq.c, xyr, lane, m, S.cbits);
-    if ((lane & ((1 << LB) - 1)) == 0) pq.e[(xyr + lane) >> LB] = static_cast<int16_t>(e);
+    store_row(pq.c, (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0), lane, m[t], S.cbits);
+  }
+  if ((lane & ((1 << LB) - 1)) == 0) {
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+      const int rr = out_row<NW>(wv, t);
+      if (rr >= TY) continue;
+      const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
+      pq.e[(xyr + lane) >> LB] = static_cast<int16_t>(e[t]);
+    }
   }
 }
 
@@ -222,8 +239,6 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
   uint32_t xy[K][2];
   unsigned fl[K];
   col_setup<H, TY, NT>(tid, X0, Y0, level, pos, xy, fl, oidx);
-  const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
-  auto wave_has = [&](int k) { return k * NT + wbase < T::NPAIR; };
   auto launder = [&]() {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -247,20 +262,14 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
 #pragma unroll
       for (int i = 0; i < S + 1; ++i) r[k][c][i] = 0.0f;
     }
+  // Codes of plane p.  Unconditional: a plane outside the level reads
+  // plane 1, and its right-hand side is zeroed where it enters.
   auto fetch = [&](int p) {
-    if (p >= 1 && p < n) {
-      const PlanePtr gq = plane_of(G, p);
+    const PlanePtr gq = plane_of(G, min(max(p, 1), n - 1));
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (wave_has(k))
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-          for (int c = 0; c < 2; ++c) gpre[k][c] = raw_at<LB, HI>(gq, xy[k][c], G.cbits);
-    } else {
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) gpre[k][c] = raw_none();
-    }
+      for (int c = 0; c < 2; ++c) gpre[k][c] = raw_at<LB, HI>(gq, xy[k][c], G.cbits);
   };
 
   auto step = [&](auto jpc, const int j) {
@@ -272,12 +281,12 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
       if (po >= Z0 && po < Z0 + TZ) quantise_rows<LB, TY, NT>(outb[1 - JP], Y, po, X0, Y0, level, tid);
     }
     // plane j enters: y = 0, rhs from the prefetched codes
+    const bool jin = j >= 1 && j < n;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (!wave_has(k)) continue;
       const bool sw = (fl[k] >> kSwap) & 1u;
-      const float g0 = raw_f32(gpre[k][0], xy[k][0], G.cbits, G.w);
-      const float g1 = raw_f32(gpre[k][1], xy[k][1], G.cbits, G.w);
+      const float g0 = jin ? raw_f32(gpre[k][0], xy[k][0], G.cbits, G.w) : 0.0f;
+      const float g1 = jin ? raw_f32(gpre[k][1], xy[k][1], G.cbits, G.w) : 0.0f;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
 #pragma unroll
@@ -290,15 +299,34 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
       r[k][1][S] = sw ? g0 : g1;
     }
     fetch(j + 1);
-#pragma unroll
-    for (int s = 1; s <= S; ++s) {
+    // Stage s on plane j - s.  The in-plane neighbours of stage s + 1 are
+    // loaded before stage s stores (they are the other colour of another
+    // plane), so the loads overlap the arithmetic.  Stages run on every
+    // plane of the march: a plane outside the dependence cone of the
+    // chunk's output planes is never read by a plane inside it.
+    float nb[2][K][4];
+    auto load_stage = [&](int s, float (&d)[K][4]) {
       const int p = j - s;
-      if (p < max(1, Z0 - (S - s)) || p > min(n - 1, Z0 + TZ + (S - s) - 1)) continue;
-      const int iy = S + 1 - s;
-      float* yb = lds + PAD + (p % NB) * PS;
+      const float* yb = lds + PAD + ((p + 4 * NB) % NB) * PS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (!wave_has(k)) continue;
+        const unsigned sw = (fl[k] >> kSwap) & 1u;
+        const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
+        d[k][0] = yb[pa - 1];
+        d[k][1] = yb[pa + 1];
+        d[k][2] = yb[pa - EXW];
+        d[k][3] = yb[pa + EXW];
+      }
+    };
+#pragma unroll
+    for (int s = 1; s <= S; ++s) {
+      if (s < S) load_stage(s + 1, nb[s & 1]);
+      const int p = j - s;
+      const bool act = p >= 1 && p < n;
+      const int iy = S + 1 - s;
+      float* yb = lds + PAD + ((p + 4 * NB) % NB) * PS;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
         const unsigned sw = (fl[k] >> kSwap) & 1u;
         const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
         const float yc = y[k][SG][iy];
@@ -307,18 +335,19 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
         if (s == 1) {
           v = cp * rhs;
         } else {
+          const float* d = nb[(s - 1) & 1][k];
           float a = 6.0f * yc;
-          a = a - yb[pa - 1];
-          a = a - yb[pa + 1];
-          a = a - yb[pa - EXW];
-          a = a - yb[pa + EXW];
+          a = a - d[0];
+          a = a - d[1];
+          a = a - d[2];
+          a = a - d[3];
           a = a - y[k][SG][iy - 1];
           a = a - y[k][SG][iy + 1];
           a = a * ih2;
           const float rr = rhs - a;
           v = yc + cp * rr;
         }
-        const float yv = ((fl[k] >> (kInnerSlot + SG)) & 1u) ? v : yc;
+        const float yv = (act && ((fl[k] >> (kInnerSlot + SG)) & 1u)) ? v : yc;
         y[k][SG][iy] = yv;
         if (s < S) yb[pa] = yv;
       }
@@ -428,8 +457,6 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     const int ly = q < T::NPAIR ? q / T::PW : 0, lx0 = q < T::NPAIR ? 2 * (q - ly * T::PW) : 0;
     cb[k] = (((Y0 - H + ly) >> 1) - CY0) * CW + (((X0 - H + lx0) >> 1) - CX0);
   }
-  const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
-  auto wave_has = [&](int k) { return k * NT + wbase < T::NPAIR; };
   auto launder = [&]() {
     opaque(lane);
     opaque_s(wv);
@@ -475,9 +502,11 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const int t = tid + k * NT;
       const int cy = t / CW, cx = t - cy * CW;
       const int gx = CX0 + cx, gy = CY0 + cy;
-      cpf[k] = 0.0f;
-      if (zin && t < CPL && gx >= 0 && gx < nc && gy >= 0 && gy < nc)
-        cpf[k] = src[(static_cast<uint32_t>(gy) << levelc) | static_cast<uint32_t>(gx)];
+      const bool in = zin && t < CPL && gx >= 0 && gx < nc && gy >= 0 && gy < nc;
+      // every lane loads (a node of the level); the value is selected
+      const float v = src[(static_cast<uint32_t>(min(max(gy, 0), nc - 1)) << levelc) |
+                          static_cast<uint32_t>(min(max(gx, 0), nc - 1))];
+      cpf[k] = in ? v : 0.0f;
     }
   };
   auto cstore = [&](int cz) {
@@ -488,62 +517,93 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       if (t < CPL) dst[t] = cpf[k];
     }
   };
-  auto fetch_gy = [&](int p) {  // codes of plane p for the own columns
-    if (p >= 1 && p < n) {
-      const PlanePtr gq = plane_of(G, p), yq = plane_of(Y, p);
+  // Codes of plane p for the own columns.  Unconditional: a plane outside
+  // the level reads plane 1, and the right-hand side part zeroes its values.
+  auto fetch_gy = [&](int p) {
+    const int pc = min(max(p, 1), n - 1);
+    const PlanePtr gq = plane_of(G, pc), yq = plane_of(Y, pc);
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (wave_has(k))
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            gpre[k][c] = raw_at<LB, HI>(gq, xy[k][c], G.cbits);
-            ypre[k][c] = raw_at<LB, HI>(yq, xy[k][c], Y.cbits);
-          }
-    } else {
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          gpre[k][c] = raw_none();
-          ypre[k][c] = raw_none();
+      for (int c = 0; c < 2; ++c) {
+        if (HI) {
+          gpre[k][c] = raw_at<LB, HI>(gq, xy[k][c], G.cbits);
+          ypre[k][c] = raw_at<LB, HI>(yq, xy[k][c], Y.cbits);
+        } else if (c == 0) {
+          gpre[k][0] = pair_at<LB>(gq, xy[k][0], G.cbits);
+          ypre[k][0] = pair_at<LB>(yq, xy[k][0], Y.cbits);
         }
-    }
+      }
   };
-  auto fetch_u = [&](int po) {  // codes of the output rows of plane po
-    if (po < Z0 || po >= Z0 + TZ) return;
-    const PlanePtr uq = plane_of(U, po);
+  // Rows of a wave: out_row(wv, t) for t < RPW; a wave with fewer than RPW
+  // rows repeats its first row in the missing slots (computed, not stored),
+  // so that the quantisation of all its rows is one straight-line block.
+  auto row_of = [&](int t) {
+    const int rr = out_row<NW>(wv, t);
+    return rr < TY ? rr : out_row<NW>(wv, 0);
+  };
+  // Codes of the output rows of plane po.  Unconditional (a plane outside
+  // the chunk reads a chunk plane, unused): the loads are only waited for at
+  // the next step, after the stores issued before them.
+  auto fetch_u = [&](int po) {
+    const PlanePtr uq = plane_of(U, min(max(po, Z0), Z0 + TZ - 1));
 #pragma unroll
-    for (int t = 0; t < RPW; ++t) {
-      const int rr = out_row<NW>(wv, t);
-      if (rr < TY) upre[t] = raw_at<LB>(uq, ((static_cast<uint32_t>(Y0 + rr) << level) | X0) + lane, U.cbits);
-    }
+    for (int t = 0; t < RPW; ++t)
+      upre[t] = raw_at<LB, HI>(uq, ((static_cast<uint32_t>(Y0 + row_of(t)) << level) | X0) + lane, U.cbits);
   };
-  auto finish = [&](auto pkc, int po, const float* ob) {  // quantise y', correct u', write e
+  // Output plane po: quantise y' (Yp), correct u' (float64), e = dec Yp + z.
+  // The arithmetic of all rows of the wave is one straight-line block
+  // (finish_compute); the stores follow in finish_store, issued after the
+  // loads of the step so that no wait for those loads includes them.
+  struct Fin {
+    int my[RPW], ey[RPW], eu[RPW];
+    int64_t mu[RPW];
+    float ev[RPW];
+  };
+  auto finish_compute = [&](auto pkc, int po, const float* ob, Fin& F) {
     constexpr int PK = decltype(pkc)::value;
     if (po < Z0 || po >= Z0 + TZ) return;
-    const PlanePtr yq = plane_of(Yp, po), uq = plane_of(U, po);
     const float* c0 = cs + ((po >> 1) & (NC - 1)) * CPL;
     const float* c1 = cs + (((po >> 1) + 1) & (NC - 1)) * CPL;
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+      const int rr = row_of(t);
+      const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
+      F.my[t] = quant_f32<LB>(ob[rr * kTX + lane], Yp.w, lane, &F.ey[t]);
+      const double dy = F.ey[t] == kZeroExp ? 0.0 : ldexp(static_cast<double>(F.my[t]), F.ey[t] - (Yp.w - 1));
+      const double vu = raw_f64(upre[t], xyl, U.cbits, U.w) + dy;
+      F.mu[t] = quant_f64<LB>(vu, U.w, lane, &F.eu[t]);
+      F.ev[t] = static_cast<float>(dy);
+    }
+    if (eout != nullptr) {
+#pragma unroll
+      for (int t = 0; t < RPW; ++t) {
+        const int rr = row_of(t);
+        const int ci = ((rr >> 1) + H / 2) * CW + (lane >> 1) + H / 2;
+        F.ev[t] = F.ev[t] + prolong_node<float, PK, CW>(c0, c1, ci, lane & 1, rr & 1);
+      }
+    }
+  };
+  auto finish_store = [&](int po, const Fin& F) {
+    if (po < Z0 || po >= Z0 + TZ) return;
+    const PlanePtr yq = plane_of(Yp, po), uq = plane_of(U, po);
 #pragma unroll
     for (int t = 0; t < RPW; ++t) {
       const int rr = out_row<NW>(wv, t);
       if (rr >= TY) continue;
       const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
-      const uint32_t xyl = xyr + lane;
-      int ey;
-      const int my = quant_f32<LB>(ob[rr * kTX + lane], Yp.w, lane, &ey);
-      store_row(yq.c, xyr, lane, my, Yp.cbits);
-      if ((lane & ((1 << LB) - 1)) == 0) yq.e[xyl >> LB] = static_cast<int16_t>(ey);
-      const double dy = ey == kZeroExp ? 0.0 : ldexp(static_cast<double>(my), ey - (Yp.w - 1));
-      const double vu = raw_f64(upre[t], xyl, U.cbits, U.w) + dy;
-      int eu;
-      const int64_t mu = quant_f64<LB>(vu, U.w, lane, &eu);
-      store_row(uq.c, xyr, lane, mu, U.cbits);
-      if ((lane & ((1 << LB) - 1)) == 0) uq.e[xyl >> LB] = static_cast<int16_t>(eu);
-      if (eout != nullptr) {
-        const int ci = ((rr >> 1) + H / 2) * CW + (lane >> 1) + H / 2;
-        const float zz = prolong_node<float, PK, CW>(c0, c1, ci, lane & 1, rr & 1);
-        eout[(static_cast<uint64_t>(po) << (2 * level)) + xyl] = static_cast<float>(dy) + zz;
+      store_row(yq.c, xyr, lane, F.my[t], Yp.cbits);
+      store_row(uq.c, xyr, lane, F.mu[t], U.cbits);
+      if (eout != nullptr) eout[(static_cast<uint64_t>(po) << (2 * level)) + xyr + lane] = F.ev[t];
+    }
+    if ((lane & ((1 << LB) - 1)) == 0) {
+#pragma unroll
+      for (int t = 0; t < RPW; ++t) {
+        const int rr = out_row<NW>(wv, t);
+        if (rr >= TY) continue;
+        const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
+        yq.e[xyl >> LB] = static_cast<int16_t>(F.ey[t]);
+        uq.e[xyl >> LB] = static_cast<int16_t>(F.eu[t]);
       }
     }
   };
@@ -552,16 +612,19 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     constexpr int JP = decltype(jpc)::value;
     constexpr int SG = JP;  // slot updated by every stage at this step
     launder();
-    finish(jpc, j - 2 - S, outb[1 - JP]);
-    fetch_u(j - 1 - S);
-    if (JP == 0) cfetch((j + 2) >> 1);  // z(j + 1) needs coarse plane (j + 2) / 2
+    {
+      Fin F;
+      finish_compute(jpc, j - 2 - S, outb[1 - JP], F);
+      fetch_u(j - 1 - S);
+      if (JP == 1) cfetch((j + 3) >> 1);  // stored at the next step: z(j + 2) needs coarse plane (j + 3) / 2
+      finish_store(j - 2 - S, F);
+    }
     {  // z of plane j
       const float* c0 = cs + ((j >> 1) & (NC - 1)) * CPL;
       const float* c1 = cs + (((j >> 1) + 1) & (NC - 1)) * CPL;
       float* zb = lds + PAD + JP * PS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (!wave_has(k)) continue;
         const bool py = (fl[k] >> kOddY) & 1u;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -579,7 +642,6 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       float* yb = lds + PAD + (2 + (p + 4 * NB) % NB) * PS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (!wave_has(k)) continue;
         float rv[2], yv[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -593,8 +655,10 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
           a = a - z[k][c][2];
           a = a * ih2;
           const bool keep = pin && ((fl[k] >> (kInnerCol + c)) & 1u);
-          const float gv = raw_f32(gpre[k][c], xy[k][c], G.cbits, G.w) - a;
-          const float y0 = raw_f32(ypre[k][c], xy[k][c], Y.cbits, Y.w);
+          const float gv = (HI ? raw_f32(gpre[k][c], xy[k][c], G.cbits, G.w)
+                               : pair_f32(gpre[k][0], xy[k][0], c, G.cbits, G.w)) - a;
+          const float y0 = HI ? raw_f32(ypre[k][c], xy[k][c], Y.cbits, Y.w)
+                              : pair_f32(ypre[k][0], xy[k][0], c, Y.cbits, Y.w);
           rv[c] = keep ? gv : 0.0f;
           yv[c] = keep ? y0 : 0.0f;
           yb[pc] = yv[c];
@@ -614,29 +678,53 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       }
       fetch_gy(j);
     }
-#pragma unroll
-    for (int s = 1; s <= S; ++s) {  // post-smoothing: stage s on plane j - 1 - s
+    // Post-smoothing: stage s on plane j - 1 - s.  The in-plane neighbours
+    // of stage s + 1 are loaded before stage s stores (they are the other
+    // colour of another plane), so the loads overlap the arithmetic.  As in
+    // the down sweep, stages run on every plane of the march.
+    auto active = [&](int s) {
       const int p = j - 1 - s;
-      if (p < max(1, Z0 - (S - s)) || p > min(n - 1, Z0 + TZ + (S - s) - 1)) continue;
-      const int iy = S + 1 - s;
-      float* yb = lds + PAD + (2 + p % NB) * PS;
+      return p >= 1 && p < n;
+    };
+    float nb[2][K][4];
+    auto load_stage = [&](int s, float (&d)[K][4]) {
+      const int p = j - 1 - s;
+      const float* yb = lds + PAD + (2 + (p + 4 * NB) % NB) * PS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (!wave_has(k)) continue;
+        const unsigned sw = (fl[k] >> kSwap) & 1u;
+        const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
+        d[k][0] = yb[pa - 1];
+        d[k][1] = yb[pa + 1];
+        d[k][2] = yb[pa - EXW];
+        d[k][3] = yb[pa + EXW];
+      }
+    };
+    load_stage(1, nb[0]);
+#pragma unroll
+    for (int s = 1; s <= S; ++s) {
+      if (s < S) load_stage(s + 1, nb[s & 1]);
+      const bool act = active(s);
+      const int p = j - 1 - s;
+      const int iy = S + 1 - s;
+      float* yb = lds + PAD + (2 + (p + 4 * NB) % NB) * PS;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
         const unsigned sw = (fl[k] >> kSwap) & 1u;
         const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
         const float yc = y[k][SG][iy];
+        const float* d = nb[(s - 1) & 1][k];
         float a = 6.0f * yc;
-        a = a - yb[pa - 1];
-        a = a - yb[pa + 1];
-        a = a - yb[pa - EXW];
-        a = a - yb[pa + EXW];
+        a = a - d[0];
+        a = a - d[1];
+        a = a - d[2];
+        a = a - d[3];
         a = a - y[k][SG][iy - 1];
         a = a - y[k][SG][iy + 1];
         a = a * ih2;
         const float rr = r[k][SG][S - s] - a;
         const float v = yc + cp * rr;
-        const float yv = ((fl[k] >> (kInnerSlot + SG)) & 1u) ? v : yc;
+        const float yv = (act && ((fl[k] >> (kInnerSlot + SG)) & 1u)) ? v : yc;
         y[k][SG][iy] = yv;
         if (s < S) yb[pa] = yv;
       }
@@ -660,6 +748,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   const int jbeg = Z0 - S, jend = Z0 + TZ + S + 2;  // an even number of steps
   cfetch(jbeg >> 1);
   cstore(jbeg >> 1);
+  cfetch((jbeg + 2) >> 1);
   fetch_gy(jbeg - 1);
   __syncthreads();
 #pragma unroll 1
@@ -720,9 +809,8 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
     xy[k] = dom ? ((static_cast<uint32_t>(gy) << level) | static_cast<uint32_t>(gx)) : 0u;
     fl[k] = (dom ? 1u : 0u) | (tcol ? 2u : 0u) | (inner ? 4u : 0u);
   }
-  const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
-  auto wave_has = [&](int k) { return k * NT + wbase < NCOL; };
-
+  // Every column slot computes: a slot past NCOL works on the spare words
+  // (plane offset 0 for its loads), so that no load sits under a branch.
   float yr[K][3];  // y' of planes s-2 .. s
   RawCode ypre[K], gpre[K];
   float sc[CRW];   // running coarse sums
@@ -730,27 +818,17 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
   for (int k = 0; k < K; ++k) yr[k][0] = yr[k][1] = yr[k][2] = 0.0f;
 #pragma unroll
   for (int r = 0; r < CRW; ++r) sc[r] = 0.0f;
+  // Codes of plane p (a plane outside the level reads a level plane; the
+  // stages zero the values of planes outside it).
   auto fetch_y = [&](int p) {
-    if (p >= 0 && p < n) {
-      const PlanePtr yq = plane_of(Y, p);
+    const PlanePtr yq = plane_of(Y, min(max(p, 0), n - 1));
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (wave_has(k)) ypre[k] = raw_at<LB, HI>(yq, xy[k], Y.cbits);
-    } else {
-#pragma unroll
-      for (int k = 0; k < K; ++k) ypre[k] = raw_none();
-    }
+    for (int k = 0; k < K; ++k) ypre[k] = raw_at<LB, HI>(yq, xy[k], Y.cbits);
   };
   auto fetch_g = [&](int p) {
-    if (p >= 1 && p < n) {
-      const PlanePtr gq = plane_of(G, p);
+    const PlanePtr gq = plane_of(G, min(max(p, 1), n - 1));
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (wave_has(k)) gpre[k] = raw_at<LB, HI>(gq, xy[k], G.cbits);
-    } else {
-#pragma unroll
-      for (int k = 0; k < K; ++k) gpre[k] = raw_none();
-    }
+    for (int k = 0; k < K; ++k) gpre[k] = raw_at<LB, HI>(gq, xy[k], G.cbits);
   };
 
   auto step = [&](auto spc, const int s) {
@@ -774,7 +852,6 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
       float* yb = yl + YPAD + ((s + 3) % 3) * YPS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (!wave_has(k)) continue;
         yr[k][0] = yr[k][1];
         yr[k][1] = yr[k][2];
         const float v = raw_f32(ypre[k], xy[k], Y.cbits, Y.w);
@@ -789,7 +866,6 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
       float* tb = tl + ((p + 2) & 1) * TPS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (!wave_has(k)) continue;
         const int c = pos[k];
         float a = 6.0f * yr[k][1];
         a = a - ya[c - 1];
@@ -872,7 +948,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
 // also decode one node of the one-node x-y halo.  Every plane of u goes
 // through a ring of three LDS planes, so that a single barrier per step
 // separates the writes of plane j from the reads of plane j - 2.
-template <int TY, int NT, int LB>
+template <int TY, int NT, int LB, bool HI>
 __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __restrict__ uc,
                                                     const double* __restrict__ f, int Lfull, int level, int levelc,
                                                     double ih2, PSec Gout, int TZ, int* nonfinite, double* sumsq) {
@@ -935,9 +1011,11 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
       const int t = tid + k * NT;
       const int cy = t / CW, cx = t - cy * CW;
       const int gx = CX0 + cx, gy = CY0 + cy;
-      cpf[k] = 0.0;
-      if (zin && t < CPL && gx >= 0 && gx < nc && gy >= 0 && gy < nc)
-        cpf[k] = src[(static_cast<uint32_t>(gy) << levelc) | static_cast<uint32_t>(gx)];
+      const bool in = zin && t < CPL && gx >= 0 && gx < nc && gy >= 0 && gy < nc;
+      // every lane loads (a node of the level); the value is selected
+      const double v = src[(static_cast<uint32_t>(min(max(gy, 0), nc - 1)) << levelc) |
+                           static_cast<uint32_t>(min(max(gx, 0), nc - 1))];
+      cpf[k] = in ? v : 0.0;
     }
   };
   auto cstore = [&](int cz) {
@@ -948,27 +1026,26 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
       if (t < CPL) dst[t] = cpf[k];
     }
   };
+  // The loads below are unconditional (a plane outside the level reads a
+  // level plane, a halo node outside it reads node 0, f on the boundary is
+  // read and replaced): a load under a branch makes the compiler wait for
+  // it, and for every memory operation issued before it, where the
+  // branches join.  The consumers zero what lies outside.
   auto fetch_u = [&](int p) {
-    if (p >= 0 && p < n) {
-      const PlanePtr uq = plane_of(U, p);
+    const PlanePtr uq = plane_of(U, min(max(p, 0), n - 1));
 #pragma unroll
-      for (int t = 0; t < RPT; ++t) upre[t] = raw_at<LB>(uq, xy_own(t), U.cbits);
-      hpre = hdom ? raw_at<LB>(uq, xyh, U.cbits) : raw_none();
-    } else {
-#pragma unroll
-      for (int t = 0; t < RPT; ++t) upre[t] = raw_none();
-      hpre = raw_none();
-    }
+    for (int t = 0; t < RPT; ++t) upre[t] = raw_at<LB, HI>(uq, xy_own(t), U.cbits);
+    hpre = raw_at<LB, HI>(uq, xyh, U.cbits);
   };
   auto fetch_f = [&](int p) {  // f at the own columns of plane p (0 on the boundary)
     const bool pin = p >= 1 && p < n;
-    const double* fp = f + static_cast<uint64_t>(pin ? p : 0) * fst * N * N;
+    const double* fp = f + static_cast<uint64_t>(min(max(p, 0), n - 1)) * fst * N * N;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
       const int gx = X0 + lane, gy = Y0 + wv + NW * t;
-      fpre[t] = 0.0;
-      if (pin && gx >= 1 && gy >= 1)
-        fpre[t] = fp[static_cast<uint32_t>(gy * fst) * static_cast<uint32_t>(N) + static_cast<uint32_t>(gx * fst)];
+      const double v =
+          fp[static_cast<uint32_t>(gy * fst) * static_cast<uint32_t>(N) + static_cast<uint32_t>(gx * fst)];
+      fpre[t] = (pin && gx >= 1 && gy >= 1) ? v : 0.0;
     }
   };
 
@@ -1014,6 +1091,10 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
     if (p >= Z0 && p < Z0 + TZ) {  // residual on plane p
       const double* ua = us + ((p + 3) % 3) * LPL;
       const PlanePtr gq = plane_of(Gout, p);
+      // all rows are quantised in one straight-line block, then stored
+      double tv[RPT];
+      int64_t m[RPT];
+      int e[RPT];
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
         const int rr = wv + NW * t;
@@ -1027,18 +1108,33 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         a = a - u[t][2];
         a = a * ih2;
         const bool inside = p >= 1 && X0 + lane >= 1 && Y0 + rr >= 1;
-        const double tv = inside ? fpre[t] - a : 0.0;
-        if (nonfinite != nullptr && !isfinite(tv)) atomicOr(nonfinite, 1);
-        if (sumsq != nullptr) {
-          double a2 = tv * tv;
-          for (int off = 32; off > 0; off >>= 1) a2 += __shfl_xor(a2, off, 64);
-          if (lane == 0) atomicAdd(sumsq, a2);
+        tv[t] = inside ? fpre[t] - a : 0.0;
+        m[t] = quant_f64<LB>(tv[t], Gout.w, lane, &e[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const uint32_t xyr = (static_cast<uint32_t>(Y0 + wv + NW * t) << level) | static_cast<uint32_t>(X0);
+        store_row(gq.c, xyr, lane, m[t], Gout.cbits);
+      }
+      if ((lane & ((1 << LB) - 1)) == 0) {
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          const uint32_t xyr = (static_cast<uint32_t>(Y0 + wv + NW * t) << level) | static_cast<uint32_t>(X0);
+          gq.e[(xyr + lane) >> LB] = static_cast<int16_t>(e[t]);
         }
-        const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
-        int e;
-        const int64_t m = quant_f64<LB>(tv, Gout.w, lane, &e);
-        store_row(gq.c, xyr, lane, m, Gout.cbits);
-        if ((lane & ((1 << LB) - 1)) == 0) gq.e[(xyr + lane) >> LB] = static_cast<int16_t>(e);
+      }
+      if (nonfinite != nullptr) {
+        bool bad = false;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) bad = bad || !isfinite(tv[t]);
+        if (bad) atomicOr(nonfinite, 1);
+      }
+      if (sumsq != nullptr) {
+        double a2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) a2 += tv[t] * tv[t];
+        for (int off = 32; off > 0; off >>= 1) a2 += __shfl_xor(a2, off, 64);
+        if (lane == 0) atomicAdd(sumsq, a2);
       }
     }
     fetch_f(j);
@@ -1225,7 +1321,7 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
   const dim3 grid((g.n / kTX) * (g.n / kUpTY) * (g.n / tz)), block(kUpNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Yp) + 2.0 * sec_b(U) + 4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
   const PSec pg = psec(G, g), py = psec(Y, g), pp = psec(Yp, g), pu = psec(U, g);
-  const bool hi = G.cbits == 12 || Y.cbits == 12;
+  const bool hi = G.cbits == 12 || Y.cbits == 12 || U.cbits == 12 || U.cbits == 64;
 #define CMG_UP(S_, LB_, HI_)                                                                                     \
   CMG_FLAUNCH("k_up_smooth<" #S_ ">", bytes, (k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_>), grid, block, st, ec, pg, py, \
               pp, pu, eout, g.level, gc.level, cp, ih2, tz)
@@ -1273,12 +1369,16 @@ bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int L
   const dim3 grid((g.n / kTX) * (g.n / kResTY) * (g.n / tz)), block(kResNT);
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size + sec_b(Gout);
   const PSec pu = psec(U, g), pg = psec(Gout, g);
-  if (U.B == 64)
-    CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, 6>), grid, block, st, pu, uc, f, Lfull, g.level,
-                gc.level, ih2, pg, tz, nonfinite, sumsq);
-  else
-    CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, 5>), grid, block, st, pu, uc, f, Lfull, g.level,
-                gc.level, ih2, pg, tz, nonfinite, sumsq);
+  const bool hi = U.cbits == 12 || U.cbits == 64;
+#define CMG_IR(LB_, HI_)                                                                                           \
+  CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, LB_, HI_>), grid, block, st, pu, uc, f, Lfull, \
+              g.level, gc.level, ih2, pg, tz, nonfinite, sumsq)
+  if (U.B == 64) {
+    if (hi) CMG_IR(6, true); else CMG_IR(6, false);
+  } else {
+    if (hi) CMG_IR(5, true); else CMG_IR(5, false);
+  }
+#undef CMG_IR
   return true;
 }
 

@@ -44,6 +44,9 @@ __device__ __forceinline__ PlanePtr plane_of(const PSec& s, int p) {
 
 // Raw words and block exponent of in-plane value xy (see RawCode).  Sections
 // carry 16 bytes of padding, so the second word is always readable.  With
+// HI = true the second word is always loaded (no branch on the container:
+// a load under a branch makes the compiler wait for it, and for every
+// memory operation issued before it, where the branches join).  With
 // HI = false the caller guarantees an 8-, 16- or 32-bit container, whose
 // codes never straddle two words: the second word is not loaded and the
 // compiler knows it is zero.
@@ -53,9 +56,32 @@ __device__ __forceinline__ RawCode raw_at(const PlanePtr& pp, uint32_t xy, int c
   const uint32_t* wp = reinterpret_cast<const uint32_t*>(pp.c + ((bit >> 5) << 2));
   RawCode r;
   r.lo = wp[0];
-  r.hi = (HI && (cbits == 12 || cbits == 64)) ? wp[1] : 0u;
+  r.hi = HI ? wp[1] : 0u;
   r.e = pp.e[xy >> LB];
   return r;
+}
+
+// Codes of the pair of values xy0, xy0 + 1 (xy0 even) of a plane whose
+// container has at most 32 bits.  Value xy0 starts at bit 0, 8, 16 or 24 of
+// its word, so the two codes lie within that word and the next (one 8-byte
+// load; the padding covers the word after the last), and they share one
+// block exponent (a block holds at least 32 values).
+template <int LB>
+__device__ __forceinline__ RawCode pair_at(const PlanePtr& pp, uint32_t xy0, int cbits) {
+  const uint32_t bit = xy0 * static_cast<uint32_t>(cbits);
+  uint2 v;
+  __builtin_memcpy(&v, pp.c + ((bit >> 5) << 2), 8);
+  return RawCode{v.x, v.y, pp.e[xy0 >> LB]};
+}
+
+// Value c (0 or 1) of a pair read by pair_at, as float (w <= 24).
+__device__ __forceinline__ float pair_f32(const RawCode& r, uint32_t xy0, int c, int cbits, int w) {
+  const uint32_t sh = ((xy0 * static_cast<uint32_t>(cbits)) & 31u) + (c != 0 ? static_cast<uint32_t>(cbits) : 0u);
+  const bool up = sh >= 32u;
+  const uint32_t x = __builtin_amdgcn_alignbit(up ? 0u : r.hi, up ? r.hi : r.lo, sh & 31u);
+  const int m = static_cast<int>(x << (32 - cbits)) >> (32 - cbits);
+  const float v = ldexpf(static_cast<float>(m), r.e - (w - 1));
+  return r.e == kZeroExp ? 0.0f : v;
 }
 
 // Value of a raw code of width w <= 24 (container at most 32 bits) as float:
@@ -69,17 +95,15 @@ __device__ __forceinline__ float raw_f32(const RawCode& r, uint32_t xy, int cbit
   return r.e == kZeroExp ? 0.0f : v;
 }
 
-// Exact value of a raw code of any container as double.
+// Exact value of a raw code of any container as double (branch-free: both
+// the 64-bit and the narrow reading are formed and one is selected).
 __device__ __forceinline__ double raw_f64(const RawCode& r, uint32_t xy, int cbits, int w) {
-  double d;
-  if (cbits == 64) {
-    d = static_cast<double>(static_cast<int64_t>((static_cast<uint64_t>(r.hi) << 32) | r.lo));
-  } else {
-    const uint32_t sh = (xy * static_cast<uint32_t>(cbits)) & 31u;
-    const uint32_t x = __builtin_amdgcn_alignbit(r.hi, r.lo, sh);
-    d = static_cast<double>(static_cast<int>(x << (32 - cbits)) >> (32 - cbits));
-  }
-  const double v = ldexp(d, r.e - (w - 1));
+  const double d64 = static_cast<double>(static_cast<int64_t>((static_cast<uint64_t>(r.hi) << 32) | r.lo));
+  const uint32_t sh = (xy * static_cast<uint32_t>(cbits)) & 31u;
+  const uint32_t x = __builtin_amdgcn_alignbit(r.hi, r.lo, sh);
+  const int sb = cbits == 64 ? 0 : 32 - cbits;
+  const double d32 = static_cast<double>(static_cast<int>(x << sb) >> sb);
+  const double v = ldexp(cbits == 64 ? d64 : d32, r.e - (w - 1));
   return r.e == kZeroExp ? 0.0 : v;
 }
 
