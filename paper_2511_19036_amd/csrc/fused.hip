@@ -276,10 +276,6 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
     constexpr int JP = decltype(jpc)::value;
     constexpr int SG = 1 - JP;  // slot updated by every stage at this step
     launder();
-    {
-      const int po = j - 1 - S;  // completed at the previous step
-      if (po >= Z0 && po < Z0 + TZ) quantise_rows<LB, TY, NT>(outb[1 - JP], Y, po, X0, Y0, level, tid);
-    }
     // plane j enters: y = 0, rhs from the prefetched codes
     const bool jin = j >= 1 && j < n;
 #pragma unroll
@@ -299,6 +295,13 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
       r[k][1][S] = sw ? g0 : g1;
     }
     fetch(j + 1);
+    // The plane completed at the previous step is quantised and stored after
+    // the codes of plane j were used and those of plane j + 1 requested: a
+    // wait for a load does not then include these stores.
+    {
+      const int po = j - 1 - S;
+      if (po >= Z0 && po < Z0 + TZ) quantise_rows<LB, TY, NT>(outb[1 - JP], Y, po, X0, Y0, level, tid);
+    }
     // Stage s on plane j - s.  The in-plane neighbours of stage s + 1 are
     // loaded before stage s stores (they are the other colour of another
     // plane), so the loads overlap the arithmetic.  Stages run on every
@@ -481,7 +484,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   float z[K][2][3];      // column-indexed, planes j-2 .. j
   float r[K][2][S + 1];  // slot-indexed, planes j-1-S .. j-1
   float y[K][2][S + 2];  // slot-indexed, planes j-2-S .. j-1
-  RawCode gpre[K][2], ypre[K][2], upre[RPW];
+  RawCode gpre[K], ypre[K], upre[RPW];
   float cpf[CPT];
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -517,23 +520,18 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       if (t < CPL) dst[t] = cpf[k];
     }
   };
-  // Codes of plane p for the own columns.  Unconditional: a plane outside
-  // the level reads plane 1, and the right-hand side part zeroes its values.
+  // Codes of plane p for the own column pairs (G and Y have containers of
+  // at most 32 bits: widths of at most 24 with the float32 V-cycle).
+  // Unconditional: a plane outside the level reads plane 1, and the
+  // right-hand side part zeroes its values.
   auto fetch_gy = [&](int p) {
     const int pc = min(max(p, 1), n - 1);
     const PlanePtr gq = plane_of(G, pc), yq = plane_of(Y, pc);
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        if (HI) {
-          gpre[k][c] = raw_at<LB, HI>(gq, xy[k][c], G.cbits);
-          ypre[k][c] = raw_at<LB, HI>(yq, xy[k][c], Y.cbits);
-        } else if (c == 0) {
-          gpre[k][0] = pair_at<LB>(gq, xy[k][0], G.cbits);
-          ypre[k][0] = pair_at<LB>(yq, xy[k][0], Y.cbits);
-        }
-      }
+    for (int k = 0; k < K; ++k) {
+      gpre[k] = pair_at<LB>(gq, xy[k][0], G.cbits);
+      ypre[k] = pair_at<LB>(yq, xy[k][0], Y.cbits);
+    }
   };
   // Rows of a wave: out_row(wv, t) for t < RPW; a wave with fewer than RPW
   // rows repeats its first row in the missing slots (computed, not stored),
@@ -655,10 +653,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
           a = a - z[k][c][2];
           a = a * ih2;
           const bool keep = pin && ((fl[k] >> (kInnerCol + c)) & 1u);
-          const float gv = (HI ? raw_f32(gpre[k][c], xy[k][c], G.cbits, G.w)
-                               : pair_f32(gpre[k][0], xy[k][0], c, G.cbits, G.w)) - a;
-          const float y0 = HI ? raw_f32(ypre[k][c], xy[k][c], Y.cbits, Y.w)
-                              : pair_f32(ypre[k][0], xy[k][0], c, Y.cbits, Y.w);
+          const float gv = pair_f32(gpre[k], xy[k][0], c, G.cbits, G.w) - a;
+          const float y0 = pair_f32(ypre[k], xy[k][0], c, Y.cbits, Y.w);
           rv[c] = keep ? gv : 0.0f;
           yv[c] = keep ? y0 : 0.0f;
           yb[pc] = yv[c];
@@ -1321,7 +1317,7 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
   const dim3 grid((g.n / kTX) * (g.n / kUpTY) * (g.n / tz)), block(kUpNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Yp) + 2.0 * sec_b(U) + 4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
   const PSec pg = psec(G, g), py = psec(Y, g), pp = psec(Yp, g), pu = psec(U, g);
-  const bool hi = G.cbits == 12 || Y.cbits == 12 || U.cbits == 12 || U.cbits == 64;
+  const bool hi = U.cbits == 12 || U.cbits == 64;  // the codes of u' may straddle two words
 #define CMG_UP(S_, LB_, HI_)                                                                                     \
   CMG_FLAUNCH("k_up_smooth<" #S_ ">", bytes, (k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_>), grid, block, st, ec, pg, py, \
               pp, pu, eout, g.level, gc.level, cp, ih2, tz)

@@ -183,7 +183,9 @@ __device__ __forceinline__ int64_t quant_f64(double v, int w, int lane, int* e_o
 }
 
 // Store the codes of one row of 64 values (in-plane offset xy0, a multiple
-// of 64) held by the 64 lanes; the 12-bit container is packed by lanes 0..23.
+// of 64) held by the 64 lanes.  In the 12-bit container two values take
+// three bytes: each even lane joins its code with its odd neighbour's (one
+// DPP move) and writes the three bytes as a byte and an aligned short.
 __device__ __forceinline__ void store_row(char* pc, uint32_t xy0, int lane, int64_t m, int cbits) {
   switch (cbits) {
     case 8: reinterpret_cast<int8_t*>(pc)[xy0 + lane] = static_cast<int8_t>(m); break;
@@ -191,18 +193,15 @@ __device__ __forceinline__ void store_row(char* pc, uint32_t xy0, int lane, int6
     case 32: reinterpret_cast<int32_t*>(pc)[xy0 + lane] = static_cast<int32_t>(m); break;
     case 64: reinterpret_cast<int64_t*>(pc)[xy0 + lane] = m; break;
     default: {
-      const uint32_t c = static_cast<uint32_t>(m) & 0xFFFu;
-      const int bit0 = 32 * lane;
-      const int v0 = bit0 / 12;
-      uint32_t acc = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int v = v0 + k;
-        const uint32_t cv = __shfl(c, v & 63, 64);
-        const int sh = 12 * v - bit0;
-        if (v < 64 && sh < 32) acc |= sh >= 0 ? (cv << sh) : (cv >> (-sh));
+      const int c = static_cast<int>(m) & 0xFFF;
+      const uint32_t p24 = static_cast<uint32_t>(c) | (static_cast<uint32_t>(dpp_int<0xB1>(c)) << 12);
+      if ((lane & 1) == 0) {
+        const int i = lane >> 1;  // pair i: bytes 3 i .. 3 i + 2 of the row
+        char* b = pc + static_cast<size_t>(xy0 >> 6) * 96 + 3 * i;
+        const bool odd = (i & 1) != 0;  // 3 i odd: byte, then short at 3 i + 1
+        *reinterpret_cast<uint8_t*>(b + (odd ? 0 : 2)) = static_cast<uint8_t>(odd ? p24 : p24 >> 16);
+        *reinterpret_cast<uint16_t*>(b + (odd ? 1 : 0)) = static_cast<uint16_t>(odd ? p24 >> 8 : p24);
       }
-      if (lane < 24) reinterpret_cast<uint32_t*>(pc)[(xy0 >> 6) * 24 + lane] = acc;
     }
   }
 }
