@@ -118,6 +118,42 @@ def _time_solves(s, f, reps):
     return e0.elapsed_time(e1) / reps, u
 
 
+def codec_rates(x, bits, reps=3):
+    """Adaptive-exponent BFP (Sec. 6.1.3) encode and decode of the solution
+    vector: one pass each; algorithmic bytes = the float64 values plus the
+    codes (the block list and the look-back words are negligible)."""
+    import torch
+
+    from paper_2511_19036_amd import abfp_decode, abfp_encode, abfp_workspace
+    n = x.numel()
+    log(f"[bench] adaptive-exponent codec on the {n}-value solution, {bits} bits")
+    ws = abfp_workspace(n)
+    enc = abfp_encode(x, bits, workspace=ws)
+    dec = abfp_decode(*enc, n, bits)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    for _ in range(reps):
+        enc = abfp_encode(x, bits, workspace=ws)
+    e[1].record()
+    e[2].record()
+    for _ in range(reps):
+        dec = abfp_decode(*enc, n, bits)
+    e[3].record()
+    torch.cuda.synchronize()
+    t_enc, t_dec = e[0].elapsed_time(e[1]) / reps, e[2].elapsed_time(e[3]) / reps
+    nb = int(enc[3].item())
+    cbytes = enc[0].numel()
+    moved = 8.0 * n + cbytes
+    err = float(torch.max(torch.abs(dec - x)))
+    amax = float(torch.max(torch.abs(x)))
+    return dict(n=n, bits=bits, nblocks=nb, encode_ms=t_enc, encode_gbs=moved / (t_enc * 1e-3) / 1e9,
+                encode_frac=moved / (t_enc * 1e-3) / HBM_PEAK, decode_ms=t_dec,
+                decode_gbs=moved / (t_dec * 1e-3) / 1e9, decode_frac=moved / (t_dec * 1e-3) / HBM_PEAK,
+                storage_bytes=cbytes + 10 * max(nb, 0), fixed_block64_bytes=cbytes + 2 * ((n + 63) // 64),
+                max_abs_err=err, max_abs=amax)
+
+
 def other_workloads():
     """Solve times of the other workloads (same library, same GPU)."""
     import torch
@@ -176,6 +212,7 @@ def main():
     ap.add_argument("--cpu-L", type=int, default=8)
     ap.add_argument("--no-sweep", action="store_true", help="skip the 8/12-bit and tuned-width runs")
     ap.add_argument("--no-workloads", action="store_true", help="skip the timings of the other workloads")
+    ap.add_argument("--no-codec", action="store_true", help="skip the adaptive-exponent codec timing")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for counter runs: one warm-up solve, a calibration copy of 1 GiB, one solve; no JSON")
     args = ap.parse_args()
@@ -245,6 +282,8 @@ def main():
     mem = s.memory_stats()
     s.close()
     del s
+
+    codec = None if args.no_codec else codec_rates(u.view(-1), args.bits)
 
     achieved = rep["bytes"] / (rep["ms"] * 1e-3)
     traffic = stored_traffic(dom)
@@ -348,6 +387,7 @@ def main():
         "width_sweep": sweep,
         "other_workloads": others,
         "cpu_baseline": cpu,
+        "adaptive_bfp": codec,
     }
     print(json.dumps(out), flush=True)
 

@@ -193,6 +193,43 @@ cmg_status cmg_bfp_decode(const void* codes, const int16_t* exps, int64_t n, int
                           int32_t bits, double* x, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Adaptive-exponent BFP codec (Sec. 6.1.3, Exponents: the exponent need not
+ * be known in advance).  Entries are visited in index order and normalised
+ * to the largest exponent seen so far (the running exponent R_i); a block
+ * starts wherever R_i rises, and only the last `bits` blocks (the `bits`
+ * largest exponents) are kept: every other block's entries would round to
+ * zero at the largest exponent.  An entry's exponent is the fixed-block
+ * exponent of a block holding that entry alone (frexp exponent of |x|,
+ * plus one if |x| rounds to 2^(bits-1)); code m_i = RNE(x_i 2^(bits-1-R_i)),
+ * 0 before the first nonzero entry, in the containers of the fixed-block
+ * codec; a kept block is an int64 start index and an int16 exponent.
+ * Entries before the first kept block decode to 0.  One pass over x
+ * (decoupled look-back scan over tiles of 4096 values).
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of the code buffer for n values (ceil(n/64)*64 codes). */
+int64_t cmg_abfp_code_bytes(int64_t n, int32_t bits);
+
+/* Bytes of the device workspace an encode of n values needs. */
+int64_t cmg_abfp_workspace_bytes(int64_t n);
+
+/* Encode n values x (device, float64 if x_is_f64 else float32) into codes
+ * (device, cmg_abfp_code_bytes, 16-byte aligned), starts (device, `bits`
+ * int64) and exps (device, `bits` int16); *nblocks (device int32) receives
+ * the number of kept blocks, or -1 if x held NaN/Inf, or -2 if the scan
+ * failed.  workspace: device, cmg_abfp_workspace_bytes(n), owned by the
+ * caller and not shared by overlapping calls.  Asynchronous on hip_stream
+ * (read *nblocks after synchronising).  CMG_ERR_INVALID_ARG for a bad size,
+ * width, NULL or misaligned buffer. */
+cmg_status cmg_abfp_encode(const void* x, int32_t x_is_f64, int64_t n, int32_t bits, void* codes, int64_t* starts,
+                           int16_t* exps, int32_t* nblocks, void* workspace, void* hip_stream);
+
+/* Decode n values into x (device float64) from an encode's outputs (a
+ * negative *nblocks decodes as no block: all zeros); exact for bits <= 53. */
+cmg_status cmg_abfp_decode(const void* codes, const int64_t* starts, const int16_t* exps, const int32_t* nblocks,
+                           int64_t n, int32_t bits, double* x, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
  * Section inspection and stepwise driving (tests, checkpoint/resume).
  * Sections use the padded level layout: level l holds (2^l)^dim values, C
  * order; index 0 on each axis is the boundary node (always 0), the node at

@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import CmgError, load  # noqa: F401
 
-__all__ = ["Solver", "bfp_encode", "bfp_decode", "bfp_code_bytes", "CmgError", "load", "options"]
+__all__ = ["Solver", "bfp_encode", "bfp_decode", "bfp_code_bytes", "abfp_encode", "abfp_decode", "abfp_workspace",
+           "CmgError", "load", "options"]
 
 _SMOOTHERS = {"wjacobi": _lib.WJACOBI, "rbgs": _lib.RBGS}
 _OPS = {"poisson": _lib.POISSON, "diffusion": _lib.DIFFUSION}
@@ -247,4 +248,44 @@ def bfp_decode(codes, exps, n: int, block: int, bits: int, stream=None):
     x = torch.empty(n, dtype=torch.float64, device=codes.device)
     _lib.check(lib.cmg_bfp_decode(_lib.ptr(codes), _lib.ptr(exps), n, block, bits, _lib.ptr(x),
                                   _lib.stream_ptr(stream)))
+    return x
+
+
+# ------------------------------------------------------- adaptive codec
+def abfp_workspace(n: int, device="cuda"):
+    """Device workspace for one adaptive encode of ``n`` values."""
+    import torch
+    return torch.empty(int(load().cmg_abfp_workspace_bytes(n)), dtype=torch.uint8, device=device)
+
+
+def abfp_encode(x, bits: int, stream=None, workspace=None):
+    """Adaptive-exponent BFP encode of a float32/float64 CUDA tensor (Sec. 6.1.3).
+
+    Returns ``(codes uint8, starts int64[bits], exps int16[bits], nblocks
+    int32[1])``, all on the device; ``nblocks`` holds the kept block count
+    (-1: non-finite input).  Asynchronous: nothing is synchronised here."""
+    import torch
+    lib = load()
+    x = x.contiguous()
+    n = x.numel()
+    dev = x.device
+    codes = torch.empty(max(int(lib.cmg_abfp_code_bytes(n, bits)), 16), dtype=torch.uint8, device=dev)
+    starts = torch.empty(bits, dtype=torch.int64, device=dev)
+    exps = torch.empty(bits, dtype=torch.int16, device=dev)
+    nblocks = torch.empty(1, dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = abfp_workspace(n, dev)
+    _lib.check(lib.cmg_abfp_encode(_lib.ptr(x), 1 if x.dtype == torch.float64 else 0, n, bits, _lib.ptr(codes),
+                                   _lib.ptr(starts), _lib.ptr(exps), _lib.ptr(nblocks), _lib.ptr(workspace),
+                                   _lib.stream_ptr(stream)))
+    return codes, starts, exps, nblocks
+
+
+def abfp_decode(codes, starts, exps, nblocks, n: int, bits: int, stream=None):
+    """Float64 values of an adaptive encode's outputs."""
+    import torch
+    lib = load()
+    x = torch.empty(n, dtype=torch.float64, device=codes.device)
+    _lib.check(lib.cmg_abfp_decode(_lib.ptr(codes), _lib.ptr(starts), _lib.ptr(exps), _lib.ptr(nblocks), n, bits,
+                                   _lib.ptr(x), _lib.stream_ptr(stream)))
     return x

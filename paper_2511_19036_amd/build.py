@@ -13,7 +13,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/kernels.hip", "csrc/fused.hip", "csrc/coarse.hip", "csrc/solver.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/fused.hip", "csrc/coarse.hip", "csrc/abfp.hip", "csrc/solver.hip"]
 LIB = os.path.join(HERE, "libcmg.so")
 
 FLAGS = [

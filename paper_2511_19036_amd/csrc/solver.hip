@@ -14,6 +14,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "abfp.h"
 #include "cmg.h"
 #include "coarse.h"
 #include "fused.h"
@@ -842,6 +843,48 @@ cmg_status cmg_bfp_decode(const void* codes, const int16_t* exps, int64_t n, int
     if (n == 0) return;
     SecRef s{const_cast<void*>(codes), const_cast<int16_t*>(exps), n, block, bits, container_bits(bits)};
     launch_decode<double>(s, n, x, static_cast<hipStream_t>(hip_stream));
+    KCK();
+  });
+}
+
+int64_t cmg_abfp_code_bytes(int64_t n, int32_t bits) {
+  if (n < 0 || bits < 2 || bits > 53) return -1;
+  return code_bytes(n, 64, bits);
+}
+
+int64_t cmg_abfp_workspace_bytes(int64_t n) { return n < 0 ? -1 : abfp_workspace_bytes(n); }
+
+cmg_status cmg_abfp_encode(const void* x, int32_t x_is_f64, int64_t n, int32_t bits, void* codes, int64_t* starts,
+                           int16_t* exps, int32_t* nblocks, void* workspace, void* hip_stream) {
+  return guard(nullptr, [&] {
+    need(n >= 0 && bits >= 2 && bits <= 53, "bad size or bits");
+    need(n <= (int64_t{1} << 43), "n too large for the tile ticket");
+    need(starts != nullptr && exps != nullptr && nblocks != nullptr && workspace != nullptr, "NULL buffer");
+    need(n == 0 || (x != nullptr && codes != nullptr), "NULL buffer");
+    need(reinterpret_cast<uintptr_t>(codes) % 16 == 0 && reinterpret_cast<uintptr_t>(workspace) % 8 == 0,
+         "codes must be 16-byte and workspace 8-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int cb = container_bits(bits);
+    if (x_is_f64)
+      launch_abfp_encode<double>(static_cast<const double*>(x), n, bits, cb, codes, starts, exps, nblocks, workspace,
+                                 st);
+    else
+      launch_abfp_encode<float>(static_cast<const float*>(x), n, bits, cb, codes, starts, exps, nblocks, workspace,
+                                st);
+    KCK();
+  });
+}
+
+cmg_status cmg_abfp_decode(const void* codes, const int64_t* starts, const int16_t* exps, const int32_t* nblocks,
+                           int64_t n, int32_t bits, double* x, void* hip_stream) {
+  return guard(nullptr, [&] {
+    need(n >= 0 && bits >= 2 && bits <= 53, "bad size or bits");
+    need(starts != nullptr && exps != nullptr && nblocks != nullptr, "NULL buffer");
+    need(n == 0 || (x != nullptr && codes != nullptr), "NULL buffer");
+    need(reinterpret_cast<uintptr_t>(codes) % 16 == 0, "codes must be 16-byte aligned");
+    if (n == 0) return;
+    launch_abfp_decode(codes, starts, exps, nblocks, n, bits, container_bits(bits), x,
+                       static_cast<hipStream_t>(hip_stream));
     KCK();
   });
 }

@@ -26,7 +26,7 @@ __all__ = [
     "nodes_1d", "sine_solution", "sine_rhs", "gaussian_noise_rhs",
     "splitmix64_uniform", "splitmix64_uniform_torch", "hash_noise_rhs",
     "hash_noise_rhs_torch", "gaussian_random_field", "lognormal_kappa",
-    "smoothed_noise_rhs", "WORKLOADS",
+    "smoothed_noise_rhs", "exponent_mix", "WORKLOADS",
 ]
 
 
@@ -307,3 +307,33 @@ WORKLOADS = {
                               kappa_corr=0.05, kappa_seed=4, kappa_obs_seed=5,
                               rhs="smoothed_noise", rhs_seeds=tuple(range(100, 108))),
 }
+
+
+# ------------------------------------------------------ codec test vectors
+EXPONENT_MIX_KINDS = ("normal", "binades", "rising", "zeros", "ties", "float32")
+
+
+def exponent_mix(n: int, kind: str, seed: int) -> np.ndarray:
+    """Seeded vectors for codec tests, with magnitudes that exercise block
+    exponents: ``normal`` N(0,1); ``binades`` N(0,1) scaled by 2**k, k
+    uniform in [-40, 40); ``rising`` magnitudes 2**-60 .. 2**60 in order
+    (a new exponent every few entries) with random signs; ``zeros`` N(0,1)
+    with a leading third and a fifth of the rest zero; ``ties`` multiples of
+    1/4 (exact binary ties); ``float32`` N(0,1) as float32."""
+    rng = np.random.default_rng(seed)
+    if kind == "normal":
+        return rng.standard_normal(n)
+    if kind == "binades":
+        return rng.standard_normal(n) * np.exp2(rng.integers(-40, 40, n).astype(np.float64))
+    if kind == "rising":
+        return np.exp2(np.linspace(-60.0, 60.0, n)) * rng.choice([-1.0, 1.0], n)
+    if kind == "zeros":
+        z = rng.standard_normal(n)
+        z[: n // 3] = 0.0
+        z[rng.random(n) < 0.2] = 0.0
+        return z
+    if kind == "ties":
+        return np.round(rng.standard_normal(n) * 8.0) / 4.0
+    if kind == "float32":
+        return rng.standard_normal(n).astype(np.float32)
+    raise ValueError(kind)
