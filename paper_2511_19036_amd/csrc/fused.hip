@@ -569,8 +569,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
       F.my[t] = quant_f32<LB>(ob[rr * kTX + lane], Yp.w, lane, &F.ey[t]);
       const double dy = F.ey[t] == kZeroExp ? 0.0 : ldexp(static_cast<double>(F.my[t]), F.ey[t] - (Yp.w - 1));
-      const double vu = raw_f64(upre[t], xyl, U.cbits, U.w) + dy;
-      F.mu[t] = quant_f64<LB>(vu, U.w, lane, &F.eu[t]);
+      const double vu = raw_f64<HI>(upre[t], xyl, U.cbits, U.w) + dy;
+      F.mu[t] = quant_f64<LB, HI>(vu, U.w, lane, &F.eu[t]);
       F.ev[t] = static_cast<float>(dy);
     }
     if (eout != nullptr) {
@@ -944,7 +944,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
 // also decode one node of the one-node x-y halo.  Every plane of u goes
 // through a ring of three LDS planes, so that a single barrier per step
 // separates the writes of plane j from the reads of plane j - 2.
-template <int TY, int NT, int LB, bool HI>
+template <int TY, int NT, int LB, bool HI, bool GW64>
 __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __restrict__ uc,
                                                     const double* __restrict__ f, int Lfull, int level, int levelc,
                                                     double ih2, PSec Gout, int TZ, int* nonfinite, double* sumsq) {
@@ -1070,13 +1070,14 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         u[t][0] = u[t][1];
         u[t][1] = u[t][2];
         const int ci = ((rr >> 1) + 1) * CW + (lane >> 1) + 1;
-        const double v = raw_f64(upre[t], xy_own(t), U.cbits, U.w) +
+        const double v = raw_f64<HI>(upre[t], xy_own(t), U.cbits, U.w) +
                          prolong_node<double, JP, CW>(c0, c1, ci, lane & 1, rr & 1);
         u[t][2] = pin ? v : 0.0;
         ub[(rr + 1) * EXW + lane + 1] = u[t][2];
       }
       if (has_h) {
-        const double v = raw_f64(hpre, xyh, U.cbits, U.w) + prolong_node<double, JP, CW>(c0, c1, hci, gxh & 1, gyh & 1);
+        const double v =
+            raw_f64<HI>(hpre, xyh, U.cbits, U.w) + prolong_node<double, JP, CW>(c0, c1, hci, gxh & 1, gyh & 1);
         ub[hpos] = (pin && hdom) ? v : 0.0;
       }
     }
@@ -1105,7 +1106,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         a = a * ih2;
         const bool inside = p >= 1 && X0 + lane >= 1 && Y0 + rr >= 1;
         tv[t] = inside ? fpre[t] - a : 0.0;
-        m[t] = quant_f64<LB>(tv[t], Gout.w, lane, &e[t]);
+        m[t] = quant_f64<LB, GW64>(tv[t], Gout.w, lane, &e[t]);
       }
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
@@ -1158,7 +1159,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
 // boundary column / row at node 2^l; the last chunk writes plane 2^l.
 // PAD: write the padded level layout (2^l per axis) instead, as one step of
 // the decode chain u_l = dec u'_l + P u_{l-1}.
-template <int TY, int LB, bool PAD>
+template <int TY, int LB, bool PAD, bool HI>
 __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* __restrict__ uc, int level,
                                                          int levelc, int TZ, double* __restrict__ full) {
   constexpr int NT = 64 * TY;
@@ -1184,9 +1185,10 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
       const int t = tid + k * NT;
       const int cy = t / CW, cx = t - cy * CW;
       const int gx = CX0 + cx, gy = CY0 + cy;
-      cpf[k] = 0.0;
-      if (zin && t < CPL && gx < nc && gy < nc)
-        cpf[k] = src[(static_cast<uint32_t>(gy) << levelc) | static_cast<uint32_t>(gx)];
+      const bool in = zin && t < CPL && gx < nc && gy < nc;
+      // every lane loads (a node of the level); the value is selected
+      const double v = src[(static_cast<uint32_t>(min(gy, nc - 1)) << levelc) | static_cast<uint32_t>(min(gx, nc - 1))];
+      cpf[k] = in ? v : 0.0;
     }
   };
   auto cstore = [&](int cz) {
@@ -1198,8 +1200,8 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     }
   };
   auto xy_own = [&]() { return (static_cast<uint32_t>(Y0 + wv) << level) | static_cast<uint32_t>(X0 + lane); };
-  auto fetch_u = [&](int k) {
-    if (k < n) upre = raw_at<LB>(plane_of(U, k), xy_own(), U.cbits);
+  auto fetch_u = [&](int k) {  // unconditional: past the last plane it reads that plane again, unused
+    upre = raw_at<LB, HI>(plane_of(U, min(k, n - 1)), xy_own(), U.cbits);
   };
   auto step = [&](auto kpc, const int k) {
     constexpr int KP = decltype(kpc)::value;
@@ -1214,15 +1216,10 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     const double* c0 = cs + ((k >> 1) & (NC - 1)) * CPL;
     const double* c1 = cs + (((k >> 1) + 1) & (NC - 1)) * CPL;
     const int ci = (wv >> 1) * CW + (lane >> 1);
-    const double v = raw_f64(r, xy_own(), U.cbits, U.w) + prolong_node<double, KP, CW>(c0, c1, ci, lane & 1, wv & 1);
+    const double v =
+        raw_f64<HI>(r, xy_own(), U.cbits, U.w) + prolong_node<double, KP, CW>(c0, c1, ci, lane & 1, wv & 1);
     double* row = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(Y0 + wv)) * N;
-    row[X0 + lane] = v;
-    if (!PAD && X0 + kTX == n && lane == 63) row[n] = 0.0;
-    if (!PAD && Y0 + TY == n && wv == TY - 1) {
-      double* last = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(n)) * N;
-      last[X0 + lane] = 0.0;
-      if (X0 + kTX == n && lane == 63) last[n] = 0.0;
-    }
+    row[X0 + lane] = v;  // (the faces at 2^l of a full array are written by k_far_faces)
     if (KP == 0) cstore((k >> 1) + 1);
     __syncthreads();
   };
@@ -1235,14 +1232,18 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     step(std::integral_constant<int, 0>(), k);
     step(std::integral_constant<int, 1>(), k + 1);
   }
-  if (!PAD && Z0 + TZ == n) {  // plane 2^l
-    double* plane = full + static_cast<uint64_t>(n) * N * N;
-    plane[static_cast<uint64_t>(Y0 + wv) * N + X0 + lane] = 0.0;
-    if (X0 + kTX == n && lane == 63) plane[static_cast<uint64_t>(Y0 + wv) * N + n] = 0.0;
-    if (Y0 + TY == n && wv == TY - 1) {
-      plane[static_cast<uint64_t>(n) * N + X0 + lane] = 0.0;
-      if (X0 + kTX == n && lane == 63) plane[static_cast<uint64_t>(n) * N + n] = 0.0;
-    }
+}
+
+// The Dirichlet faces x = 2^l, y = 2^l and z = 2^l of a full node array
+// (N = 2^l + 1 per axis) are zero; the z-march above writes the rest, with
+// no conditional store in its loop.
+__global__ void k_far_faces(double* __restrict__ full, int n) {
+  const uint64_t N = static_cast<uint64_t>(n) + 1, face = N * N;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < 3 * face;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t f = i / face, r = i - f * face, a = r / N, b = r - a * N;
+    const uint64_t off = f == 0 ? (a * N + b) * N + n : f == 1 ? (a * N + n) * N + b : (n * N + a) * N + b;
+    full[off] = 0.0;
   }
 }
 
@@ -1365,15 +1366,24 @@ bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int L
   const dim3 grid((g.n / kTX) * (g.n / kResTY) * (g.n / tz)), block(kResNT);
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size + sec_b(Gout);
   const PSec pu = psec(U, g), pg = psec(Gout, g);
-  const bool hi = U.cbits == 12 || U.cbits == 64;
-#define CMG_IR(LB_, HI_)                                                                                           \
-  CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, LB_, HI_>), grid, block, st, pu, uc, f, Lfull, \
-              g.level, gc.level, ih2, pg, tz, nonfinite, sumsq)
-  if (U.B == 64) {
-    if (hi) CMG_IR(6, true); else CMG_IR(6, false);
-  } else {
-    if (hi) CMG_IR(5, true); else CMG_IR(5, false);
+  const bool hi = U.cbits == 12 || U.cbits == 64, g64 = Gout.cbits == 64;
+#define CMG_IR(LB_, HI_, GW_)                                                                                     \
+  CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, LB_, HI_, GW_>), grid, block, st, pu, uc, f, \
+              Lfull, g.level, gc.level, ih2, pg, tz, nonfinite, sumsq)
+#define CMG_IR2(LB_)                      \
+  if (hi) {                               \
+    if (g64) CMG_IR(LB_, true, true);     \
+    else CMG_IR(LB_, true, false);        \
+  } else {                                \
+    if (g64) CMG_IR(LB_, false, true);    \
+    else CMG_IR(LB_, false, false);       \
   }
+  if (U.B == 64) {
+    CMG_IR2(6)
+  } else {
+    CMG_IR2(5)
+  }
+#undef CMG_IR2
 #undef CMG_IR
   return true;
 }
@@ -1386,12 +1396,17 @@ bool fused_decode_full(const SecRef& U, const double* uc, const Geom& g, const G
   const PSec pu = psec(U, g);
   const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDecTY), 16);
   const dim3 grid((g.n / kTX) * (g.n / kDecTY) * (g.n / tz)), block(64 * kDecTY);
-  if (U.B == 64)
-    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, 6, false>), grid, block, st, pu, uc, g.level, gc.level,
-                tz, full);
-  else
-    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, 5, false>), grid, block, st, pu, uc, g.level, gc.level,
-                tz, full);
+  const bool hi = U.cbits == 12 || U.cbits == 64;
+#define CMG_DEC(LB_, HI_)                                                                                       \
+  CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, LB_, false, HI_>), grid, block, st, pu, uc, g.level, \
+              gc.level, tz, full)
+  if (U.B == 64) {
+    if (hi) CMG_DEC(6, true); else CMG_DEC(6, false);
+  } else {
+    if (hi) CMG_DEC(5, true); else CMG_DEC(5, false);
+  }
+#undef CMG_DEC
+  hipLaunchKernelGGL(k_far_faces, dim3(1024), dim3(256), 0, st, full, g.n);
   return true;
 }
 
@@ -1402,12 +1417,16 @@ bool fused_decode_level(const SecRef& U, const double* uc, const Geom& g, const 
   const PSec pu = psec(U, g);
   const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDecTY), 16);
   const dim3 grid((g.n / kTX) * (g.n / kDecTY) * (g.n / tz)), block(64 * kDecTY);
-  if (U.B == 64)
-    CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, 6, true>), grid, block, st, pu, uc, g.level,
-                gc.level, tz, out);
-  else
-    CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, 5, true>), grid, block, st, pu, uc, g.level,
-                gc.level, tz, out);
+  const bool hi = U.cbits == 12 || U.cbits == 64;
+#define CMG_DEC(LB_, HI_)                                                                                        \
+  CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, LB_, true, HI_>), grid, block, st, pu, uc, g.level, \
+              gc.level, tz, out)
+  if (U.B == 64) {
+    if (hi) CMG_DEC(6, true); else CMG_DEC(6, false);
+  } else {
+    if (hi) CMG_DEC(5, true); else CMG_DEC(5, false);
+  }
+#undef CMG_DEC
   return true;
 }
 

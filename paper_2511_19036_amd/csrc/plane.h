@@ -95,15 +95,23 @@ __device__ __forceinline__ float raw_f32(const RawCode& r, uint32_t xy, int cbit
   return r.e == kZeroExp ? 0.0f : v;
 }
 
-// Exact value of a raw code of any container as double (branch-free: both
-// the 64-bit and the narrow reading are formed and one is selected).
+// Exact value of a raw code as double (branch-free: both the 64-bit and the
+// narrow reading are formed and one is selected).  With C64 = false the
+// caller guarantees a container of at most 32 bits.
+template <bool C64 = true>
 __device__ __forceinline__ double raw_f64(const RawCode& r, uint32_t xy, int cbits, int w) {
-  const double d64 = static_cast<double>(static_cast<int64_t>((static_cast<uint64_t>(r.hi) << 32) | r.lo));
   const uint32_t sh = (xy * static_cast<uint32_t>(cbits)) & 31u;
   const uint32_t x = __builtin_amdgcn_alignbit(r.hi, r.lo, sh);
-  const int sb = cbits == 64 ? 0 : 32 - cbits;
-  const double d32 = static_cast<double>(static_cast<int>(x << sb) >> sb);
-  const double v = ldexp(cbits == 64 ? d64 : d32, r.e - (w - 1));
+  double d;
+  if (C64) {
+    const double d64 = static_cast<double>(static_cast<int64_t>((static_cast<uint64_t>(r.hi) << 32) | r.lo));
+    const int sb = cbits == 64 ? 0 : 32 - cbits;
+    const double d32 = static_cast<double>(static_cast<int>(x << sb) >> sb);
+    d = cbits == 64 ? d64 : d32;
+  } else {
+    d = static_cast<double>(static_cast<int>(x << (32 - cbits)) >> (32 - cbits));
+  }
+  const double v = ldexp(d, r.e - (w - 1));
   return r.e == kZeroExp ? 0.0 : v;
 }
 
@@ -173,12 +181,14 @@ __device__ __forceinline__ int quant_f32(float v, int w, int lane, int* e_out) {
   return static_cast<int>(rintf(ldexpf(v, w - 1 - Eq)));
 }
 
-template <int LB>
+// With W64 = false the caller guarantees w <= 32 (a 32-bit conversion).
+template <int LB, bool W64 = true>
 __device__ __forceinline__ int64_t quant_f64(double v, int w, int lane, int* e_out) {
   const int E = block_max_int<LB>(lane_exp(v, w, ldexp(1.0, w - 1)), lane);
   const int Eq = E == kNoExp ? 0 : E;
   *e_out = E == kNoExp ? kZeroExp : E;
   const double q = rint(ldexp(v, w - 1 - Eq));
+  if (!W64) return static_cast<int64_t>(static_cast<int>(q));
   return w <= 32 ? static_cast<int64_t>(static_cast<int>(q)) : static_cast<int64_t>(q);
 }
 
