@@ -120,3 +120,48 @@ def test_poisson3d_1025_headline_configuration(cmg):
     assert math.sqrt(err2 / disc2) <= 2.0
     assert math.sqrt(dev2 / disc2) <= 0.5
     assert mem["total"] / 1023 ** 3 < 13.0
+
+
+@pytest.mark.slow
+def test_poisson3d_1025_ir_residual_sampled_blocks(cmg):
+    """Alg. 2 at full size, in the configuration bench.py times (1025^3,
+    b = 16, B = 64, the fused float64 residual kernel): random compact
+    sections are imported on every level, one IR residual runs on the GPU,
+    and sampled residual blocks (boundary rows included) equal the
+    node-by-node oracle bit for bit."""
+    from oracle import bfp as ob
+    from oracle import pointwise as pw
+    L, B = 10, 64
+    n = 1 << L
+    f = S.hash_noise_rhs_torch(3, L, amp=1e-4, seed=3, device="cuda")[None].contiguous()
+    rng = np.random.default_rng(21)
+    Uc = {}
+    dtypes = {8: np.int8, 16: np.int16, 32: np.int32, 64: np.int64}
+    with cmg.Solver(3, L, smoother="rbgs", bfp_block=B, bits=16, ir_iters=2, vcycle_prec="fp32") as s:
+        for level in range(1, L + 1):
+            s.enter_level(level, f)
+        for level in range(1, L + 1):
+            w = s.section_info("u", level)["bits"]
+            m = 1 << level
+            lim = (1 << (w - 1)) - 1
+            nblk = (m ** 3 + B - 1) // B                     # sections hold whole blocks
+            codes = np.zeros(nblk * B, dtype=dtypes[ob.container_bits(w)])
+            codes[: m ** 3] = rng.integers(-lim, lim + 1, size=m ** 3, dtype=codes.dtype)
+            c3 = codes[: m ** 3].reshape(m, m, m)
+            c3[0], c3[:, 0], c3[:, :, 0] = 0, 0, 0          # Dirichlet nodes hold 0
+            exps = rng.integers(-2 * level - 6, -2 * level + 3, size=nblk, dtype=np.int16)
+            s.import_section("u", level, w, codes.view(np.uint8), exps)
+            Uc[level] = pw.Codes(codes, exps, B, w)
+        s.ir_residual(f)
+        gcodes, gexps, gw = s.export_section("r", L)
+    assert ob.container_bits(gw) == 16
+    gm = gcodes.view(np.int16).reshape(n, n, n // B, B)
+    ge = gexps.reshape(n, n, n // B)
+    rows = [(0, 3, 0), (5, 0, 2), (1, 1, 0), (n - 1, n - 1, n // B - 1), (n - 1, 1, 0)]
+    rows += [tuple(int(v) for v in r) for r in np.stack([rng.integers(0, n, 150), rng.integers(0, n, 150),
+                                                         rng.integers(0, n // B, 150)], axis=1)]
+    for z, y, bx in rows:
+        fb = f[0, z, y, bx * B:(bx + 1) * B].cpu().numpy()
+        mo, eo = pw.ir_residual_block(Uc, 1, L, fb, z, y, bx, B, gw)
+        assert int(ge[z, y, bx]) == eo, (z, y, bx)
+        assert np.array_equal(gm[z, y, bx].astype(np.int64), mo), (z, y, bx)

@@ -15,6 +15,7 @@ import pytest
 
 import synthetic as S
 from oracle import bfp, compact, dense, grid, plain
+from oracle import pointwise as pw
 
 
 def _closed_form(dim, L):
@@ -236,3 +237,48 @@ def test_width_schedule():
     assert cfg16.w_r(1, 10) == 24                       # FP32 V-cycle cap
     assert compact.Config(dim=3, L=10, vcycle_dtype=np.float64).w_r(1, 10) == 25
     assert bfp.container_bits(cfg.w_u(1, 10)) == 64
+
+
+# ------------------------------------------------- node-by-node residual
+def _section_codes(sec):
+    dt = {8: np.int8, 16: np.int16, 32: np.int32, 64: np.int64}[bfp.container_bits(sec.w)]
+    return pw.Codes(sec.m.astype(dt), sec.e, sec.block, sec.w)
+
+
+def _random_compact(L, bits, seed):
+    cfg = compact.Config(dim=3, L=L, bits_u=bits, bits_r=bits, bits_y=bits)
+    rng = np.random.default_rng(seed)
+    U = {}
+    for level in range(1, L + 1):
+        n = 1 << level
+        x = np.zeros((n,) * 3)
+        x[1:, 1:, 1:] = rng.standard_normal((n - 1,) * 3) * 2.0 ** (-2 * level)
+        U[level] = compact.Section.quantize(x, cfg.block, cfg.w_u(level, L))
+    return cfg, U, rng
+
+
+@pytest.mark.parametrize("L,bits", [(4, 16), (5, 17), (5, 30)])
+def test_pointwise_decode_chain_equals_whole_array(L, bits):
+    """The node-by-node decode chain (used at full size) equals the
+    whole-array chain of eq. compact-to-standard at every node."""
+    cfg, U, _ = _random_compact(L, bits, 100 * L + bits)
+    n = 1 << L
+    idx = np.stack(np.meshgrid(*[np.arange(n + 1)] * 3, indexing="ij"), axis=-1).reshape(-1, 3)
+    got = pw.decode_chain_at({lv: _section_codes(s) for lv, s in U.items()}, 1, L, idx)
+    assert np.array_equal(got.reshape((n + 1,) * 3), grid.to_full(compact.decode_chain(U, 1, L)))
+
+
+def test_pointwise_residual_blocks_equal_whole_array():
+    """Residual blocks of Alg. 2 evaluated node by node equal the
+    whole-array residual section (64^3, sampled blocks incl. boundary rows)."""
+    L = 6
+    cfg, U, rng = _random_compact(L, 16, 7)
+    n = 1 << L
+    f = rng.standard_normal((n + 1,) * 3)
+    g = compact.ir_residual(U, grid.inject(f, L, L), grid.hierarchy(3, L, 1), cfg, L)
+    gm, ge = g.m.reshape(n, n, n), g.e.reshape(n, n)
+    Uc = {lv: _section_codes(s) for lv, s in U.items()}
+    rows = [(0, 5), (3, 0), (1, 1), (n - 1, n - 1)] + [tuple(r) for r in rng.integers(0, n, (12, 2))]
+    for z, y in rows:
+        m, e = pw.ir_residual_block(Uc, 1, L, f[z, y, :n], z, y, 0, cfg.block, cfg.w_r(L, L))
+        assert np.array_equal(m, gm[z, y]) and e == int(ge[z, y]), (z, y)
