@@ -222,7 +222,8 @@ __device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, in
 // right-hand side of plane j enters and stage s updates plane j - s; the
 // first half-sweep is pointwise (y = c g), hence a halo of S - 1.
 template <int S, int TY, int NT, int LB, bool HI>
-__global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level, float cp, float ih2, int TZ) {
+// (at most 80 VGPRs: two 11-wave workgroups per CU)
+__global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level, float cp, float ih2, int TZ) {
   constexpr int H = S - 1;
   using T = ColTile<H, TY, NT>;
   constexpr int K = T::K, EXW = T::EXW, PS = T::PS, PAD = T::PAD;
@@ -302,28 +303,13 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
       const int po = j - 1 - S;
       if (po >= Z0 && po < Z0 + TZ) quantise_rows<LB, TY, NT>(outb[1 - JP], Y, po, X0, Y0, level, tid);
     }
-    // Stage s on plane j - s.  The in-plane neighbours of stage s + 1 are
-    // loaded before stage s stores (they are the other colour of another
-    // plane), so the loads overlap the arithmetic.  Stages run on every
-    // plane of the march: a plane outside the dependence cone of the
-    // chunk's output planes is never read by a plane inside it.
-    float nb[2][K][4];
-    auto load_stage = [&](int s, float (&d)[K][4]) {
-      const int p = j - s;
-      const float* yb = lds + PAD + ((p + 4 * NB) % NB) * PS;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const unsigned sw = (fl[k] >> kSwap) & 1u;
-        const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
-        d[k][0] = yb[pa - 1];
-        d[k][1] = yb[pa + 1];
-        d[k][2] = yb[pa - EXW];
-        d[k][3] = yb[pa + EXW];
-      }
-    };
+    // Stage s on plane j - s.  Stages run on every plane of the march: a
+    // plane outside the dependence cone of the chunk's output planes is
+    // never read by a plane inside it.  (No neighbour pre-loads here, unlike
+    // the up sweep: at 80 VGPRs two workgroups share a CU, and the second
+    // hides the LDS latency better than pre-loads at 98 VGPRs and one.)
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
-      if (s < S) load_stage(s + 1, nb[s & 1]);
       const int p = j - s;
       const bool act = p >= 1 && p < n;
       const int iy = S + 1 - s;
@@ -338,12 +324,11 @@ __global__ void __launch_bounds__(NT, 2) k_down_smooth(PSec G, PSec Y, int level
         if (s == 1) {
           v = cp * rhs;
         } else {
-          const float* d = nb[(s - 1) & 1][k];
           float a = 6.0f * yc;
-          a = a - d[0];
-          a = a - d[1];
-          a = a - d[2];
-          a = a - d[3];
+          a = a - yb[pa - 1];
+          a = a - yb[pa + 1];
+          a = a - yb[pa - EXW];
+          a = a - yb[pa + EXW];
           a = a - y[k][SG][iy - 1];
           a = a - y[k][SG][iy + 1];
           a = a * ih2;
