@@ -59,7 +59,8 @@ enum { CMG_POISSON = 0, CMG_DIFFUSION = 1 };          /* cmg_problem.op         
 enum { CMG_WJACOBI = 0, CMG_RBGS = 1 };               /* cmg_opts.smoother        */
 enum { CMG_PLAIN_FP64 = 0, CMG_COMPACT_BFP = 1 };     /* cmg_opts.storage         */
 enum { CMG_FP32 = 0, CMG_FP64 = 1 };                  /* cmg_opts.vcycle_prec     */
-enum { CMG_SECTION_U = 0, CMG_SECTION_R = 1, CMG_SECTION_Y = 2 }; /* section kind */
+enum { CMG_SECTION_U = 0, CMG_SECTION_R = 1, CMG_SECTION_Y = 2, CMG_SECTION_YPRE = 3 }; /* section kind:
+   solution u', residual g = r - s, correction y' after post-smoothing, y' after pre-smoothing */
 
 typedef struct {
   int32_t dim;      /* 2 or 3                                                 */
@@ -233,7 +234,9 @@ cmg_status cmg_abfp_decode(const void* codes, const int64_t* starts, const int16
  * Section inspection and stepwise driving (tests, checkpoint/resume).
  * Sections use the padded level layout: level l holds (2^l)^dim values, C
  * order; index 0 on each axis is the boundary node (always 0), the node at
- * 2^l is implicit.  `which` is CMG_SECTION_U / _R / _Y.
+ * 2^l is implicit.  `which` is CMG_SECTION_U / _R / _Y, or _YPRE: the
+ * correction as the down sweep left it (the up sweep reads it and writes
+ * its post-smoothed value to _Y).
  * ------------------------------------------------------------------------- */
 
 /* Shape of a stored section: values, current width, container bits, bytes of

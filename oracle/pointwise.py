@@ -99,3 +99,122 @@ def ir_residual_block(U: dict, lc: int, L: int, f_block: np.ndarray, z: int, y: 
     t = np.where(interior, np.asarray(f_block, dtype=np.float64) - au, 0.0)
     m, e = bfp.encode(t, block, w)
     return m, int(e[0])
+
+
+# --------------------------------------------------- the down sweep, locally
+def _apply_box(y: np.ndarray, level: int, T) -> np.ndarray:
+    """Poisson ``A y`` at the inner nodes of a box (all six neighbours in the
+    box), the terms in the order of :meth:`oracle.grid.Level.apply`; 0 on the
+    box's outer shell."""
+    out = np.zeros_like(y)
+    c = (slice(1, -1),) * 3
+    s = T(6) * y[c]
+    for ax in (2, 1, 0):                     # -x, +x, -y, +y, -z, +z
+        for off in (-1, 1):
+            sl = [slice(1, -1)] * 3
+            sl[ax] = slice(1 + off, y.shape[ax] - 1 + off)
+            s = s - y[tuple(sl)]
+    out[c] = s * T(4 ** level)
+    return out
+
+
+def rbgs_box(g: np.ndarray, origin, level: int, nu: int, T=np.float32) -> np.ndarray:
+    """``nu`` red-black Gauss-Seidel sweeps from ``y = 0`` on ``A y = g``
+    restricted to a box of level ``level`` whose node ``[0, 0, 0]`` has the
+    padded coordinates ``origin`` (the box may hold far-boundary nodes ``n``).
+    Same arithmetic as :func:`oracle.grid.smooth` (red = even parity first,
+    ``c = 1 / (6 * 4**level)`` rounded to ``T``).  Nodes on the box's outer
+    shell keep 0, so values are exact at depth greater than ``2 nu`` inside
+    the box (each half-sweep carries information one node)."""
+    n = 1 << level
+    rhs = np.asarray(g, dtype=T)
+    y = np.zeros_like(rhs)
+    cz, cy, cx = (origin[a] + np.arange(rhs.shape[a]) for a in range(3))
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    interior = (Z >= 1) & (Z < n) & (Y >= 1) & (Y < n) & (X >= 1) & (X < n)
+    inner = np.zeros(rhs.shape, dtype=bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    c = T(1.0 / (2 * 3 * float(4 ** level)))
+    for _ in range(nu):
+        for colour in (0, 1):
+            mask = interior & inner & (((Z + Y + X) % 2) == colour)
+            r = rhs - _apply_box(y, level, T)
+            y[mask] = y[mask] + c * r[mask]
+    return y
+
+
+def down_sweep_block(G: Codes, level: int, nu: int, z: int, y: int, bx: int, block: int, w: int,
+                     T=np.float32):
+    """Codes and exponent of ``y'_level = Q_w(S^nu(0; g))`` (generalised
+    Alg. 1, fine to coarse) at one block, from the residual section ``G``."""
+    n = 1 << level
+    M = 2 * nu + 1
+    x0 = bx * block
+    lo = np.array([z - M, y - M, x0 - M])
+    hi = np.array([z + M, y + M, x0 + block - 1 + M])
+    lo_c, hi_c = np.maximum(lo, 0), np.minimum(hi, n)
+    gb = _box_values(G, level, lo_c, hi_c, T)
+    yb = rbgs_box(gb, lo_c, level, nu, T)
+    row = yb[z - lo_c[0], y - lo_c[1], x0 - lo_c[2]: x0 - lo_c[2] + block]
+    m, e = bfp.encode(row.astype(np.float64), block, w)
+    return m, int(e[0])
+
+
+def _box_values(S: Codes, level: int, lo, hi, T) -> np.ndarray:
+    """Decoded values (in ``T``) of a section on the box ``lo .. hi``
+    (inclusive padded coordinates; far-boundary nodes are 0)."""
+    n = 1 << level
+    axes = [np.arange(lo[a], hi[a] + 1) for a in range(3)]
+    Zc, Yc, Xc = np.meshgrid(*axes, indexing="ij")
+    idx = np.stack([Zc.ravel(), Yc.ravel(), Xc.ravel()], axis=1)
+    far = np.any(idx == n, axis=1)
+    v = np.zeros(idx.shape[0])
+    v[~far] = S.at(_flat(idx[~far], n))
+    return v.reshape(Zc.shape).astype(T)
+
+
+def restrict_block(G: Codes, level: int, nu: int, Kc: int, Jc: int, bxc: int, block: int, w_y: int, w_r: int,
+                   T=np.float32):
+    """Codes and exponent of ``g_{level-1} = Q_{w_r}(R(g - A y'))`` at one
+    block of the coarse level (coarse row ``(Kc, Jc)``, x from
+    ``bxc * block``), with ``y' = Q_{w_y}(S^nu(0; g))`` formed locally: the
+    fine-to-coarse step of the generalised Alg. 1 written for ``g = r - s``."""
+    n, m = 1 << level, 1 << (level - 1)
+    M = 2 * nu + 1
+    fx0 = 2 * bxc * block
+    # fine rows whose y' enters: 2Kc-2 .. 2Kc+2, 2Jc-2 .. 2Jc+2; x over the
+    # fine blocks covering 2 bxc*block - 2 .. 2 (bxc+1)*block
+    xb0 = max(0, (fx0 - 2) // block)
+    xb1 = min(n // block - 1, (fx0 + 2 * block) // block)
+    lo = np.array([2 * Kc - 2 - M, 2 * Jc - 2 - M, xb0 * block - M])
+    hi = np.array([2 * Kc + 2 + M, 2 * Jc + 2 + M, (xb1 + 1) * block - 1 + M])
+    lo_c, hi_c = np.maximum(lo, 0), np.minimum(hi, n)
+    gb = _box_values(G, level, lo_c, hi_c, T)
+    yb = rbgs_box(gb, lo_c, level, nu, T)
+    # y' on whole fine blocks of the rows 2Kc-2 .. 2Kc+2, 2Jc-2 .. 2Jc+2
+    yq = np.zeros_like(yb)
+    for fz in range(max(0, 2 * Kc - 2), min(n - 1, 2 * Kc + 2) + 1):
+        for fy in range(max(0, 2 * Jc - 2), min(n - 1, 2 * Jc + 2) + 1):
+            for xb in range(xb0, xb1 + 1):
+                a = xb * block - lo_c[2]
+                row = yb[fz - lo_c[0], fy - lo_c[1], a: a + block].astype(np.float64)
+                mq, eq = bfp.encode(row, block, w_y)
+                yq[fz - lo_c[0], fy - lo_c[1], a: a + block] = bfp.decode(mq, eq, block, w_y, dtype=T)
+    # t = g - A y' at the fine nodes 2K-1 .. 2K+1 (boundary nodes: t = g = 0)
+    t = gb - _apply_box(yq, level, T)
+    cz, cy, cx = (lo_c[a] + np.arange(gb.shape[a]) for a in range(3))
+    Zf, Yf, Xf = np.meshgrid(cz, cy, cx, indexing="ij")
+    t = np.where((Zf >= 1) & (Zf < n) & (Yf >= 1) & (Yf < n) & (Xf >= 1) & (Xf < n), t, gb)
+    # full weighting of the coarse row, terms in C order of the offsets
+    I = bxc * block + np.arange(block)
+    s = None
+    for oz, oy, ox in itertools.product((-1, 0, 1), repeat=3):
+        wgt = (0.5 if oz == 0 else 0.25) * (0.5 if oy == 0 else 0.25) * (0.5 if ox == 0 else 0.25)
+        fz, fy, fx = 2 * Kc + oz, 2 * Jc + oy, 2 * I + ox
+        v = t[fz - lo_c[0], fy - lo_c[1], np.clip(fx - lo_c[2], 0, t.shape[2] - 1)]
+        term = T(wgt) * v
+        s = term if s is None else s + term
+    inside = (I >= 1) & (I < m) & (Kc >= 1) & (Kc < m) & (Jc >= 1) & (Jc < m)
+    c = np.where(inside, s, T(0)).astype(np.float64)
+    mq, eq = bfp.encode(c, block, w_r)
+    return mq, int(eq[0])

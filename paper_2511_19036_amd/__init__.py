@@ -25,7 +25,7 @@ _SMOOTHERS = {"wjacobi": _lib.WJACOBI, "rbgs": _lib.RBGS}
 _OPS = {"poisson": _lib.POISSON, "diffusion": _lib.DIFFUSION}
 _STORAGE = {"plain": _lib.PLAIN_FP64, "compact": _lib.COMPACT_BFP}
 _PREC = {"fp32": _lib.FP32, "fp64": _lib.FP64}
-_WHICH = {"u": _lib.SECTION_U, "r": _lib.SECTION_R, "y": _lib.SECTION_Y}
+_WHICH = {"u": _lib.SECTION_U, "r": _lib.SECTION_R, "y": _lib.SECTION_Y, "ypre": _lib.SECTION_YPRE}
 
 
 def options(**kw) -> _lib.cmg_opts:

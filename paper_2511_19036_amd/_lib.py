@@ -20,7 +20,7 @@ POISSON, DIFFUSION = 0, 1
 WJACOBI, RBGS = 0, 1
 PLAIN_FP64, COMPACT_BFP = 0, 1
 FP32, FP64 = 0, 1
-SECTION_U, SECTION_R, SECTION_Y = 0, 1, 2
+SECTION_U, SECTION_R, SECTION_Y, SECTION_YPRE = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "CMG_OK", 1: "CMG_ERR_INVALID_ARG", 2: "CMG_ERR_UNSUPPORTED",
                 3: "CMG_ERR_OUT_OF_MEMORY", 4: "CMG_ERR_HIP", 5: "CMG_ERR_NONFINITE",

@@ -652,6 +652,7 @@ Section& section_of(cmg_ctx c, int which, int level) {
   if (which == CMG_SECTION_U) return D.U;
   if (which == CMG_SECTION_R) return D.G;
   if (which == CMG_SECTION_Y) return D.Yp;
+  if (which == CMG_SECTION_YPRE) return D.Y;
   fail(CMG_ERR_INVALID_ARG, "unknown section kind");
 }
 

@@ -165,3 +165,53 @@ def test_poisson3d_1025_ir_residual_sampled_blocks(cmg):
         mo, eo = pw.ir_residual_block(Uc, 1, L, fb, z, y, bx, B, gw)
         assert int(ge[z, y, bx]) == eo, (z, y, bx)
         assert np.array_equal(gm[z, y, bx].astype(np.int64), mo), (z, y, bx)
+
+
+@pytest.mark.slow
+def test_poisson3d_1025_down_sweep_sampled_blocks(cmg):
+    """The fused down sweep and residual restriction at full size (1025^3,
+    b = 16, B = 64, V(2,2)): a random residual section is imported on the
+    finest level, one V-cycle runs on the GPU, and sampled blocks of the
+    pre-smoothed correction y'_L and of the restricted g_{L-1} (boundary rows
+    included) equal the node-local oracle bit for bit."""
+    from oracle import bfp as ob
+    from oracle import pointwise as pw
+    L, B, nu = 10, 64, 2
+    n, m = 1 << L, 1 << (L - 1)
+    f = torch.zeros((1,) + ((n + 1),) * 3, dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(31)
+    with cmg.Solver(3, L, smoother="rbgs", bfp_block=B, bits=16, ir_iters=2, vcycle_prec="fp32") as s:
+        for level in range(1, L + 1):
+            s.enter_level(level, f)
+        w = s.section_info("r", L)["bits"]
+        assert ob.container_bits(w) == 16
+        lim = (1 << (w - 1)) - 1
+        codes = rng.integers(-lim, lim + 1, size=n ** 3, dtype=np.int16)
+        c3 = codes.reshape(n, n, n)
+        c3[0], c3[:, 0], c3[:, :, 0] = 0, 0, 0              # Dirichlet nodes hold 0
+        exps = rng.integers(-3, 4, size=n ** 3 // B, dtype=np.int16)
+        s.import_section("r", L, w, codes.view(np.uint8), exps)
+        s.vcycle_correct()
+        ym, ye, yw = s.export_section("ypre", L)
+        gm, ge, gw = s.export_section("r", L - 1)
+    del f
+    G = pw.Codes(codes, exps, B, w)
+    ym = ym.view(np.int16).reshape(n, n, n // B, B)
+    ye = ye.reshape(n, n, n // B)
+    rows = [(0, 3, 0), (1, 1, 0), (n - 1, n - 1, n // B - 1), (2, n - 1, 3), (n - 1, 1, 5)]
+    rows += [tuple(int(v) for v in r) for r in np.stack([rng.integers(0, n, 40), rng.integers(0, n, 40),
+                                                         rng.integers(0, n // B, 40)], axis=1)]
+    for z, y, bx in rows:
+        mo, eo = pw.down_sweep_block(G, L, nu, z, y, bx, B, yw)
+        assert int(ye[z, y, bx]) == eo, (z, y, bx)
+        assert np.array_equal(ym[z, y, bx].astype(np.int64), mo), (z, y, bx)
+    dt = {8: np.int8, 16: np.int16, 32: np.int32, 64: np.int64}[ob.container_bits(gw)]
+    gm = gm.view(dt).reshape(m, m, m // B, B)
+    ge = ge.reshape(m, m, m // B)
+    crow = [(0, 2, 0), (1, 1, 0), (m - 1, m - 1, m // B - 1), (3, m - 1, 2)]
+    crow += [tuple(int(v) for v in r) for r in np.stack([rng.integers(0, m, 25), rng.integers(0, m, 25),
+                                                         rng.integers(0, m // B, 25)], axis=1)]
+    for K, J, bxc in crow:
+        mo, eo = pw.restrict_block(G, L, nu, K, J, bxc, B, yw, gw)
+        assert int(ge[K, J, bxc]) == eo, (K, J, bxc)
+        assert np.array_equal(gm[K, J, bxc].astype(np.int64), mo), (K, J, bxc)

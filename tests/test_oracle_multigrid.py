@@ -282,3 +282,33 @@ def test_pointwise_residual_blocks_equal_whole_array():
     for z, y in rows:
         m, e = pw.ir_residual_block(Uc, 1, L, f[z, y, :n], z, y, 0, cfg.block, cfg.w_r(L, L))
         assert np.array_equal(m, gm[z, y]) and e == int(ge[z, y]), (z, y)
+
+
+def test_pointwise_down_sweep_and_restriction_equal_whole_array():
+    """The node-local down sweep (y' = Q(S^nu(0; g))) and the residual
+    restriction (g_{L-1} = Q(R(g - A y'))) equal the whole-array V-cycle's
+    first level, traced, on sampled blocks of a 128^3 grid."""
+    L, nu = 7, 2
+    cfg = compact.Config(dim=3, L=L, bits_u=16, bits_r=16, bits_y=16, nu_pre=nu, nu_post=nu)
+    rng = np.random.default_rng(3)
+    n = 1 << L
+    x = np.zeros((n,) * 3)
+    x[1:, 1:, 1:] = rng.standard_normal((n - 1,) * 3)
+    g = compact.Section.quantize(x, cfg.block, cfg.w_r(L, L))
+    U = {lv: compact.Section.zeros(3, lv, cfg.block, cfg.w_u(lv, L)) for lv in range(1, L + 1)}
+    trace = {}
+    compact.vcycle_correct(U, g, grid.hierarchy(3, L, 1), cfg, L, trace=trace)
+    yp, gc = trace["Ypre"][L], trace["G"][L - 1]
+    G = _section_codes(g)
+    m = n // 2
+    rows = [(0, 3), (1, 1), (n - 1, n - 2), (5, n - 1)] + [tuple(r) for r in rng.integers(0, n, (8, 2))]
+    for z, y in rows:
+        for bx in range(n // cfg.block):
+            mm, e = pw.down_sweep_block(G, L, nu, z, y, bx, cfg.block, cfg.w_y(L, L))
+            k = (z * n + y) * n + bx * cfg.block
+            assert np.array_equal(mm, yp.m[k:k + cfg.block]) and e == int(yp.e[k // cfg.block]), (z, y, bx)
+    crow = [(0, 2), (1, 1), (m - 1, m - 1), (7, 0)] + [tuple(r) for r in rng.integers(0, m, (6, 2))]
+    for K, J in crow:
+        mm, e = pw.restrict_block(G, L, nu, K, J, 0, cfg.block, cfg.w_y(L, L), cfg.w_r(L - 1, L))
+        k = (K * m + J) * m
+        assert np.array_equal(mm, gc.m[k:k + cfg.block]) and e == int(gc.e[k // cfg.block]), (K, J)
