@@ -30,12 +30,19 @@ def log(msg):
 
 
 def kernel_source_digest():
-    """SHA-256 of the fused-kernel source, to tell whether stored counter
-    readings still describe the kernels being run."""
+    """SHA-256 of the fused-kernel sources (fused.hip and the device headers
+    it includes) with comments and blank lines removed, to tell whether
+    stored counter readings still describe the kernels being run."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2511_19036_amd", "csrc", "fused.hip")
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    import re
+    h = hashlib.sha256()
+    for name in ("fused.hip", "plane.h", "device.h"):
+        with open(os.path.join(ROOT, "paper_2511_19036_amd", "csrc", name)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(l.rstrip() for l in text.splitlines() if l.strip()).encode())
+    return h.hexdigest()
 
 
 def stored_traffic(kernel):

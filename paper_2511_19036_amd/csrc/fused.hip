@@ -14,6 +14,14 @@
 // The per-node arithmetic is exactly that of the per-operation kernels in
 // kernels.hip (same operand order, no contraction), so both paths give
 // bit-identical results.
+//
+// Template parameters: S half-sweeps per smoothing kernel (2 nu), TY rows
+// and NT threads per tile, LB = log2 of the BFP block (5 or 6), and HI: a
+// section read value by value may have a 12- or 64-bit container, so a code
+// may straddle two words (the launchers pick HI from the containers; with
+// HI = false the second word is neither loaded nor used).  Container-width
+// flags of the float64 helpers (C64, W64, GW64) likewise remove the 64-bit
+// paths where the launcher knows the container is at most 32 bits.
 #include <type_traits>
 
 #include "device.h"
