@@ -139,14 +139,14 @@ __global__ void __launch_bounds__(kAbNT) k_abfp_encode(const T* __restrict__ x, 
 #pragma unroll
     for (int k = 0; k < kAbPT; ++k) v[k] = i0 + k < n ? static_cast<double>(x[i0 + k]) : 0.0;
   }
-  const double top = ldexp(1.0, w - 1);
+  const double lim = exp_lim(0.0, w);
   bool bad = false;
   int run[kAbPT];  // running exponent over this thread's values
   int r = kNoExp;
 #pragma unroll
   for (int k = 0; k < kAbPT; ++k) {
     bad = bad || !isfinite(v[k]);
-    r = max(r, lane_exp(v[k], w, top));
+    r = max(r, lane_exp(v[k], lim));
     run[k] = r;
   }
   if (bad) atomicOr(&hdr->flags, 1u);

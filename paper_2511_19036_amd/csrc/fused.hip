@@ -563,7 +563,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const int rr = row_of(t);
       const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
       F.my[t] = quant_f32<LB>(ob[rr * kTX + lane], Yp.w, lane, &F.ey[t]);
-      const double dy = F.ey[t] == kZeroExp ? 0.0 : ldexp(static_cast<double>(F.my[t]), F.ey[t] - (Yp.w - 1));
+      const double dy = ldexp(static_cast<double>(F.my[t]), F.ey[t] - (Yp.w - 1));  // codes 0 in a zero block
       const double vu = raw_f64<HI>(upre[t], xyl, U.cbits, U.w) + dy;
       F.mu[t] = quant_f64<LB, HI>(vu, U.w, lane, &F.eu[t]);
       F.ev[t] = static_cast<float>(dy);

@@ -74,14 +74,16 @@ __device__ __forceinline__ RawCode pair_at(const PlanePtr& pp, uint32_t xy0, int
   return RawCode{v.x, v.y, pp.e[xy0 >> LB]};
 }
 
+// The decoders below need no test for the all-zero block: its codes are 0,
+// and its sentinel exponent (-32768) would scale any code to zero anyway.
+
 // Value c (0 or 1) of a pair read by pair_at, as float (w <= 24).
 __device__ __forceinline__ float pair_f32(const RawCode& r, uint32_t xy0, int c, int cbits, int w) {
   const uint32_t sh = ((xy0 * static_cast<uint32_t>(cbits)) & 31u) + (c != 0 ? static_cast<uint32_t>(cbits) : 0u);
   const bool up = sh >= 32u;
   const uint32_t x = __builtin_amdgcn_alignbit(up ? 0u : r.hi, up ? r.hi : r.lo, sh & 31u);
   const int m = static_cast<int>(x << (32 - cbits)) >> (32 - cbits);
-  const float v = ldexpf(static_cast<float>(m), r.e - (w - 1));
-  return r.e == kZeroExp ? 0.0f : v;
+  return ldexpf(static_cast<float>(m), r.e - (w - 1));
 }
 
 // Value of a raw code of width w <= 24 (container at most 32 bits) as float:
@@ -91,8 +93,7 @@ __device__ __forceinline__ float raw_f32(const RawCode& r, uint32_t xy, int cbit
   const uint32_t sh = (xy * static_cast<uint32_t>(cbits)) & 31u;
   const uint32_t x = __builtin_amdgcn_alignbit(r.hi, r.lo, sh);
   const int m = static_cast<int>(x << (32 - cbits)) >> (32 - cbits);
-  const float v = ldexpf(static_cast<float>(m), r.e - (w - 1));
-  return r.e == kZeroExp ? 0.0f : v;
+  return ldexpf(static_cast<float>(m), r.e - (w - 1));
 }
 
 // Exact value of a raw code as double (branch-free: both the 64-bit and the
@@ -111,8 +112,7 @@ __device__ __forceinline__ double raw_f64(const RawCode& r, uint32_t xy, int cbi
   } else {
     d = static_cast<double>(static_cast<int>(x << (32 - cbits)) >> (32 - cbits));
   }
-  const double v = ldexp(d, r.e - (w - 1));
-  return r.e == kZeroExp ? 0.0 : v;
+  return ldexp(d, r.e - (w - 1));
 }
 
 // Hide a per-lane value from loop-invariant code motion, so that values
@@ -143,39 +143,51 @@ __device__ __forceinline__ int dpp_int(int v) {
 }
 
 // Max over the lanes of each block of B = 2^LB lanes.  All 64 lanes active.
+// Four DPP steps leave every lane with the maximum of its row of 16; a
+// row_bcast:15 step folds row 0 into row 1 and row 2 into row 3, and for
+// B = 64 a row_bcast:31 step folds lane 31 into rows 2 and 3.  The block
+// maximum is then read from the block's last lane: for B = 64 the result is
+// wave-uniform (a scalar register).
 template <int LB>
 __device__ __forceinline__ int block_max_int(int a, int lane) {
   a = max(a, dpp_int<0xB1>(a));   // quad_perm 1,0,3,2
   a = max(a, dpp_int<0x4E>(a));   // quad_perm 2,3,0,1
   a = max(a, dpp_int<0x141>(a));  // row_half_mirror
   a = max(a, dpp_int<0x140>(a));  // row_mirror
-  const int r0 = __builtin_amdgcn_readlane(a, 0), r1 = __builtin_amdgcn_readlane(a, 16);
-  const int r2 = __builtin_amdgcn_readlane(a, 32), r3 = __builtin_amdgcn_readlane(a, 48);
-  if (LB == 6) return max(max(r0, r1), max(r2, r3));
-  return lane < 32 ? max(r0, r1) : max(r2, r3);
+  a = max(a, __builtin_amdgcn_update_dpp(INT32_MIN, a, 0x142, 0xA, 0xF, false));  // row_bcast:15, rows 1 and 3
+  if (LB == 6) {
+    a = max(a, __builtin_amdgcn_update_dpp(INT32_MIN, a, 0x143, 0xC, 0xF, false));  // row_bcast:31, rows 2 and 3
+    return __builtin_amdgcn_readlane(a, 63);
+  }
+  const int h0 = __builtin_amdgcn_readlane(a, 31), h1 = __builtin_amdgcn_readlane(a, 63);
+  return lane < 32 ? h0 : h1;
 }
 
-// Per-lane exponent E(|v|) at width w (kNoExp for 0); top = 2^(w-1).
-__device__ __forceinline__ int lane_exp(float v, int w, float top) {
-  const float a = fabsf(v);
-  int e;
-  (void)frexpf(a, &e);
-  const int up = rintf(ldexpf(a, w - 1 - e)) == top ? 1 : 0;
-  return a == 0.0f ? kNoExp : e + up;
+// Per-lane exponent E(|v|) at width w (kNoExp for 0).  With frexp |v| =
+// m 2^e (1/2 <= m < 1), the scaled value m 2^(w-1) rounds to 2^(w-1) at w
+// bits exactly when m >= 1 - 2^-w (its tie rounds to the even 2^(w-1)), so
+// E = e + [m >= lim] with lim = 1 - 2^-w, which is exact in the value's
+// type for the widths used (w <= 24 in float, w <= 53 in double).
+__device__ __forceinline__ float exp_lim(float, int w) { return __int_as_float(0x3F800000 - (1 << (24 - w))); }
+__device__ __forceinline__ double exp_lim(double, int w) {
+  return __longlong_as_double(0x3FF0000000000000LL - (1LL << (53 - w)));
 }
-__device__ __forceinline__ int lane_exp(double v, int w, double top) {
+__device__ __forceinline__ int lane_exp(float v, float lim) {
+  const float a = fabsf(v);
+  const int up = __builtin_amdgcn_frexp_mantf(a) >= lim ? 1 : 0;
+  return a == 0.0f ? kNoExp : __builtin_amdgcn_frexp_expf(a) + up;
+}
+__device__ __forceinline__ int lane_exp(double v, double lim) {
   const double a = fabs(v);
-  int e;
-  (void)frexp(a, &e);
-  const int up = rint(ldexp(a, w - 1 - e)) == top ? 1 : 0;
-  return a == 0.0 ? kNoExp : e + up;
+  const int up = __builtin_amdgcn_frexp_mant(a) >= lim ? 1 : 0;
+  return a == 0.0 ? kNoExp : __builtin_amdgcn_frexp_exp(a) + up;
 }
 
 // Quantise the value of each lane into its block (w <= 24): returns the code,
 // *e_out the block exponent (kZeroExp for an all-zero block).
 template <int LB>
 __device__ __forceinline__ int quant_f32(float v, int w, int lane, int* e_out) {
-  const int E = block_max_int<LB>(lane_exp(v, w, ldexpf(1.0f, w - 1)), lane);
+  const int E = block_max_int<LB>(lane_exp(v, exp_lim(v, w)), lane);
   const int Eq = E == kNoExp ? 0 : E;
   *e_out = E == kNoExp ? kZeroExp : E;
   return static_cast<int>(rintf(ldexpf(v, w - 1 - Eq)));
@@ -184,7 +196,7 @@ __device__ __forceinline__ int quant_f32(float v, int w, int lane, int* e_out) {
 // With W64 = false the caller guarantees w <= 32 (a 32-bit conversion).
 template <int LB, bool W64 = true>
 __device__ __forceinline__ int64_t quant_f64(double v, int w, int lane, int* e_out) {
-  const int E = block_max_int<LB>(lane_exp(v, w, ldexp(1.0, w - 1)), lane);
+  const int E = block_max_int<LB>(lane_exp(v, exp_lim(v, w)), lane);
   const int Eq = E == kNoExp ? 0 : E;
   *e_out = E == kNoExp ? kZeroExp : E;
   const double q = rint(ldexp(v, w - 1 - Eq));
