@@ -22,6 +22,7 @@
 // HI = false the second word is neither loaded nor used).  Container-width
 // flags of the float64 helpers (C64, W64, GW64) likewise remove the 64-bit
 // paths where the launcher knows the container is at most 32 bits.
+#include <initializer_list>
 #include <type_traits>
 
 #include "device.h"
@@ -195,7 +196,7 @@ __device__ __forceinline__ void col_setup(int tid, int X0, int Y0, int level, in
 // Quantise the output rows of plane po (tile values in `ob`) into section S.
 // The rows of a wave are quantised in one straight-line block (a wave with
 // fewer than RPW rows repeats its first row, unstored), then stored.
-template <int LB, int TY, int NT>
+template <int LB, int TY, int NT, int CB>
 __device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, int po, int X0, int Y0, int level,
                                               int tid) {
   constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;
@@ -212,7 +213,7 @@ __device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, in
   for (int t = 0; t < RPW; ++t) {
     const int rr = out_row<NW>(wv, t);
     if (rr >= TY) continue;
-    store_row(pq.c, (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0), lane, m[t], S.cbits);
+    store_row(pq.c, (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0), lane, m[t], cbits_of<CB>(S));
   }
   if ((lane & ((1 << LB) - 1)) == 0) {
 #pragma unroll
@@ -229,7 +230,7 @@ __device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, in
 // y'_l = Q(S^nu1(0; g_l)): S = 2 nu1 half-sweeps from zero.  At step j the
 // right-hand side of plane j enters and stage s updates plane j - s; the
 // first half-sweep is pointwise (y = c g), hence a halo of S - 1.
-template <int S, int TY, int NT, int LB, bool HI>
+template <int S, int TY, int NT, int LB, bool HI, int CB>
 // (at most 80 VGPRs: two 11-wave workgroups per CU)
 __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level, float cp, float ih2, int TZ) {
   constexpr int H = S - 1;
@@ -278,7 +279,7 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) gpre[k][c] = raw_at<LB, HI>(gq, xy[k][c], G.cbits);
+      for (int c = 0; c < 2; ++c) gpre[k][c] = raw_at<LB, HI>(gq, xy[k][c], cbits_of<CB>(G));
   };
 
   auto step = [&](auto jpc, const int j) {
@@ -290,8 +291,8 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const bool sw = (fl[k] >> kSwap) & 1u;
-      const float g0 = jin ? raw_f32(gpre[k][0], xy[k][0], G.cbits, G.w) : 0.0f;
-      const float g1 = jin ? raw_f32(gpre[k][1], xy[k][1], G.cbits, G.w) : 0.0f;
+      const float g0 = jin ? raw_f32(gpre[k][0], xy[k][0], cbits_of<CB>(G), G.w) : 0.0f;
+      const float g1 = jin ? raw_f32(gpre[k][1], xy[k][1], cbits_of<CB>(G), G.w) : 0.0f;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
 #pragma unroll
@@ -309,7 +310,7 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
     // wait for a load does not then include these stores.
     {
       const int po = j - 1 - S;
-      if (po >= Z0 && po < Z0 + TZ) quantise_rows<LB, TY, NT>(outb[1 - JP], Y, po, X0, Y0, level, tid);
+      if (po >= Z0 && po < Z0 + TZ) quantise_rows<LB, TY, NT, CB>(outb[1 - JP], Y, po, X0, Y0, level, tid);
     }
     // Stage s on plane j - s.  Stages run on every plane of the march: a
     // plane outside the dependence cone of the chunk's output planes is
@@ -420,7 +421,7 @@ __device__ __forceinline__ T prolong_node(const T* c0, const T* c1, int ci, bool
   return s;
 }
 
-template <int S, int TY, int NT, int LB, bool HI>
+template <int S, int TY, int NT, int LB, bool HI, int CB>
 __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ ec, PSec G, PSec Y, PSec Yp, PSec U,
                                                      float* __restrict__ eout, int level, int levelc, float cp,
                                                      float ih2, int TZ) {
@@ -524,8 +525,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     const PlanePtr gq = plane_of(G, pc), yq = plane_of(Y, pc);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      gpre[k] = pair_at<LB>(gq, xy[k][0], G.cbits);
-      ypre[k] = pair_at<LB>(yq, xy[k][0], Y.cbits);
+      gpre[k] = pair_at<LB>(gq, xy[k][0], cbits_of<CB>(G));
+      ypre[k] = pair_at<LB>(yq, xy[k][0], cbits_of<CB>(Y));
     }
   };
   // Rows of a wave: out_row(wv, t) for t < RPW; a wave with fewer than RPW
@@ -542,7 +543,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     const PlanePtr uq = plane_of(U, min(max(po, Z0), Z0 + TZ - 1));
 #pragma unroll
     for (int t = 0; t < RPW; ++t)
-      upre[t] = raw_at<LB, HI>(uq, ((static_cast<uint32_t>(Y0 + row_of(t)) << level) | X0) + lane, U.cbits);
+      upre[t] = raw_at<LB, HI>(uq, ((static_cast<uint32_t>(Y0 + row_of(t)) << level) | X0) + lane, cbits_of<CB>(U));
   };
   // Output plane po: quantise y' (Yp), correct u' (float64), e = dec Yp + z.
   // The arithmetic of all rows of the wave is one straight-line block
@@ -564,7 +565,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
       F.my[t] = quant_f32<LB>(ob[rr * kTX + lane], Yp.w, lane, &F.ey[t]);
       const double dy = ldexp(static_cast<double>(F.my[t]), F.ey[t] - (Yp.w - 1));  // codes 0 in a zero block
-      const double vu = raw_f64<HI>(upre[t], xyl, U.cbits, U.w) + dy;
+      const double vu = raw_f64<HI>(upre[t], xyl, cbits_of<CB>(U), U.w) + dy;
       F.mu[t] = quant_f64<LB, HI>(vu, U.w, lane, &F.eu[t]);
       F.ev[t] = static_cast<float>(dy);
     }
@@ -585,8 +586,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const int rr = out_row<NW>(wv, t);
       if (rr >= TY) continue;
       const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
-      store_row(yq.c, xyr, lane, F.my[t], Yp.cbits);
-      store_row(uq.c, xyr, lane, F.mu[t], U.cbits);
+      store_row(yq.c, xyr, lane, F.my[t], cbits_of<CB>(Yp));
+      store_row(uq.c, xyr, lane, F.mu[t], cbits_of<CB>(U));
       if (eout != nullptr) eout[(static_cast<uint64_t>(po) << (2 * level)) + xyr + lane] = F.ev[t];
     }
     if ((lane & ((1 << LB) - 1)) == 0) {
@@ -648,8 +649,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
           a = a - z[k][c][2];
           a = a * ih2;
           const bool keep = pin && ((fl[k] >> (kInnerCol + c)) & 1u);
-          const float gv = pair_f32(gpre[k], xy[k][0], c, G.cbits, G.w) - a;
-          const float y0 = pair_f32(ypre[k], xy[k][0], c, Y.cbits, Y.w);
+          const float gv = pair_f32(gpre[k], xy[k][0], c, cbits_of<CB>(G), G.w) - a;
+          const float y0 = pair_f32(ypre[k], xy[k][0], c, cbits_of<CB>(Y), Y.w);
           rv[c] = keep ? gv : 0.0f;
           yv[c] = keep ? y0 : 0.0f;
           yb[pc] = yv[c];
@@ -763,7 +764,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
 //      the sum of plane K + 1 starts with the same nine products.
 // The t planes are stored split by x parity so that the stride-two reads of
 // the coarse nodes are consecutive.
-template <int CTY, int NT, int LB, bool HI>
+template <int CTY, int NT, int LB, bool HI, int CB>
 __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, int level, float ih2, int TZc) {
   constexpr int YW = 2 * kTX + 4, YH = 2 * CTY + 3;  // y' region, origin (2 CX0 - 2, 2 CY0 - 2)
   constexpr int NCOL = YW * YH, YPS = NCOL + 1, K = (NCOL + NT - 1) / NT;
@@ -814,12 +815,12 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
   auto fetch_y = [&](int p) {
     const PlanePtr yq = plane_of(Y, min(max(p, 0), n - 1));
 #pragma unroll
-    for (int k = 0; k < K; ++k) ypre[k] = raw_at<LB, HI>(yq, xy[k], Y.cbits);
+    for (int k = 0; k < K; ++k) ypre[k] = raw_at<LB, HI>(yq, xy[k], cbits_of<CB>(Y));
   };
   auto fetch_g = [&](int p) {
     const PlanePtr gq = plane_of(G, min(max(p, 1), n - 1));
 #pragma unroll
-    for (int k = 0; k < K; ++k) gpre[k] = raw_at<LB, HI>(gq, xy[k], G.cbits);
+    for (int k = 0; k < K; ++k) gpre[k] = raw_at<LB, HI>(gq, xy[k], cbits_of<CB>(G));
   };
 
   auto step = [&](auto spc, const int s) {
@@ -845,7 +846,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
       for (int k = 0; k < K; ++k) {
         yr[k][0] = yr[k][1];
         yr[k][1] = yr[k][2];
-        const float v = raw_f32(ypre[k], xy[k], Y.cbits, Y.w);
+        const float v = raw_f32(ypre[k], xy[k], cbits_of<CB>(Y), Y.w);
         yr[k][2] = (pin && (fl[k] & 1u)) ? v : 0.0f;
         yb[pos[k]] = yr[k][2];
       }
@@ -866,7 +867,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
         a = a - yr[k][0];
         a = a - yr[k][2];
         a = a * ih2;
-        const float v = raw_f32(gpre[k], xy[k], G.cbits, G.w) - a;
+        const float v = raw_f32(gpre[k], xy[k], cbits_of<CB>(G), G.w) - a;
         tb[tpos[k]] = (pin && (fl[k] & 4u)) ? v : 0.0f;
       }
     }
@@ -939,7 +940,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
 // also decode one node of the one-node x-y halo.  Every plane of u goes
 // through a ring of three LDS planes, so that a single barrier per step
 // separates the writes of plane j from the reads of plane j - 2.
-template <int TY, int NT, int LB, bool HI, bool GW64>
+template <int TY, int NT, int LB, bool HI, bool GW64, int CB>
 __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __restrict__ uc,
                                                     const double* __restrict__ f, int Lfull, int level, int levelc,
                                                     double ih2, PSec Gout, int TZ, int* nonfinite, double* sumsq) {
@@ -1027,8 +1028,8 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
   auto fetch_u = [&](int p) {
     const PlanePtr uq = plane_of(U, min(max(p, 0), n - 1));
 #pragma unroll
-    for (int t = 0; t < RPT; ++t) upre[t] = raw_at<LB, HI>(uq, xy_own(t), U.cbits);
-    hpre = raw_at<LB, HI>(uq, xyh, U.cbits);
+    for (int t = 0; t < RPT; ++t) upre[t] = raw_at<LB, HI>(uq, xy_own(t), cbits_of<CB>(U));
+    hpre = raw_at<LB, HI>(uq, xyh, cbits_of<CB>(U));
   };
   auto fetch_f = [&](int p) {  // f at the own columns of plane p
     const double* fp = f + static_cast<uint64_t>(min(max(p, 0), n - 1)) * fst * N * N;
@@ -1066,14 +1067,14 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         u[t][0] = u[t][1];
         u[t][1] = u[t][2];
         const int ci = ((rr >> 1) + 1) * CW + (lane >> 1) + 1;
-        const double v = raw_f64<HI>(upre[t], xy_own(t), U.cbits, U.w) +
+        const double v = raw_f64<HI>(upre[t], xy_own(t), cbits_of<CB>(U), U.w) +
                          prolong_node<double, JP, CW>(c0, c1, ci, lane & 1, rr & 1);
         u[t][2] = pin ? v : 0.0;
         ub[(rr + 1) * EXW + lane + 1] = u[t][2];
       }
       if (has_h) {
         const double v =
-            raw_f64<HI>(hpre, xyh, U.cbits, U.w) + prolong_node<double, JP, CW>(c0, c1, hci, gxh & 1, gyh & 1);
+            raw_f64<HI>(hpre, xyh, cbits_of<CB>(U), U.w) + prolong_node<double, JP, CW>(c0, c1, hci, gxh & 1, gyh & 1);
         ub[hpos] = (pin && hdom) ? v : 0.0;
       }
     }
@@ -1107,7 +1108,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
         const uint32_t xyr = (static_cast<uint32_t>(Y0 + wv + NW * t) << level) | static_cast<uint32_t>(X0);
-        store_row(gq.c, xyr, lane, m[t], Gout.cbits);
+        store_row(gq.c, xyr, lane, m[t], cbits_of<CB>(Gout));
       }
       if ((lane & ((1 << LB) - 1)) == 0) {
 #pragma unroll
@@ -1156,7 +1157,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
 // boundary column / row at node 2^l; the last chunk writes plane 2^l.
 // PAD: write the padded level layout (2^l per axis) instead, as one step of
 // the decode chain u_l = dec u'_l + P u_{l-1}.
-template <int TY, int LB, bool PAD, bool HI>
+template <int TY, int LB, bool PAD, bool HI, int CB>
 __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* __restrict__ uc, int level,
                                                          int levelc, int TZ, double* __restrict__ full) {
   constexpr int NT = 64 * TY;
@@ -1200,7 +1201,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
   };
   auto xy_own = [&]() { return (static_cast<uint32_t>(Y0 + wv) << level) | static_cast<uint32_t>(X0 + lane); };
   auto fetch_u = [&](int k) {  // unconditional: past the last plane it reads that plane again, unused
-    upre = raw_at<LB, HI>(plane_of(U, min(k, n - 1)), xy_own(), U.cbits);
+    upre = raw_at<LB, HI>(plane_of(U, min(k, n - 1)), xy_own(), cbits_of<CB>(U));
   };
   auto step = [&](auto kpc, const int k) {
     constexpr int KP = decltype(kpc)::value;
@@ -1216,7 +1217,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     const double* c1 = cs + (((k >> 1) + 1) & (NC - 1)) * CPL;
     const int ci = (wv >> 1) * CW + (lane >> 1);
     const double v =
-        raw_f64<HI>(r, xy_own(), U.cbits, U.w) + prolong_node<double, KP, CW>(c0, c1, ci, lane & 1, wv & 1);
+        raw_f64<HI>(r, xy_own(), cbits_of<CB>(U), U.w) + prolong_node<double, KP, CW>(c0, c1, ci, lane & 1, wv & 1);
     double* row = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(Y0 + wv)) * N;
     row[X0 + lane] = v;  // (the faces at 2^l of a full array are written by k_far_faces)
     if (KP == 0) cstore((k >> 1) + 1);
@@ -1268,6 +1269,26 @@ static double sec_b(const SecRef& s) {
 constexpr int kDownTY = 32, kUpTY = 32, kResTY = 32, kRRCTY = 8, kDownNT = 704, kUpNT = 768, kResNT = 512,
               kRRNT = 512, kDecTY = 8;
 
+// Container shared by the sections a kernel reads value by value, when the
+// kernels have a compile-time variant for it (8, 16 or 32 bits), else 0.
+static int common_cb(std::initializer_list<const SecRef*> ss) {
+  const int cb = (*ss.begin())->cbits;
+  for (const SecRef* s : ss)
+    if (s->cbits != cb) return 0;
+  return (cb == 8 || cb == 16 || cb == 32) ? cb : 0;
+}
+
+// Launch L(..., HI, CB) with CB = cb for the compile-time containers (only
+// without straddling codes), else the run-time variant.
+#define CMG_BY_CB(L, hi, cb, ...)                      \
+  do {                                                 \
+    if (hi) L(__VA_ARGS__, true, 0);                   \
+    else if ((cb) == 8) L(__VA_ARGS__, false, 8);      \
+    else if ((cb) == 16) L(__VA_ARGS__, false, 16);    \
+    else if ((cb) == 32) L(__VA_ARGS__, false, 32);    \
+    else L(__VA_ARGS__, false, 0);                     \
+  } while (0)
+
 static PSec psec(const SecRef& s, const Geom& g) {
   const uint64_t pv = static_cast<uint64_t>(1) << (2 * g.level);  // values per plane
   PSec p;
@@ -1288,21 +1309,16 @@ bool fused_down_smooth(const SecRef& G, const SecRef& Y, const Geom& g, int nu, 
   const double bytes = sec_b(G) + sec_b(Y);
   const PSec pg = psec(G, g), py = psec(Y, g);
   const bool hi = G.cbits == 12;
-#define CMG_DOWN(S_, LB_, HI_)                                                                                  \
-  CMG_FLAUNCH("k_down_smooth<" #S_ ">", bytes, (k_down_smooth<S_, kDownTY, kDownNT, LB_, HI_>), grid, block, st, pg, \
-              py, g.level, cp, ih2, tz)
+  const int cb = common_cb({&G, &Y});
+#define CMG_DOWN(S_, LB_, HI_, CB_)                                                                      \
+  CMG_FLAUNCH("k_down_smooth<" #S_ ">", bytes, (k_down_smooth<S_, kDownTY, kDownNT, LB_, HI_, CB_>), grid, block, \
+              st, pg, py, g.level, cp, ih2, tz)
   if (nu == 2) {
-    if (G.B == 64) {
-      if (hi) CMG_DOWN(4, 6, true); else CMG_DOWN(4, 6, false);
-    } else {
-      if (hi) CMG_DOWN(4, 5, true); else CMG_DOWN(4, 5, false);
-    }
+    if (G.B == 64) CMG_BY_CB(CMG_DOWN, hi, cb, 4, 6);
+    else CMG_BY_CB(CMG_DOWN, hi, cb, 4, 5);
   } else {
-    if (G.B == 64) {
-      if (hi) CMG_DOWN(2, 6, true); else CMG_DOWN(2, 6, false);
-    } else {
-      if (hi) CMG_DOWN(2, 5, true); else CMG_DOWN(2, 5, false);
-    }
+    if (G.B == 64) CMG_BY_CB(CMG_DOWN, hi, cb, 2, 6);
+    else CMG_BY_CB(CMG_DOWN, hi, cb, 2, 5);
   }
 #undef CMG_DOWN
   return true;
@@ -1318,21 +1334,16 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Yp) + 2.0 * sec_b(U) + 4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
   const PSec pg = psec(G, g), py = psec(Y, g), pp = psec(Yp, g), pu = psec(U, g);
   const bool hi = U.cbits == 12 || U.cbits == 64;  // the codes of u' may straddle two words
-#define CMG_UP(S_, LB_, HI_)                                                                                     \
-  CMG_FLAUNCH("k_up_smooth<" #S_ ">", bytes, (k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_>), grid, block, st, ec, pg, py, \
-              pp, pu, eout, g.level, gc.level, cp, ih2, tz)
+  const int cb = common_cb({&G, &Y, &Yp, &U});
+#define CMG_UP(S_, LB_, HI_, CB_)                                                                                 \
+  CMG_FLAUNCH("k_up_smooth<" #S_ ">", bytes, (k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_, CB_>), grid, block, st, ec, pg, \
+              py, pp, pu, eout, g.level, gc.level, cp, ih2, tz)
   if (nu == 2) {
-    if (G.B == 64) {
-      if (hi) CMG_UP(4, 6, true); else CMG_UP(4, 6, false);
-    } else {
-      if (hi) CMG_UP(4, 5, true); else CMG_UP(4, 5, false);
-    }
+    if (G.B == 64) CMG_BY_CB(CMG_UP, hi, cb, 4, 6);
+    else CMG_BY_CB(CMG_UP, hi, cb, 4, 5);
   } else {
-    if (G.B == 64) {
-      if (hi) CMG_UP(2, 6, true); else CMG_UP(2, 6, false);
-    } else {
-      if (hi) CMG_UP(2, 5, true); else CMG_UP(2, 5, false);
-    }
+    if (G.B == 64) CMG_BY_CB(CMG_UP, hi, cb, 2, 6);
+    else CMG_BY_CB(CMG_UP, hi, cb, 2, 5);
   }
 #undef CMG_UP
   return true;
@@ -1346,14 +1357,12 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Gc);
   const PSec pg = psec(G, g), py = psec(Y, g), pc = psec(Gc, gc);
   const bool hi = G.cbits == 12 || Y.cbits == 12;
-#define CMG_RR(LB_, HI_)                                                                                      \
-  CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, kRRNT, LB_, HI_>), grid, block, st, pg, py, pc, \
-              g.level, ih2, tz)
-  if (G.B == 64) {
-    if (hi) CMG_RR(6, true); else CMG_RR(6, false);
-  } else {
-    if (hi) CMG_RR(5, true); else CMG_RR(5, false);
-  }
+  const int cb = common_cb({&G, &Y});
+#define CMG_RR(LB_, HI_, CB_)                                                                                      \
+  CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, kRRNT, LB_, HI_, CB_>), grid, block, st, pg, py, \
+              pc, g.level, ih2, tz)
+  if (G.B == 64) CMG_BY_CB(CMG_RR, hi, cb, 6);
+  else CMG_BY_CB(CMG_RR, hi, cb, 5);
 #undef CMG_RR
   return true;
 }
@@ -1366,22 +1375,22 @@ bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int L
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size + sec_b(Gout);
   const PSec pu = psec(U, g), pg = psec(Gout, g);
   const bool hi = U.cbits == 12 || U.cbits == 64, g64 = Gout.cbits == 64;
-#define CMG_IR(LB_, HI_, GW_)                                                                                     \
-  CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, LB_, HI_, GW_>), grid, block, st, pu, uc, f, \
-              Lfull, g.level, gc.level, ih2, pg, tz, nonfinite, sumsq)
-#define CMG_IR2(LB_)                      \
-  if (hi) {                               \
-    if (g64) CMG_IR(LB_, true, true);     \
-    else CMG_IR(LB_, true, false);        \
-  } else {                                \
-    if (g64) CMG_IR(LB_, false, true);    \
-    else CMG_IR(LB_, false, false);       \
-  }
+  const int cb = common_cb({&U, &Gout});
+#define CMG_IR(LB_, HI_, GW_, CB_)                                                                                \
+  CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, LB_, HI_, GW_, CB_>), grid, block, st, pu, uc, \
+              f, Lfull, g.level, gc.level, ih2, pg, tz, nonfinite, sumsq)
+#define CMG_IRG(LB_, HI_, CB_)          \
+  do {                                  \
+    if (g64) CMG_IR(LB_, HI_, true, 0); \
+    else CMG_IR(LB_, HI_, false, CB_);  \
+  } while (0)
+#define CMG_IR2(LB_) CMG_BY_CB(CMG_IRG, hi, cb, LB_)
   if (U.B == 64) {
-    CMG_IR2(6)
+    CMG_IR2(6);
   } else {
-    CMG_IR2(5)
+    CMG_IR2(5);
   }
+#undef CMG_IRG
 #undef CMG_IR2
 #undef CMG_IR
   return true;
@@ -1396,14 +1405,12 @@ bool fused_decode_full(const SecRef& U, const double* uc, const Geom& g, const G
   const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDecTY), 16);
   const dim3 grid((g.n / kTX) * (g.n / kDecTY) * (g.n / tz)), block(64 * kDecTY);
   const bool hi = U.cbits == 12 || U.cbits == 64;
-#define CMG_DEC(LB_, HI_)                                                                                       \
-  CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, LB_, false, HI_>), grid, block, st, pu, uc, g.level, \
+  const int cb = common_cb({&U});
+#define CMG_DEC(LB_, HI_, CB_)                                                                                  \
+  CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, LB_, false, HI_, CB_>), grid, block, st, pu, uc, g.level, \
               gc.level, tz, full)
-  if (U.B == 64) {
-    if (hi) CMG_DEC(6, true); else CMG_DEC(6, false);
-  } else {
-    if (hi) CMG_DEC(5, true); else CMG_DEC(5, false);
-  }
+  if (U.B == 64) CMG_BY_CB(CMG_DEC, hi, cb, 6);
+  else CMG_BY_CB(CMG_DEC, hi, cb, 5);
 #undef CMG_DEC
   hipLaunchKernelGGL(k_far_faces, dim3(1024), dim3(256), 0, st, full, g.n);
   return true;
@@ -1417,14 +1424,12 @@ bool fused_decode_level(const SecRef& U, const double* uc, const Geom& g, const 
   const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDecTY), 16);
   const dim3 grid((g.n / kTX) * (g.n / kDecTY) * (g.n / tz)), block(64 * kDecTY);
   const bool hi = U.cbits == 12 || U.cbits == 64;
-#define CMG_DEC(LB_, HI_)                                                                                        \
-  CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, LB_, true, HI_>), grid, block, st, pu, uc, g.level, \
+  const int cb = common_cb({&U});
+#define CMG_DEC(LB_, HI_, CB_)                                                                                  \
+  CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, LB_, true, HI_, CB_>), grid, block, st, pu, uc, g.level, \
               gc.level, tz, out)
-  if (U.B == 64) {
-    if (hi) CMG_DEC(6, true); else CMG_DEC(6, false);
-  } else {
-    if (hi) CMG_DEC(5, true); else CMG_DEC(5, false);
-  }
+  if (U.B == 64) CMG_BY_CB(CMG_DEC, hi, cb, 6);
+  else CMG_BY_CB(CMG_DEC, hi, cb, 5);
 #undef CMG_DEC
   return true;
 }

@@ -36,6 +36,15 @@ struct PlanePtr {
   int16_t* e;
 };
 
+// Container width of a section: the kernels' compile-time value CB when
+// nonzero (every section the kernel reads value by value then shares it,
+// which removes the run-time bit arithmetic of the generic path), else the
+// section's own.
+template <int CB>
+__device__ __forceinline__ int cbits_of(const PSec& s) {
+  return CB != 0 ? CB : s.cbits;
+}
+
 // Plane p >= 0 of a section.
 __device__ __forceinline__ PlanePtr plane_of(const PSec& s, int p) {
   const uint32_t up = static_cast<uint32_t>(p);
