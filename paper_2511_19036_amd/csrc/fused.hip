@@ -201,7 +201,7 @@ __device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, in
                                               int tid) {
   constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;
   const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const PlanePtr pq = plane_of(S, po);
+  const PlanePtr pq = plane_at<CB, LB>(S, po, level);
   int m[RPW], e[RPW];
 #pragma unroll
   for (int t = 0; t < RPW; ++t) {
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
   // Codes of plane p.  Unconditional: a plane outside the level reads
   // plane 1, and its right-hand side is zeroed where it enters.
   auto fetch = [&](int p) {
-    const PlanePtr gq = plane_of(G, min(max(p, 1), n - 1));
+    const PlanePtr gq = plane_at<CB, LB>(G, min(max(p, 1), n - 1), level);
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -460,10 +460,10 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     opaque_s(X0);
     opaque_s(Y0);
     opaque_s(level);
-    opaque_s(G);
-    opaque_s(Y);
-    opaque_s(Yp);
-    opaque_s(U);
+    opaque_sec<CB>(G);
+    opaque_sec<CB>(Y);
+    opaque_sec<CB>(Yp);
+    opaque_sec<CB>(U);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       opaque(pos[k]);
@@ -522,7 +522,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   // right-hand side part zeroes its values.
   auto fetch_gy = [&](int p) {
     const int pc = min(max(p, 1), n - 1);
-    const PlanePtr gq = plane_of(G, pc), yq = plane_of(Y, pc);
+    const PlanePtr gq = plane_at<CB, LB>(G, pc, level), yq = plane_at<CB, LB>(Y, pc, level);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       gpre[k] = pair_at<LB>(gq, xy[k][0], cbits_of<CB>(G));
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   // the chunk reads a chunk plane, unused): the loads are only waited for at
   // the next step, after the stores issued before them.
   auto fetch_u = [&](int po) {
-    const PlanePtr uq = plane_of(U, min(max(po, Z0), Z0 + TZ - 1));
+    const PlanePtr uq = plane_at<CB, LB>(U, min(max(po, Z0), Z0 + TZ - 1), level);
 #pragma unroll
     for (int t = 0; t < RPW; ++t)
       upre[t] = raw_at<LB, HI>(uq, ((static_cast<uint32_t>(Y0 + row_of(t)) << level) | X0) + lane, cbits_of<CB>(U));
@@ -580,7 +580,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   };
   auto finish_store = [&](int po, const Fin& F) {
     if (po < Z0 || po >= Z0 + TZ) return;
-    const PlanePtr yq = plane_of(Yp, po), uq = plane_of(U, po);
+    const PlanePtr yq = plane_at<CB, LB>(Yp, po, level), uq = plane_at<CB, LB>(U, po, level);
 #pragma unroll
     for (int t = 0; t < RPW; ++t) {
       const int rr = out_row<NW>(wv, t);
@@ -813,12 +813,12 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
   // Codes of plane p (a plane outside the level reads a level plane; the
   // stages zero the values of planes outside it).
   auto fetch_y = [&](int p) {
-    const PlanePtr yq = plane_of(Y, min(max(p, 0), n - 1));
+    const PlanePtr yq = plane_at<CB, LB>(Y, min(max(p, 0), n - 1), level);
 #pragma unroll
     for (int k = 0; k < K; ++k) ypre[k] = raw_at<LB, HI>(yq, xy[k], cbits_of<CB>(Y));
   };
   auto fetch_g = [&](int p) {
-    const PlanePtr gq = plane_of(G, min(max(p, 1), n - 1));
+    const PlanePtr gq = plane_at<CB, LB>(G, min(max(p, 1), n - 1), level);
 #pragma unroll
     for (int k = 0; k < K; ++k) gpre[k] = raw_at<LB, HI>(gq, xy[k], cbits_of<CB>(G));
   };
@@ -829,9 +829,9 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
     opaque_s(wv);
     opaque_s(CX0);
     opaque_s(CY0);
-    opaque_s(G);
-    opaque_s(Y);
-    opaque_s(Gc);
+    opaque_sec<CB>(G);
+    opaque_sec<CB>(Y);
+    opaque_sec<0>(Gc);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       opaque(pos[k]);
@@ -1026,7 +1026,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
   // it, and for every memory operation issued before it, where the
   // branches join.  The consumers zero what lies outside.
   auto fetch_u = [&](int p) {
-    const PlanePtr uq = plane_of(U, min(max(p, 0), n - 1));
+    const PlanePtr uq = plane_at<CB, LB>(U, min(max(p, 0), n - 1), level);
 #pragma unroll
     for (int t = 0; t < RPT; ++t) upre[t] = raw_at<LB, HI>(uq, xy_own(t), cbits_of<CB>(U));
     hpre = raw_at<LB, HI>(uq, xyh, cbits_of<CB>(U));
@@ -1053,8 +1053,8 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
     opaque_s(wv);
     opaque_s(X0);
     opaque_s(Y0);
-    opaque_s(U);
-    opaque_s(Gout);
+    opaque_sec<CB>(U);
+    opaque_sec<CB>(Gout);
     if (JP == 0) cfetch((j + 2) >> 1);  // u(j + 1) needs coarse plane (j + 2) / 2
     {  // u of plane j
       const bool pin = j >= 0 && j < n;
@@ -1084,7 +1084,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
     const int p = j - 1;
     if (p >= Z0 && p < Z0 + TZ) {  // residual on plane p
       const double* ua = us + ((p + 3) % 3) * LPL;
-      const PlanePtr gq = plane_of(Gout, p);
+      const PlanePtr gq = plane_at<CB, LB>(Gout, p, level);
       // all rows are quantised in one straight-line block, then stored
       double tv[RPT];
       int64_t m[RPT];
@@ -1201,7 +1201,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
   };
   auto xy_own = [&]() { return (static_cast<uint32_t>(Y0 + wv) << level) | static_cast<uint32_t>(X0 + lane); };
   auto fetch_u = [&](int k) {  // unconditional: past the last plane it reads that plane again, unused
-    upre = raw_at<LB, HI>(plane_of(U, min(k, n - 1)), xy_own(), cbits_of<CB>(U));
+    upre = raw_at<LB, HI>(plane_at<CB, LB>(U, min(k, n - 1), level), xy_own(), cbits_of<CB>(U));
   };
   auto step = [&](auto kpc, const int k) {
     constexpr int KP = decltype(kpc)::value;
@@ -1209,7 +1209,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     opaque_s(wv);
     opaque_s(X0);
     opaque_s(Y0);
-    opaque_s(U);
+    opaque_sec<CB>(U);
     if (KP == 0) cfetch((k >> 1) + 1);  // plane k + 1 needs coarse plane k / 2 + 1
     const RawCode r = upre;
     fetch_u(k + 1);

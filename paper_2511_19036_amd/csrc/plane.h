@@ -51,6 +51,16 @@ __device__ __forceinline__ PlanePtr plane_of(const PSec& s, int p) {
   return PlanePtr{s.codes + static_cast<uint64_t>(up) * s.plane_bytes, s.exps + static_cast<uint64_t>(up) * s.plane_blks};
 }
 
+// Plane p of a section with the compile-time container CB (plane_of when
+// CB = 0): the offsets follow from the level, so the kernel needs neither
+// the plane size nor the block count of the section.
+template <int CB, int LB>
+__device__ __forceinline__ PlanePtr plane_at(const PSec& s, int p, int level) {
+  if (CB == 0) return plane_of(s, p);
+  const uint64_t v = static_cast<uint64_t>(static_cast<uint32_t>(p)) << (2 * level);  // values before plane p
+  return PlanePtr{s.codes + v * (CB / 8), s.exps + (v >> LB)};
+}
+
 // Raw words and block exponent of in-plane value xy (see RawCode).  Sections
 // carry 16 bytes of padding, so the second word is always readable.  With
 // HI = true the second word is always loaded (no branch on the container:
@@ -136,10 +146,15 @@ template <typename T>
 __device__ __forceinline__ void opaque_s(T& v) {
   asm volatile("" : "+s"(v));
 }
-__device__ __forceinline__ void opaque_s(PSec& s) {
-  opaque_s(s.plane_bytes);
-  opaque_s(s.plane_blks);
-  opaque_s(s.cbits);
+// The scalar fields of a section that a kernel with compile-time container
+// CB reads (with CB != 0 only the width).
+template <int CB = 0>
+__device__ __forceinline__ void opaque_sec(PSec& s) {
+  if (CB == 0) {
+    opaque_s(s.plane_bytes);
+    opaque_s(s.plane_blks);
+    opaque_s(s.cbits);
+  }
   opaque_s(s.w);
 }
 
