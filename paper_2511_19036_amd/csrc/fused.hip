@@ -22,7 +22,11 @@
 // HI = false the second word is neither loaded nor used).  Container-width
 // flags of the float64 helpers (C64, W64, GW64) likewise remove the 64-bit
 // paths where the launcher knows the container is at most 32 bits.
+#include <cstdint>
 #include <initializer_list>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <type_traits>
 
 #include "device.h"
@@ -1248,10 +1252,45 @@ __global__ void k_far_faces(double* __restrict__ full, int n) {
 }
 
 // =============================================================== launchers
-static int pick_tz(int n, int tiles_xy, int min_tz) {
-  int tz = n;
-  while (tz > min_tz && static_cast<int64_t>(tiles_xy) * (n / tz) < 2048) tz >>= 1;
-  return tz;
+// Workgroups of `kernel` (launched with nthreads threads) that the device
+// holds at once: resident workgroups per CU times the CUs.  Cached per
+// device and kernel.
+static int resident_slots(const void* kernel, int nthreads) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(dev, kernel);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nthreads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  return cache[key] = per_cu * cus;
+}
+
+// Planes per workgroup (chunk) of a z-march over n planes and tiles_xy
+// tiles.  A workgroup's run time is about proportional to the steps it
+// takes, step_mul * tz + halo_steps (its chunk plus the z-halo), and a
+// launch takes one such time per round of workgroups over the resident
+// slots.  The chunk, a power of two from 2 to n, minimises rounds x steps;
+// ties go to the longer chunk (less redundant halo work).  Small levels get
+// short chunks (their launches are latency bound), large ones few rounds.
+static int chunk_planes(const void* kernel, int nthreads, int n, int tiles_xy, int step_mul, int halo_steps) {
+  const int64_t slots = resident_slots(kernel, nthreads);
+  int best = n;
+  int64_t best_cost = INT64_MAX;
+  for (int tz = n; tz >= 2; tz >>= 1) {
+    const int64_t wgs = static_cast<int64_t>(tiles_xy) * (n / tz);
+    const int64_t cost = ((wgs + slots - 1) / slots) * (static_cast<int64_t>(step_mul) * tz + halo_steps);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = tz;
+    }
+  }
+  return best;
 }
 
 static double sec_b(const SecRef& s) {
@@ -1304,15 +1343,19 @@ static PSec psec(const SecRef& s, const Geom& g) {
 bool fused_down_smooth(const SecRef& G, const SecRef& Y, const Geom& g, int nu, float cp, float ih2,
                        hipStream_t st) {
   if (g.dim != 3 || g.n < kTX || (nu != 1 && nu != 2) || (G.B != 32 && G.B != 64) || Y.B != G.B) return false;
-  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDownTY), 16);
-  const dim3 grid((g.n / kTX) * (g.n / kDownTY) * (g.n / tz)), block(kDownNT);
+  const int tiles = (g.n / kTX) * (g.n / kDownTY);
+  const dim3 block(kDownNT);
   const double bytes = sec_b(G) + sec_b(Y);
   const PSec pg = psec(G, g), py = psec(Y, g);
   const bool hi = G.cbits == 12;
   const int cb = common_cb({&G, &Y});
-#define CMG_DOWN(S_, LB_, HI_, CB_)                                                                      \
-  CMG_FLAUNCH("k_down_smooth<" #S_ ">", bytes, (k_down_smooth<S_, kDownTY, kDownNT, LB_, HI_, CB_>), grid, block, \
-              st, pg, py, g.level, cp, ih2, tz)
+#define CMG_DOWN(S_, LB_, HI_, CB_)                                                                             \
+  do {                                                                                                        \
+    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_down_smooth<S_, kDownTY, kDownNT, LB_, HI_, CB_>), \
+                                kDownNT, g.n, tiles, 1, 2 * (S_) + 2);                                        \
+    CMG_FLAUNCH("k_down_smooth<" #S_ ">", bytes, (k_down_smooth<S_, kDownTY, kDownNT, LB_, HI_, CB_>),           \
+                dim3(tiles * (g.n / tz)), block, st, pg, py, g.level, cp, ih2, tz);                           \
+  } while (0)
   if (nu == 2) {
     if (G.B == 64) CMG_BY_CB(CMG_DOWN, hi, cb, 4, 6);
     else CMG_BY_CB(CMG_DOWN, hi, cb, 4, 5);
@@ -1329,15 +1372,19 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
   if (g.dim != 3 || g.n < kTX || (nu != 1 && nu != 2) || (G.B != 32 && G.B != 64) || Y.B != G.B || Yp.B != G.B ||
       U.B != G.B)
     return false;
-  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kUpTY), 16);
-  const dim3 grid((g.n / kTX) * (g.n / kUpTY) * (g.n / tz)), block(kUpNT);
+  const int tiles = (g.n / kTX) * (g.n / kUpTY);
+  const dim3 block(kUpNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Yp) + 2.0 * sec_b(U) + 4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
   const PSec pg = psec(G, g), py = psec(Y, g), pp = psec(Yp, g), pu = psec(U, g);
   const bool hi = U.cbits == 12 || U.cbits == 64;  // the codes of u' may straddle two words
   const int cb = common_cb({&G, &Y, &Yp, &U});
-#define CMG_UP(S_, LB_, HI_, CB_)                                                                                 \
-  CMG_FLAUNCH("k_up_smooth<" #S_ ">", bytes, (k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_, CB_>), grid, block, st, ec, pg, \
-              py, pp, pu, eout, g.level, gc.level, cp, ih2, tz)
+#define CMG_UP(S_, LB_, HI_, CB_)                                                                                \
+  do {                                                                                                           \
+    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_, CB_>), kUpNT, \
+                                g.n, tiles, 1, 2 * (S_) + 2);                                                    \
+    CMG_FLAUNCH("k_up_smooth<" #S_ ">", bytes, (k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_, CB_>),                     \
+                dim3(tiles * (g.n / tz)), block, st, ec, pg, py, pp, pu, eout, g.level, gc.level, cp, ih2, tz);  \
+  } while (0)
   if (nu == 2) {
     if (G.B == 64) CMG_BY_CB(CMG_UP, hi, cb, 4, 6);
     else CMG_BY_CB(CMG_UP, hi, cb, 4, 5);
@@ -1352,15 +1399,19 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
 bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, const Geom& g, const Geom& gc,
                           float ih2, hipStream_t st) {
   if (g.dim != 3 || gc.n < kTX || (G.B != 32 && G.B != 64) || Y.B != G.B || Gc.B != G.B) return false;
-  const int tz = pick_tz(gc.n, (gc.n / kTX) * (gc.n / kRRCTY), 8);
-  const dim3 grid((gc.n / kTX) * (gc.n / kRRCTY) * (gc.n / tz)), block(kRRNT);
+  const int tiles = (gc.n / kTX) * (gc.n / kRRCTY);
+  const dim3 block(kRRNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Gc);
   const PSec pg = psec(G, g), py = psec(Y, g), pc = psec(Gc, gc);
   const bool hi = G.cbits == 12 || Y.cbits == 12;
   const int cb = common_cb({&G, &Y});
-#define CMG_RR(LB_, HI_, CB_)                                                                                      \
-  CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, kRRNT, LB_, HI_, CB_>), grid, block, st, pg, py, \
-              pc, g.level, ih2, tz)
+#define CMG_RR(LB_, HI_, CB_)                                                                                   \
+  do {                                                                                                          \
+    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_resid_restrict<kRRCTY, kRRNT, LB_, HI_, CB_>), \
+                                kRRNT, gc.n, tiles, 2, 4);                                                      \
+    CMG_FLAUNCH("k_resid_restrict", bytes, (k_resid_restrict<kRRCTY, kRRNT, LB_, HI_, CB_>),                      \
+                dim3(tiles * (gc.n / tz)), block, st, pg, py, pc, g.level, ih2, tz);                            \
+  } while (0)
   if (G.B == 64) CMG_BY_CB(CMG_RR, hi, cb, 6);
   else CMG_BY_CB(CMG_RR, hi, cb, 5);
 #undef CMG_RR
@@ -1370,15 +1421,20 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
                        double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st) {
   if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64) || Gout.B != U.B) return false;
-  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kResTY), 16);
-  const dim3 grid((g.n / kTX) * (g.n / kResTY) * (g.n / tz)), block(kResNT);
+  const int tiles = (g.n / kTX) * (g.n / kResTY);
+  const dim3 block(kResNT);
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size + sec_b(Gout);
   const PSec pu = psec(U, g), pg = psec(Gout, g);
   const bool hi = U.cbits == 12 || U.cbits == 64, g64 = Gout.cbits == 64;
   const int cb = common_cb({&U, &Gout});
-#define CMG_IR(LB_, HI_, GW_, CB_)                                                                                \
-  CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, LB_, HI_, GW_, CB_>), grid, block, st, pu, uc, \
-              f, Lfull, g.level, gc.level, ih2, pg, tz, nonfinite, sumsq)
+#define CMG_IR(LB_, HI_, GW_, CB_)                                                                                 \
+  do {                                                                                                             \
+    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_ir_residual<kResTY, kResNT, LB_, HI_, GW_, CB_>), \
+                                kResNT, g.n, tiles, 1, 2);                                                         \
+    CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, LB_, HI_, GW_, CB_>),                         \
+                dim3(tiles * (g.n / tz)), block, st, pu, uc, f, Lfull, g.level, gc.level, ih2, pg, tz, nonfinite,  \
+                sumsq);                                                                                            \
+  } while (0)
 #define CMG_IRG(LB_, HI_, CB_)          \
   do {                                  \
     if (g64) CMG_IR(LB_, HI_, true, 0); \
@@ -1402,13 +1458,17 @@ bool fused_decode_full(const SecRef& U, const double* uc, const Geom& g, const G
   const int64_t N = g.n + 1;
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * N * N * N;
   const PSec pu = psec(U, g);
-  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDecTY), 16);
-  const dim3 grid((g.n / kTX) * (g.n / kDecTY) * (g.n / tz)), block(64 * kDecTY);
+  const int tiles = (g.n / kTX) * (g.n / kDecTY);
+  const dim3 block(64 * kDecTY);
   const bool hi = U.cbits == 12 || U.cbits == 64;
   const int cb = common_cb({&U});
-#define CMG_DEC(LB_, HI_, CB_)                                                                                  \
-  CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, LB_, false, HI_, CB_>), grid, block, st, pu, uc, g.level, \
-              gc.level, tz, full)
+#define CMG_DEC(LB_, HI_, CB_)                                                                                 \
+  do {                                                                                                        \
+    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_decode_full<kDecTY, LB_, false, HI_, CB_>),  \
+                                64 * kDecTY, g.n, tiles, 1, 2);                                               \
+    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, LB_, false, HI_, CB_>), dim3(tiles * (g.n / tz)), \
+                block, st, pu, uc, g.level, gc.level, tz, full);                                              \
+  } while (0)
   if (U.B == 64) CMG_BY_CB(CMG_DEC, hi, cb, 6);
   else CMG_BY_CB(CMG_DEC, hi, cb, 5);
 #undef CMG_DEC
@@ -1421,13 +1481,17 @@ bool fused_decode_level(const SecRef& U, const double* uc, const Geom& g, const 
   if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64)) return false;
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size;
   const PSec pu = psec(U, g);
-  const int tz = pick_tz(g.n, (g.n / kTX) * (g.n / kDecTY), 16);
-  const dim3 grid((g.n / kTX) * (g.n / kDecTY) * (g.n / tz)), block(64 * kDecTY);
+  const int tiles = (g.n / kTX) * (g.n / kDecTY);
+  const dim3 block(64 * kDecTY);
   const bool hi = U.cbits == 12 || U.cbits == 64;
   const int cb = common_cb({&U});
 #define CMG_DEC(LB_, HI_, CB_)                                                                                  \
-  CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, LB_, true, HI_, CB_>), grid, block, st, pu, uc, g.level, \
-              gc.level, tz, out)
+  do {                                                                                                         \
+    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_decode_full<kDecTY, LB_, true, HI_, CB_>),    \
+                                64 * kDecTY, g.n, tiles, 1, 2);                                                \
+    CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, LB_, true, HI_, CB_>), dim3(tiles * (g.n / tz)), \
+                block, st, pu, uc, g.level, gc.level, tz, out);                                                \
+  } while (0)
   if (U.B == 64) CMG_BY_CB(CMG_DEC, hi, cb, 6);
   else CMG_BY_CB(CMG_DEC, hi, cb, 5);
 #undef CMG_DEC
