@@ -390,10 +390,30 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
 // needs y' at d + 1 for d <= S - 1, so the halo is S.
 //
 // Interpolation weights are powers of two: 2^-(number of odd coordinates);
-// the weighted coarse neighbours are summed in C order (z, y, x).
-template <typename T, int PK, int CW>
+// the weighted coarse neighbours are summed in C order (z, y, x).  With
+// LANEP (the x parity varies over the lanes) every neighbour is added with
+// its weight or a zero weight, which is cheaper than selecting the sums: a
+// zero term (of a finite value; a non-finite one ends the solve with an
+// error) leaves the sum unchanged, as no sum is ever -0 (the coarse values
+// are sums of decoded codes, which are +0 or nonzero).  Otherwise (parities
+// fixed per column at compile time) the terms are selected.
+template <typename T, int PK, int CW, bool LANEP = false>
 __device__ __forceinline__ T prolong_node(const T* c0, const T* c1, int ci, bool px, bool py) {
   const T w = (px ? T(0.5) : T(1)) * (py ? T(0.5) : T(1)) * (PK ? T(0.5) : T(1));
+  if (LANEP) {
+    const T wx = px ? w : T(0), wy = py ? w : T(0), wxy = (px && py) ? w : T(0);
+    T s = w * c0[ci];
+    s = s + wx * c0[ci + 1];
+    s = s + wy * c0[ci + CW];
+    s = s + wxy * c0[ci + CW + 1];
+    if (PK) {
+      s = s + w * c1[ci];
+      s = s + wx * c1[ci + 1];
+      s = s + wy * c1[ci + CW];
+      s = s + wxy * c1[ci + CW + 1];
+    }
+    return s;
+  }
   T s = w * c0[ci];
   {
     const T t = w * c0[ci + 1];
@@ -1072,13 +1092,13 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         u[t][1] = u[t][2];
         const int ci = ((rr >> 1) + 1) * CW + (lane >> 1) + 1;
         const double v = raw_f64<HI>(upre[t], xy_own(t), cbits_of<CB>(U), U.w) +
-                         prolong_node<double, JP, CW>(c0, c1, ci, lane & 1, rr & 1);
+                         prolong_node<double, JP, CW, true>(c0, c1, ci, lane & 1, rr & 1);
         u[t][2] = pin ? v : 0.0;
         ub[(rr + 1) * EXW + lane + 1] = u[t][2];
       }
       if (has_h) {
         const double v =
-            raw_f64<HI>(hpre, xyh, cbits_of<CB>(U), U.w) + prolong_node<double, JP, CW>(c0, c1, hci, gxh & 1, gyh & 1);
+            raw_f64<HI>(hpre, xyh, cbits_of<CB>(U), U.w) + prolong_node<double, JP, CW, true>(c0, c1, hci, gxh & 1, gyh & 1);
         ub[hpos] = (pin && hdom) ? v : 0.0;
       }
     }
@@ -1221,7 +1241,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     const double* c1 = cs + (((k >> 1) + 1) & (NC - 1)) * CPL;
     const int ci = (wv >> 1) * CW + (lane >> 1);
     const double v =
-        raw_f64<HI>(r, xy_own(), cbits_of<CB>(U), U.w) + prolong_node<double, KP, CW>(c0, c1, ci, lane & 1, wv & 1);
+        raw_f64<HI>(r, xy_own(), cbits_of<CB>(U), U.w) + prolong_node<double, KP, CW, true>(c0, c1, ci, lane & 1, wv & 1);
     double* row = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(Y0 + wv)) * N;
     row[X0 + lane] = v;  // (the faces at 2^l of a full array are written by k_far_faces)
     if (KP == 0) cstore((k >> 1) + 1);
