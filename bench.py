@@ -22,6 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+# VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes per SIMD), 2.4 GHz.
+VALU_PEAK = 256 * 4 / 4 * 2.4e9  # wave instructions per second
 CALIB_BYTES = 1 << 30  # size of the calibration copy of the --pmc-pass mode
 
 
@@ -45,11 +48,11 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def stored_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of known size), or
-    None when no summary exists or the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_fused_kernels_poisson3d_1025.md")
+def _stored_column(fname, kernel, col):
+    """Column `col` of `kernel`'s row in a committed counter summary under
+    profiles/, or None when the summary is missing or the kernel sources
+    changed since its counters were taken."""
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     digest, per_launch = None, {}
@@ -57,15 +60,27 @@ def stored_traffic(kernel):
         for line in fh:
             if line.startswith("source_sha256:"):
                 digest = line.split(":", 1)[1].strip()
-            elif line.startswith("| `") and line.count("|") >= 8:
+            elif line.startswith("| `") and line.count("|") > col + 1:
                 cells = [c.strip() for c in line.strip().strip("|").split("|")]
                 try:
-                    per_launch[cells[0].strip("`")] = float(cells[6])
+                    per_launch[cells[0].strip("`")] = float(cells[col])
                 except ValueError:
                     pass
     if digest != kernel_source_digest():
         return None
     return per_launch.get(kernel)
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
+    against a copy of known size) from the committed counter summary."""
+    return _stored_column("hbm_traffic_fused_kernels_poisson3d_1025.md", kernel, 5)
+
+
+def stored_valu(kernel):
+    """VALU wave instructions per launch of `kernel` (SQ_INSTS_VALU) from the
+    committed counter summary."""
+    return _stored_column("valu_issue_fused_kernels_poisson3d_1025.md", kernel, 2)
 
 
 def discretisation_check(u, L, dim=3):
@@ -298,6 +313,14 @@ def main():
                     frac=achieved / HBM_PEAK, traffic=traffic,
                     bytes_per_launch=rep["bytes"] / rep["launches"],
                     avg_launch_us=1e3 * rep["ms"] / rep["launches"], launches=rep["launches"])
+    # the same kernel against its instruction-issue ceiling: counted VALU
+    # instructions per launch over the live average launch time
+    valu = stored_valu(dom)
+    issue = None
+    if valu is not None:
+        avg_s = 1e-3 * rep["ms"] / rep["launches"]
+        issue = dict(kernel=dom, valu_insts_per_launch=valu, peak_insts_per_s=VALU_PEAK,
+                     frac=valu / VALU_PEAK / avg_s)
 
     plain = None
     if not args.no_plain:
@@ -387,6 +410,7 @@ def main():
         "logical_bits_per_dof": mem["logical_bits_per_dof"],
         "setup_s": setup_s,
         "roofline": roofline,
+        "issue": issue,
         "kernels": [dict(kernel=r["kernel"], ms=r["ms"], launches=r["launches"],
                          gbs=(r["bytes"] / (r["ms"] * 1e-3) / 1e9) if r["ms"] > 0 else None)
                     for r in per_kernel[:12]],
