@@ -589,8 +589,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
       F.my[t] = quant_f32<LB>(ob[rr * kTX + lane], Yp.w, lane, &F.ey[t]);
       const double dy = ldexp(static_cast<double>(F.my[t]), F.ey[t] - (Yp.w - 1));  // codes 0 in a zero block
-      const double vu = raw_f64<HI>(upre[t], xyl, cbits_of<CB>(U), U.w) + dy;
-      F.mu[t] = quant_f64<LB, HI>(vu, U.w, lane, &F.eu[t]);
+      const double vu = raw_f64<may64<CB, HI>()>(upre[t], xyl, cbits_of<CB>(U), U.w) + dy;
+      F.mu[t] = quant_f64<LB, may64<CB, HI>()>(vu, U.w, lane, &F.eu[t]);
       F.ev[t] = static_cast<float>(dy);
     }
     if (eout != nullptr) {
@@ -1091,14 +1091,14 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         u[t][0] = u[t][1];
         u[t][1] = u[t][2];
         const int ci = ((rr >> 1) + 1) * CW + (lane >> 1) + 1;
-        const double v = raw_f64<HI>(upre[t], xy_own(t), cbits_of<CB>(U), U.w) +
+        const double v = raw_f64<may64<CB, HI>()>(upre[t], xy_own(t), cbits_of<CB>(U), U.w) +
                          prolong_node<double, JP, CW, true>(c0, c1, ci, lane & 1, rr & 1);
         u[t][2] = pin ? v : 0.0;
         ub[(rr + 1) * EXW + lane + 1] = u[t][2];
       }
       if (has_h) {
         const double v =
-            raw_f64<HI>(hpre, xyh, cbits_of<CB>(U), U.w) + prolong_node<double, JP, CW, true>(c0, c1, hci, gxh & 1, gyh & 1);
+            raw_f64<may64<CB, HI>()>(hpre, xyh, cbits_of<CB>(U), U.w) + prolong_node<double, JP, CW, true>(c0, c1, hci, gxh & 1, gyh & 1);
         ub[hpos] = (pin && hdom) ? v : 0.0;
       }
     }
@@ -1241,7 +1241,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     const double* c1 = cs + (((k >> 1) + 1) & (NC - 1)) * CPL;
     const int ci = (wv >> 1) * CW + (lane >> 1);
     const double v =
-        raw_f64<HI>(r, xy_own(), cbits_of<CB>(U), U.w) + prolong_node<double, KP, CW, true>(c0, c1, ci, lane & 1, wv & 1);
+        raw_f64<may64<CB, HI>()>(r, xy_own(), cbits_of<CB>(U), U.w) + prolong_node<double, KP, CW, true>(c0, c1, ci, lane & 1, wv & 1);
     double* row = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(Y0 + wv)) * N;
     row[X0 + lane] = v;  // (the faces at 2^l of a full array are written by k_far_faces)
     if (KP == 0) cstore((k >> 1) + 1);
@@ -1338,19 +1338,20 @@ constexpr int kDownTY = 32, kUpTY = 32, kResTY = 32, kRRCTY = 8, kDownNT = 704, 
               kRRNT = 512, kDecTY = 8;
 
 // Container shared by the sections a kernel reads value by value, when the
-// kernels have a compile-time variant for it (8, 16 or 32 bits), else 0.
+// kernels have a compile-time variant for it (8, 12, 16 or 32 bits), else 0.
 static int common_cb(std::initializer_list<const SecRef*> ss) {
   const int cb = (*ss.begin())->cbits;
   for (const SecRef* s : ss)
     if (s->cbits != cb) return 0;
-  return (cb == 8 || cb == 16 || cb == 32) ? cb : 0;
+  return (cb == 8 || cb == 12 || cb == 16 || cb == 32) ? cb : 0;
 }
 
-// Launch L(..., HI, CB) with CB = cb for the compile-time containers (only
-// without straddling codes), else the run-time variant.
+// Launch L(..., HI, CB) with CB = cb for the compile-time containers (the
+// 12-bit one with straddling codes), else the run-time variant.
 #define CMG_BY_CB(L, hi, cb, ...)                      \
   do {                                                 \
-    if (hi) L(__VA_ARGS__, true, 0);                   \
+    if (hi && (cb) == 12) L(__VA_ARGS__, true, 12);    \
+    else if (hi) L(__VA_ARGS__, true, 0);              \
     else if ((cb) == 8) L(__VA_ARGS__, false, 8);      \
     else if ((cb) == 16) L(__VA_ARGS__, false, 16);    \
     else if ((cb) == 32) L(__VA_ARGS__, false, 32);    \

@@ -45,6 +45,13 @@ __device__ __forceinline__ int cbits_of(const PSec& s) {
   return CB != 0 ? CB : s.cbits;
 }
 
+// Whether a code of a kernel with compile-time container CB (0: run-time)
+// and straddle flag HI may need more than 32 bits.
+template <int CB, bool HI>
+constexpr bool may64() {
+  return CB == 0 ? HI : CB == 64;
+}
+
 // Plane p >= 0 of a section.
 __device__ __forceinline__ PlanePtr plane_of(const PSec& s, int p) {
   const uint32_t up = static_cast<uint32_t>(p);
@@ -58,7 +65,7 @@ template <int CB, int LB>
 __device__ __forceinline__ PlanePtr plane_at(const PSec& s, int p, int level) {
   if (CB == 0) return plane_of(s, p);
   const uint64_t v = static_cast<uint64_t>(static_cast<uint32_t>(p)) << (2 * level);  // values before plane p
-  return PlanePtr{s.codes + v * (CB / 8), s.exps + (v >> LB)};
+  return PlanePtr{s.codes + ((v * CB) >> 3), s.exps + (v >> LB)};
 }
 
 // Raw words and block exponent of in-plane value xy (see RawCode).  Sections
