@@ -239,7 +239,7 @@ def main():
                     help="for counter runs: one warm-up solve, a calibration copy of 1 GiB, one solve; no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the solver is a single-GPU level sweep); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
