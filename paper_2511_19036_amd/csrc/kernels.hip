@@ -195,15 +195,21 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(const T* __restrict__ y, co
   ynew[idx] = y[idx] + c * r;
 }
 
+// One thread per node of the colour: thread t takes node i = 2 (t mod n/2)
+// + ((j + k + colour) & 1) of row t div (n/2), so every lane of a wave has
+// a node to update (n is even on every level).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_rbgs(T* __restrict__ y, const T* __restrict__ rhs,
                                                    const T* __restrict__ kap, Geom g, T inv_h2, T cpois,
                                                    int colour) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  if (idx >= g.size) return;
-  int i, j, k;
-  unflatten(g, idx, i, j, k);
-  if (!is_interior(g, i, j, k) || ((i + j + k) & 1) != colour) return;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (t >= (g.size >> 1)) return;
+  const int64_t row = t >> (g.level - 1);  // j + n k
+  const int j = static_cast<int>(row & (g.n - 1));
+  const int k = g.dim == 3 ? static_cast<int>(row >> g.level) : 0;
+  const int i = 2 * static_cast<int>(t & ((g.n >> 1) - 1)) + ((j + k + colour) & 1);
+  if (!is_interior(g, i, j, k)) return;
+  const int64_t idx = flat(g, i, j, k);
   const T r = rhs[idx] - apply_A(y, kap, g, i, j, k, inv_h2);
   const T c = smooth_coeff(kap, g, i, j, k, inv_h2, cpois, T(1));
   y[idx] = y[idx] + c * r;
@@ -437,7 +443,7 @@ template <typename T>
 void launch_rbgs(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, int colour, hipStream_t st) {
   // reads y everywhere and rhs on one colour, writes y on one colour
   const double b = (2.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
-  CMG_TLAUNCH(tname("k_rbgs", TName<T>::s).c_str(), b, k_rbgs<T>, g.size, st, y, rhs, kap, g, inv_h2, cpois,
+  CMG_TLAUNCH(tname("k_rbgs", TName<T>::s).c_str(), b, k_rbgs<T>, g.size / 2, st, y, rhs, kap, g, inv_h2, cpois,
               colour);
 }
 template <typename T>
