@@ -115,8 +115,63 @@ __global__ void __launch_bounds__(kThreads) k_correct(SecRef u, SecRef y) {
 }
 
 // ============================================================ level kernels
-// out = rhs - A u on interior nodes, 0 on the boundary.
+// Diffusion operator at interior node (i, j, k): (A u)_p and, when diag is
+// not null, the diagonal of A.  The same arithmetic as apply_A and diag_A
+// (edge coefficients as in edge_coeffs, same order), but each of the 2^d
+// cells around the node is loaded once, at a fixed offset from the first.
 template <typename T>
+__device__ __forceinline__ T diffusion_at(const T* __restrict__ u, const T* __restrict__ kap, const Geom& g, int i,
+                                          int j, int k, T inv_h2, T* diag) {
+  const int64_t n = g.n;
+  const int64_t p = flat(g, i, j, k);
+  const T up = u[p];
+  T ke[6], nb[6];
+  if (g.dim == 3) {
+    const int64_t b = flat(g, i - 1, j - 1, k - 1), n2 = n * n;
+    const T c000 = kap[b], c100 = kap[b + 1], c010 = kap[b + n], c110 = kap[b + n + 1];
+    const T c001 = kap[b + n2], c101 = kap[b + n2 + 1], c011 = kap[b + n2 + n], c111 = kap[b + n2 + n + 1];
+    const T q = T(0.25);
+    ke[0] = (((c000 + c010) + c001) + c011) * q;
+    ke[1] = (((c100 + c110) + c101) + c111) * q;
+    ke[2] = (((c000 + c100) + c001) + c101) * q;
+    ke[3] = (((c010 + c110) + c011) + c111) * q;
+    ke[4] = (((c000 + c100) + c010) + c110) * q;
+    ke[5] = (((c001 + c101) + c011) + c111) * q;
+    nb[0] = u[p - 1];
+    nb[1] = i + 1 < g.n ? u[p + 1] : T(0);
+    nb[2] = u[p - n];
+    nb[3] = j + 1 < g.n ? u[p + n] : T(0);
+    nb[4] = u[p - n2];
+    nb[5] = k + 1 < g.n ? u[p + n2] : T(0);
+  } else {
+    const int64_t b = flat(g, i - 1, j - 1, 0);
+    const T c00 = kap[b], c10 = kap[b + 1], c01 = kap[b + n], c11 = kap[b + n + 1];
+    const T q = T(0.5);
+    ke[0] = (c00 + c01) * q;
+    ke[1] = (c10 + c11) * q;
+    ke[2] = (c00 + c10) * q;
+    ke[3] = (c01 + c11) * q;
+    nb[0] = u[p - 1];
+    nb[1] = i + 1 < g.n ? u[p + 1] : T(0);
+    nb[2] = u[p - n];
+    nb[3] = j + 1 < g.n ? u[p + n] : T(0);
+  }
+  const int nd = 2 * g.dim;
+  T s = ke[0] * (up - nb[0]);
+  for (int t = 1; t < nd; ++t) s = s + ke[t] * (up - nb[t]);
+  if (diag != nullptr) {
+    T d = ke[0];
+    for (int t = 1; t < nd; ++t) d = d + ke[t];
+    *diag = d * inv_h2;
+  }
+  return s * inv_h2;
+}
+
+// out = rhs - A u on interior nodes, 0 on the boundary.
+// DIFF: the diffusion operator (kap holds the cell coefficients), else
+// Poisson (kap is null); one instantiation each, so neither carries the
+// other's code.
+template <typename T, bool DIFF>
 __global__ void __launch_bounds__(kThreads) k_rhs_minus_A(const T* __restrict__ rhs, const T* __restrict__ u,
                                                           const T* __restrict__ kap, Geom g, T inv_h2,
                                                           T* __restrict__ out) {
@@ -124,7 +179,12 @@ __global__ void __launch_bounds__(kThreads) k_rhs_minus_A(const T* __restrict__ 
   if (idx >= g.size) return;
   int i, j, k;
   unflatten(g, idx, i, j, k);
-  out[idx] = is_interior(g, i, j, k) ? rhs[idx] - apply_A(u, kap, g, i, j, k, inv_h2) : T(0);
+  if (!is_interior(g, i, j, k)) {
+    out[idx] = T(0);
+    return;
+  }
+  const T au = DIFF ? diffusion_at<T>(u, kap, g, i, j, k, inv_h2, nullptr) : apply_A<T>(u, nullptr, g, i, j, k, inv_h2);
+  out[idx] = rhs[idx] - au;
 }
 
 template <typename T>
@@ -178,7 +238,7 @@ __global__ void __launch_bounds__(kThreads) k_restrict(const T* __restrict__ fin
   coarse[idx] = s;
 }
 
-template <typename T>
+template <typename T, bool DIFF>
 __global__ void __launch_bounds__(kThreads) k_jacobi(const T* __restrict__ y, const T* __restrict__ rhs,
                                                      const T* __restrict__ kap, Geom g, T inv_h2, T cpois,
                                                      T omega, T* __restrict__ ynew) {
@@ -190,15 +250,21 @@ __global__ void __launch_bounds__(kThreads) k_jacobi(const T* __restrict__ y, co
     ynew[idx] = T(0);
     return;
   }
-  const T r = rhs[idx] - apply_A(y, kap, g, i, j, k, inv_h2);
-  const T c = smooth_coeff(kap, g, i, j, k, inv_h2, cpois, omega);
-  ynew[idx] = y[idx] + c * r;
+  if (DIFF) {
+    T d;
+    const T r = rhs[idx] - diffusion_at<T>(y, kap, g, i, j, k, inv_h2, &d);
+    const T c = omega / d;
+    ynew[idx] = y[idx] + c * r;
+  } else {
+    const T r = rhs[idx] - apply_A<T>(y, nullptr, g, i, j, k, inv_h2);
+    ynew[idx] = y[idx] + cpois * r;
+  }
 }
 
 // One thread per node of the colour: thread t takes node i = 2 (t mod n/2)
 // + ((j + k + colour) & 1) of row t div (n/2), so every lane of a wave has
 // a node to update (n is even on every level).
-template <typename T>
+template <typename T, bool DIFF>
 __global__ void __launch_bounds__(kThreads) k_rbgs(T* __restrict__ y, const T* __restrict__ rhs,
                                                    const T* __restrict__ kap, Geom g, T inv_h2, T cpois,
                                                    int colour) {
@@ -210,9 +276,15 @@ __global__ void __launch_bounds__(kThreads) k_rbgs(T* __restrict__ y, const T* _
   const int i = 2 * static_cast<int>(t & ((g.n >> 1) - 1)) + ((j + k + colour) & 1);
   if (!is_interior(g, i, j, k)) return;
   const int64_t idx = flat(g, i, j, k);
-  const T r = rhs[idx] - apply_A(y, kap, g, i, j, k, inv_h2);
-  const T c = smooth_coeff(kap, g, i, j, k, inv_h2, cpois, T(1));
-  y[idx] = y[idx] + c * r;
+  if (DIFF) {
+    T d;
+    const T r = rhs[idx] - diffusion_at<T>(y, kap, g, i, j, k, inv_h2, &d);
+    const T c = T(1) / d;
+    y[idx] = y[idx] + c * r;
+  } else {
+    const T r = rhs[idx] - apply_A<T>(y, nullptr, g, i, j, k, inv_h2);
+    y[idx] = y[idx] + cpois * r;
+  }
 }
 
 template <typename T>
@@ -414,8 +486,12 @@ void launch_correct(const SecRef& u, const SecRef& y, hipStream_t st) {
 template <typename T>
 void launch_rhs_minus_A(const T* rhs, const T* u, const T* kap, const Geom& g, T inv_h2, T* out, hipStream_t st) {
   const double b = (3.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
-  CMG_TLAUNCH(tname("k_rhs_minus_A", TName<T>::s).c_str(), b, k_rhs_minus_A<T>, g.size, st, rhs, u, kap, g, inv_h2,
-              out);
+  if (kap != nullptr)
+    CMG_TLAUNCH(tname("k_rhs_minus_A", TName<T>::s).c_str(), b, (k_rhs_minus_A<T, true>), g.size, st, rhs, u, kap, g,
+                inv_h2, out);
+  else
+    CMG_TLAUNCH(tname("k_rhs_minus_A", TName<T>::s).c_str(), b, (k_rhs_minus_A<T, false>), g.size, st, rhs, u, kap,
+                g, inv_h2, out);
 }
 template <typename T>
 void launch_prolong(const T* coarse, const Geom& gf, const Geom& gc, T* fine, hipStream_t st) {
@@ -436,15 +512,23 @@ template <typename T>
 void launch_jacobi(const T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, T omega, T* ynew,
                    hipStream_t st) {
   const double b = (3.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
-  CMG_TLAUNCH(tname("k_jacobi", TName<T>::s).c_str(), b, k_jacobi<T>, g.size, st, y, rhs, kap, g, inv_h2, cpois,
-              omega, ynew);
+  if (kap != nullptr)
+    CMG_TLAUNCH(tname("k_jacobi", TName<T>::s).c_str(), b, (k_jacobi<T, true>), g.size, st, y, rhs, kap, g, inv_h2,
+                cpois, omega, ynew);
+  else
+    CMG_TLAUNCH(tname("k_jacobi", TName<T>::s).c_str(), b, (k_jacobi<T, false>), g.size, st, y, rhs, kap, g, inv_h2,
+                cpois, omega, ynew);
 }
 template <typename T>
 void launch_rbgs(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, int colour, hipStream_t st) {
   // reads y everywhere and rhs on one colour, writes y on one colour
   const double b = (2.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
-  CMG_TLAUNCH(tname("k_rbgs", TName<T>::s).c_str(), b, k_rbgs<T>, g.size / 2, st, y, rhs, kap, g, inv_h2, cpois,
-              colour);
+  if (kap != nullptr)
+    CMG_TLAUNCH(tname("k_rbgs", TName<T>::s).c_str(), b, (k_rbgs<T, true>), g.size / 2, st, y, rhs, kap, g, inv_h2,
+                cpois, colour);
+  else
+    CMG_TLAUNCH(tname("k_rbgs", TName<T>::s).c_str(), b, (k_rbgs<T, false>), g.size / 2, st, y, rhs, kap, g, inv_h2,
+                cpois, colour);
 }
 template <typename T>
 void launch_add(const T* a, const T* b, T* out, int64_t n, hipStream_t st) {
