@@ -21,8 +21,8 @@ static inline dim3 grid_for(int64_t n) { return dim3(static_cast<unsigned>((n + 
 
 // ===================================================================== BFP
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_encode(const T* __restrict__ x, int64_t n, SecRef s,
-                                                     int* nonfinite) {
+__global__ void __launch_bounds__(kThreads) k_encode(const T* x, int64_t n, SecRef s, int* nonfinite, T* out,
+                                                     const T* __restrict__ add) {
   const int lane = threadIdx.x & 63;
   const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
   const int64_t limit = limit_of(s);
@@ -34,6 +34,11 @@ __global__ void __launch_bounds__(kThreads) k_encode(const T* __restrict__ x, in
   const int64_t m = quantise_lane(v, s.B, s.w, &e);
   store_codes_wave(s, base, lane, m, limit);
   if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
+  // the decoded value of the new code, as k_decode gives it (plus add)
+  if (out != nullptr && i < n) {
+    const T d = static_cast<T>(e == kZeroExp ? 0.0 : ldexp(static_cast<double>(m), e - (s.w - 1)));
+    out[i] = add != nullptr ? d + add[i] : d;
+  }
 }
 
 template <typename T>
@@ -458,7 +463,13 @@ template <typename T>
 void launch_encode(const T* x, int64_t n, const SecRef& s, int* nonfinite, hipStream_t st) {
   const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
   CMG_TLAUNCH(tname("k_encode", TName<T>::s).c_str(), n * sizeof(T) + sec_bytes(s), k_encode<T>, limit, st, x, n,
-              s, nonfinite);
+              s, nonfinite, static_cast<T*>(nullptr), static_cast<const T*>(nullptr));
+}
+template <typename T>
+void launch_encode_dec(const T* x, int64_t n, const SecRef& s, int* nonfinite, T* out, const T* add, hipStream_t st) {
+  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  const double b = n * sizeof(T) * (out != nullptr ? (add != nullptr ? 3.0 : 2.0) : 1.0) + sec_bytes(s);
+  CMG_TLAUNCH(tname("k_encode", TName<T>::s).c_str(), b, k_encode<T>, limit, st, x, n, s, nonfinite, out, add);
 }
 template <typename T>
 void launch_decode(const SecRef& s, int64_t n, T* x, hipStream_t st) {
@@ -584,6 +595,7 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
 
 #define CMG_INST_T(T)                                                                                   \
   template void launch_encode<T>(const T*, int64_t, const SecRef&, int*, hipStream_t);                  \
+  template void launch_encode_dec<T>(const T*, int64_t, const SecRef&, int*, T*, const T*, hipStream_t); \
   template void launch_decode<T>(const SecRef&, int64_t, T*, hipStream_t);                              \
   template void launch_rhs_minus_A<T>(const T*, const T*, const T*, const Geom&, T, T*, hipStream_t);   \
   template void launch_prolong<T>(const T*, const Geom&, const Geom&, T*, hipStream_t);                 \

@@ -335,9 +335,10 @@ void vcycle_correct(cmg_ctx c, int Lp) {
       launch_fill<T>(yf, T(0), F.g.size, st);
       KCK();
       smooth<T>(c, l, yf, gf, static_cast<T*>(F.ef), c->o.nu_pre);
-      launch_encode<T>(yf, F.g.size, F.Y.ref(), nf, st);
+      launch_encode_dec<T>(yf, F.g.size, F.Y.ref(), nf, yf, nullptr, st);  // y' = Q(y); yf = dec y'
+    } else {
+      launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
     }
-    launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
     launch_rhs_minus_A<T>(gf, yf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);
     launch_restrict<T>(rf, C.g, F.g, static_cast<T*>(C.rf), st);
     launch_encode<T>(static_cast<T*>(C.rf), C.g.size, C.G.ref(), nf, st);
@@ -410,12 +411,9 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
     KCK();
     smooth<T>(c, l, yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
-    launch_encode<T>(yf, F.g.size, F.Yp.ref(), nf, st);
+    // y' = Q(y), and below the top level e_l = dec y' + z
+    launch_encode_dec<T>(yf, F.g.size, F.Yp.ref(), nf, l < Lp ? static_cast<T*>(F.ef) : nullptr, zf, st);
     launch_correct(F.U.ref(), F.Yp.ref(), st);
-    if (l < Lp) {
-      launch_decode<T>(F.Yp.ref(), F.g.size, yf, st);
-      launch_add<T>(yf, zf, static_cast<T*>(F.ef), F.g.size, st);
-    }
     KCK();
   }
 }
