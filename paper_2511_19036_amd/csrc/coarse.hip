@@ -38,8 +38,10 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
   auto decode64 = [&](const SecRef& s, int64_t n, double* x) {
     each(n, [&](int64_t i) { x[i] = decode_value(s, i); });
   };
-  // one wave per 64 consecutive values (one block of 64 or two of 32)
-  auto encode = [&](auto* x, int64_t n, const SecRef& s) {
+  // One wave per 64 consecutive values (one block of 64 or two of 32).
+  // With dec_out, the decoded values of the new codes (as decode() gives
+  // them, plus add[i] when add is not null) go to dec_out (which may be x).
+  auto encode = [&](auto* x, int64_t n, const SecRef& s, T* dec_out = nullptr, const T* add = nullptr) {
     const int64_t limit = limit_of(s);
     for (int64_t base = static_cast<int64_t>(wv) * 64; base < limit; base += NW * 64) {
       const int64_t i = base + lane;
@@ -49,6 +51,10 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
       const int64_t m = quantise_lane(v, s.B, s.w, &e);
       store_codes_wave(s, base, lane, m, limit);
       if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
+      if (dec_out != nullptr && i < n) {
+        const T d = static_cast<T>(e == kZeroExp ? 0.0 : ldexp(static_cast<double>(m), e - (s.w - 1)));
+        dec_out[i] = add != nullptr ? d + add[i] : d;
+      }
     }
   };
   auto correct = [&](const SecRef& u, const SecRef& y) {  // u' <- Q(dec u' + dec y')
@@ -159,9 +165,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
     each(F.g.size, [&](int64_t i) { yf[i] = T(0); });
     sync();
     smooth(F, yf, gf, arr(l, 4), a.nu_pre);
-    encode(yf, F.g.size, F.Y);
-    sync();
-    decode(F.Y, F.g.size, yf);
+    encode(yf, F.g.size, F.Y, yf);  // y' = Q(y); yf = dec y'
     sync();
     rhs_minus_A(gf, yf, static_cast<const T*>(F.kap), F.g, static_cast<T>(F.ih2), rf);
     sync();
@@ -184,10 +188,9 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
       s64[c] = t64[c] / diag;
     }
     sync();
-    encode(s64, B.g.size, B.Yp);
+    encode(s64, B.g.size, B.Yp, arr(a.lc, 4));  // y' = Q(A^-1 g); e = dec y'
     sync();
     correct(B.U, B.Yp);
-    decode(B.Yp, B.g.size, arr(a.lc, 4));
     sync();
   }
   // ------------------------------------------------------------ up sweep
@@ -205,15 +208,9 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
     decode(F.Y, F.g.size, yf);
     sync();
     smooth(F, yf, rf, arr(l, 4), a.nu_post);
-    encode(yf, F.g.size, F.Yp);
+    encode(yf, F.g.size, F.Yp, l < a.Lp ? arr(l, 4) : nullptr, zf);  // y' = Q(y); e = dec y' + z
     sync();
     correct(F.U, F.Yp);
-    if (l < a.Lp) {
-      decode(F.Yp, F.g.size, yf);
-      sync();
-      T* ef = arr(l, 4);
-      each(F.g.size, [&](int64_t i) { ef[i] = yf[i] + zf[i]; });
-    }
     sync();
   }
   if (a.Lc < a.Lp) {  // e[Lc] for the next finer level
