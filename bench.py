@@ -216,8 +216,19 @@ def other_workloads():
         s.adjoint(u, u)
         e1.record()
         torch.cuda.synchronize()
+        # one more solve with every kernel timed: the dominant kernel's
+        # algorithmic bytes over its launch time, against the HBM peak
+        s.timing(True)
+        s.solve(f, u)
+        torch.cuda.synchronize()
+        top = s.timing_report()[0]
+        s.timing(False)
+    gbs = top["bytes"] / (top["ms"] * 1e-3)
     out["diffusion3d_513x8_b16"] = dict(ms_per_solve=ms, dof_per_s=8 * 511 ** 3 / (ms * 1e-3),
                                         ms_adjoint_and_gradient=e0.elapsed_time(e1),
+                                        dominant_kernel=dict(kernel=top["kernel"], ms_per_solve=top["ms"],
+                                                             launches=top["launches"], gbs=gbs / 1e9,
+                                                             hbm_frac=gbs / HBM_PEAK),
                                         note="diffusion runs the per-operation kernels (no fused path)")
     return out
 
