@@ -69,6 +69,7 @@ CFGS = {
     # L >= 6 runs the fused 3-D kernels on the fine levels, per-operation below
     "3d-L7-b16": dict(dim=3, L=7, smoother="rbgs", omega=1.0, block=64, bits=16),
     "3d-L7-b12-B32": dict(dim=3, L=7, smoother="rbgs", omega=1.0, block=32, bits=12),
+    "3d-L7-b12": dict(dim=3, L=7, smoother="rbgs", omega=1.0, block=64, bits=12),
     "3d-L7-b8-nu1": dict(dim=3, L=7, smoother="rbgs", omega=1.0, block=64, bits=8, nu=1),
     "3d-L6-b10": dict(dim=3, L=6, smoother="rbgs", omega=1.0, block=64, bits=10),
     "3d-rbgs-b16": dict(dim=3, L=5, smoother="rbgs", omega=1.0, block=64, bits=16),
