@@ -125,12 +125,8 @@ __global__ void __launch_bounds__(kThreads) k_correct(SecRef u, SecRef y) {
 // (edge coefficients as in edge_coeffs, same order), but each of the 2^d
 // cells around the node is loaded once, at a fixed offset from the first.
 template <typename T>
-__device__ __forceinline__ T diffusion_at(const T* __restrict__ u, const T* __restrict__ kap, const Geom& g, int i,
-                                          int j, int k, T inv_h2, T* diag) {
+__device__ __forceinline__ void cell_edges(const T* __restrict__ kap, const Geom& g, int i, int j, int k, T* ke) {
   const int64_t n = g.n;
-  const int64_t p = flat(g, i, j, k);
-  const T up = u[p];
-  T ke[6], nb[6];
   if (g.dim == 3) {
     const int64_t b = flat(g, i - 1, j - 1, k - 1), n2 = n * n;
     const T c000 = kap[b], c100 = kap[b + 1], c010 = kap[b + n], c110 = kap[b + n + 1];
@@ -142,12 +138,6 @@ __device__ __forceinline__ T diffusion_at(const T* __restrict__ u, const T* __re
     ke[3] = (((c010 + c110) + c011) + c111) * q;
     ke[4] = (((c000 + c100) + c010) + c110) * q;
     ke[5] = (((c001 + c101) + c011) + c111) * q;
-    nb[0] = u[p - 1];
-    nb[1] = i + 1 < g.n ? u[p + 1] : T(0);
-    nb[2] = u[p - n];
-    nb[3] = j + 1 < g.n ? u[p + n] : T(0);
-    nb[4] = u[p - n2];
-    nb[5] = k + 1 < g.n ? u[p + n2] : T(0);
   } else {
     const int64_t b = flat(g, i - 1, j - 1, 0);
     const T c00 = kap[b], c10 = kap[b + 1], c01 = kap[b + n], c11 = kap[b + n + 1];
@@ -156,6 +146,37 @@ __device__ __forceinline__ T diffusion_at(const T* __restrict__ u, const T* __re
     ke[1] = (c10 + c11) * q;
     ke[2] = (c00 + c10) * q;
     ke[3] = (c01 + c11) * q;
+  }
+}
+
+// Diagonal of the diffusion operator at an interior node (as diag_A).
+template <typename T>
+__device__ __forceinline__ T diffusion_diag(const T* __restrict__ kap, const Geom& g, int i, int j, int k,
+                                            T inv_h2) {
+  T ke[6];
+  cell_edges(kap, g, i, j, k, ke);
+  T d = ke[0];
+  for (int t = 1; t < 2 * g.dim; ++t) d = d + ke[t];
+  return d * inv_h2;
+}
+
+template <typename T>
+__device__ __forceinline__ T diffusion_at(const T* __restrict__ u, const T* __restrict__ kap, const Geom& g, int i,
+                                          int j, int k, T inv_h2, T* diag) {
+  const int64_t n = g.n;
+  const int64_t p = flat(g, i, j, k);
+  const T up = u[p];
+  T ke[6], nb[6];
+  cell_edges(kap, g, i, j, k, ke);
+  if (g.dim == 3) {
+    const int64_t n2 = n * n;
+    nb[0] = u[p - 1];
+    nb[1] = i + 1 < g.n ? u[p + 1] : T(0);
+    nb[2] = u[p - n];
+    nb[3] = j + 1 < g.n ? u[p + n] : T(0);
+    nb[4] = u[p - n2];
+    nb[5] = k + 1 < g.n ? u[p + n2] : T(0);
+  } else {
     nb[0] = u[p - 1];
     nb[1] = i + 1 < g.n ? u[p + 1] : T(0);
     nb[2] = u[p - n];
@@ -290,6 +311,24 @@ __global__ void __launch_bounds__(kThreads) k_rbgs(T* __restrict__ y, const T* _
     const T r = rhs[idx] - apply_A<T>(y, nullptr, g, i, j, k, inv_h2);
     y[idx] = y[idx] + cpois * r;
   }
+}
+
+// The first red half-sweep from y = 0, over all nodes: red interior nodes
+// take 0 + c (rhs - A 0) = 0 + c rhs (A 0 is +0, so this is what k_rbgs
+// computes after a fill with zeros), every other node 0.
+template <typename T, bool DIFF>
+__global__ void __launch_bounds__(kThreads) k_rbgs_zero(T* __restrict__ y, const T* __restrict__ rhs,
+                                                        const T* __restrict__ kap, Geom g, T inv_h2, T cpois) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= g.size) return;
+  int i, j, k;
+  unflatten(g, idx, i, j, k);
+  if (!is_interior(g, i, j, k) || ((i + j + k) & 1) != 0) {
+    y[idx] = T(0);
+    return;
+  }
+  const T c = DIFF ? T(1) / diffusion_diag<T>(kap, g, i, j, k, inv_h2) : cpois;
+  y[idx] = T(0) + c * (rhs[idx] - T(0));
 }
 
 template <typename T>
@@ -542,6 +581,16 @@ void launch_rbgs(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cp
                 cpois, colour);
 }
 template <typename T>
+void launch_rbgs_zero(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, hipStream_t st) {
+  const double b = (2.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
+  if (kap != nullptr)
+    CMG_TLAUNCH(tname("k_rbgs_zero", TName<T>::s).c_str(), b, (k_rbgs_zero<T, true>), g.size, st, y, rhs, kap, g,
+                inv_h2, cpois);
+  else
+    CMG_TLAUNCH(tname("k_rbgs_zero", TName<T>::s).c_str(), b, (k_rbgs_zero<T, false>), g.size, st, y, rhs, kap, g,
+                inv_h2, cpois);
+}
+template <typename T>
 void launch_add(const T* a, const T* b, T* out, int64_t n, hipStream_t st) {
   CMG_TLAUNCH(tname("k_add", TName<T>::s).c_str(), 3.0 * n * sizeof(T), k_add<T>, n, st, a, b, out, n);
 }
@@ -602,6 +651,7 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
   template void launch_restrict<T>(const T*, const Geom&, const Geom&, T*, hipStream_t);                \
   template void launch_jacobi<T>(const T*, const T*, const T*, const Geom&, T, T, T, T*, hipStream_t);  \
   template void launch_rbgs<T>(T*, const T*, const T*, const Geom&, T, T, int, hipStream_t);            \
+  template void launch_rbgs_zero<T>(T*, const T*, const T*, const Geom&, T, T, hipStream_t);             \
   template void launch_add<T>(const T*, const T*, T*, int64_t, hipStream_t);                            \
   template void launch_fill<T>(T*, T, int64_t, hipStream_t);
 CMG_INST_T(float)

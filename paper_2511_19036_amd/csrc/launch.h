@@ -32,6 +32,10 @@ void launch_jacobi(const T* y, const T* rhs, const T* kap, const Geom& g, T inv_
                    hipStream_t st);
 template <typename T>
 void launch_rbgs(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, int colour, hipStream_t st);
+// The first red half-sweep from y = 0, writing all of y (the other nodes 0):
+// the same values as filling y with zeros and running launch_rbgs(colour 0).
+template <typename T>
+void launch_rbgs_zero(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, hipStream_t st);
 template <typename T> void launch_add(const T* a, const T* b, T* out, int64_t n, hipStream_t st);
 template <typename T> void launch_fill(T* x, T v, int64_t n, hipStream_t st);
 template <typename S, typename D> void launch_convert(const S* a, D* b, int64_t n, hipStream_t st);

@@ -289,6 +289,26 @@ void smooth(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) {
     HIPCK(hipMemcpyAsync(y, a, static_cast<size_t>(D.g.size) * sizeof(T), hipMemcpyDeviceToDevice, c->st));
 }
 
+// nu sweeps of the smoother from y = 0 (y is overwritten).  Red-black
+// Gauss-Seidel starts with a pointwise red half-sweep that writes all of y.
+template <typename T>
+void smooth_from_zero(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) {
+  LevelData& D = c->lv[l];
+  if (c->o.smoother != CMG_RBGS || nu < 1) {
+    launch_fill<T>(y, T(0), D.g.size, c->st);
+    KCK();
+    smooth<T>(c, l, y, rhs, scratch, nu);
+    return;
+  }
+  const double ih2 = inv_h2(l);
+  const T* kap = kapT<T>(c, l);
+  const T cp = static_cast<T>(1.0 / (2.0 * c->p.dim * ih2));
+  launch_rbgs_zero<T>(y, rhs, kap, D.g, static_cast<T>(ih2), cp, c->st);
+  launch_rbgs<T>(y, rhs, kap, D.g, static_cast<T>(ih2), cp, 1, c->st);
+  KCK();
+  smooth<T>(c, l, y, rhs, scratch, nu - 1);
+}
+
 // One compact V-cycle from zero on G[Lp], then u' += y' (Alg. 1, Alg. 3).
 // Levels with rows of >= 64 nodes run the fused 3-D kernels; the others (and
 // every 2-D, Jacobi or diffusion level) run one kernel per operation.
@@ -332,9 +352,7 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     T* rf = static_cast<T*>(F.rf);
     launch_decode<T>(F.G.ref(), F.g.size, gf, st);
     if (!fs) {
-      launch_fill<T>(yf, T(0), F.g.size, st);
-      KCK();
-      smooth<T>(c, l, yf, gf, static_cast<T*>(F.ef), c->o.nu_pre);
+      smooth_from_zero<T>(c, l, yf, gf, static_cast<T*>(F.ef), c->o.nu_pre);
       launch_encode_dec<T>(yf, F.g.size, F.Y.ref(), nf, yf, nullptr, st);  // y' = Q(y); yf = dec y'
     } else {
       launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
@@ -523,8 +541,7 @@ void cs_vcycle(cmg_ctx c, int Lp) {
     T* yf = static_cast<T*>(F.yf);
     T* rf = static_cast<T*>(F.rf);
     T* zf = static_cast<T*>(F.zf);
-    launch_fill<T>(yf, T(0), F.g.size, st);
-    smooth<T>(c, l, yf, rf, zf, c->o.nu_pre);
+    smooth_from_zero<T>(c, l, yf, rf, zf, c->o.nu_pre);
     launch_rhs_minus_A<T>(rf, yf, kapT<T>(c, l), F.g, static_cast<T>(inv_h2(l)), zf, st);
     launch_restrict<T>(zf, C.g, F.g, static_cast<T*>(C.rf), st);
     KCK();
