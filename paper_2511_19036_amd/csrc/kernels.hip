@@ -331,6 +331,106 @@ __global__ void __launch_bounds__(kThreads) k_rbgs_zero(T* __restrict__ y, const
   y[idx] = T(0) + c * (rhs[idx] - T(0));
 }
 
+// A full red-black Gauss-Seidel sweep of a 3-D level (n >= 64) in one
+// launch, out of place (yin -> yout, so that no workgroup reads a value
+// another one has already replaced).  A workgroup owns a 64 x kSwTY tile
+// and marches along z through a chunk of TZ planes: at step p it updates
+// the red nodes of plane p on the tile and a one-node halo, then the black
+// nodes of plane p - 1 on the tile, whose red neighbours (planes p - 2 to
+// p) are updated by then, and writes plane p - 1.  Planes of y pass through
+// a ring of four LDS planes holding the tile and a two-node halo.  Every
+// node gets the arithmetic of k_rbgs (same operands in the same order), so
+// the sweep equals a red and a black half-sweep launch bit for bit.  With
+// ZERO, y is taken as 0 (the first sweep from zero) and yin is not read.
+constexpr int kSwTX = 64, kSwTY = 8, kSwNT = 256;
+template <typename T, bool DIFF, bool ZERO>
+__global__ void __launch_bounds__(kSwNT) k_rbgs_sweep(const T* __restrict__ yin, T* __restrict__ yout,
+                                                      const T* __restrict__ rhs, const T* __restrict__ kap, Geom g,
+                                                      T inv_h2, T cpois, int TZ) {
+  constexpr int W = kSwTX + 4, H = kSwTY + 4, PL = W * H;
+  __shared__ T ring[4 * PL];
+  const int tid = threadIdx.x;
+  const int n = g.n;
+  const int ntx = n / kSwTX, nty = n / kSwTY;
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int X0 = bx * kSwTX, Y0 = by * kSwTY, Z0 = bz * TZ;
+  const int64_t pn = static_cast<int64_t>(n) * n;  // values per plane
+  auto slot = [&](int q) { return ring + (q & 3) * PL; };
+  // plane q of y on the tile and a two-node halo; 0 outside the level
+  auto load = [&](int q) {
+    T* d = slot(q);
+    for (int t = tid; t < PL; t += kSwNT) {
+      const int ly = t / W, lx = t - ly * W;
+      const int gx = X0 - 2 + lx, gy = Y0 - 2 + ly;
+      T v = T(0);
+      if (!ZERO && q >= 0 && q < n && gx >= 0 && gx < n && gy >= 0 && gy < n)
+        v = yin[q * pn + static_cast<int64_t>(gy) * n + gx];
+      d[t] = v;
+    }
+  };
+  // new value of interior node (lx, ly) of plane q (neighbours in the ring)
+  auto update = [&](int lx, int ly, int q) -> T {
+    const T* c = slot(q);
+    const int t = ly * W + lx;
+    const int gx = X0 - 2 + lx, gy = Y0 - 2 + ly;
+    const T up = c[t];
+    const T nb[6] = {c[t - 1], c[t + 1], c[t - W], c[t + W], slot(q - 1)[t], slot(q + 1)[t]};
+    T s, cc;
+    if (DIFF) {
+      T ke[6];
+      cell_edges(kap, g, gx, gy, q, ke);
+      s = ke[0] * (up - nb[0]);
+      for (int e = 1; e < 6; ++e) s = s + ke[e] * (up - nb[e]);
+      T d = ke[0];
+      for (int e = 1; e < 6; ++e) d = d + ke[e];
+      cc = T(1) / (d * inv_h2);
+    } else {
+      s = T(6) * up;
+      for (int e = 0; e < 6; ++e) s = s - nb[e];
+      cc = cpois;
+    }
+    const T r = rhs[q * pn + static_cast<int64_t>(gy) * n + gx] - s * inv_h2;
+    return up + cc * r;
+  };
+  load(Z0 - 2);
+  load(Z0 - 1);
+  for (int p = Z0 - 1; p <= Z0 + TZ; ++p) {
+    load(p + 1);
+    __syncthreads();
+    // Red nodes of plane p on the tile and its one-node halo (they read only
+    // black neighbours).  X0 is even, so in row ly the red nodes are every
+    // other lx from lx0 = 2 - ((gy + p) & 1): 33 per row.
+    if (p >= 1 && p < n) {
+      T* c = slot(p);
+      constexpr int RW = (W - 2) / 2;
+      for (int t = tid; t < RW * (H - 2); t += kSwNT) {
+        const int ly = 1 + t / RW, gy = Y0 - 2 + ly;
+        const int lx = 2 - ((gy + p) & 1) + 2 * (t % RW), gx = X0 - 2 + lx;
+        if (gx >= 1 && gx < n && gy >= 1 && gy < n) c[ly * W + lx] = update(lx, ly, p);
+      }
+    }
+    __syncthreads();
+    // Black nodes of plane q = p - 1 on the tile, and plane q out: each
+    // thread takes one red and one black node of a row (the pair at lx and
+    // lx + 1, lx even).
+    const int q = p - 1;
+    if (q >= Z0 && q < Z0 + TZ) {
+      const T* c = slot(q);
+      static_assert(kSwTX * kSwTY == 2 * kSwNT, "one pair of nodes per thread");
+      const int ly = 2 + tid / (kSwTX / 2), gy = Y0 + ly - 2;
+      const int lx = 2 + 2 * (tid % (kSwTX / 2)), gx = X0 + lx - 2;
+      const int lb = lx + ((gx + gy + q + 1) & 1);  // the black node of the pair
+      const int gb = X0 + lb - 2;
+      T v[2] = {c[ly * W + lx], c[ly * W + lx + 1]};
+      if (q >= 1 && gb >= 1 && gy >= 1) v[lb - lx] = update(lb, ly, q);
+      T* o = yout + q * pn + static_cast<int64_t>(gy) * n + gx;
+      o[0] = v[0];
+      o[1] = v[1];
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_add(const T* __restrict__ a, const T* __restrict__ b,
                                                   T* __restrict__ out, int64_t n) {
@@ -591,6 +691,27 @@ void launch_rbgs_zero(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2,
                 inv_h2, cpois);
 }
 template <typename T>
+bool launch_rbgs_sweep(const T* yin, T* yout, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois,
+                       bool zero, hipStream_t st) {
+  if (g.dim != 3 || g.n < kSwTX) return false;
+  const int tiles = (g.n / kSwTX) * (g.n / kSwTY);
+  int tz = g.n;  // chunks: at least 4096 workgroups where the level allows
+  while (tz > 4 && static_cast<int64_t>(tiles) * (g.n / tz) < 4096) tz >>= 1;
+  const dim3 grid(static_cast<unsigned>(tiles * (g.n / tz))), block(kSwNT);
+  const double bytes = ((zero ? 2.0 : 3.0) + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
+  const std::string name = tname("k_rbgs_sweep", TName<T>::s);
+#define CMG_SW(D_, Z_)                                                                                              do {                                                                                                                if (g_timing != nullptr) g_timing->begin(name.c_str(), bytes, st);                                                hipLaunchKernelGGL((k_rbgs_sweep<T, D_, Z_>), grid, block, 0, st, yin, yout, rhs, kap, g, inv_h2, cpois, tz);     if (g_timing != nullptr) g_timing->end(st);                                                                     } while (0)
+  if (kap != nullptr) {
+    if (zero) CMG_SW(true, true);
+    else CMG_SW(true, false);
+  } else {
+    if (zero) CMG_SW(false, true);
+    else CMG_SW(false, false);
+  }
+#undef CMG_SW
+  return true;
+}
+template <typename T>
 void launch_add(const T* a, const T* b, T* out, int64_t n, hipStream_t st) {
   CMG_TLAUNCH(tname("k_add", TName<T>::s).c_str(), 3.0 * n * sizeof(T), k_add<T>, n, st, a, b, out, n);
 }
@@ -652,6 +773,7 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
   template void launch_jacobi<T>(const T*, const T*, const T*, const Geom&, T, T, T, T*, hipStream_t);  \
   template void launch_rbgs<T>(T*, const T*, const T*, const Geom&, T, T, int, hipStream_t);            \
   template void launch_rbgs_zero<T>(T*, const T*, const T*, const Geom&, T, T, hipStream_t);             \
+  template bool launch_rbgs_sweep<T>(const T*, T*, const T*, const T*, const Geom&, T, T, bool, hipStream_t); \
   template void launch_add<T>(const T*, const T*, T*, int64_t, hipStream_t);                            \
   template void launch_fill<T>(T*, T, int64_t, hipStream_t);
 CMG_INST_T(float)

@@ -269,6 +269,17 @@ void smooth(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) {
   const int d = c->p.dim;
   if (c->o.smoother == CMG_RBGS) {
     const T cp = static_cast<T>(1.0 / (2.0 * d * ih2));
+    if (nu > 0 && d == 3 && D.g.n >= 64) {  // one launch per sweep, out of place between y and scratch
+      T* a = y;
+      T* b = scratch;
+      for (int s = 0; s < nu; ++s) {
+        launch_rbgs_sweep<T>(a, b, rhs, kap, D.g, static_cast<T>(ih2), cp, false, c->st);
+        KCK();
+        std::swap(a, b);
+      }
+      if (a != y) HIPCK(hipMemcpyAsync(y, a, static_cast<size_t>(D.g.size) * sizeof(T), hipMemcpyDeviceToDevice, c->st));
+      return;
+    }
     for (int s = 0; s < nu; ++s)
       for (int colour = 0; colour < 2; ++colour) {
         launch_rbgs<T>(y, rhs, kap, D.g, static_cast<T>(ih2), cp, colour, c->st);
@@ -303,6 +314,16 @@ void smooth_from_zero(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) 
   const double ih2 = inv_h2(l);
   const T* kap = kapT<T>(c, l);
   const T cp = static_cast<T>(1.0 / (2.0 * c->p.dim * ih2));
+  if (c->p.dim == 3 && D.g.n >= 64) {  // one launch per sweep, the first from zero; the last writes y
+    T* a = (nu & 1) ? scratch : y;
+    T* b = (nu & 1) ? y : scratch;
+    for (int s = 0; s < nu; ++s) {
+      launch_rbgs_sweep<T>(a, b, rhs, kap, D.g, static_cast<T>(ih2), cp, s == 0, c->st);
+      KCK();
+      std::swap(a, b);
+    }
+    return;
+  }
   launch_rbgs_zero<T>(y, rhs, kap, D.g, static_cast<T>(ih2), cp, c->st);
   launch_rbgs<T>(y, rhs, kap, D.g, static_cast<T>(ih2), cp, 1, c->st);
   KCK();
