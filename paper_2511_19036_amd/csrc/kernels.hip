@@ -410,22 +410,24 @@ __global__ void __launch_bounds__(kSwNT) k_rbgs_sweep(const T* __restrict__ yin,
       }
     }
     __syncthreads();
-    // Black nodes of plane q = p - 1 on the tile, and plane q out: each
-    // thread takes one red and one black node of a row (the pair at lx and
-    // lx + 1, lx even).
+    // Black nodes of plane q = p - 1 on the tile, and plane q out: a
+    // thread takes the pair of nodes at lx and lx + 1 (lx even) of a row, one
+    // red and one black.
     const int q = p - 1;
     if (q >= Z0 && q < Z0 + TZ) {
       const T* c = slot(q);
-      static_assert(kSwTX * kSwTY == 2 * kSwNT, "one pair of nodes per thread");
-      const int ly = 2 + tid / (kSwTX / 2), gy = Y0 + ly - 2;
-      const int lx = 2 + 2 * (tid % (kSwTX / 2)), gx = X0 + lx - 2;
-      const int lb = lx + ((gx + gy + q + 1) & 1);  // the black node of the pair
-      const int gb = X0 + lb - 2;
-      T v[2] = {c[ly * W + lx], c[ly * W + lx + 1]};
-      if (q >= 1 && gb >= 1 && gy >= 1) v[lb - lx] = update(lb, ly, q);
-      T* o = yout + q * pn + static_cast<int64_t>(gy) * n + gx;
-      o[0] = v[0];
-      o[1] = v[1];
+      static_assert(kSwTX * kSwTY % (2 * kSwNT) == 0, "whole pairs per thread");
+      for (int t = tid; t < kSwTX * kSwTY / 2; t += kSwNT) {
+        const int ly = 2 + t / (kSwTX / 2), gy = Y0 + ly - 2;
+        const int lx = 2 + 2 * (t % (kSwTX / 2)), gx = X0 + lx - 2;
+        const int lb = lx + ((gx + gy + q + 1) & 1);  // the black node of the pair
+        const int gb = X0 + lb - 2;
+        T v[2] = {c[ly * W + lx], c[ly * W + lx + 1]};
+        if (q >= 1 && gb >= 1 && gy >= 1) v[lb - lx] = update(lb, ly, q);
+        T* o = yout + q * pn + static_cast<int64_t>(gy) * n + gx;
+        o[0] = v[0];
+        o[1] = v[1];
+      }
     }
     __syncthreads();
   }
