@@ -213,6 +213,24 @@ __global__ void __launch_bounds__(kThreads) k_rhs_minus_A(const T* __restrict__ 
   out[idx] = rhs[idx] - au;
 }
 
+// out = dec(gs) - A u on interior nodes, 0 on the boundary: k_decode of the
+// right-hand side section followed by k_rhs_minus_A, in one pass.
+template <typename T, bool DIFF>
+__global__ void __launch_bounds__(kThreads) k_dec_minus_A(SecRef gs, const T* __restrict__ u,
+                                                          const T* __restrict__ kap, Geom g, T inv_h2,
+                                                          T* __restrict__ out) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= g.size) return;
+  int i, j, k;
+  unflatten(g, idx, i, j, k);
+  if (!is_interior(g, i, j, k)) {
+    out[idx] = T(0);
+    return;
+  }
+  const T au = DIFF ? diffusion_at<T>(u, kap, g, i, j, k, inv_h2, nullptr) : apply_A<T>(u, nullptr, g, i, j, k, inv_h2);
+  out[idx] = static_cast<T>(decode_value(gs, idx)) - au;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_prolong(const T* __restrict__ coarse, Geom gf, Geom gc,
                                                       T* __restrict__ fine) {
@@ -646,6 +664,16 @@ void launch_rhs_minus_A(const T* rhs, const T* u, const T* kap, const Geom& g, T
                 g, inv_h2, out);
 }
 template <typename T>
+void launch_dec_minus_A(const SecRef& gs, const T* u, const T* kap, const Geom& g, T inv_h2, T* out, hipStream_t st) {
+  const double b = (2.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T) + sec_bytes(gs);
+  if (kap != nullptr)
+    CMG_TLAUNCH(tname("k_dec_minus_A", TName<T>::s).c_str(), b, (k_dec_minus_A<T, true>), g.size, st, gs, u, kap, g,
+                inv_h2, out);
+  else
+    CMG_TLAUNCH(tname("k_dec_minus_A", TName<T>::s).c_str(), b, (k_dec_minus_A<T, false>), g.size, st, gs, u, kap, g,
+                inv_h2, out);
+}
+template <typename T>
 void launch_prolong(const T* coarse, const Geom& gf, const Geom& gc, T* fine, hipStream_t st) {
   CMG_TLAUNCH(tname("k_prolong", TName<T>::s).c_str(), (gf.size + gc.size) * sizeof(T), k_prolong<T>, gf.size, st,
               coarse, gf, gc, fine);
@@ -770,6 +798,7 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
   template void launch_encode_dec<T>(const T*, int64_t, const SecRef&, int*, T*, const T*, hipStream_t); \
   template void launch_decode<T>(const SecRef&, int64_t, T*, hipStream_t);                              \
   template void launch_rhs_minus_A<T>(const T*, const T*, const T*, const Geom&, T, T*, hipStream_t);   \
+  template void launch_dec_minus_A<T>(const SecRef&, const T*, const T*, const Geom&, T, T*, hipStream_t); \
   template void launch_prolong<T>(const T*, const Geom&, const Geom&, T*, hipStream_t);                 \
   template void launch_restrict<T>(const T*, const Geom&, const Geom&, T*, hipStream_t);                \
   template void launch_jacobi<T>(const T*, const T*, const T*, const Geom&, T, T, T, T*, hipStream_t);  \

@@ -23,6 +23,10 @@ void launch_correct(const SecRef& u, const SecRef& y, hipStream_t st);
 
 template <typename T>
 void launch_rhs_minus_A(const T* rhs, const T* u, const T* kap, const Geom& g, T inv_h2, T* out, hipStream_t st);
+// out = dec(gs) - A u (interior; 0 on the boundary): a decode of the
+// right-hand side section and launch_rhs_minus_A in one pass.
+template <typename T>
+void launch_dec_minus_A(const SecRef& gs, const T* u, const T* kap, const Geom& g, T inv_h2, T* out, hipStream_t st);
 template <typename T> void launch_prolong(const T* coarse, const Geom& gf, const Geom& gc, T* fine, hipStream_t st);
 void launch_prolong_add_dec(const SecRef& s, const double* coarse, const Geom& gf, const Geom& gc, double* out,
                             hipStream_t st);

@@ -440,13 +440,11 @@ void vcycle_correct(cmg_ctx c, int Lp) {
       KCK();
       continue;
     }
-    T* gf = static_cast<T*>(F.gf);
     T* yf = static_cast<T*>(F.yf);
     T* zf = static_cast<T*>(F.zf);
     T* rf = static_cast<T*>(F.rf);
     launch_prolong<T>(static_cast<T*>(C.ef), F.g, C.g, zf, st);
-    launch_decode<T>(F.G.ref(), F.g.size, gf, st);
-    launch_rhs_minus_A<T>(gf, zf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);
+    launch_dec_minus_A<T>(F.G.ref(), zf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);  // dec g - A z
     launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
     KCK();
     smooth<T>(c, l, yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
