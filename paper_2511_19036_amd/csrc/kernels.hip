@@ -22,7 +22,7 @@ static inline dim3 grid_for(int64_t n) { return dim3(static_cast<unsigned>((n + 
 // ===================================================================== BFP
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_encode(const T* x, int64_t n, SecRef s, int* nonfinite, T* out,
-                                                     const T* __restrict__ add) {
+                                                     const T* __restrict__ add, SecRef u, int correct) {
   const int lane = threadIdx.x & 63;
   const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
   const int64_t limit = limit_of(s);
@@ -35,9 +35,18 @@ __global__ void __launch_bounds__(kThreads) k_encode(const T* x, int64_t n, SecR
   store_codes_wave(s, base, lane, m, limit);
   if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
   // the decoded value of the new code, as k_decode gives it (plus add)
+  const double dv = e == kZeroExp ? 0.0 : ldexp(static_cast<double>(m), e - (s.w - 1));
   if (out != nullptr && i < n) {
-    const T d = static_cast<T>(e == kZeroExp ? 0.0 : ldexp(static_cast<double>(m), e - (s.w - 1)));
+    const T d = static_cast<T>(dv);
     out[i] = add != nullptr ? d + add[i] : d;
+  }
+  // u <- Q(dec u + dec s), as k_correct computes it (u has the blocks of s)
+  if (correct) {
+    const double vu = (i < limit) ? decode_value(u, i) + dv : 0.0;
+    int eu;
+    const int64_t mu = quantise_lane(vu, u.B, u.w, &eu);
+    store_codes_wave(u, base, lane, mu, limit);
+    if ((lane & (u.B - 1)) == 0 && i < limit) u.exps[blk(u, i)] = static_cast<int16_t>(eu);
   }
 }
 
@@ -622,13 +631,16 @@ template <typename T>
 void launch_encode(const T* x, int64_t n, const SecRef& s, int* nonfinite, hipStream_t st) {
   const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
   CMG_TLAUNCH(tname("k_encode", TName<T>::s).c_str(), n * sizeof(T) + sec_bytes(s), k_encode<T>, limit, st, x, n,
-              s, nonfinite, static_cast<T*>(nullptr), static_cast<const T*>(nullptr));
+              s, nonfinite, static_cast<T*>(nullptr), static_cast<const T*>(nullptr), s, 0);
 }
 template <typename T>
-void launch_encode_dec(const T* x, int64_t n, const SecRef& s, int* nonfinite, T* out, const T* add, hipStream_t st) {
+void launch_encode_dec(const T* x, int64_t n, const SecRef& s, int* nonfinite, T* out, const T* add,
+                       const SecRef* correct_u, hipStream_t st) {
   const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
-  const double b = n * sizeof(T) * (out != nullptr ? (add != nullptr ? 3.0 : 2.0) : 1.0) + sec_bytes(s);
-  CMG_TLAUNCH(tname("k_encode", TName<T>::s).c_str(), b, k_encode<T>, limit, st, x, n, s, nonfinite, out, add);
+  const double b = n * sizeof(T) * (out != nullptr ? (add != nullptr ? 3.0 : 2.0) : 1.0) + sec_bytes(s) +
+                   (correct_u != nullptr ? 2.0 * sec_bytes(*correct_u) : 0.0);
+  CMG_TLAUNCH(tname("k_encode", TName<T>::s).c_str(), b, k_encode<T>, limit, st, x, n, s, nonfinite, out, add,
+              correct_u != nullptr ? *correct_u : s, correct_u != nullptr ? 1 : 0);
 }
 template <typename T>
 void launch_decode(const SecRef& s, int64_t n, T* x, hipStream_t st) {
@@ -795,7 +807,8 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
 
 #define CMG_INST_T(T)                                                                                   \
   template void launch_encode<T>(const T*, int64_t, const SecRef&, int*, hipStream_t);                  \
-  template void launch_encode_dec<T>(const T*, int64_t, const SecRef&, int*, T*, const T*, hipStream_t); \
+  template void launch_encode_dec<T>(const T*, int64_t, const SecRef&, int*, T*, const T*, const SecRef*,   \
+                                     hipStream_t);                                                        \
   template void launch_decode<T>(const SecRef&, int64_t, T*, hipStream_t);                              \
   template void launch_rhs_minus_A<T>(const T*, const T*, const T*, const Geom&, T, T*, hipStream_t);   \
   template void launch_dec_minus_A<T>(const SecRef&, const T*, const T*, const Geom&, T, T*, hipStream_t); \

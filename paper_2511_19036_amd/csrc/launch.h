@@ -11,9 +11,11 @@ namespace cmg {
 template <typename T> void launch_encode(const T* x, int64_t n, const SecRef& s, int* nonfinite, hipStream_t st);
 // The encode, and the decoded values of the new codes written to out (plus
 // add[i] when add is not null): an encode followed by a decode (and an add)
-// in one pass.  out may be x.
+// in one pass.  out may be x.  With correct_u (a section with the blocks of
+// s), also u <- Q(dec u + dec s), as launch_correct does.
 template <typename T>
-void launch_encode_dec(const T* x, int64_t n, const SecRef& s, int* nonfinite, T* out, const T* add, hipStream_t st);
+void launch_encode_dec(const T* x, int64_t n, const SecRef& s, int* nonfinite, T* out, const T* add,
+                       const SecRef* correct_u, hipStream_t st);
 template <typename T> void launch_decode(const SecRef& s, int64_t n, T* x, hipStream_t st);
 void launch_widen(const SecRef& s, int k, hipStream_t st);
 // Encode the interior of a full node array (boundary and far nodes 0).

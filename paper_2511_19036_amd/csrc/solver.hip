@@ -374,7 +374,7 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     launch_decode<T>(F.G.ref(), F.g.size, gf, st);
     if (!fs) {
       smooth_from_zero<T>(c, l, yf, gf, static_cast<T*>(F.ef), c->o.nu_pre);
-      launch_encode_dec<T>(yf, F.g.size, F.Y.ref(), nf, yf, nullptr, st);  // y' = Q(y); yf = dec y'
+      launch_encode_dec<T>(yf, F.g.size, F.Y.ref(), nf, yf, nullptr, nullptr, st);  // y' = Q(y); yf = dec y'
     } else {
       launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
     }
@@ -448,9 +448,9 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
     KCK();
     smooth<T>(c, l, yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
-    // y' = Q(y), and below the top level e_l = dec y' + z
-    launch_encode_dec<T>(yf, F.g.size, F.Yp.ref(), nf, l < Lp ? static_cast<T*>(F.ef) : nullptr, zf, st);
-    launch_correct(F.U.ref(), F.Yp.ref(), st);
+    // y' = Q(y); u' = Q(dec u' + dec y'); below the top level e_l = dec y' + z
+    const SecRef u = F.U.ref();
+    launch_encode_dec<T>(yf, F.g.size, F.Yp.ref(), nf, l < Lp ? static_cast<T*>(F.ef) : nullptr, zf, &u, st);
     KCK();
   }
 }
