@@ -368,10 +368,12 @@ __global__ void __launch_bounds__(kThreads) k_rbgs_zero(T* __restrict__ y, const
 // a ring of four LDS planes holding the tile and a two-node halo.  Every
 // node gets the arithmetic of k_rbgs (same operands in the same order), so
 // the sweep equals a red and a black half-sweep launch bit for bit.  With
-// ZERO, y is taken as 0 (the first sweep from zero) and yin is not read.
+// ZERO, y is taken as 0 (the first sweep from zero) and yin is not read;
+// with SEC, y is the decoded section ysec (as k_decode gives it) and yin is
+// not read.
 constexpr int kSwTX = 64, kSwTY = 8, kSwNT = 256;
-template <typename T, bool DIFF, bool ZERO>
-__global__ void __launch_bounds__(kSwNT) k_rbgs_sweep(const T* __restrict__ yin, T* __restrict__ yout,
+template <typename T, bool DIFF, bool ZERO, bool SEC>
+__global__ void __launch_bounds__(kSwNT) k_rbgs_sweep(const T* __restrict__ yin, SecRef ysec, T* __restrict__ yout,
                                                       const T* __restrict__ rhs, const T* __restrict__ kap, Geom g,
                                                       T inv_h2, T cpois, int TZ) {
   constexpr int W = kSwTX + 4, H = kSwTY + 4, PL = W * H;
@@ -390,8 +392,10 @@ __global__ void __launch_bounds__(kSwNT) k_rbgs_sweep(const T* __restrict__ yin,
       const int ly = t / W, lx = t - ly * W;
       const int gx = X0 - 2 + lx, gy = Y0 - 2 + ly;
       T v = T(0);
-      if (!ZERO && q >= 0 && q < n && gx >= 0 && gx < n && gy >= 0 && gy < n)
-        v = yin[q * pn + static_cast<int64_t>(gy) * n + gx];
+      if (!ZERO && q >= 0 && q < n && gx >= 0 && gx < n && gy >= 0 && gy < n) {
+        const int64_t idx = q * pn + static_cast<int64_t>(gy) * n + gx;
+        v = SEC ? static_cast<T>(decode_value(ysec, idx)) : yin[idx];
+      }
       d[t] = v;
     }
   };
@@ -733,8 +737,8 @@ void launch_rbgs_zero(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2,
                 inv_h2, cpois);
 }
 template <typename T>
-bool launch_rbgs_sweep(const T* yin, T* yout, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois,
-                       bool zero, hipStream_t st) {
+bool launch_rbgs_sweep(const T* yin, const SecRef* ysec, T* yout, const T* rhs, const T* kap, const Geom& g, T inv_h2,
+                       T cpois, bool zero, hipStream_t st) {
   if (g.dim != 3 || g.n < kSwTX) return false;
   const int tiles = (g.n / kSwTX) * (g.n / kSwTY);
   int tz = g.n;  // chunks: at least 4096 workgroups where the level allows
@@ -742,13 +746,22 @@ bool launch_rbgs_sweep(const T* yin, T* yout, const T* rhs, const T* kap, const 
   const dim3 grid(static_cast<unsigned>(tiles * (g.n / tz))), block(kSwNT);
   const double bytes = ((zero ? 2.0 : 3.0) + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
   const std::string name = tname("k_rbgs_sweep", TName<T>::s);
-#define CMG_SW(D_, Z_)                                                                                              do {                                                                                                                if (g_timing != nullptr) g_timing->begin(name.c_str(), bytes, st);                                                hipLaunchKernelGGL((k_rbgs_sweep<T, D_, Z_>), grid, block, 0, st, yin, yout, rhs, kap, g, inv_h2, cpois, tz);     if (g_timing != nullptr) g_timing->end(st);                                                                     } while (0)
+  const SecRef ys = ysec != nullptr ? *ysec : SecRef{};
+#define CMG_SW(D_, Z_, S_)                                                                                      \
+  do {                                                                                                          \
+    if (g_timing != nullptr) g_timing->begin(name.c_str(), bytes, st);                                          \
+    hipLaunchKernelGGL((k_rbgs_sweep<T, D_, Z_, S_>), grid, block, 0, st, yin, ys, yout, rhs, kap, g, inv_h2,    \
+                       cpois, tz);                                                                              \
+    if (g_timing != nullptr) g_timing->end(st);                                                                 \
+  } while (0)
   if (kap != nullptr) {
-    if (zero) CMG_SW(true, true);
-    else CMG_SW(true, false);
+    if (zero) CMG_SW(true, true, false);
+    else if (ysec != nullptr) CMG_SW(true, false, true);
+    else CMG_SW(true, false, false);
   } else {
-    if (zero) CMG_SW(false, true);
-    else CMG_SW(false, false);
+    if (zero) CMG_SW(false, true, false);
+    else if (ysec != nullptr) CMG_SW(false, false, true);
+    else CMG_SW(false, false, false);
   }
 #undef CMG_SW
   return true;
@@ -817,7 +830,8 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
   template void launch_jacobi<T>(const T*, const T*, const T*, const Geom&, T, T, T, T*, hipStream_t);  \
   template void launch_rbgs<T>(T*, const T*, const T*, const Geom&, T, T, int, hipStream_t);            \
   template void launch_rbgs_zero<T>(T*, const T*, const T*, const Geom&, T, T, hipStream_t);             \
-  template bool launch_rbgs_sweep<T>(const T*, T*, const T*, const T*, const Geom&, T, T, bool, hipStream_t); \
+  template bool launch_rbgs_sweep<T>(const T*, const SecRef*, T*, const T*, const T*, const Geom&, T, T, bool,    \
+                                     hipStream_t);                                                              \
   template void launch_add<T>(const T*, const T*, T*, int64_t, hipStream_t);                            \
   template void launch_fill<T>(T*, T, int64_t, hipStream_t);
 CMG_INST_T(float)

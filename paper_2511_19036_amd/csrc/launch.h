@@ -44,12 +44,12 @@ template <typename T>
 void launch_rbgs_zero(T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, hipStream_t st);
 // One red-black Gauss-Seidel sweep (red then black) of a 3-D level with at
 // least 64 nodes per axis in one launch, out of place (yin -> yout; with
-// zero, y is taken as 0 and yin is not read).  The same values as the two
-// launch_rbgs half-sweeps.  Returns false (nothing launched) for other
-// levels.
+// zero, y is taken as 0, and with ysec not null, y is the decoded section;
+// then yin is not read).  The same values as the two launch_rbgs
+// half-sweeps.  Returns false (nothing launched) for other levels.
 template <typename T>
-bool launch_rbgs_sweep(const T* yin, T* yout, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois,
-                       bool zero, hipStream_t st);
+bool launch_rbgs_sweep(const T* yin, const SecRef* ysec, T* yout, const T* rhs, const T* kap, const Geom& g, T inv_h2,
+                       T cpois, bool zero, hipStream_t st);
 template <typename T> void launch_add(const T* a, const T* b, T* out, int64_t n, hipStream_t st);
 template <typename T> void launch_fill(T* x, T v, int64_t n, hipStream_t st);
 template <typename S, typename D> void launch_convert(const S* a, D* b, int64_t n, hipStream_t st);

@@ -273,7 +273,7 @@ void smooth(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) {
       T* a = y;
       T* b = scratch;
       for (int s = 0; s < nu; ++s) {
-        launch_rbgs_sweep<T>(a, b, rhs, kap, D.g, static_cast<T>(ih2), cp, false, c->st);
+        launch_rbgs_sweep<T>(a, nullptr, b, rhs, kap, D.g, static_cast<T>(ih2), cp, false, c->st);
         KCK();
         std::swap(a, b);
       }
@@ -318,7 +318,7 @@ void smooth_from_zero(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) 
     T* a = (nu & 1) ? scratch : y;
     T* b = (nu & 1) ? y : scratch;
     for (int s = 0; s < nu; ++s) {
-      launch_rbgs_sweep<T>(a, b, rhs, kap, D.g, static_cast<T>(ih2), cp, s == 0, c->st);
+      launch_rbgs_sweep<T>(a, nullptr, b, rhs, kap, D.g, static_cast<T>(ih2), cp, s == 0, c->st);
       KCK();
       std::swap(a, b);
     }
@@ -328,6 +328,29 @@ void smooth_from_zero(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) 
   launch_rbgs<T>(y, rhs, kap, D.g, static_cast<T>(ih2), cp, 1, c->st);
   KCK();
   smooth<T>(c, l, y, rhs, scratch, nu - 1);
+}
+
+// nu sweeps of the smoother starting from the decoded section ys (written
+// to y).  With one launch per sweep the first sweep reads the codes itself.
+template <typename T>
+void smooth_from_section(cmg_ctx c, int l, const SecRef& ys, T* y, const T* rhs, T* scratch, int nu) {
+  LevelData& D = c->lv[l];
+  if (c->o.smoother == CMG_RBGS && nu >= 1 && c->p.dim == 3 && D.g.n >= 64) {
+    const double ih2 = inv_h2(l);
+    const T* kap = kapT<T>(c, l);
+    const T cp = static_cast<T>(1.0 / (2.0 * c->p.dim * ih2));
+    T* a = (nu & 1) ? scratch : y;  // the last sweep writes y
+    T* b = (nu & 1) ? y : scratch;
+    for (int s = 0; s < nu; ++s) {
+      launch_rbgs_sweep<T>(a, s == 0 ? &ys : nullptr, b, rhs, kap, D.g, static_cast<T>(ih2), cp, false, c->st);
+      KCK();
+      std::swap(a, b);
+    }
+    return;
+  }
+  launch_decode<T>(ys, D.g.size, y, c->st);
+  KCK();
+  smooth<T>(c, l, y, rhs, scratch, nu);
 }
 
 // One compact V-cycle from zero on G[Lp], then u' += y' (Alg. 1, Alg. 3).
@@ -445,9 +468,7 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     T* rf = static_cast<T*>(F.rf);
     launch_prolong<T>(static_cast<T*>(C.ef), F.g, C.g, zf, st);
     launch_dec_minus_A<T>(F.G.ref(), zf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);  // dec g - A z
-    launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
-    KCK();
-    smooth<T>(c, l, yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
+    smooth_from_section<T>(c, l, F.Y.ref(), yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
     // y' = Q(y); u' = Q(dec u' + dec y'); below the top level e_l = dec y' + z
     const SecRef u = F.U.ref();
     launch_encode_dec<T>(yf, F.g.size, F.Yp.ref(), nf, l < Lp ? static_cast<T*>(F.ef) : nullptr, zf, &u, st);
