@@ -240,6 +240,36 @@ __global__ void __launch_bounds__(kThreads) k_dec_minus_A(SecRef gs, const T* __
   out[idx] = static_cast<T>(decode_value(gs, idx)) - au;
 }
 
+// The float64 residual of iterative refinement encoded into s: t = f - A u
+// on interior nodes (0 elsewhere), quantised into its blocks.  The same
+// values as k_rhs_minus_A<double> followed by k_encode<double>, without the
+// t array; one wave per 64 consecutive values.
+template <bool DIFF>
+__global__ void __launch_bounds__(kThreads) k_res_encode(const double* __restrict__ f, const double* __restrict__ u,
+                                                         const double* __restrict__ kap, Geom g, double inv_h2,
+                                                         SecRef s, int* nonfinite) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
+  const int64_t limit = limit_of(s);
+  if (base >= limit) return;  // whole wave
+  const int64_t i = base + lane;
+  double v = 0.0;
+  if (i < g.size) {
+    int x, y, z;
+    unflatten(g, i, x, y, z);
+    if (is_interior(g, x, y, z)) {
+      const double au = DIFF ? diffusion_at<double>(u, kap, g, x, y, z, inv_h2, nullptr)
+                             : apply_A<double>(u, nullptr, g, x, y, z, inv_h2);
+      v = f[i] - au;
+    }
+  }
+  if (nonfinite != nullptr && !isfinite(v)) atomicOr(nonfinite, 1);
+  int e;
+  const int64_t m = quantise_lane(v, s.B, s.w, &e);
+  store_codes_wave(s, base, lane, m, limit);
+  if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_prolong(const T* __restrict__ coarse, Geom gf, Geom gc,
                                                       T* __restrict__ fine) {
@@ -688,6 +718,15 @@ void launch_dec_minus_A(const SecRef& gs, const T* u, const T* kap, const Geom& 
   else
     CMG_TLAUNCH(tname("k_dec_minus_A", TName<T>::s).c_str(), b, (k_dec_minus_A<T, false>), g.size, st, gs, u, kap, g,
                 inv_h2, out);
+}
+void launch_res_encode(const double* f, const double* u, const double* kap, const Geom& g, double inv_h2,
+                       const SecRef& s, int* nonfinite, hipStream_t st) {
+  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  const double b = (2.0 + (kap ? 1.0 : 0.0)) * g.size * 8.0 + sec_bytes(s);
+  if (kap != nullptr)
+    CMG_TLAUNCH("k_res_encode", b, k_res_encode<true>, limit, st, f, u, kap, g, inv_h2, s, nonfinite);
+  else
+    CMG_TLAUNCH("k_res_encode", b, k_res_encode<false>, limit, st, f, u, kap, g, inv_h2, s, nonfinite);
 }
 template <typename T>
 void launch_prolong(const T* coarse, const Geom& gf, const Geom& gc, T* fine, hipStream_t st) {

@@ -25,6 +25,11 @@ void launch_correct(const SecRef& u, const SecRef& y, hipStream_t st);
 
 template <typename T>
 void launch_rhs_minus_A(const T* rhs, const T* u, const T* kap, const Geom& g, T inv_h2, T* out, hipStream_t st);
+// s = Q(f - A u) in float64 (interior; 0 on the boundary): the residual of
+// iterative refinement and its encode in one pass (flags non-finite values
+// in *nonfinite like launch_encode).
+void launch_res_encode(const double* f, const double* u, const double* kap, const Geom& g, double inv_h2,
+                       const SecRef& s, int* nonfinite, hipStream_t st);
 // out = dec(gs) - A u (interior; 0 on the boundary): a decode of the
 // right-hand side section and launch_rhs_minus_A in one pass.
 template <typename T>

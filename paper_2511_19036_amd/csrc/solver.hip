@@ -513,9 +513,14 @@ void ir_residual(cmg_ctx c, int Lp, const double* f, cmg_stats* st) {
     KCK();
   } else {
     decode_chain(c, Lp);
-    launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.t64, c->st);
-    launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
-    KCK();
+    if (!rec) {  // residual and encode in one pass
+      launch_res_encode(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.G.ref(), c->flags + 1, c->st);
+      KCK();
+    } else {  // the recorded norm needs the residual array
+      launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.t64, c->st);
+      launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
+      KCK();
+    }
     if (rec) {
       HIPCK(hipMemsetAsync(c->red, 0, 8, c->st));
       launch_sumsq(F.t64, F.g.size, c->red, c->st);
