@@ -290,18 +290,11 @@ __global__ void __launch_bounds__(kThreads) k_prolong_add_dec(SecRef sec, const 
   out[idx] = decode_value(sec, idx) + prolong_at(coarse, gc, i, j, k);
 }
 
-// coarse = R fine (full weighting); gc is the coarse level.
+// (R fine) at coarse node (I, J, K) (full weighting; 0 off the interior).
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_restrict(const T* __restrict__ fine, Geom gc, Geom gf,
-                                                       T* __restrict__ coarse) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  if (idx >= gc.size) return;
-  int I, J, K;
-  unflatten(gc, idx, I, J, K);
-  if (!is_interior(gc, I, J, K)) {
-    coarse[idx] = T(0);
-    return;
-  }
+__device__ __forceinline__ T restrict_at(const T* __restrict__ fine, const Geom& gc, const Geom& gf, int I, int J,
+                                         int K) {
+  if (!is_interior(gc, I, J, K)) return T(0);
   T s = T(0);
   bool first = true;
   const int z0 = gc.dim == 3 ? -1 : 0, z1 = gc.dim == 3 ? 1 : 0;
@@ -318,7 +311,41 @@ __global__ void __launch_bounds__(kThreads) k_restrict(const T* __restrict__ fin
       }
     }
   }
-  coarse[idx] = s;
+  return s;
+}
+
+// coarse = R fine (full weighting); gc is the coarse level.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_restrict(const T* __restrict__ fine, Geom gc, Geom gf,
+                                                       T* __restrict__ coarse) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= gc.size) return;
+  int I, J, K;
+  unflatten(gc, idx, I, J, K);
+  coarse[idx] = restrict_at(fine, gc, gf, I, J, K);
+}
+
+// s = Q(R fine): k_restrict followed by k_encode, without the coarse array
+// (one wave per 64 consecutive coarse values).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_restrict_encode(const T* __restrict__ fine, Geom gc, Geom gf, SecRef s,
+                                                              int* nonfinite) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
+  const int64_t limit = limit_of(s);
+  if (base >= limit) return;  // whole wave
+  const int64_t i = base + lane;
+  double v = 0.0;
+  if (i < gc.size) {
+    int I, J, K;
+    unflatten(gc, i, I, J, K);
+    v = static_cast<double>(restrict_at(fine, gc, gf, I, J, K));
+  }
+  if (nonfinite != nullptr && !isfinite(v)) atomicOr(nonfinite, 1);
+  int e;
+  const int64_t m = quantise_lane(v, s.B, s.w, &e);
+  store_codes_wave(s, base, lane, m, limit);
+  if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
 }
 
 template <typename T, bool DIFF>
@@ -744,6 +771,13 @@ void launch_restrict(const T* fine, const Geom& gc, const Geom& gf, T* coarse, h
               st, fine, gc, gf, coarse);
 }
 template <typename T>
+void launch_restrict_encode(const T* fine, const Geom& gc, const Geom& gf, const SecRef& s, int* nonfinite,
+                            hipStream_t st) {
+  const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
+  CMG_TLAUNCH(tname("k_restrict_encode", TName<T>::s).c_str(), gf.size * sizeof(T) + sec_bytes(s),
+              k_restrict_encode<T>, limit, st, fine, gc, gf, s, nonfinite);
+}
+template <typename T>
 void launch_jacobi(const T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, T omega, T* ynew,
                    hipStream_t st) {
   const double b = (3.0 + (kap ? 1.0 : 0.0)) * g.size * sizeof(T);
@@ -866,6 +900,7 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
   template void launch_dec_minus_A<T>(const SecRef&, const T*, const T*, const Geom&, T, T*, hipStream_t); \
   template void launch_prolong<T>(const T*, const Geom&, const Geom&, T*, hipStream_t);                 \
   template void launch_restrict<T>(const T*, const Geom&, const Geom&, T*, hipStream_t);                \
+  template void launch_restrict_encode<T>(const T*, const Geom&, const Geom&, const SecRef&, int*, hipStream_t); \
   template void launch_jacobi<T>(const T*, const T*, const T*, const Geom&, T, T, T, T*, hipStream_t);  \
   template void launch_rbgs<T>(T*, const T*, const T*, const Geom&, T, T, int, hipStream_t);            \
   template void launch_rbgs_zero<T>(T*, const T*, const T*, const Geom&, T, T, hipStream_t);             \

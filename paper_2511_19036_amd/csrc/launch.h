@@ -38,6 +38,10 @@ template <typename T> void launch_prolong(const T* coarse, const Geom& gf, const
 void launch_prolong_add_dec(const SecRef& s, const double* coarse, const Geom& gf, const Geom& gc, double* out,
                             hipStream_t st);
 template <typename T> void launch_restrict(const T* fine, const Geom& gc, const Geom& gf, T* coarse, hipStream_t st);
+// s = Q(R fine): the restriction and the encode of its result in one pass.
+template <typename T>
+void launch_restrict_encode(const T* fine, const Geom& gc, const Geom& gf, const SecRef& s, int* nonfinite,
+                            hipStream_t st);
 template <typename T>
 void launch_jacobi(const T* y, const T* rhs, const T* kap, const Geom& g, T inv_h2, T cpois, T omega, T* ynew,
                    hipStream_t st);

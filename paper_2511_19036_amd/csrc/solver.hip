@@ -402,8 +402,7 @@ void vcycle_correct(cmg_ctx c, int Lp) {
       launch_decode<T>(F.Y.ref(), F.g.size, yf, st);
     }
     launch_rhs_minus_A<T>(gf, yf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);
-    launch_restrict<T>(rf, C.g, F.g, static_cast<T*>(C.rf), st);
-    launch_encode<T>(static_cast<T*>(C.rf), C.g.size, C.G.ref(), nf, st);
+    launch_restrict_encode<T>(rf, C.g, F.g, C.G.ref(), nf, st);  // g_{l-1} = Q(R(g - A y'))
     KCK();
   }
   LevelData& B = c->lv[lc];  // coarsest, float64
