@@ -229,7 +229,8 @@ def other_workloads():
                                         dominant_kernel=dict(kernel=top["kernel"], ms_per_solve=top["ms"],
                                                              launches=top["launches"], gbs=gbs / 1e9,
                                                              hbm_frac=gbs / HBM_PEAK),
-                                        note="diffusion runs the per-operation kernels (no fused path)")
+                                        note="diffusion runs the per-operation kernels (one launch per red-black "
+                                             "sweep; the fused level kernels are Poisson-only)")
     return out
 
 
