@@ -210,7 +210,11 @@ def test_vcycle_entry_matches_oracle(cmg, name):
     assert np.array_equal(y, oc.vcycle_standard(r_np, cfg))
 
 
-@pytest.mark.parametrize("dim,L,smoother,omega,block", [(3, 4, "rbgs", 1.0, 64), (2, 5, "wjacobi", 0.8, 32)])
+# 3-D L = 4 runs in the single-workgroup V-cycle; L >= 6 also runs the
+# one-launch sweeps and the fused per-operation kernels of levels 5 and up.
+@pytest.mark.parametrize("dim,L,smoother,omega,block",
+                         [(3, 4, "rbgs", 1.0, 64), (2, 5, "wjacobi", 0.8, 32), (3, 6, "rbgs", 1.0, 64),
+                          (3, 7, "rbgs", 1.0, 32)])
 def test_diffusion_fmg_and_gradient_match_oracle(cmg, dim, L, smoother, omega, block):
     kappa = S.lognormal_kappa(dim, L, 0.2, 1)
     kobs = S.lognormal_kappa(dim, L, 0.2, 2)
@@ -229,6 +233,28 @@ def test_diffusion_fmg_and_gradient_match_oracle(cmg, dim, L, smoother, omega, b
         lam, g = s.adjoint(u, torch.from_numpy(dj).cuda()[None])
     assert np.array_equal(lam[0].cpu().numpy(), lam_ref)
     assert np.array_equal(g.cpu().numpy(), g_ref)
+
+
+@pytest.mark.parametrize("op_,nu", [("diffusion", 1), ("poisson", 1), ("poisson", 2)])
+def test_per_operation_fmg_matches_oracle(cmg, op_, nu):
+    """Compact FMG on the per-operation kernels at 65^3: diffusion, or Poisson
+    with the float64 V-cycle (no fused level kernels), V(nu, nu); nu = 1 ends
+    a smoothing with its one-launch sweep in the scratch array."""
+    dim, L = 3, 6
+    f_np = S.gaussian_noise_rhs(dim, L, sigma=1e-3, seed=4)
+    kw = dict(op=op_)
+    if op_ == "diffusion":
+        kappa = S.lognormal_kappa(dim, L, 0.2, 3)
+        cfg = oc.Config(dim=dim, L=L, op=op_, nu_pre=nu, nu_post=nu)
+        u_ref, _ = oc.fmg_solve(f_np, cfg, kappa)
+        kw.update(kappa=torch.from_numpy(kappa).cuda())
+    else:
+        cfg = oc.Config(dim=dim, L=L, nu_pre=nu, nu_post=nu, vcycle_dtype=np.float64)
+        u_ref, _ = oc.fmg_solve(f_np, cfg)
+        kw.update(vcycle_prec="fp64")
+    with cmg.Solver(dim, L, smoother="rbgs", bfp_block=64, bits=16, nu_pre=nu, nu_post=nu, **kw) as s:
+        u = s.solve(torch.from_numpy(f_np).cuda()[None])[0].cpu().numpy()
+    assert np.array_equal(u, u_ref)
 
 
 def test_residual_norms_recorded(cmg):
