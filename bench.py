@@ -325,6 +325,20 @@ def main():
                     frac=achieved / HBM_PEAK, traffic=traffic,
                     bytes_per_launch=rep["bytes"] / rep["launches"],
                     avg_launch_us=1e3 * rep["ms"] / rep["launches"], launches=rep["launches"])
+    # All fused level kernels of one solve together (from the per-kernel
+    # timing pass): algorithmic bytes and, from the stored counter readings,
+    # measured HBM bytes over their summed launch time.
+    fams = ("k_up_smooth<4>", "k_down_smooth<4>", "k_ir_residual", "k_resid_restrict", "k_decode_full",
+            "k_decode_level")
+    sweep_rows = [r for r in per_kernel if r["kernel"] in fams]
+    sweep_s = sum(r["ms"] for r in sweep_rows) * 1e-3
+    sweep_alg = sum(r["bytes"] for r in sweep_rows)
+    hbm = [stored_traffic(r["kernel"]) for r in sweep_rows]
+    sweep_hbm = sum(h * r["launches"] for h, r in zip(hbm, sweep_rows)) if all(h is not None for h in hbm) else None
+    level_sweep = dict(kernels=[r["kernel"] for r in sweep_rows], ms_per_solve=sweep_s * 1e3,
+                       algorithmic_gbs=sweep_alg / sweep_s / 1e9, algorithmic_frac=sweep_alg / sweep_s / HBM_PEAK,
+                       measured_gbs=None if sweep_hbm is None else sweep_hbm / sweep_s / 1e9,
+                       measured_frac=None if sweep_hbm is None else sweep_hbm / sweep_s / HBM_PEAK)
     # the same kernel against its instruction-issue ceiling: counted VALU
     # instructions per launch over the live average launch time
     valu = stored_valu(dom)
@@ -423,6 +437,7 @@ def main():
         "setup_s": setup_s,
         "roofline": roofline,
         "issue": issue,
+        "level_sweep": level_sweep,
         "kernels": [dict(kernel=r["kernel"], ms=r["ms"], launches=r["launches"],
                          gbs=(r["bytes"] / (r["ms"] * 1e-3) / 1e9) if r["ms"] > 0 else None)
                     for r in per_kernel[:12]],
