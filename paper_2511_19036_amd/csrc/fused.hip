@@ -456,7 +456,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   constexpr int NB = S + 1;  // y buffers: plane j - 1 - s in flight from step j - s to j - s + S
   constexpr int NC = 8, CW = EXW / 2 + 2, CH = T::EXH / 2 + 1, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
   __shared__ float cs[NC * CPL];
-  __shared__ float lds[2 * PAD + (2 + NB) * PS];  // z of planes j, j - 1; then y buffers
+  __shared__ __align__(8) float lds[2 * PAD + (2 + NB) * PS];  // z of planes j, j - 1; then y buffers
+  static_assert(PAD % 2 == 0 && PS % 2 == 0 && T::LPL % 2 == 0, "column pairs at 8-byte offsets");
   __shared__ float outb[2][TY * kTX];
   const int tid = threadIdx.x;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -649,8 +650,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
           z[k][c][0] = z[k][c][1];
           z[k][c][1] = z[k][c][2];
           z[k][c][2] = prolong_node<float, JP, CW>(c0, c1, cb[k], c == 1, py);
-          zb[pos[k] + c] = z[k][c][2];
         }
+        *reinterpret_cast<float2*>(zb + pos[k]) = make_float2(z[k][0][2], z[k][1][2]);
       }
     }
     {  // plane j - 1: rhs = g - A z, and y' as stage 0
@@ -677,8 +678,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
           const float y0 = pair_f32(ypre[k], xy[k][0], c, cbits_of<CB>(Y), Y.w);
           rv[c] = keep ? gv : 0.0f;
           yv[c] = keep ? y0 : 0.0f;
-          yb[pc] = yv[c];
         }
+        *reinterpret_cast<float2*>(yb + pos[k]) = make_float2(yv[0], yv[1]);
         const bool sw = (fl[k] >> kSwap) & 1u;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
