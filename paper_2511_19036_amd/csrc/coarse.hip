@@ -116,10 +116,14 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
     if (a.rbgs) {
       for (int s = 0; s < nu; ++s)
         for (int colour = 0; colour < 2; ++colour) {
-          each(g.size, [&](int64_t idx) {
-            int i, j, k;
-            unflatten(g, idx, i, j, k);
-            if (!is_interior(g, i, j, k) || ((i + j + k) & 1) != colour) return;
+          // the nodes of one colour: node i = 2 (t mod n/2) + ((j + k + colour) & 1) of row t div (n/2)
+          each(g.size >> 1, [&](int64_t t) {
+            const int64_t row = t >> (g.level - 1);  // j + n k
+            const int j = static_cast<int>(row & (g.n - 1));
+            const int k = g.dim == 3 ? static_cast<int>(row >> g.level) : 0;
+            const int i = 2 * static_cast<int>(t & ((g.n >> 1) - 1)) + ((j + k + colour) & 1);
+            if (!is_interior(g, i, j, k)) return;
+            const int64_t idx = flat(g, i, j, k);
             const T r = rhs[idx] - apply_A(y, kap, g, i, j, k, ih2);
             const T c = smooth_coeff(kap, g, i, j, k, ih2, cp, T(1));
             y[idx] = y[idx] + c * r;
