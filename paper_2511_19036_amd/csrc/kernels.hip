@@ -8,6 +8,7 @@
 // wave to 64 consecutive values (one block of 64 or two of 32) so that the
 // shared exponent is a wave-level max reduction.
 #include <string>
+#include <type_traits>
 
 #include "device.h"
 #include "launch.h"
@@ -31,7 +32,10 @@ __global__ void __launch_bounds__(kThreads) k_encode(const T* x, int64_t n, SecR
   const double v = (i < n) ? static_cast<double>(x[i]) : 0.0;
   if (nonfinite != nullptr && !isfinite(v)) atomicOr(nonfinite, 1);
   int e;
-  const int64_t m = quantise_lane(v, s.B, s.w, &e);
+  // float input and w <= 24: the float quantiser gives the same codes
+  const int64_t m = (std::is_same<T, float>::value && s.w <= 24)
+                        ? quantise_lane_f32(static_cast<float>(v), s.B, s.w, lane, &e)
+                        : quantise_lane(v, s.B, s.w, &e);
   store_codes_wave(s, base, lane, m, limit);
   if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
   // the decoded value of the new code, as k_decode gives it (plus add)
