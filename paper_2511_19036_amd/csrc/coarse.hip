@@ -9,6 +9,7 @@
 // Each operation computes exactly what the corresponding per-operation
 // kernel computes (same expressions in the same order), so the results are
 // bit-identical.
+#include <type_traits>
 #include "coarse.h"
 #include "timing.h"
 
@@ -48,7 +49,10 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
       const double v = (i < n) ? static_cast<double>(x[i]) : 0.0;
       if (a.nonfinite != nullptr && !isfinite(v)) atomicOr(a.nonfinite, 1);
       int e;
-      const int64_t m = quantise_lane(v, s.B, s.w, &e);
+      // float input and w <= 24: the float quantiser gives the same codes
+      constexpr bool F32 = std::is_same<std::remove_cv_t<std::remove_reference_t<decltype(*x)>>, float>::value;
+      const int64_t m = (F32 && s.w <= 24) ? quantise_lane_f32(static_cast<float>(v), s.B, s.w, lane, &e)
+                                           : quantise_lane(v, s.B, s.w, &e);
       store_codes_wave(s, base, lane, m, limit);
       if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
       if (dec_out != nullptr && i < n) {

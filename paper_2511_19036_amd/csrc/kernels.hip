@@ -347,7 +347,9 @@ __global__ void __launch_bounds__(kThreads) k_restrict_encode(const T* __restric
   }
   if (nonfinite != nullptr && !isfinite(v)) atomicOr(nonfinite, 1);
   int e;
-  const int64_t m = quantise_lane(v, s.B, s.w, &e);
+  const int64_t m = (std::is_same<T, float>::value && s.w <= 24)
+                        ? quantise_lane_f32(static_cast<float>(v), s.B, s.w, lane, &e)
+                        : quantise_lane(v, s.B, s.w, &e);
   store_codes_wave(s, base, lane, m, limit);
   if ((lane & (s.B - 1)) == 0 && i < limit) s.exps[blk(s, i)] = static_cast<int16_t>(e);
 }
