@@ -249,11 +249,16 @@ def main():
     ap.add_argument("--no-codec", action="store_true", help="skip the adaptive-exponent codec timing")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for counter runs: one warm-up solve, a calibration copy of 1 GiB, one solve; no JSON")
+    ap.add_argument("--only-workloads", action="store_true",
+                    help="for kernel traces: time only the other workloads and print their figures as JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the solver is a single-GPU level sweep); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.only_workloads:
+        print(json.dumps(other_workloads()), flush=True)
+        return
 
     import torch
 
