@@ -6,7 +6,10 @@ Follows the paper's algorithms step by step on whole-level numpy arrays:
   (Sec. 2, eq. compact-to-standard); sections in regressive precision
   ``k (L - l) + b`` bits on level ``l`` (Sec. 2.1, eq. regressive);
 * residual: decode the standard representation level by level, form
-  ``t = f - A u_L`` and round it to the residual precision (Alg. 2);
+  ``t = f - A u_L`` and round it to the residual precision; when the cycle
+  has no pre-smoothing (V(0, nu2), the paper's own cycle) also restrict the
+  unrounded ``t`` level by level in float64 and round each level once,
+  ``r_l = fix(R_{l+1} ... R_L t)`` (Alg. 2, "restrict residual");
 * V-cycle: the compact FAS cycle relaxes, on every level, eq. cfas
   ``A_l y'_l = r_l - s_l - A_l z_l`` (Sec. 3.2, Alg. 1).  With the initial
   guess ``y' = 0`` that IR guarantees (Sec. 4, nu = 1) and ``nu1`` pre- and
@@ -15,7 +18,8 @@ Follows the paper's algorithms step by step on whole-level numpy arrays:
   - fine to coarse, ``g_l := r_l - s_l`` obeys
     ``g_{l-1} = R_l (g_l - A_l y'_l)`` where ``y'_l`` is the pre-smoothed
     (and stored, i.e. rounded) section: this is the recursion for ``s`` in
-    Alg. 1 written for ``r - s``;
+    Alg. 1 written for ``r - s``.  Without pre-smoothing ``y' = 0`` on the
+    way down, so ``s = 0`` and ``g_l = r_l`` comes from Alg. 2's chain;
   - on the coarsest level the equation is solved exactly;
   - coarse to fine, ``z_l = P_l (y'_{l-1} + z_{l-1})`` (Alg. 1) and the
     post-smoother relaxes ``A_l y'_l = g_l - A_l z_l``;
@@ -31,7 +35,12 @@ Precision reading (Table 1 mapped to IEEE types): sections of ``u'`` carry
 and coarsest solve run in float64; the V-cycle arithmetic runs in
 ``vcycle_dtype`` (float32 by default), which caps residual/correction widths
 at 24 bits (53 in float64).  The paper leaves the precision of ``s`` open
-(Sec. 4); here ``g = r - s`` is stored at the residual's width.
+(Sec. 4); here ``g = r - s`` is stored at the residual's width
+(``s_mode = "fold"``, what the GPU computes).  ``s_mode = "fp64"`` keeps
+instead ``r_l`` from Alg. 2's chain and ``s_l`` unrounded in float64
+(``s_{l-1} = R_l (A_l y'_l + s_l)``, Alg. 1's fine-to-coarse sweep) and
+relaxes with ``r_l - s_l``: it measures what the fold reading changes when
+``nu1 > 0`` (with ``nu1 = 0`` both modes are the same computation).
 """
 from __future__ import annotations
 
@@ -64,6 +73,7 @@ class Config:
     inc_ry: int = 1
     vcycle_dtype: type = np.float32
     quantize: bool = True
+    s_mode: str = "fold"           # "fold" | "fp64" (see the module docstring)
 
     def cap_ry(self) -> int:
         return 24 if self.vcycle_dtype == np.float32 else 53
@@ -125,35 +135,86 @@ def decode_chain(U: dict, lc: int, Lp: int) -> np.ndarray:
     return uh
 
 
-def ir_residual(U, f_level, ops, cfg: Config, Lp: int) -> Section:
-    """Alg. 2 on FMG level ``Lp``: ``g_Lp = round(f - A u_Lp)`` in float64."""
+def restrict_chain(t: np.ndarray, cfg: Config, Lp: int, top: int) -> dict:
+    """Alg. 2, "restrict residual": ``t_{l-1} = R_l t_l`` in float64 from the
+    unrounded ``t`` of level ``top``, each level rounded once to its residual
+    width, ``r_l = fix(t_l)``.  Returns ``{level: Section}`` for levels
+    ``coarsest .. top``."""
+    out = {top: Section.quantize(t, cfg.block, cfg.w_r(top, Lp), cfg.quantize)}
+    for level in range(top - 1, cfg.coarsest - 1, -1):
+        t = restrict(t, np.float64)
+        out[level] = Section.quantize(t, cfg.block, cfg.w_r(level, Lp), cfg.quantize)
+    return out
+
+
+def chain_needed(cfg: Config) -> bool:
+    """Whether the V-cycle takes the whole residual hierarchy from Alg. 2:
+    without pre-smoothing (V(0, nu2)), or when ``s`` is kept separately."""
+    return cfg.nu_pre == 0 or cfg.s_mode == "fp64"
+
+
+def residual_hierarchy(U, f_level, ops, cfg: Config, Lp: int) -> dict:
+    """Alg. 2 on FMG level ``Lp``: ``t = f - A u_Lp`` in float64 from the
+    decoded solution, ``r_Lp = fix(t)``, and, when the V-cycle needs them,
+    the restricted residuals of every coarser level.  Returns
+    ``{level: Section}``."""
     uh = decode_chain(U, cfg.coarsest, Lp)
     t = f_level - ops[Lp].apply(uh, np.float64)
-    return Section.quantize(t, cfg.block, cfg.w_r(Lp, Lp), cfg.quantize)
+    if chain_needed(cfg):
+        return restrict_chain(t, cfg, Lp, Lp)
+    return {Lp: Section.quantize(t, cfg.block, cfg.w_r(Lp, Lp), cfg.quantize)}
 
 
-def vcycle_correct(U, g_top: Section, ops, cfg: Config, Lp: int, trace=None):
+def ir_residual(U, f_level, ops, cfg: Config, Lp: int) -> Section:
+    """The finest section ``g_Lp = fix(f - A u_Lp)`` of Alg. 2 (float64)."""
+    return residual_hierarchy(U, f_level, ops, cfg, Lp)[Lp]
+
+
+def vcycle_correct(U, g_top, ops, cfg: Config, Lp: int, trace=None):
     """One compact V(nu1, nu2) cycle from a zero correction, then ``u' += y'``.
 
-    Returns the correction sections ``Y`` (after post-smoothing).  If
-    ``trace`` is a dict it receives the intermediate sections (``G``, the
-    pre-smoothed ``Y``) for inspection.
+    ``g_top`` is the residual hierarchy of :func:`residual_hierarchy` (or
+    its finest section alone, when the cycle restricts by itself).  Returns
+    the correction sections ``Y`` (after post-smoothing).  If ``trace`` is a
+    dict it receives the intermediate sections (``G``, the pre-smoothed
+    ``Y``) for inspection.
     """
     T = cfg.vcycle_dtype
     lc, B, on = cfg.coarsest, cfg.block, cfg.quantize
-    G = {Lp: g_top}
+    R = dict(g_top) if isinstance(g_top, dict) else {Lp: g_top}
+    exact_s = cfg.s_mode == "fp64"
+    if cfg.s_mode not in ("fold", "fp64"):
+        raise ValueError(cfg.s_mode)
+    if chain_needed(cfg) and len(R) != Lp - lc + 1:
+        raise ValueError("this cycle needs the residual of every level (Alg. 2)")
+    G = {Lp: R[Lp]}
+    s64 = {Lp: np.zeros((1 << Lp,) * cfg.dim)}            # s of the "fp64" reading
     Y = {}
+
+    def rhs_of(level):                                     # r_l - s_l in the V-cycle type
+        if exact_s:
+            return (G[level].value(np.float64) - s64[level]).astype(T)
+        return G[level].value(T)
+
     for level in range(Lp, lc, -1):                       # fine to coarse
         lv = ops[level]
-        g = G[level].value(T)
+        g = rhs_of(level)
         y = smooth(lv, np.zeros_like(g), g, cfg.nu_pre, cfg.smoother, cfg.omega, T)
         Y[level] = Section.quantize(y, B, cfg.w_y(level, Lp), on)
-        rc = restrict(g - lv.apply(Y[level].value(T), T), T)
-        G[level - 1] = Section.quantize(rc, B, cfg.w_r(level - 1, Lp), on)
+        if exact_s:                                       # s_{l-1} = R (A y'_l + s_l), float64
+            s64[level - 1] = restrict(lv.apply(Y[level].value(np.float64), np.float64) + s64[level],
+                                      np.float64)
+            G[level - 1] = R[level - 1]
+        elif cfg.nu_pre == 0:                             # y' = 0, s = 0: g_{l-1} = r_{l-1} (Alg. 2)
+            G[level - 1] = R[level - 1]
+        else:
+            rc = restrict(g - lv.apply(Y[level].value(T), T), T)
+            G[level - 1] = Section.quantize(rc, B, cfg.w_r(level - 1, Lp), on)
     if trace is not None:
         trace["G"] = dict(G)
         trace["Ypre"] = dict(Y)
-    yc = coarse_solve(ops[lc], G[lc].value(np.float64))   # coarsest, float64
+    gc = G[lc].value(np.float64) - (s64[lc] if exact_s else 0.0)
+    yc = coarse_solve(ops[lc], gc)                        # coarsest, float64
     Y[lc] = Section.quantize(yc, B, cfg.w_y(lc, Lp), on)
     U[lc] = Section.quantize(U[lc].value(np.float64) + Y[lc].value(np.float64),
                              B, cfg.w_u(lc, Lp), on)
@@ -161,7 +222,7 @@ def vcycle_correct(U, g_top: Section, ops, cfg: Config, Lp: int, trace=None):
     for level in range(lc + 1, Lp + 1):                   # coarse to fine
         lv = ops[level]
         z = prolong(E, T)
-        rhs = G[level].value(T) - lv.apply(z, T)
+        rhs = rhs_of(level) - lv.apply(z, T)
         y = smooth(lv, Y[level].value(T), rhs, cfg.nu_post, cfg.smoother, cfg.omega, T)
         Y[level] = Section.quantize(y, B, cfg.w_y(level, Lp), on)
         U[level] = Section.quantize(U[level].value(np.float64) + Y[level].value(np.float64),
@@ -194,7 +255,7 @@ def fmg_solve(f_full: np.ndarray, cfg: Config, kappa=None, history=None, levels=
         f_level = inject(f_full, L, Lp)
         iters = cfg.ir_iters + (cfg.final_iters if Lp == L else 0)
         for _ in range(iters):
-            g = ir_residual(U, f_level, ops, cfg, Lp)
+            g = residual_hierarchy(U, f_level, ops, cfg, Lp)
             if history is not None:
                 uh = decode_chain(U, lc, Lp)
                 history.append(float(np.linalg.norm(f_level - ops[Lp].apply(uh, np.float64))))
@@ -206,12 +267,17 @@ def fmg_solve(f_full: np.ndarray, cfg: Config, kappa=None, history=None, levels=
 
 def vcycle_standard(r_full: np.ndarray, cfg: Config, kappa=None):
     """One compact V-cycle on a standard FP64 fine residual (the ``cmg_vcycle``
-    entry): round ``r`` to the finest residual width, run the cycle from zero
-    on a zero solution, and return the decoded correction on the node grid."""
+    entry): round ``r`` to the finest residual width (and, when the cycle
+    needs them, restrict it unrounded to every level first, Alg. 2), run the
+    cycle from zero on a zero solution, and return the decoded correction
+    on the node grid."""
     lc, L = cfg.coarsest, cfg.L
     ops = hierarchy(cfg.dim, L, lc, cfg.op, kappa)
     r = inject(r_full, L, L)
-    g = Section.quantize(r, cfg.block, cfg.w_r(L, L), cfg.quantize)
+    if chain_needed(cfg):
+        g = restrict_chain(r, cfg, L, L)
+    else:
+        g = Section.quantize(r, cfg.block, cfg.w_r(L, L), cfg.quantize)
     U = {level: Section.zeros(cfg.dim, level, cfg.block, cfg.w_u(level, L), cfg.quantize)
          for level in range(lc, L + 1)}
     vcycle_correct(U, g, ops, cfg, L)

@@ -312,3 +312,94 @@ def test_pointwise_down_sweep_and_restriction_equal_whole_array():
         mm, e = pw.restrict_block(G, L, nu, K, J, 0, cfg.block, cfg.w_y(L, L), cfg.w_r(L - 1, L))
         k = (K * m + J) * m
         assert np.array_equal(mm, gc.m[k:k + cfg.block]) and e == int(gc.e[k // cfg.block]), (K, J)
+
+
+# ------------------------------------------------ Alg. 2 restriction chain
+@pytest.mark.parametrize("dim,L,w", [(2, 5, 6), (3, 4, 6), (3, 4, 12)])
+def test_restrict_chain_against_dense_products(dim, L, w):
+    # Alg. 2 restricts the unrounded t and rounds every level once:
+    # r_l = fix(R_{l+1} ... R_L t).  With integer t every product and sum is
+    # an exact dyadic rational, so the dense products R = 2^-d P^T applied
+    # one after another give the exact values, and the codes must be equal.
+    rng = np.random.default_rng(11)
+    n = 1 << L
+    t = np.zeros((n,) * dim)
+    t[(slice(1, None),) * dim] = rng.integers(-1000, 1001, size=(n - 1,) * dim)
+    B = 32 if dim == 2 else 64
+    cfg = compact.Config(dim=dim, L=L, block=B, bits_r=w, nu_pre=0, nu_post=1)
+    got = compact.restrict_chain(t, cfg, L, L)
+    v = t[(slice(1, None),) * dim].reshape(-1)
+    differs = 0
+    for level in range(L, 0, -1):
+        if level < L:
+            v = (0.5 ** dim) * dense.prolongation(dim, level + 1).T @ v
+        m = 1 << level
+        x = np.zeros((m,) * dim)
+        x[(slice(1, None),) * dim] = v.reshape((m - 1,) * dim)
+        wl = cfg.w_r(level, L)
+        codes, exps = bfp.encode(x.reshape(-1), B, wl)
+        assert got[level].w == wl
+        assert np.array_equal(got[level].e, exps) and np.array_equal(got[level].m, codes), level
+        if level < L:
+            # restricting the rounded finer level instead (the departure this
+            # pin guards against) gives other codes at these widths
+            rc = grid.restrict(got[level + 1].value(np.float64), np.float64)
+            mc, _ = bfp.encode(rc.reshape(-1), B, wl)
+            differs += int(np.count_nonzero(mc != codes))
+    assert differs > 0
+
+
+def test_residual_hierarchy_without_presmoothing():
+    # V(0, nu2): the cycle takes every level's residual from Alg. 2; with
+    # pre-smoothing only the finest one (the cycle restricts g - A y')
+    dim, L = 3, 4
+    f = S.gaussian_noise_rhs(dim, L, sigma=0.1, seed=2)
+    ops = grid.hierarchy(dim, L, 1)
+    for nu1, levels in ((0, list(range(1, L + 1))), (2, [L])):
+        cfg = compact.Config(dim=dim, L=L, bits_u=10, bits_r=10, bits_y=10, nu_pre=nu1, nu_post=1)
+        U = {lv: compact.Section.zeros(dim, lv, 64, cfg.w_u(lv, L)) for lv in range(1, L + 1)}
+        R = compact.residual_hierarchy(U, grid.inject(f, L, L), ops, cfg, L)
+        assert sorted(R) == levels
+        chain = compact.restrict_chain(grid.inject(f, L, L), cfg, L, L)
+        for lv in levels:
+            assert np.array_equal(R[lv].m, chain[lv].m) and np.array_equal(R[lv].e, chain[lv].e)
+    with pytest.raises(ValueError):
+        cfg = compact.Config(dim=dim, L=L, nu_pre=0, nu_post=1)
+        compact.vcycle_correct(U, R[L], ops, cfg, L)
+
+
+@pytest.mark.parametrize("nu1", [0, 2])
+def test_exact_s_reading_unquantised_equals_correction_scheme(nu1):
+    # keeping s apart in float64 (Alg. 1's fine-to-coarse sweep) is the same
+    # cycle as the correction scheme when nothing is rounded
+    dim, L = 3, 4
+    cfg = compact.Config(dim=dim, L=L, quantize=False, vcycle_dtype=np.float64, s_mode="fp64",
+                         nu_pre=nu1, nu_post=2)
+    r = S.gaussian_noise_rhs(dim, L, sigma=1.0, seed=9)
+    y_c = compact.vcycle_standard(r, cfg)
+    ops = grid.hierarchy(dim, L, 1)
+    y_p = plain.cs_vcycle(ops, L, grid.inject(r, L, L), cfg, np.float64)
+    assert np.abs(y_c[(slice(0, 1 << L),) * dim] - y_p).max() <= 1e-13 * np.abs(y_p).max()
+
+
+@pytest.mark.parametrize("bits,tol", [(8, 0.15), (16, 0.01)])
+def test_fold_reading_changes_the_solution_little(bits, tol):
+    # The paper leaves the precision of s open (Sec. 4).  Storing g = r - s
+    # at the residual width ("fold", the GPU's reading) against keeping r
+    # from Alg. 2's chain and s unrounded in float64: both meet the
+    # acceptance test, and the solutions differ by a small fraction of the
+    # discretisation error (measured 0.08 / 0.005 / 0.0003 at 8 / 12 / 16
+    # bits, 3-D L = 5).
+    dim, L = 3, 5
+    us, uh, h = _closed_form(dim, L)
+    disc = grid.norm_h(uh - us, h)
+    sols = {}
+    for mode in ("fold", "fp64"):
+        cfg = compact.Config(dim=dim, L=L, bits_u=bits, bits_r=bits, bits_y=bits, s_mode=mode)
+        u, _ = compact.fmg_solve(S.sine_rhs(dim, L), cfg)
+        assert grid.norm_h(u - us, h) <= 2.0 * disc
+        assert grid.norm_h(u - uh, h) <= 0.5 * disc
+        sols[mode] = u
+    diff = grid.norm_h(sols["fold"] - sols["fp64"], h) / disc
+    print(f"fold vs fp64 s at {bits} bits: |u_fold - u_fp64| / disc = {diff:.3e}")
+    assert diff <= tol
