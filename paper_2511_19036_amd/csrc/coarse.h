@@ -33,6 +33,7 @@ struct CoarseArgs {
   const double* kap64;                  // coarsest level coefficients (null for Poisson)
   int lc, Lc, Lp;                       // coarsest level, top level of this call, FMG level
   int nu_pre, nu_post, rbgs;
+  int chain;                            // 1: every G is given (Alg. 2 chain, nu_pre = 0); no restriction
   double omega;
   int* nonfinite;
 };

@@ -175,6 +175,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
     smooth(F, yf, gf, arr(l, 4), a.nu_pre);
     encode(yf, F.g.size, F.Y, yf);  // y' = Q(y); yf = dec y'
     sync();
+    if (a.chain) continue;  // g_{l-1} is the restricted IR residual, given
     rhs_minus_A(gf, yf, static_cast<const T*>(F.kap), F.g, static_cast<T>(F.ih2), rf);
     sync();
     restrict_to(rf, C.g, F.g, arr(l - 1, 3));

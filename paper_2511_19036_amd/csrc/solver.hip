@@ -115,6 +115,10 @@ struct cmg_ctx_s {
     return p.dim == 3 ? N * N * N : N * N;
   }
   bool compact() const { return o.storage == CMG_COMPACT_BFP; }
+  // Without pre-smoothing (V(0, nu2)) the V-cycle takes the residual of
+  // every level from the IR residual: Alg. 2 restricts the unrounded float64
+  // residual level by level and rounds each level once.
+  bool chain() const { return compact() && o.nu_pre == 0; }
   // Levels handled by the fused 3-D kernels (rows of at least 64 nodes).
   bool fused3d() const {
     return compact() && p.dim == 3 && p.op == CMG_POISSON && o.smoother == CMG_RBGS &&
@@ -122,7 +126,7 @@ struct cmg_ctx_s {
   }
   bool smooth_fused(int l) const { return fused3d() && l >= 6; }
   bool rr_fused(int l) const { return fused3d() && l >= 7; }
-  bool res_fused(int l) const { return compact() && p.dim == 3 && p.op == CMG_POISSON && l >= 6; }
+  bool res_fused(int l) const { return compact() && p.dim == 3 && p.op == CMG_POISSON && l >= 6 && !chain(); }
 };
 
 namespace {
@@ -207,10 +211,8 @@ void setup_levels(cmg_ctx c, const double* kappa) {
       if (l < L || v1s) D.ef = c->alloc(n * tsz, work);
       const bool v1res = !c->res_fused(l);
       if (l < L || d == 2 || v1res) D.uh = static_cast<double*>(c->alloc(n * 8, f64c));
-      if (v1res || l == lc) {
-        D.t64 = static_cast<double*>(c->alloc(n * 8, f64c));
-        D.f64 = static_cast<double*>(c->alloc(n * 8, f64c));
-      }
+      if (v1res || l == lc || (c->chain() && l < L)) D.t64 = static_cast<double*>(c->alloc(n * 8, f64c));
+      if (v1res || l == lc) D.f64 = static_cast<double*>(c->alloc(n * 8, f64c));
     } else {
       D.yf = c->alloc(n * tsz, work);
       D.zf = c->alloc(n * tsz, work);
@@ -375,6 +377,11 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     LevelData& C = c->lv[l - 1];
     const double ih2 = inv_h2(l);
     F.Y.w = c->wy(l, Lp);
+    if (c->chain()) {  // V(0, nu2): y' = Q(0), s = 0; g_{l-1} = r_{l-1} came from the IR residual
+      launch_zero_section(F.Y.ref(), st);
+      KCK();
+      continue;
+    }
     C.G.w = c->wr(l - 1, Lp);
     const bool fs = f32 && c->smooth_fused(l);
     if (fs && c->o.nu_pre == 0) {  // V(0, nu2): y' = Q(0)
@@ -434,6 +441,7 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     a.nu_post = c->o.nu_post;
     a.rbgs = c->o.smoother == CMG_RBGS ? 1 : 0;
     a.omega = c->o.omega;
+    a.chain = c->chain() ? 1 : 0;
     a.nonfinite = nf;
     launch_coarse_vcycle<T>(a, st);
     KCK();
@@ -498,7 +506,21 @@ void decode_to_full(cmg_ctx c, int Lp, double* u) {
   KCK();
 }
 
-// IR residual (Alg. 2) into G[Lp].  f is the caller's finest node array; the
+// Alg. 2, "restrict residual": t_{l-1} = R t_l in float64 from the
+// unrounded t64[top], every level rounded once into its residual section
+// (levels top - 1 .. lc).
+void residual_chain(cmg_ctx c, int Lp, int top) {
+  for (int l = top - 1; l >= c->lc(); --l) {
+    LevelData& D = c->lv[l];
+    launch_restrict<double>(c->lv[l + 1].t64, D.g, c->lv[l + 1].g, D.t64, c->st);
+    D.G.w = c->wr(l, Lp);
+    launch_encode<double>(D.t64, D.g.size, D.G.ref(), c->flags + 1, c->st);
+  }
+  KCK();
+}
+
+// IR residual (Alg. 2) into G[Lp] (and, for a cycle without pre-smoothing,
+// into every coarser G).  f is the caller's finest node array; the
 // per-operation path uses the injected copy in f64[Lp].
 void ir_residual(cmg_ctx c, int Lp, const double* f, cmg_stats* st) {
   LevelData& F = c->lv[Lp];
@@ -512,13 +534,14 @@ void ir_residual(cmg_ctx c, int Lp, const double* f, cmg_stats* st) {
     KCK();
   } else {
     decode_chain(c, Lp);
-    if (!rec) {  // residual and encode in one pass
+    if (!rec && !c->chain()) {  // residual and encode in one pass
       launch_res_encode(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.G.ref(), c->flags + 1, c->st);
       KCK();
-    } else {  // the recorded norm needs the residual array
+    } else {  // the recorded norm and the restriction chain need the residual array
       launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.t64, c->st);
       launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
       KCK();
+      if (c->chain()) residual_chain(c, Lp, Lp);
     }
     if (rec) {
       HIPCK(hipMemsetAsync(c->red, 0, 8, c->st));
@@ -804,7 +827,14 @@ cmg_status cmg_vcycle(cmg_ctx c, const double* r, double* y) {
       LevelData& F = c->lv[L];
       if (c->compact()) {
         F.G.w = c->wr(L, L);  // r rounded to the finest residual width
-        launch_encode_full(r + b * M, L, F.g, F.G.ref(), c->flags + 1, c->st);
+        if (c->chain()) {  // and restricted unrounded to every level (Alg. 2)
+          launch_inject(r + b * M, L, F.g, F.t64, c->st);
+          launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
+          KCK();
+          residual_chain(c, L, L);
+        } else {
+          launch_encode_full(r + b * M, L, F.g, F.G.ref(), c->flags + 1, c->st);
+        }
         for (int l = lc; l <= L; ++l) {
           c->lv[l].U.w = c->wu(l, L);
           launch_zero_section(c->lv[l].U.ref(), c->st);

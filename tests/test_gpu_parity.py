@@ -135,12 +135,16 @@ def test_ir_residual_bit_exact(cmg, name):
         for level, sec in U.items():
             s.import_section("u", level, sec.w, np.frombuffer(ob.pack(sec.m, sec.w), dtype=np.uint8), sec.e)
         s.ir_residual(f)
-        m, e, bits = _export(s, "r", L)
-    ops = og.hierarchy(c["dim"], L, 1)
-    g = oc.ir_residual(U, og.inject(f_np, L, L), ops, cfg, L)
-    assert bits == g.w
-    assert np.array_equal(e, g.e)
-    assert np.array_equal(m, g.m)
+        ops = og.hierarchy(c["dim"], L, 1)
+        # without pre-smoothing every level's residual comes from Alg. 2's chain
+        R = oc.residual_hierarchy(U, og.inject(f_np, L, L), ops, cfg, L)
+        got = {level: _export(s, "r", level) for level in R}
+    assert sorted(R) == (list(range(1, L + 1)) if _nus(c)[0] == 0 else [L])
+    for level, g in R.items():
+        m, e, bits = got[level]
+        assert bits == g.w, level
+        assert np.array_equal(e, g.e), level
+        assert np.array_equal(m, g.m), level
 
 
 @pytest.mark.parametrize("name", list(CFGS))
@@ -159,7 +163,7 @@ def test_vcycle_step_bit_exact(cmg, name):
         s.vcycle_correct()
         got = {(w, level): _export(s, w, level) for w in ("u", "y", "r") for level in range(1, L + 1)}
     ops = og.hierarchy(c["dim"], L, 1)
-    g = oc.ir_residual(U, og.inject(f_np, L, L), ops, cfg, L)
+    g = oc.residual_hierarchy(U, og.inject(f_np, L, L), ops, cfg, L)
     trace = {}
     Y = oc.vcycle_correct(U, g, ops, cfg, L, trace=trace)
     for level in range(1, L + 1):
@@ -200,7 +204,7 @@ def test_plain_fmg_matches_oracle(cmg, dim, L, smoother, omega, prec):
     assert np.array_equal(u, u_ref)
 
 
-@pytest.mark.parametrize("name", ["3d-rbgs-b16", "2d-wjacobi-b16", "3d-L7-b16"])
+@pytest.mark.parametrize("name", ["3d-rbgs-b16", "2d-wjacobi-b16", "3d-L7-b16", "3d-L7-V01-b12", "2d-L6-V01-b16"])
 def test_vcycle_entry_matches_oracle(cmg, name):
     c = CFGS[name]
     cfg = _oracle_cfg(c)
