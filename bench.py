@@ -83,6 +83,36 @@ def stored_valu(kernel):
     return _stored_column("valu_issue_fused_kernels_poisson3d_1025.md", kernel, 2)
 
 
+def model_bytes_per_dof(kernel, bits, block):
+    """Algorithmic HBM bytes per interior DoF of one launch of a fused level
+    kernel on the finest level (every section at the finest width `bits`,
+    one int16 exponent per block): beta = bits / 8 + 2 / block bytes per
+    stored value; the coarse level has 1/8 of the values.
+      up sweep:     g, y' read; u' read and written; coarse y' and FP32 z read
+      down sweep:   g read, y' written
+      restriction:  g, y' read, coarse g written
+      IR residual:  u' read, coarse FP64 u read, FP64 f read, g written
+      final decode: u' read, coarse FP64 u read, FP64 u written"""
+    beta = bits / 8.0 + 2.0 / block
+    name = kernel.partition("<")[0]
+    table = {"k_up_smooth": 4 * beta + (beta + 4.0) / 8.0, "k_down_smooth": 2 * beta,
+             "k_resid_restrict": 2 * beta + beta / 8.0, "k_ir_residual": 2 * beta + 1.0 + 8.0,
+             "k_decode_full": beta + 1.0 + 8.0}
+    return table[name]
+
+
+def _by_kernel(rows):
+    """Per-level timing rows ("name@l") summed per kernel name."""
+    acc = {}
+    for r in rows:
+        name = r["kernel"].partition("@")[0]
+        a = acc.setdefault(name, dict(kernel=name, launches=0, ms=0.0, bytes=0.0))
+        a["launches"] += r["launches"]
+        a["ms"] += r["ms"]
+        a["bytes"] += r["bytes"]
+    return sorted(acc.values(), key=lambda r: -r["ms"])
+
+
 def discretisation_check(u, L, dim=3):
     """Errors of u against the closed-form discrete solution of the sine part.
 
@@ -108,22 +138,74 @@ def discretisation_check(u, L, dim=3):
     return math.sqrt(err2 / disc2), math.sqrt(dev2 / disc2)
 
 
-def cpu_baseline(L_sample: int, bits: int):
-    """The oracle (numpy, as it stands) on the same problem at a smaller grid."""
-    import numpy as np  # noqa: F401
+_ORACLE_CHILD = """
+import sys, time
+sys.path.insert(0, {root!r})
+import synthetic
+from oracle import compact as oc
+f = synthetic.hash_noise_rhs(3, {L}, amp=1e-4, seed=3)
+cfg = oc.Config(dim=3, L={L}, smoother="rbgs", omega=1.0, block=64, bits_u={b}, bits_r={b}, bits_y={b})
+print("start", time.time(), flush=True)
+sys.stdin.readline()
+t0 = time.time()
+oc.fmg_solve(f, cfg)
+print("solve", t0, time.time(), flush=True)
+"""
 
-    import synthetic
-    from oracle import compact as oc
-    f = synthetic.hash_noise_rhs(3, L_sample, amp=1e-4, seed=3)
-    cfg = oc.Config(dim=3, L=L_sample, smoother="rbgs", omega=1.0, block=64,
-                    bits_u=bits, bits_r=bits, bits_y=bits)
-    t = time.perf_counter()
-    oc.fmg_solve(f, cfg)
-    t = time.perf_counter() - t
+
+def host_info():
+    """Host cores and CPU model of the machine the benchmark runs on."""
+    model = None
+    try:
+        import subprocess
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return dict(nproc=os.cpu_count(), lscpu_model=model)
+
+
+def cpu_baseline(L_sample: int, bits: int, procs: int):
+    """The oracle (numpy, as it stands: single-threaded) on the same problem
+    at a smaller grid: one solve on one host thread, then `procs` independent
+    solves at once in child processes (one thread each) for the rate of all
+    the host cores the GPU's share allows."""
+    import subprocess
+    code = _ORACLE_CHILD.format(root=ROOT, L=L_sample, b=bits)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     dofs = ((1 << L_sample) - 1) ** 3
-    return dict(value=dofs / t, unit="DoF/s", cores=1, kind="oracle",
-                sample=f"the same problem and solver settings at {(1 << L_sample) + 1}^3 "
-                       f"({dofs} DoF), one FMG solve, {t:.1f} s on one host thread")
+
+    def run(n):
+        ch = [subprocess.Popen([sys.executable, "-c", code], stdin=subprocess.PIPE, stdout=subprocess.PIPE,
+                               text=True, env=env) for _ in range(n)]
+        for c in ch:  # every child has built its input; then all solve at once
+            c.stdout.readline()
+        for c in ch:
+            c.stdin.write("go\n")
+            c.stdin.flush()
+        spans = []
+        for c in ch:
+            out, _ = c.communicate(timeout=600)
+            if c.returncode != 0:
+                raise RuntimeError("oracle child process failed")
+            t0, t1 = [float(v) for v in out.split()[1:3]]
+            spans.append((t0, t1))
+        return min(a for a, _ in spans), max(b for _, b in spans)
+
+    a, b = run(1)
+    t1 = b - a
+    a, b = run(procs)
+    tp = b - a
+    info = host_info()
+    return dict(value=procs * dofs / tp, unit="DoF/s", cores=procs, kind="oracle",
+                sample=f"the same problem and solver settings at {(1 << L_sample) + 1}^3 ({dofs} DoF): {procs} "
+                       f"independent FMG solves at once, one per host core, {tp:.1f} s wall",
+                single_thread=dict(value=dofs / t1, unit="DoF/s", cores=1,
+                                   sample=f"one FMG solve at {(1 << L_sample) + 1}^3, {t1:.1f} s on one thread"),
+                nproc=info["nproc"], lscpu_model=info["lscpu_model"],
+                note="the oracle is plain numpy (no threading of its own); the all-core rate runs one solve per "
+                     "core, capped at the host share of one GPU")
 
 
 def _time_solves(s, f, reps):
@@ -176,18 +258,71 @@ def codec_rates(x, bits, reps=3):
                 max_abs_err=err, max_abs=amax)
 
 
+def _rel(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def _converged(dim, L, f, iters=30, **kw):
+    """A float64 solve run to stagnation (plain storage, float64 V-cycles,
+    `iters` extra IR iterations on the finest level): the reference the
+    other solves' errors are stated against."""
+    from paper_2511_19036_amd import Solver
+    with Solver(dim, L, batch=f.shape[0], storage="plain", vcycle_prec="fp64", final_iters=iters, **kw) as s:
+        return s.solve(f)
+
+
+def _coarsen_cells(k):
+    n = k.shape[0] // 2
+    return k.reshape(n, 2, n, 2, n, 2).mean(dim=(1, 3, 5)).contiguous()
+
+
+def _richardson(uh, u2h):
+    """Relative discretisation-error estimate of the second-order scheme
+    from solutions on h and 2h at coincident nodes: |u_h - u_2h| / 3."""
+    import torch
+    c = uh[::2, ::2, ::2]
+    return float(torch.linalg.vector_norm(c - u2h) / 3.0 / torch.linalg.vector_norm(c))
+
+
+def _timed(fn, reps):
+    import torch
+    out = fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, out
+
+
 def other_workloads():
-    """Solve times of the other workloads (same library, same GPU)."""
+    """Solve times of the other workloads (same library, same GPU), each
+    with its error against a converged float64 solve of the same system."""
     import torch
 
     import synthetic
     from paper_2511_19036_amd import Solver
+    W = synthetic.WORKLOADS
     out = {}
     log("[bench] other workloads: 2-D 129^2, 3-D 257^3, diffusion 129^3 and 513^3 x 8")
+    # config 1: 2-D, weighted Jacobi, compact against plain float64 FMG
     f = torch.from_numpy(synthetic.gaussian_noise_rhs(2, 7, 1e-3, 0)).cuda()[None].contiguous()
+    ref = _converged(2, 7, f, smoother="wjacobi", omega=0.8)
     with Solver(2, 7, smoother="wjacobi", omega=0.8, bfp_block=32, bits=16) as s:
-        ms, _ = _time_solves(s, f, 20)
-    out["poisson2d_129_b16"] = dict(ms_per_solve=ms, dof_per_s=127 ** 2 / (ms * 1e-3))
+        ms, u = _timed(lambda: s.solve(f), 20)
+    with Solver(2, 7, smoother="wjacobi", omega=0.8, storage="plain", vcycle_prec="fp64") as s:
+        pms, up = _timed(lambda: s.solve(f), 20)
+    h = 2.0 ** -7
+    disc = ((math.pi * h / 2) / math.sin(math.pi * h / 2)) ** 2 - 1.0
+    out["poisson2d_129_b16"] = dict(ms_per_solve=ms, dof_per_s=127 ** 2 / (ms * 1e-3),
+                                    err_vs_fp64=_rel(u[0], ref[0]), plain_fp64_ms_per_solve=pms,
+                                    plain_fp64_err_vs_fp64=_rel(up[0], ref[0]), disc_rel_sine_part=disc,
+                                    note="errors: relative L2 against a converged float64 solve; disc_rel_sine_part "
+                                         "= c_h - 1, the relative discretisation error of the noise-free problem")
+    # config 2: 3-D 257^3 sine problem (closed-form discrete solution)
     f = torch.from_numpy(synthetic.sine_rhs(3, 8)).cuda()[None].contiguous()
     for b in (8, 12, 16):
         with Solver(3, 8, smoother="rbgs", bfp_block=64, bits=b) as s:
@@ -195,27 +330,50 @@ def other_workloads():
         e, dv = discretisation_check(u[0], 8)
         out[f"poisson3d_257_b{b}"] = dict(ms_per_solve=ms, dof_per_s=255 ** 3 / (ms * 1e-3), err_over_disc=e,
                                           dev_over_disc=dv)
-    kap = torch.from_numpy(synthetic.lognormal_kappa(3, 7, 0.1, 1)).cuda()
-    f = torch.zeros((1, 129, 129, 129), dtype=torch.float64, device="cuda")
+    # config 4: diffusion 129^3, forward + adjoint + gradient
+    c4 = W["diffusion3d_129"]
+    L = c4["L"]
+    kap = torch.from_numpy(synthetic.lognormal_kappa(3, L, c4["kappa_corr"], c4["kappa_seed"])).cuda()
+    kobs = torch.from_numpy(synthetic.lognormal_kappa(3, L, c4["kappa_corr"], c4["kappa_obs_seed"])).cuda()
+    f = torch.zeros((1,) + ((1 << L) + 1,) * 3, dtype=torch.float64, device="cuda")
     f[:, 1:-1, 1:-1, 1:-1] = 1.0
-    with Solver(3, 7, op="diffusion", kappa=kap, bits=16) as s:
+    uobs = _converged(3, L, f, op="diffusion", kappa=kobs)
+    uref = _converged(3, L, f, op="diffusion", kappa=kap)
+    with Solver(3, L, op="diffusion", kappa=kap, batch=1, storage="plain", vcycle_prec="fp64",
+                final_iters=30) as s:
+        lref, gref = s.adjoint(uref, uref - uobs)
+    u2h = _converged(3, L - 1, f[:, ::2, ::2, ::2].contiguous(), op="diffusion", kappa=_coarsen_cells(kap))
+    with Solver(3, L, op="diffusion", kappa=kap, bits=16, ir_iters=c4["ir_iters"]) as s:
         ms, u = _time_solves(s, f, 5)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        s.adjoint(u, u)
-        e1.record()
-        torch.cuda.synchronize()
-    out["diffusion3d_129_b16"] = dict(ms_per_solve=ms, dof_per_s=127 ** 3 / (ms * 1e-3),
-                                      ms_adjoint_and_gradient=e0.elapsed_time(e1))
-    kap = synthetic.lognormal_kappa_torch(3, 9, 0.05, 4, device="cuda")
-    f = torch.stack([synthetic.smoothed_noise_rhs_torch(3, 9, sd, device="cuda") for sd in range(100, 108)])
-    with Solver(3, 9, op="diffusion", kappa=kap, batch=8, bits=16) as s:
+        ams, (lam, grad) = _timed(lambda: s.adjoint(u, u - uobs), 3)
+    disc4 = _richardson(uref[0], u2h[0])
+    out["diffusion3d_129_b16"] = dict(ms_per_solve=ms, dof_per_s=127 ** 3 / (ms * 1e-3), ir_iters=c4["ir_iters"],
+                                      ms_adjoint_and_gradient=ams, err_vs_fp64=_rel(u[0], uref[0]),
+                                      adjoint_err_vs_fp64=_rel(lam[0], lref[0]), grad_err_vs_fp64=_rel(grad, gref),
+                                      disc_rel_richardson=disc4, err_over_disc=_rel(u[0], uref[0]) / disc4,
+                                      note="J = 1/2 |u - u_obs|^2; errors relative L2 against converged float64 "
+                                           "solves; disc_rel_richardson = |u_h - u_2h| / 3 / |u_h| at coincident "
+                                           "nodes (2h: children-mean kappa, same f)")
+    del kap, kobs, uobs, uref, lref, gref, u2h, u, lam, grad
+    # config 5: diffusion 513^3 x 8, batched forward + adjoint
+    c5 = W["diffusion3d_513x8"]
+    L, seeds, B = c5["L"], c5["rhs_seeds"], len(c5["rhs_seeds"])
+    kap = synthetic.lognormal_kappa_torch(3, L, c5["kappa_corr"], c5["kappa_seed"], device="cuda")
+    kobs = synthetic.lognormal_kappa_torch(3, L, c5["kappa_corr"], c5["kappa_obs_seed"], device="cuda")
+    f = torch.stack([synthetic.smoothed_noise_rhs_torch(3, L, sd, device="cuda") for sd in seeds])
+    log("[bench] diffusion 513^3 x 8: converged float64 references")
+    uobs = _converged(3, L, f, op="diffusion", kappa=kobs)
+    del kobs
+    uref = _converged(3, L, f, op="diffusion", kappa=kap)
+    with Solver(3, L, op="diffusion", kappa=kap, batch=B, storage="plain", vcycle_prec="fp64", final_iters=30) as s:
+        lref, _ = s.adjoint(uref, uref - uobs, want_grad=False)
+    u2h = _converged(3, L - 1, f[:, ::2, ::2, ::2].contiguous(), op="diffusion", kappa=_coarsen_cells(kap))
+    disc5 = [_richardson(uref[b], u2h[b]) for b in range(B)]
+    del u2h
+    with Solver(3, L, op="diffusion", kappa=kap, batch=B, bits=16, ir_iters=c5["ir_iters"]) as s:
         ms, u = _time_solves(s, f, 2)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        s.adjoint(u, u)
-        e1.record()
-        torch.cuda.synchronize()
+        dJ = u - uobs
+        ams, (lam, _) = _timed(lambda: s.adjoint(u, dJ), 1)
         # one more solve with every kernel timed: the dominant kernel's
         # algorithmic bytes over its launch time, against the HBM peak
         s.timing(True)
@@ -224,13 +382,20 @@ def other_workloads():
         top = s.timing_report()[0]
         s.timing(False)
     gbs = top["bytes"] / (top["ms"] * 1e-3)
-    out["diffusion3d_513x8_b16"] = dict(ms_per_solve=ms, dof_per_s=8 * 511 ** 3 / (ms * 1e-3),
-                                        ms_adjoint_and_gradient=e0.elapsed_time(e1),
+    fwd = [_rel(u[b], uref[b]) for b in range(B)]
+    adj = [_rel(lam[b], lref[b]) for b in range(B)]
+    out["diffusion3d_513x8_b16"] = dict(ms_per_solve=ms, dof_per_s=B * 511 ** 3 / (ms * 1e-3),
+                                        ir_iters=c5["ir_iters"], ms_adjoint_and_gradient=ams,
+                                        err_vs_fp64_per_rhs=fwd, adjoint_err_vs_fp64_per_rhs=adj,
+                                        disc_rel_richardson_per_rhs=disc5,
+                                        max_err_over_disc=max(e / d for e, d in zip(fwd, disc5)),
                                         dominant_kernel=dict(kernel=top["kernel"], ms_per_solve=top["ms"],
                                                              launches=top["launches"], gbs=gbs / 1e9,
                                                              hbm_frac=gbs / HBM_PEAK),
-                                        note="diffusion runs the per-operation kernels (one launch per red-black "
-                                             "sweep; the fused level kernels are Poisson-only)")
+                                        note="errors relative L2 against converged float64 solves of the same "
+                                             "system; the right-hand sides vary on the grid scale, so the "
+                                             "Richardson estimate (2h: children-mean kappa, injected f) is a "
+                                             "scale, not a converged discretisation error")
     return out
 
 
@@ -244,6 +409,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 FMG comparison")
     ap.add_argument("--cpu-L", type=int, default=8)
+    ap.add_argument("--cpu-procs", type=int, default=16, help="oracle processes for the all-core CPU rate")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 8/12-bit and tuned-width runs")
     ap.add_argument("--no-workloads", action="store_true", help="skip the timings of the other workloads")
     ap.add_argument("--no-codec", action="store_true", help="skip the adaptive-exponent codec timing")
@@ -294,17 +460,20 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
 
-    # one untimed solve with every kernel timed: find the dominant kernel
-    s.timing(True)
+    # one untimed solve with every kernel timed per level: the dominant kernel
+    s.timing(True, "@")
     s.solve(f, u)
     torch.cuda.synchronize()
-    per_kernel = s.timing_report()
+    per_level = s.timing_report()
+    s.timing(False)
+    per_kernel = _by_kernel(per_level)
     dom = per_kernel[0]["kernel"]
     log(f"[bench] dominant kernel: {dom} ({per_kernel[0]['ms']:.2f} ms of "
         f"{sum(r['ms'] for r in per_kernel):.2f} ms per solve)")
 
-    # timed region: K solves; HIP events bracket the dominant kernel's launches
-    s.timing(True, dom)
+    # timed region: K solves; HIP events bracket the dominant kernel's
+    # launches on the finest level
+    s.timing(True, f"{dom}@{L}")
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
@@ -324,12 +493,34 @@ def main():
 
     codec = None if args.no_codec else codec_rates(u.view(-1), args.bits)
 
-    achieved = rep["bytes"] / (rep["ms"] * 1e-3)
-    traffic = stored_traffic(dom)
-    roofline = dict(bound="hbm", kernel=dom, achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                    frac=achieved / HBM_PEAK, traffic=traffic,
-                    bytes_per_launch=rep["bytes"] / rep["launches"],
-                    avg_launch_us=1e3 * rep["ms"] / rep["launches"], launches=rep["launches"])
+    # Roofline of the dominant kernel on the finest level: its algorithmic
+    # bytes per interior DoF at the finest widths (the survey's per-DoF
+    # model, logical widths), times the DoF of one launch, over the average
+    # launch time measured with HIP events inside the timed solves.
+    bpd = model_bytes_per_dof(dom, args.bits, 64)
+    avg_s = 1e-3 * rep["ms"] / rep["launches"]
+    achieved = bpd * dofs / avg_s
+    traffic = stored_traffic(f"{dom}@{L}")
+    levels = []
+    for r in per_level:
+        name, _, lv = r["kernel"].partition("@")
+        if name == dom and lv:
+            lvl = int(lv)
+            levels.append(dict(level=lvl, launches=r["launches"], avg_launch_us=1e3 * r["ms"] / r["launches"],
+                               library_bytes_per_launch=r["bytes"] / r["launches"],
+                               library_gbs=r["bytes"] / (r["ms"] * 1e-3) / 1e9,
+                               library_frac=r["bytes"] / (r["ms"] * 1e-3) / HBM_PEAK))
+    levels.sort(key=lambda d: -d["level"])
+    dom_all = [r for r in per_kernel if r["kernel"] == dom][0]
+    roofline = dict(bound="hbm", kernel=dom, level=L, achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=achieved / HBM_PEAK, traffic=traffic, bytes_per_dof=bpd, dofs_per_launch=dofs,
+                    bytes_per_launch=bpd * dofs, avg_launch_us=1e6 * avg_s, launches=rep["launches"],
+                    per_level=levels,
+                    all_levels_library_count=dict(
+                        note="every level's launches together, bytes as the library counts them (section "
+                             "containers, e.g. 17-24-bit codes in 32-bit words)",
+                        gbs=dom_all["bytes"] / (dom_all["ms"] * 1e-3) / 1e9,
+                        frac=dom_all["bytes"] / (dom_all["ms"] * 1e-3) / HBM_PEAK))
     # All fused level kernels of one solve together (from the per-kernel
     # timing pass): algorithmic bytes and, from the stored counter readings,
     # measured HBM bytes over their summed launch time.
@@ -345,12 +536,11 @@ def main():
                        measured_gbs=None if sweep_hbm is None else sweep_hbm / sweep_s / 1e9,
                        measured_frac=None if sweep_hbm is None else sweep_hbm / sweep_s / HBM_PEAK)
     # the same kernel against its instruction-issue ceiling: counted VALU
-    # instructions per launch over the live average launch time
-    valu = stored_valu(dom)
+    # instructions per finest-level launch over the live average launch time
+    valu = stored_valu(f"{dom}@{L}")
     issue = None
     if valu is not None:
-        avg_s = 1e-3 * rep["ms"] / rep["launches"]
-        issue = dict(kernel=dom, valu_insts_per_launch=valu, peak_insts_per_s=VALU_PEAK,
+        issue = dict(kernel=dom, level=L, valu_insts_per_launch=valu, peak_insts_per_s=VALU_PEAK,
                      frac=valu / VALU_PEAK / avg_s)
 
     plain = None
@@ -414,7 +604,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU baseline: oracle at {(1 << args.cpu_L) + 1}^3")
-        cpu = cpu_baseline(args.cpu_L, args.bits)
+        cpu = cpu_baseline(args.cpu_L, args.bits, max(1, min(args.cpu_procs, os.cpu_count() or 1)))
 
     out = {
         "metric": "DoF/s solved to discretization error; bytes/DoF; HBM GB/s vs peak",

@@ -52,7 +52,10 @@ typedef enum {
   CMG_ERR_OUT_OF_MEMORY = 3, /* device allocation failed                      */
   CMG_ERR_HIP = 4,           /* a HIP runtime call or kernel launch failed    */
   CMG_ERR_NONFINITE = 5,     /* NaN/Inf in an input (f, kappa, codec input)   */
-  CMG_ERR_NOT_CONVERGED = 6  /* residual grew during iterative refinement     */
+  CMG_ERR_NOT_CONVERGED = 6  /* residual grew during iterative refinement:
+                                an IR residual norm above 4 times the
+                                smallest one of its FMG level (the solve
+                                ran to its end; its output is unreliable) */
 } cmg_status;
 
 enum { CMG_POISSON = 0, CMG_DIFFUSION = 1 };          /* cmg_problem.op           */
@@ -65,7 +68,8 @@ enum { CMG_SECTION_U = 0, CMG_SECTION_R = 1, CMG_SECTION_Y = 2, CMG_SECTION_YPRE
 typedef struct {
   int32_t dim;      /* 2 or 3                                                 */
   int32_t L;        /* finest level; N = 2^L + 1 nodes per axis, 2 <= L <= 10 */
-  int32_t coarsest; /* coarsest level; 1 (one interior node)                  */
+  int32_t coarsest; /* coarsest level: 1 (one interior node) or 2 (3^dim
+                       interior nodes, dense L D L^T solve), < L              */
   int32_t op;       /* CMG_POISSON or CMG_DIFFUSION                           */
   int32_t batch;    /* number of right-hand sides solved per call, >= 1      */
 } cmg_problem;
@@ -96,6 +100,14 @@ typedef struct {
   int32_t inc_u;       /* regressive increment of u' (k = p + 1), >= 0        */
   int32_t inc_ry;      /* regressive increment of r, y' (k = m), >= 0         */
   int32_t vcycle_prec; /* CMG_FP32 or CMG_FP64 arithmetic inside the V-cycle   */
+  int32_t keep_correction; /* 1: keep the pre- and post-smoothed corrections of
+                              every level in sections of their own, for
+                              inspection (CMG_SECTION_Y / _YPRE exports; one
+                              more section of the correction's width).  0
+                              (default): the post-smoothed correction is only
+                              added to u' and not stored where the cycle does
+                              not read it again, and those exports fail with
+                              CMG_ERR_UNSUPPORTED.  Results are identical.   */
 } cmg_opts;
 
 /* Optional per-solve statistics (host struct). */
@@ -119,7 +131,8 @@ typedef struct {
 } cmg_mem;
 
 /* Fill *o with the defaults: RB-GS V(2,2), N = 2, nu = 1, compact BFP,
- * B = 64, b = 16 for u', r, y', increments 2 and 1, FP32 V-cycle. */
+ * B = 64, b = 16 for u', r, y', increments 2 and 1, FP32 V-cycle,
+ * keep_correction = 0. */
 cmg_status cmg_default_opts(cmg_opts* o);
 
 /*
@@ -236,7 +249,8 @@ cmg_status cmg_abfp_decode(const void* codes, const int64_t* starts, const int16
  * order; index 0 on each axis is the boundary node (always 0), the node at
  * 2^l is implicit.  `which` is CMG_SECTION_U / _R / _Y, or _YPRE: the
  * correction as the down sweep left it (the up sweep reads it and writes
- * its post-smoothed value to _Y).
+ * its post-smoothed value to _Y).  _Y and _YPRE exist only in contexts set
+ * up with keep_correction = 1 (else CMG_ERR_UNSUPPORTED).
  * ------------------------------------------------------------------------- */
 
 /* Shape of a stored section: values, current width, container bits, bytes of
@@ -267,6 +281,16 @@ cmg_status cmg_ir_residual(cmg_ctx ctx, const double* f);
  * section-wise correction u' += y' (Alg. 1 generalised; Alg. 3). */
 cmg_status cmg_vcycle_correct(cmg_ctx ctx);
 
+/* The up sweep and correction of one level alone (Alg. 1 coarse to fine;
+ * Alg. 3 apply correction), for inspection: with the coarse correction
+ * e_{l-1} = y'_{l-1} + z_{l-1} given by the caller (e_coarse: device, the
+ * padded layout of level - 1, float32 or float64 as the V-cycle type),
+ * z = P e_{l-1}, y = S^nu_post(dec y'_l; g_l - A z) from the current
+ * residual and pre-smoothed correction sections, y'_l = Q(y) (kept in the
+ * _Y section with keep_correction = 1), u'_l = Q(dec u'_l + dec y'_l).
+ * level: coarsest + 1 .. the current FMG level. */
+cmg_status cmg_up_sweep(cmg_ctx ctx, int32_t level, const void* e_coarse);
+
 /* Decode u' at the current FMG level Lp into u (device, (2^Lp + 1)^dim). */
 cmg_status cmg_decode_solution(cmg_ctx ctx, double* u);
 
@@ -277,7 +301,10 @@ cmg_status cmg_memory_stats(cmg_ctx ctx, cmg_mem* out);
  * Kernel timing for benchmarks.  While enabled, every kernel launch the
  * context makes (or only launches of the kernel named `kernel`, if not NULL)
  * is bracketed by two HIP events on the context stream, and its algorithmic
- * bytes (each operand read or written once) are recorded.  Each API call
+ * bytes (each operand read or written once) are recorded.  `kernel` may also
+ * be "name@l" (that kernel's launches on level l only) or "@" (every kernel,
+ * with separate totals per level, named "name@l", for the fused 3-D level
+ * kernels).  Each API call
  * that launches kernels waits for its events before returning and adds the
  * durations to per-kernel totals.  Enabling (or disabling) clears the totals.
  * ------------------------------------------------------------------------- */

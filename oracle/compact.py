@@ -177,7 +177,8 @@ def vcycle_correct(U, g_top, ops, cfg: Config, Lp: int, trace=None):
     its finest section alone, when the cycle restricts by itself).  Returns
     the correction sections ``Y`` (after post-smoothing).  If ``trace`` is a
     dict it receives the intermediate sections (``G``, the pre-smoothed
-    ``Y``) for inspection.
+    ``Y``) and the coarse corrections ``E[l] = y'_l + z_l`` that enter the
+    up sweep of level ``l + 1``, for inspection.
     """
     T = cfg.vcycle_dtype
     lc, B, on = cfg.coarsest, cfg.block, cfg.quantize
@@ -219,8 +220,12 @@ def vcycle_correct(U, g_top, ops, cfg: Config, Lp: int, trace=None):
     U[lc] = Section.quantize(U[lc].value(np.float64) + Y[lc].value(np.float64),
                              B, cfg.w_u(lc, Lp), on)
     E = Y[lc].value(T)                                    # y'_lc + z_lc, z_lc = 0
+    if trace is not None:
+        trace["E"] = {}
     for level in range(lc + 1, Lp + 1):                   # coarse to fine
         lv = ops[level]
+        if trace is not None:
+            trace["E"][level - 1] = E
         z = prolong(E, T)
         rhs = rhs_of(level) - lv.apply(z, T)
         y = smooth(lv, Y[level].value(T), rhs, cfg.nu_post, cfg.smoother, cfg.omega, T)

@@ -232,11 +232,47 @@ def smooth(lv: Level, y: np.ndarray, rhs: np.ndarray, nu: int, smoother: str,
     return y
 
 
+def ldlt_solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Solve ``A x = b`` for symmetric positive definite ``A`` in float64:
+    ``A = L D L^T`` with unit lower-triangular ``L`` and diagonal ``D``
+    (``d_j = a_jj - sum_k l_jk^2 d_k``, ``l_ij = (a_ij - sum_k l_ik l_jk d_k)
+    / d_j``), then ``L z = b``, ``L^T x = D^-1 z``; every sum is taken in
+    increasing index order, one operation at a time."""
+    m = len(b)
+    Lf = [[0.0] * m for _ in range(m)]
+    d = [0.0] * m
+    for j in range(m):
+        s = float(A[j][j])
+        for k in range(j):
+            s = s - (Lf[j][k] * Lf[j][k]) * d[k]
+        d[j] = s
+        for i in range(j + 1, m):
+            t = float(A[i][j])
+            for k in range(j):
+                t = t - (Lf[i][k] * Lf[j][k]) * d[k]
+            Lf[i][j] = t / d[j]
+    z = [0.0] * m
+    for i in range(m):
+        s = float(b[i])
+        for k in range(i):
+            s = s - Lf[i][k] * z[k]
+        z[i] = s
+    x = [0.0] * m
+    for i in range(m - 1, -1, -1):
+        s = z[i] / d[i]
+        for k in range(i + 1, m):
+            s = s - Lf[k][i] * x[k]
+        x[i] = s
+    return np.array(x)
+
+
 def coarse_solve(lv: Level, g: np.ndarray) -> np.ndarray:
     """Exact FP64 solve on the coarsest level (Alg. 3, coarse-grid solve).
 
-    One interior node: ``g / diag``.  Otherwise a dense solve of the interior
-    system assembled column by column from :meth:`Level.apply`.
+    One interior node: ``g / diag``.  Otherwise the interior system is
+    assembled column by column from :meth:`Level.apply` and solved by the
+    ``L D L^T`` factorisation of :func:`ldlt_solve` (the matrix is symmetric
+    positive definite).
     """
     d, n = lv.dim, lv.n
     inner = _inner(d, n)
@@ -253,7 +289,7 @@ def coarse_solve(lv: Level, g: np.ndarray) -> np.ndarray:
         e = np.zeros((n,) * d)
         e[inner] = e_in
         A[:, j] = lv.apply(e, np.float64)[inner].reshape(-1)
-    out[inner] = np.linalg.solve(A, g[inner].reshape(-1)).reshape((n - 1,) * d)
+    out[inner] = ldlt_solve(A, g[inner].reshape(-1)).reshape((n - 1,) * d)
     return out
 
 

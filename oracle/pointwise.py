@@ -218,3 +218,70 @@ def restrict_block(G: Codes, level: int, nu: int, Kc: int, Jc: int, bxc: int, bl
     c = np.where(inside, s, T(0)).astype(np.float64)
     mq, eq = bfp.encode(c, block, w_r)
     return mq, int(eq[0])
+
+
+# ----------------------------------------------------- the up sweep, locally
+def prolong_box(E: np.ndarray, lo, hi, T=np.float32) -> np.ndarray:
+    """``z = P E`` (d-linear interpolation of the coarse array ``E``, padded
+    layout of the next coarser level) on the fine box ``lo .. hi`` (inclusive
+    padded coordinates; the far-boundary node ``n`` is 0).  Terms as in
+    :func:`oracle.grid.prolong`: weight ``T(w)`` times the coarse value, the
+    coarse neighbours in C order of their (z, y, x) offsets."""
+    m = E.shape[0]
+    n = 2 * m
+    ce = np.pad(np.asarray(E, dtype=T), [(0, 1)] * 3)
+    axes = [np.arange(lo[a], hi[a] + 1) for a in range(3)]
+    idx = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1)
+    out = np.zeros(idx.shape[:3], dtype=T)
+    par, base = idx & 1, idx >> 1
+    for pz, py, px in itertools.product((0, 1), repeat=3):
+        sel = (par[..., 0] == pz) & (par[..., 1] == py) & (par[..., 2] == px) & np.all(idx < n, axis=-1)
+        if not sel.any():
+            continue
+        b = base[sel]
+        per_axis = [[(0, 1.0)] if p == 0 else [(0, 0.5), (1, 0.5)] for p in (pz, py, px)]
+        s = None
+        for combo in itertools.product(*per_axis):
+            w = combo[0][1] * combo[1][1] * combo[2][1]
+            t = T(w) * ce[b[:, 0] + combo[0][0], b[:, 1] + combo[1][0], b[:, 2] + combo[2][0]]
+            s = t if s is None else s + t
+        out[sel] = s
+    return out
+
+
+def up_sweep_block(G: Codes, Y: Codes, U: Codes, E: np.ndarray, level: int, nu: int, z: int, y: int, bx: int,
+                   block: int, w_y: int, w_u: int, T=np.float32):
+    """The up sweep and correction of level ``level`` (Alg. 1 coarse to
+    fine; Alg. 3 apply correction) at one block: ``z = P E``,
+    ``y = S^nu(dec y'_pre; dec g - A z)`` (red-black Gauss-Seidel in ``T``),
+    ``y' = Q_{w_y}(y)`` and ``u' = Q_{w_u}(dec u' + dec y')`` in float64.
+    Red-black sweeps carry information one node per half-sweep, so a box of
+    radius ``2 nu + 1`` around the block (its outer shell held fixed) gives
+    the whole-array values at the block.  Returns
+    ``(y' codes, y' exponent, u' codes, u' exponent)``."""
+    n = 1 << level
+    M = 2 * nu + 1
+    x0 = bx * block
+    lo = np.array([z - M, y - M, x0 - M])
+    hi = np.array([z + M, y + M, x0 + block - 1 + M])
+    lo_c, hi_c = np.maximum(lo, 0), np.minimum(hi, n)
+    zb = prolong_box(E, lo_c, hi_c, T)
+    rhs = _box_values(G, level, lo_c, hi_c, T) - _apply_box(zb, level, T)
+    yb = _box_values(Y, level, lo_c, hi_c, T)
+    cz, cy, cx = (lo_c[a] + np.arange(yb.shape[a]) for a in range(3))
+    Zc, Yc, Xc = np.meshgrid(cz, cy, cx, indexing="ij")
+    interior = (Zc >= 1) & (Zc < n) & (Yc >= 1) & (Yc < n) & (Xc >= 1) & (Xc < n)
+    inner = np.zeros(yb.shape, dtype=bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    c = T(1.0 / (2 * 3 * float(4 ** level)))
+    for _ in range(nu):
+        for colour in (0, 1):
+            mask = interior & inner & (((Zc + Yc + Xc) % 2) == colour)
+            r = rhs - _apply_box(yb, level, T)
+            yb[mask] = yb[mask] + c * r[mask]
+    row = yb[z - lo_c[0], y - lo_c[1], x0 - lo_c[2]: x0 - lo_c[2] + block].astype(np.float64)
+    my, ey = bfp.encode(row, block, w_y)
+    dy = bfp.decode(my, ey, block, w_y, dtype=np.float64)
+    flat = (z * n + y) * n + x0 + np.arange(block)
+    mu, eu = bfp.encode(U.at(flat) + dy, block, w_u)
+    return my, int(ey[0]), mu, int(eu[0])

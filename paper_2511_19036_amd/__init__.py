@@ -34,7 +34,8 @@ def options(**kw) -> _lib.cmg_opts:
     Keys: smoother ("rbgs" | "wjacobi"), omega, nu_pre, nu_post, ir_iters,
     final_iters, storage ("compact" | "plain"), bfp_block, bits (sets
     bits_u, bits_r, bits_y), bits_u, bits_r, bits_y, inc_u, inc_ry,
-    vcycle_prec ("fp32" | "fp64").
+    vcycle_prec ("fp32" | "fp64"), keep_correction (bool: keep the "y" and
+    "ypre" sections for export).
     """
     lib = load()
     o = _lib.cmg_opts()
@@ -50,6 +51,8 @@ def options(**kw) -> _lib.cmg_opts:
             v = _STORAGE[v] if isinstance(v, str) else v
         elif k == "vcycle_prec":
             v = _PREC[v] if isinstance(v, str) else v
+        elif k == "keep_correction":
+            v = int(bool(v))
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)
@@ -166,6 +169,17 @@ class Solver:
 
     def vcycle_correct(self):
         self._check(self.lib.cmg_vcycle_correct(self.ctx))
+
+    def up_sweep(self, level, e_coarse):
+        """``cmg_up_sweep``: one level's up sweep and correction from the
+        current sections and a given coarse correction ``e_coarse`` (CUDA
+        tensor of ``(2**(level-1))**dim`` values in the V-cycle type)."""
+        import torch
+        want = torch.float32 if self.opts.vcycle_prec == _lib.FP32 else torch.float64
+        n = 1 << (level - 1)
+        if e_coarse is None or not e_coarse.is_cuda or e_coarse.dtype != want or e_coarse.numel() != n ** self.dim:
+            raise ValueError(f"e_coarse must be a {want} CUDA tensor of {n ** self.dim} values")
+        self._check(self.lib.cmg_up_sweep(self.ctx, level, _lib.ptr(e_coarse.contiguous())))
 
     def decode_solution(self, level):
         import torch

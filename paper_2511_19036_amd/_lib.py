@@ -37,7 +37,8 @@ class cmg_opts(C.Structure):
                 ("nu_post", C.c_int32), ("ir_iters", C.c_int32), ("vcycles", C.c_int32),
                 ("final_iters", C.c_int32), ("storage", C.c_int32), ("bfp_block", C.c_int32),
                 ("bits_u", C.c_int32), ("bits_r", C.c_int32), ("bits_y", C.c_int32),
-                ("inc_u", C.c_int32), ("inc_ry", C.c_int32), ("vcycle_prec", C.c_int32)]
+                ("inc_u", C.c_int32), ("inc_ry", C.c_int32), ("vcycle_prec", C.c_int32),
+                ("keep_correction", C.c_int32)]
 
 
 class cmg_stats(C.Structure):
@@ -83,6 +84,7 @@ SIGNATURES = {
     "cmg_fmg_enter_level": (_ST, [_P, _I32, _P]),
     "cmg_ir_residual": (_ST, [_P, _P]),
     "cmg_vcycle_correct": (_ST, [_P]),
+    "cmg_up_sweep": (_ST, [_P, _I32, _P]),
     "cmg_decode_solution": (_ST, [_P, _P]),
     "cmg_memory_stats": (_ST, [_P, C.POINTER(cmg_mem)]),
     "cmg_timing_enable": (_ST, [_P, _I32, C.c_char_p]),

@@ -21,7 +21,7 @@ template <typename T>
 __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
   constexpr int NW = kCoarseNT / 64;
   __shared__ double pool[kCoarsePoolBytes / 8];
-  __shared__ double cpool[2 * kCoarsestMax];
+  __shared__ double cpool[3 * kCoarsestMax];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   T* const base = reinterpret_cast<T*>(pool);
   // the five arrays of level l: g, y, z, r, e (in that order)
@@ -189,13 +189,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
     decode64(B.G, B.g.size, t64);
     each(B.g.size, [&](int64_t t) { s64[t] = 0.0; });
     sync();
-    if (tid == 0) {
-      const Geom& g = B.g;
-      const int64_t c = flat(g, 1, 1, g.dim == 3 ? 1 : 0);
-      const double diag = a.kap64 == nullptr ? static_cast<double>(2 * g.dim) * B.ih2
-                                             : diag_A(a.kap64, g, 1, 1, g.dim == 3 ? 1 : 0, B.ih2);
-      s64[c] = t64[c] / diag;
-    }
+    if (tid == 0) coarse_solve_dense(t64, a.kap64, B.g, B.ih2, s64, cpool + 2 * kCoarsestMax);
     sync();
     encode(s64, B.g.size, B.Yp, arr(a.lc, 4));  // y' = Q(A^-1 g); e = dec y'
     sync();

@@ -309,4 +309,75 @@ __device__ __forceinline__ T smooth_coeff(const T* kap, const Geom& g, int i, in
   return kap == nullptr ? cpois : omega / diag_A(kap, g, i, j, k, inv_h2);
 }
 
+// IR residual monitor.  Kernels that form an IR residual add the squares of
+// its entries to one of kMonSlots partial sums (slot = workgroup id mod
+// kMonSlots, kMonStride doubles apart, so that the atomics of different
+// workgroups spread over cache lines); k_monitor_check sums the slots in
+// order.  After the slots: [0] the smallest sum of squares seen on this FMG
+// level (-1: none yet), [1] the last sum of squares.
+constexpr int kMonSlots = 64, kMonStride = 16;
+constexpr int kMonMin = kMonSlots * kMonStride, kMonLast = kMonMin + 1, kMonDoubles = kMonMin + 16;
+__device__ __forceinline__ void monitor_add(double* mon, double a) {
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(mon + (blockIdx.x % kMonSlots) * kMonStride, a);
+}
+
+// Exact float64 solve A y = g on a coarsest level with at most 27 interior
+// nodes (one thread).  One interior node: y = g / diag.  Otherwise the
+// interior matrix is assembled column by column by applying A to unit
+// vectors (the same arithmetic as every other use of A), factorised as
+// A = L D L^T (unit lower-triangular L, diagonal D; A is symmetric positive
+// definite), and solved by forward substitution, division by D and back
+// substitution, every sum taken in index order.  `e` is scratch for
+// g.size values; g, y and e use the padded level layout.
+constexpr int kDenseMax = 27;
+__device__ inline void coarse_solve_dense(const double* g_in, const double* kap, const Geom& g, double ih2,
+                                          double* y, double* e) {
+  const int kz = g.dim == 3 ? 1 : 0;
+  for (int64_t t = 0; t < g.size; ++t) y[t] = 0.0;
+  if (g.n == 2) {
+    const int64_t c = flat(g, 1, 1, kz);
+    const double diag = kap == nullptr ? static_cast<double>(2 * g.dim) * ih2 : diag_A(kap, g, 1, 1, kz, ih2);
+    y[c] = g_in[c] / diag;
+    return;
+  }
+  const int w = g.n - 1, m = g.dim == 3 ? w * w * w : w * w;
+  int64_t node[kDenseMax];
+  int ii[kDenseMax], jj[kDenseMax], kk[kDenseMax];
+  for (int t = 0; t < m; ++t) {  // interior nodes in C order, x fastest
+    ii[t] = 1 + t % w;
+    jj[t] = 1 + (t / w) % w;
+    kk[t] = g.dim == 3 ? 1 + t / (w * w) : 0;
+    node[t] = flat(g, ii[t], jj[t], kk[t]);
+  }
+  double A[kDenseMax * kDenseMax], Lf[kDenseMax * kDenseMax], d[kDenseMax], z[kDenseMax], x[kDenseMax];
+  for (int64_t t = 0; t < g.size; ++t) e[t] = 0.0;
+  for (int c = 0; c < m; ++c) {
+    e[node[c]] = 1.0;
+    for (int r = 0; r < m; ++r) A[r * m + c] = apply_A(e, kap, g, ii[r], jj[r], kk[r], ih2);
+    e[node[c]] = 0.0;
+  }
+  for (int j = 0; j < m; ++j) {
+    double s = A[j * m + j];
+    for (int k = 0; k < j; ++k) s = s - (Lf[j * m + k] * Lf[j * m + k]) * d[k];
+    d[j] = s;
+    for (int i = j + 1; i < m; ++i) {
+      double t = A[i * m + j];
+      for (int k = 0; k < j; ++k) t = t - (Lf[i * m + k] * Lf[j * m + k]) * d[k];
+      Lf[i * m + j] = t / d[j];
+    }
+  }
+  for (int i = 0; i < m; ++i) {
+    double s = g_in[node[i]];
+    for (int k = 0; k < i; ++k) s = s - Lf[i * m + k] * z[k];
+    z[i] = s;
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    double s = z[i] / d[i];
+    for (int k = i + 1; k < m; ++k) s = s - Lf[k * m + i] * x[k];
+    x[i] = s;
+  }
+  for (int i = 0; i < m; ++i) y[node[i]] = x[i];
+}
+
 }  // namespace cmg

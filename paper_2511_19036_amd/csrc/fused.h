@@ -23,7 +23,8 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
                           float ih2, hipStream_t st);
 
 // g = Q(f - A(dec u' + P uc)) in float64; f sampled from the level-Lfull grid.
-// sumsq (nullable) accumulates sum t^2 (unordered atomics; statistics only).
+// sumsq (nullable): the IR residual monitor's slots (device.h), which receive
+// sum t^2 (unordered atomics, one per wave).
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
                        double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st);
 

@@ -603,6 +603,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       }
     }
   };
+  // Yp is stored only when the caller keeps it (no buffers otherwise).
+  const bool keep = Yp.codes != nullptr;
   auto finish_store = [&](int po, const Fin& F) {
     if (po < Z0 || po >= Z0 + TZ) return;
     const PlanePtr yq = plane_at<CB, LB>(Yp, po, level), uq = plane_at<CB, LB>(U, po, level);
@@ -611,7 +613,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const int rr = out_row<NW>(wv, t);
       if (rr >= TY) continue;
       const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
-      store_row(yq.c, xyr, lane, F.my[t], cbits_of<CB>(Yp));
+      if (keep) store_row(yq.c, xyr, lane, F.my[t], cbits_of<CB>(Yp));
       store_row(uq.c, xyr, lane, F.mu[t], cbits_of<CB>(U));
       if (eout != nullptr) eout[(static_cast<uint64_t>(po) << (2 * level)) + xyr + lane] = F.ev[t];
     }
@@ -621,7 +623,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
         const int rr = out_row<NW>(wv, t);
         if (rr >= TY) continue;
         const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
-        yq.e[xyl >> LB] = static_cast<int16_t>(F.ey[t]);
+        if (keep) yq.e[xyl >> LB] = static_cast<int16_t>(F.ey[t]);
         uq.e[xyl >> LB] = static_cast<int16_t>(F.eu[t]);
       }
     }
@@ -1067,6 +1069,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
     }
   };
 
+  double acc = 0.0;  // sum of squares of this thread's residuals (monitor)
   auto step = [&](auto jpc, const int j) {
     constexpr int JP = decltype(jpc)::value;
     opaque(lane);
@@ -1148,13 +1151,8 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         for (int t = 0; t < RPT; ++t) bad = bad || !isfinite(tv[t]);
         if (bad) atomicOr(nonfinite, 1);
       }
-      if (sumsq != nullptr) {
-        double a2 = 0.0;
 #pragma unroll
-        for (int t = 0; t < RPT; ++t) a2 += tv[t] * tv[t];
-        for (int off = 32; off > 0; off >>= 1) a2 += __shfl_xor(a2, off, 64);
-        if (lane == 0) atomicAdd(sumsq, a2);
-      }
+      for (int t = 0; t < RPT; ++t) acc = acc + tv[t] * tv[t];
     }
     fetch_f(j);
   };
@@ -1172,6 +1170,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
     step(std::integral_constant<int, 1>(), j);
     step(std::integral_constant<int, 0>(), j + 1);
   }
+  if (sumsq != nullptr) monitor_add(sumsq, acc);  // the residual monitor's slots
 }
 
 // ============================================================ final decode
@@ -1328,9 +1327,9 @@ static double sec_b(const SecRef& s) {
   return nb * s.B * s.cbits / 8.0 + 2.0 * nb;
 }
 
-#define CMG_FLAUNCH(name, nbytes, kernel, grid, block, stream, ...)                        \
-  do {                                                                                    \
-    if (g_timing != nullptr) g_timing->begin((name), static_cast<double>(nbytes), stream); \
+#define CMG_FLAUNCH(name, nbytes, kernel, grid, block, stream, ...)                                 \
+  do {                                                                                             \
+    if (g_timing != nullptr) g_timing->begin((name), static_cast<double>(nbytes), stream, g.level); \
     hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);                      \
     if (g_timing != nullptr) g_timing->end(stream);                                       \
   } while (0)
@@ -1405,7 +1404,8 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
     return false;
   const int tiles = (g.n / kTX) * (g.n / kUpTY);
   const dim3 block(kUpNT);
-  const double bytes = sec_b(G) + sec_b(Y) + sec_b(Yp) + 2.0 * sec_b(U) + 4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
+  const double bytes = sec_b(G) + sec_b(Y) + (Yp.codes != nullptr ? sec_b(Yp) : 0.0) + 2.0 * sec_b(U) +
+                       4.0 * gc.size + (eout ? 4.0 * g.size : 0.0);
   const PSec pg = psec(G, g), py = psec(Y, g), pp = psec(Yp, g), pu = psec(U, g);
   const bool hi = U.cbits == 12 || U.cbits == 64;  // the codes of u' may straddle two words
   const int cb = common_cb({&G, &Y, &Yp, &U});

@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kThreads) k_dec_minus_A(SecRef gs, const T* __
 template <bool DIFF>
 __global__ void __launch_bounds__(kThreads) k_res_encode(const double* __restrict__ f, const double* __restrict__ u,
                                                          const double* __restrict__ kap, Geom g, double inv_h2,
-                                                         SecRef s, int* nonfinite) {
+                                                         SecRef s, int* nonfinite, double* mon) {
   const int lane = threadIdx.x & 63;
   const int64_t base = (static_cast<int64_t>(blockIdx.x) * kThreads + (threadIdx.x & ~63));
   const int64_t limit = limit_of(s);
@@ -268,6 +268,7 @@ __global__ void __launch_bounds__(kThreads) k_res_encode(const double* __restric
     }
   }
   if (nonfinite != nullptr && !isfinite(v)) atomicOr(nonfinite, 1);
+  if (mon != nullptr) monitor_add(mon, v * v);
   int e;
   const int64_t m = quantise_lane(v, s.B, s.w, &e);
   store_codes_wave(s, base, lane, m, limit);
@@ -578,14 +579,13 @@ __global__ void __launch_bounds__(kThreads) k_to_full(const double* __restrict__
   full[idx] = (i < g.n && j < g.n && k < g.n) ? pad[flat(g, i, j, k)] : 0.0;
 }
 
-// Exact solve on a level with a single interior node: y = g / diag (float64).
+// Exact float64 solve on the coarsest level (one interior node, or up to 27
+// by a dense L D L^T factorisation), one thread.
 __global__ void k_coarse_single(const double* __restrict__ gin, const double* __restrict__ kap, Geom g,
                                 double inv_h2, double* __restrict__ y) {
+  __shared__ double e[64];
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int64_t t = 0; t < g.size; ++t) y[t] = 0.0;
-  const int64_t c = flat(g, 1, 1, g.dim == 3 ? 1 : 0);
-  const double diag = kap == nullptr ? static_cast<double>(2 * g.dim) * inv_h2 : diag_A(kap, g, 1, 1, g.dim == 3 ? 1 : 0, inv_h2);
-  y[c] = gin[c] / diag;
+  coarse_solve_dense(gin, kap, g, inv_h2, y, e);
 }
 
 // ================================================================ kappa
@@ -657,20 +657,32 @@ __global__ void __launch_bounds__(kThreads) k_grad_kappa(const double* __restric
 
 // out[0] += sum x^2 (for residual-norm statistics; summation order is
 // unspecified).
-__global__ void __launch_bounds__(kThreads) k_sumsq(const double* __restrict__ x, int64_t n, double* out) {
-  __shared__ double part[kThreads / 64];
+__global__ void __launch_bounds__(kThreads) k_sumsq(const double* __restrict__ x, int64_t n, double* mon) {
   double a = 0.0;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; idx < n;
        idx += static_cast<int64_t>(gridDim.x) * kThreads)
     a += x[idx] * x[idx];
-  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = a;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) t += part[w];
-    atomicAdd(out, t);
-  }
+  monitor_add(mon, a);
+}
+
+// Clears the monitor's partial sums (and, on entering an FMG level, its
+// smallest sum of squares).
+__global__ void k_monitor_reset(double* mon, int entry) {
+  for (int t = threadIdx.x; t < kMonSlots; t += blockDim.x) mon[t * kMonStride] = 0.0;
+  if (entry && threadIdx.x == 0) mon[kMonMin] = -1.0;
+}
+
+// Sum of squares of this IR residual from the slots; a residual norm above
+// `growth` times the smallest one of the FMG level so far marks the solve
+// as not converging (flags[2] = level).
+__global__ void k_monitor_check(double* mon, int* flags, int level, double growth) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int t = 0; t < kMonSlots; ++t) s += mon[t * kMonStride];
+  const double lo = mon[kMonMin];
+  if (lo >= 0.0 && s > growth * growth * lo) atomicMax(flags + 2, level);
+  if (lo < 0.0 || s < lo) mon[kMonMin] = s;
+  mon[kMonLast] = s;
 }
 
 // ============================================================== launchers
@@ -753,13 +765,13 @@ void launch_dec_minus_A(const SecRef& gs, const T* u, const T* kap, const Geom& 
                 inv_h2, out);
 }
 void launch_res_encode(const double* f, const double* u, const double* kap, const Geom& g, double inv_h2,
-                       const SecRef& s, int* nonfinite, hipStream_t st) {
+                       const SecRef& s, int* nonfinite, double* mon, hipStream_t st) {
   const int64_t limit = ((s.n + s.B - 1) / s.B) * s.B;
   const double b = (2.0 + (kap ? 1.0 : 0.0)) * g.size * 8.0 + sec_bytes(s);
   if (kap != nullptr)
-    CMG_TLAUNCH("k_res_encode", b, k_res_encode<true>, limit, st, f, u, kap, g, inv_h2, s, nonfinite);
+    CMG_TLAUNCH("k_res_encode", b, k_res_encode<true>, limit, st, f, u, kap, g, inv_h2, s, nonfinite, mon);
   else
-    CMG_TLAUNCH("k_res_encode", b, k_res_encode<false>, limit, st, f, u, kap, g, inv_h2, s, nonfinite);
+    CMG_TLAUNCH("k_res_encode", b, k_res_encode<false>, limit, st, f, u, kap, g, inv_h2, s, nonfinite, mon);
 }
 template <typename T>
 void launch_prolong(const T* coarse, const Geom& gf, const Geom& gc, T* fine, hipStream_t st) {
@@ -888,13 +900,19 @@ void launch_grad_kappa(const double* u, const double* lam, const Geom& gcell, in
   CMG_TLAUNCH("k_grad_kappa", 16.0 * nodes + 8.0 * gcell.size * (accumulate ? 2 : 1), k_grad_kappa, gcell.size, st,
               u, lam, gcell, accumulate, grad);
 }
-void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st) {
+void launch_sumsq(const double* x, int64_t n, double* mon, hipStream_t st) {
   int64_t blocks = (n + kThreads - 1) / kThreads;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   if (g_timing != nullptr) g_timing->begin("k_sumsq", 8.0 * n, st);
-  hipLaunchKernelGGL(k_sumsq, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, st, x, n, out);
+  hipLaunchKernelGGL(k_sumsq, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, st, x, n, mon);
   if (g_timing != nullptr) g_timing->end(st);
+}
+void launch_monitor_reset(double* mon, bool entry, hipStream_t st) {
+  hipLaunchKernelGGL(k_monitor_reset, dim3(1), dim3(64), 0, st, mon, entry ? 1 : 0);
+}
+void launch_monitor_check(double* mon, int* flags, int level, double growth, hipStream_t st) {
+  hipLaunchKernelGGL(k_monitor_check, dim3(1), dim3(64), 0, st, mon, flags, level, growth);
 }
 
 #define CMG_INST_T(T)                                                                                   \

@@ -29,7 +29,7 @@ void launch_rhs_minus_A(const T* rhs, const T* u, const T* kap, const Geom& g, T
 // iterative refinement and its encode in one pass (flags non-finite values
 // in *nonfinite like launch_encode).
 void launch_res_encode(const double* f, const double* u, const double* kap, const Geom& g, double inv_h2,
-                       const SecRef& s, int* nonfinite, hipStream_t st);
+                       const SecRef& s, int* nonfinite, double* mon, hipStream_t st);
 // out = dec(gs) - A u (interior; 0 on the boundary): a decode of the
 // right-hand side section and launch_rhs_minus_A in one pass.
 template <typename T>
@@ -72,6 +72,9 @@ void launch_check_positive(const double* x, int64_t n, int* flags, hipStream_t s
 void launch_check_finite(const double* x, int64_t n, int* flags, hipStream_t st);
 void launch_grad_kappa(const double* u, const double* lam, const Geom& gcell, int accumulate, double* grad,
                        hipStream_t st);
-void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t st);
+// Sum of squares of x into the IR residual monitor's slots (device.h).
+void launch_sumsq(const double* x, int64_t n, double* mon, hipStream_t st);
+void launch_monitor_reset(double* mon, bool entry, hipStream_t st);
+void launch_monitor_check(double* mon, int* flags, int level, double growth, hipStream_t st);
 
 }  // namespace cmg

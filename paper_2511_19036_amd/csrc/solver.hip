@@ -67,7 +67,11 @@ struct Section {
 struct LevelData {
   Geom g{};
   Section U, G, Y;                    // compact sections u', g = r - s, pre-smoothed y'
-  Section Yp;                         // post-smoothed y' (the correction added to u')
+  // Post-smoothed y' (the correction added to u').  A section of its own only
+  // with keep_correction; otherwise the buffers of Y where the up sweep runs
+  // one kernel per operation (Y has been read before y' is rounded), and no
+  // buffers at all under the fused up sweep, which never stores it.
+  Section Yp;
   void *gf = nullptr, *yf = nullptr;  // V-cycle arrays in the arithmetic type T
   void *zf = nullptr, *rf = nullptr, *ef = nullptr;
   double* uh = nullptr;   // decoded solution (compact) / solution (plain)
@@ -90,8 +94,9 @@ struct cmg_ctx_s {
   std::vector<void*> allocs;
   int64_t mem[kNumCat] = {};
   int Lp = -1;
-  int* flags = nullptr;   // [0] non-positive kappa, [1] non-finite value
-  double* red = nullptr;  // reduction scratch
+  int* flags = nullptr;   // [0] non-positive kappa, [1] non-finite value, [2] FMG level that diverged
+  double* mon = nullptr;  // IR residual monitor (device.h: slots, smallest and last sum of squares)
+  bool mon_fresh = true;  // the next IR residual is the first one on its FMG level
   bool dead = false;
   bool timing_on = false;
   KernelTiming timing;
@@ -147,7 +152,8 @@ void validate(const cmg_problem* p, const cmg_opts* o) {
   const int maxL = p->dim == 3 ? 10 : 14;
   if (p->L < 2 || p->L > maxL) fail(CMG_ERR_INVALID_ARG, "L out of range");
   if (p->coarsest < 1 || p->coarsest >= p->L) fail(CMG_ERR_INVALID_ARG, "need 1 <= coarsest < L");
-  if (p->coarsest != 1) fail(CMG_ERR_UNSUPPORTED, "only coarsest = 1 (one interior node) is implemented");
+  if (p->coarsest > 2)
+    fail(CMG_ERR_UNSUPPORTED, "coarsest levels 1 and 2 (a dense solve of at most 27 interior nodes) are implemented");
   if (p->op != CMG_POISSON && p->op != CMG_DIFFUSION) fail(CMG_ERR_INVALID_ARG, "unknown operator");
   if (p->batch < 1) fail(CMG_ERR_INVALID_ARG, "batch must be >= 1");
   if (o->smoother != CMG_WJACOBI && o->smoother != CMG_RBGS) fail(CMG_ERR_INVALID_ARG, "unknown smoother");
@@ -169,6 +175,7 @@ void validate(const cmg_problem* p, const cmg_opts* o) {
     if (o->inc_u < 0 || o->inc_ry < 0 || o->inc_u > 8 || o->inc_ry > 8)
       fail(CMG_ERR_INVALID_ARG, "increments must lie in [0, 8]");
   }
+  if (o->keep_correction != 0 && o->keep_correction != 1) fail(CMG_ERR_INVALID_ARG, "keep_correction must be 0 or 1");
 }
 
 // ------------------------------------------------------------ setup
@@ -198,7 +205,12 @@ void setup_levels(cmg_ctx c, const double* kappa) {
       alloc_section(c, D.U, D.g, c->wu(l, L));
       alloc_section(c, D.G, D.g, c->wr(l, L));
       alloc_section(c, D.Y, D.g, c->wy(l, L));
-      alloc_section(c, D.Yp, D.g, c->wy(l, L));
+      if (c->o.keep_correction) {
+        alloc_section(c, D.Yp, D.g, c->wy(l, L));
+      } else {
+        D.Yp = D.Y;
+        if (c->smooth_fused(l)) D.Yp.codes = D.Yp.exps = nullptr;
+      }
       // per-operation scratch only where a per-operation kernel runs
       const bool v1s = !c->smooth_fused(l), v1rr = !c->rr_fused(l);
       const bool target = l < L && !c->rr_fused(l + 1);  // restriction target of level l + 1
@@ -224,7 +236,7 @@ void setup_levels(cmg_ctx c, const double* kappa) {
     if (l == lc) D.s64 = static_cast<double*>(c->alloc(n * 8, kCoarse64));
   }
   c->flags = static_cast<int*>(c->alloc(64, kOther));
-  c->red = static_cast<double*>(c->alloc(64, kOther));
+  c->mon = static_cast<double*>(c->alloc(kMonDoubles * 8, kOther));
   HIPCK(hipMemsetAsync(c->flags, 0, 64, c->st));
   if (c->p.op == CMG_DIFFUSION) {
     for (int l = lc; l <= L; ++l) {
@@ -355,6 +367,40 @@ void smooth_from_section(cmg_ctx c, int l, const SecRef& ys, T* y, const T* rhs,
   smooth<T>(c, l, y, rhs, scratch, nu);
 }
 
+// Up sweep and correction of level l (Alg. 1, coarse to fine; Alg. 3 apply
+// correction): z = P e_{l-1} (e_{l-1} in the ef array of level l - 1),
+// y = S^nu2(y'_l; g_l - A z), y'_l = Q(y), u'_l = Q(dec u'_l + dec y'_l) and,
+// below the FMG level, e_l = dec y'_l + z.
+template <typename T>
+void up_level(cmg_ctx c, int l, int Lp) {
+  hipStream_t st = c->st;
+  int* nf = c->flags + 1;
+  LevelData& F = c->lv[l];
+  LevelData& C = c->lv[l - 1];
+  const double ih2 = inv_h2(l);
+  F.Y.w = c->wy(l, Lp);
+  F.Yp.w = c->wy(l, Lp);
+  F.U.w = c->wu(l, Lp);
+  if (std::is_same<T, float>::value && c->smooth_fused(l)) {
+    const float cp = static_cast<float>(1.0 / (2.0 * c->p.dim * ih2));
+    fused_up_smooth(static_cast<const float*>(C.ef), F.G.ref(), F.Y.ref(), F.Yp.ref(), F.U.ref(),
+                    l < Lp ? static_cast<float*>(F.ef) : nullptr, F.g, C.g, c->o.nu_post, cp,
+                    static_cast<float>(ih2), st);
+    KCK();
+    return;
+  }
+  T* yf = static_cast<T*>(F.yf);
+  T* zf = static_cast<T*>(F.zf);
+  T* rf = static_cast<T*>(F.rf);
+  launch_prolong<T>(static_cast<T*>(C.ef), F.g, C.g, zf, st);
+  launch_dec_minus_A<T>(F.G.ref(), zf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);  // dec g - A z
+  smooth_from_section<T>(c, l, F.Y.ref(), yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
+  // y' = Q(y); u' = Q(dec u' + dec y'); below the top level e_l = dec y' + z
+  const SecRef u = F.U.ref();
+  launch_encode_dec<T>(yf, F.g.size, F.Yp.ref(), nf, l < Lp ? static_cast<T*>(F.ef) : nullptr, zf, &u, st);
+  KCK();
+}
+
 // One compact V-cycle from zero on G[Lp], then u' += y' (Alg. 1, Alg. 3).
 // Levels with rows of >= 64 nodes run the fused 3-D kernels; the others (and
 // every 2-D, Jacobi or diffusion level) run one kernel per operation.
@@ -455,32 +501,7 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     launch_decode<T>(B.Yp.ref(), B.g.size, static_cast<T*>(B.ef), st);
     KCK();
   }
-  for (int l = Lc + 1; l <= Lp; ++l) {  // coarse to fine
-    LevelData& F = c->lv[l];
-    LevelData& C = c->lv[l - 1];
-    const double ih2 = inv_h2(l);
-    F.Y.w = c->wy(l, Lp);
-    F.Yp.w = c->wy(l, Lp);
-    F.U.w = c->wu(l, Lp);
-    if (f32 && c->smooth_fused(l)) {
-      const float cp = static_cast<float>(1.0 / (2.0 * c->p.dim * ih2));
-      fused_up_smooth(static_cast<const float*>(C.ef), F.G.ref(), F.Y.ref(), F.Yp.ref(), F.U.ref(),
-                      l < Lp ? static_cast<float*>(F.ef) : nullptr, F.g, C.g, c->o.nu_post, cp,
-                      static_cast<float>(ih2), st);
-      KCK();
-      continue;
-    }
-    T* yf = static_cast<T*>(F.yf);
-    T* zf = static_cast<T*>(F.zf);
-    T* rf = static_cast<T*>(F.rf);
-    launch_prolong<T>(static_cast<T*>(C.ef), F.g, C.g, zf, st);
-    launch_dec_minus_A<T>(F.G.ref(), zf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);  // dec g - A z
-    smooth_from_section<T>(c, l, F.Y.ref(), yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
-    // y' = Q(y); u' = Q(dec u' + dec y'); below the top level e_l = dec y' + z
-    const SecRef u = F.U.ref();
-    launch_encode_dec<T>(yf, F.g.size, F.Yp.ref(), nf, l < Lp ? static_cast<T*>(F.ef) : nullptr, zf, &u, st);
-    KCK();
-  }
+  for (int l = Lc + 1; l <= Lp; ++l) up_level<T>(c, l, Lp);  // coarse to fine
 }
 
 // Decoded solution u_l = dec u'_l + P u_{l-1} for levels lc .. top (float64).
@@ -521,37 +542,40 @@ void residual_chain(cmg_ctx c, int Lp, int top) {
 
 // IR residual (Alg. 2) into G[Lp] (and, for a cycle without pre-smoothing,
 // into every coarser G).  f is the caller's finest node array; the
-// per-operation path uses the injected copy in f64[Lp].
-void ir_residual(cmg_ctx c, int Lp, const double* f, cmg_stats* st) {
+// per-operation path uses the injected copy in f64[Lp].  Every residual also
+// feeds the divergence monitor: its sum of squares is compared with the
+// smallest one of the same FMG level (k_monitor_check).
+constexpr double kDivergeGrowth = 4.0;  // residual norm growth that counts as divergence
+
+void ir_residual(cmg_ctx c, int Lp, const double* f, cmg_stats* st, bool watch = true) {
   LevelData& F = c->lv[Lp];
   F.G.w = c->wr(Lp, Lp);
   const bool rec = st != nullptr && st->record && st->count < 256;
+  launch_monitor_reset(c->mon, c->mon_fresh, c->st);
+  c->mon_fresh = false;
   if (c->res_fused(Lp)) {
     decode_chain(c, Lp - 1);
-    if (rec) HIPCK(hipMemsetAsync(c->red, 0, 8, c->st));
     fused_ir_residual(F.U.ref(), c->lv[Lp - 1].uh, f, c->p.L, F.g, c->lv[Lp - 1].g, inv_h2(Lp), F.G.ref(),
-                      c->flags + 1, rec ? c->red : nullptr, c->st);
+                      c->flags + 1, c->mon, c->st);
     KCK();
   } else {
     decode_chain(c, Lp);
-    if (!rec && !c->chain()) {  // residual and encode in one pass
-      launch_res_encode(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.G.ref(), c->flags + 1, c->st);
+    if (!c->chain()) {  // residual and encode in one pass
+      launch_res_encode(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.G.ref(), c->flags + 1, c->mon, c->st);
       KCK();
-    } else {  // the recorded norm and the restriction chain need the residual array
+    } else {  // the restriction chain needs the residual array
       launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, Lp), F.g, inv_h2(Lp), F.t64, c->st);
       launch_encode<double>(F.t64, F.g.size, F.G.ref(), c->flags + 1, c->st);
+      launch_sumsq(F.t64, F.g.size, c->mon, c->st);
       KCK();
-      if (c->chain()) residual_chain(c, Lp, Lp);
-    }
-    if (rec) {
-      HIPCK(hipMemsetAsync(c->red, 0, 8, c->st));
-      launch_sumsq(F.t64, F.g.size, c->red, c->st);
-      KCK();
+      residual_chain(c, Lp, Lp);
     }
   }
+  if (watch) launch_monitor_check(c->mon, c->flags, Lp, kDivergeGrowth, c->st);
+  KCK();
   if (rec) {
     double h = 0.0;
-    HIPCK(hipMemcpyAsync(&h, c->red, 8, hipMemcpyDeviceToHost, c->st));
+    HIPCK(hipMemcpyAsync(&h, c->mon + kMonLast, 8, hipMemcpyDeviceToHost, c->st));
     HIPCK(hipStreamSynchronize(c->st));
     st->residual_norm[st->count++] = std::sqrt(h);
   }
@@ -579,6 +603,7 @@ void enter_level(cmg_ctx c, int level, const double* f) {
     KCK();
   }
   c->Lp = level;
+  c->mon_fresh = true;
 }
 
 template <typename T>
@@ -647,12 +672,13 @@ void plain_fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
     for (int it = 0; it < iters; ++it) {
       launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, level), F.g, inv_h2(level), F.t64, s);
       launch_check_finite(F.t64, F.g.size, c->flags, s);
+      launch_monitor_reset(c->mon, it == 0, s);
+      launch_sumsq(F.t64, F.g.size, c->mon, s);
+      launch_monitor_check(c->mon, c->flags, level, kDivergeGrowth, s);
       KCK();
       if (st != nullptr && st->record && st->count < 256) {
-        HIPCK(hipMemsetAsync(c->red, 0, 8, s));
-        launch_sumsq(F.t64, F.g.size, c->red, s);
         double h = 0.0;
-        HIPCK(hipMemcpyAsync(&h, c->red, 8, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(&h, c->mon + kMonLast, 8, hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
         st->residual_norm[st->count++] = std::sqrt(h);
       }
@@ -679,13 +705,15 @@ void fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
 }
 
 void check_flags(cmg_ctx c) {
-  int h[2] = {0, 0};
+  int h[3] = {0, 0, 0};
   HIPCK(hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->st));
   HIPCK(hipStreamSynchronize(c->st));
-  if (h[1]) {
-    HIPCK(hipMemsetAsync(c->flags, 0, 8, c->st));
-    fail(CMG_ERR_NONFINITE, "non-finite value met during the solve (NaN/Inf in the input?)");
-  }
+  if (h[1] || h[2]) HIPCK(hipMemsetAsync(c->flags, 0, sizeof(h), c->st));
+  if (h[1]) fail(CMG_ERR_NONFINITE, "non-finite value met during the solve (NaN/Inf in the input?)");
+  if (h[2])
+    fail(CMG_ERR_NOT_CONVERGED, "the IR residual grew to more than " + std::to_string(kDivergeGrowth) +
+                                    " times its smallest norm on FMG level " + std::to_string(h[2]) +
+                                    ": the iteration diverges (smoother, widths or coefficients)");
 }
 
 // Installs the context's timing sink for the duration of one API call and
@@ -733,6 +761,8 @@ Section& section_of(cmg_ctx c, int which, int level) {
   LevelData& D = c->lv[level];
   if (which == CMG_SECTION_U) return D.U;
   if (which == CMG_SECTION_R) return D.G;
+  if ((which == CMG_SECTION_Y || which == CMG_SECTION_YPRE) && !c->o.keep_correction)
+    fail(CMG_ERR_UNSUPPORTED, "the correction sections are kept only in contexts set up with keep_correction = 1");
   if (which == CMG_SECTION_Y) return D.Yp;
   if (which == CMG_SECTION_YPRE) return D.Y;
   fail(CMG_ERR_INVALID_ARG, "unknown section kind");
@@ -1036,7 +1066,7 @@ cmg_status cmg_ir_residual(cmg_ctx c, const double* f) {
     need(c->Lp > c->lc(), "enter an FMG level above the coarsest first");
     if (c->lv[c->Lp].f64 != nullptr) launch_inject(f, c->p.L, c->lv[c->Lp].g, c->lv[c->Lp].f64, c->st);
     KCK();
-    ir_residual(c, c->Lp, f, nullptr);
+    ir_residual(c, c->Lp, f, nullptr, false);  // stepwise: not watched for divergence
   });
 }
 
@@ -1046,6 +1076,21 @@ cmg_status cmg_vcycle_correct(cmg_ctx c) {
     need(c->Lp > c->lc(), "enter an FMG level above the coarsest first");
     if (c->o.vcycle_prec == CMG_FP32) vcycle_correct<float>(c, c->Lp);
     else vcycle_correct<double>(c, c->Lp);
+  });
+}
+
+cmg_status cmg_up_sweep(cmg_ctx c, int32_t level, const void* e_coarse) {
+  if (c == nullptr) return CMG_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    need(e_coarse != nullptr, "e_coarse must not be NULL");
+    need(c->Lp > c->lc(), "enter an FMG level above the coarsest first");
+    need(level > c->lc() && level <= c->Lp, "level must lie in coarsest + 1 .. the current FMG level");
+    LevelData& C = c->lv[level - 1];
+    const size_t tsz = c->o.vcycle_prec == CMG_FP32 ? 4 : 8;
+    need(C.ef != nullptr, "no coarse correction array on that level");
+    HIPCK(hipMemcpyAsync(C.ef, e_coarse, static_cast<size_t>(C.g.size) * tsz, hipMemcpyDeviceToDevice, c->st));
+    if (c->o.vcycle_prec == CMG_FP32) up_level<float>(c, level, c->Lp);
+    else up_level<double>(c, level, c->Lp);
   });
 }
 

@@ -5,6 +5,10 @@
 // algorithmic bytes of that launch: the bytes the kernel must read and write
 // at minimum (each operand once).  flush() waits for the events and adds
 // the durations to per-kernel totals.
+//
+// Filter: empty (every kernel), a kernel name, "name@l" (that kernel's
+// launches on level l only), or "@" (every kernel, totals kept per level
+// under the name "name@l" for launchers that state their level).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,13 +51,22 @@ struct KernelTiming {
     }
     return pool[used++];
   }
-  void begin(const char* name, double nbytes, hipStream_t s) {
+  void begin(const char* name, double nbytes, hipStream_t s, int level = -1) {
     open = -1;
-    if (!filter.empty() && filter != name) return;
+    std::string key = name;
+    if (filter == "@") {
+      if (level >= 0) key += "@" + std::to_string(level);
+    } else if (!filter.empty()) {
+      const size_t at = filter.find('@');
+      if (at == std::string::npos ? filter != key
+                                  : (filter.compare(0, at, key) != 0 || at != key.size() ||
+                                     filter.substr(at + 1) != std::to_string(level)))
+        return;
+    }
     hipEvent_t a = next_event(), b = next_event();
     if (a == nullptr || b == nullptr) return;
     (void)hipEventRecord(a, s);
-    pending.push_back(Pending{id_of(name), nbytes, a, b});
+    pending.push_back(Pending{id_of(key.c_str()), nbytes, a, b});
     open = static_cast<int>(pending.size() - 1);
     st = s;
   }

@@ -299,11 +299,14 @@ WORKLOADS = {
     "poisson3d_1025": dict(dim=3, L=10, op="poisson", smoother="rbgs", omega=1.0,
                            nu_pre=2, nu_post=2, ir_iters=2, bfp_block=64, bits=(8, 12, 16),
                            rhs="hash_noise", amp=1e-4, seed=3),
+    # diffusion: N = 3, the smallest N whose error against the converged
+    # solve stays below half the Richardson estimate of the discretisation
+    # error on both problems (N = 2 reaches 0.65x on the 129^3 problem)
     "diffusion3d_129": dict(dim=3, L=7, op="diffusion", smoother="rbgs", omega=1.0,
-                            nu_pre=2, nu_post=2, ir_iters=2, bfp_block=64, bits=16,
+                            nu_pre=2, nu_post=2, ir_iters=3, bfp_block=64, bits=16,
                             kappa_corr=0.1, kappa_seed=1, kappa_obs_seed=2, rhs="ones"),
     "diffusion3d_513x8": dict(dim=3, L=9, op="diffusion", smoother="rbgs", omega=1.0,
-                              nu_pre=2, nu_post=2, ir_iters=2, bfp_block=64, bits=16,
+                              nu_pre=2, nu_post=2, ir_iters=3, bfp_block=64, bits=16,
                               kappa_corr=0.05, kappa_seed=4, kappa_obs_seed=5,
                               rhs="smoothed_noise", rhs_seeds=tuple(range(100, 108))),
 }

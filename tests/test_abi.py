@@ -55,7 +55,9 @@ def _setup(lib, **kw):
     (dict(L=1), _lib.INVALID_ARG),
     (dict(L=11), _lib.INVALID_ARG),
     (dict(coarsest=0), _lib.INVALID_ARG),
-    (dict(coarsest=2), _lib.UNSUPPORTED),
+    (dict(coarsest=3), _lib.UNSUPPORTED),                  # dense coarsest solves hold at most 27 nodes
+    (dict(coarsest=6), _lib.INVALID_ARG),                  # not below L
+    (dict(keep_correction=2), _lib.INVALID_ARG),
     (dict(op=7), _lib.INVALID_ARG),
     (dict(op=_lib.DIFFUSION), _lib.INVALID_ARG),          # kappa missing
     (dict(batch=0), _lib.INVALID_ARG),

@@ -43,3 +43,21 @@ def test_source_digest_ignores_comments(tmp_path, monkeypatch):
     assert bench.kernel_source_digest() == d0
     (csrc / "plane.h").write_text((csrc / "plane.h").read_text() + "\nint changed;\n")
     assert bench.kernel_source_digest() != d0
+
+
+def test_model_bytes_per_dof_follow_the_per_dof_model():
+    # 16-bit sections in blocks of 64: beta = 2 + 1/32 bytes per value; the
+    # up sweep reads g and y', reads and writes u', and reads the coarse
+    # correction (codes and float32 z, 1/8 of the values): 8.879 B/DoF
+    beta = 2.0 + 2.0 / 64
+    assert abs(bench.model_bytes_per_dof("k_up_smooth<4>", 16, 64) - 8.87890625) < 1e-12
+    assert bench.model_bytes_per_dof("k_ir_residual", 16, 64) == 2 * beta + 9.0
+    assert bench.model_bytes_per_dof("k_down_smooth<4>", 8, 64) == 2 * (1.0 + 2.0 / 64)
+
+
+def test_per_level_rows_are_summed_per_kernel():
+    rows = [dict(kernel="k_a@10", launches=2, ms=4.0, bytes=8.0), dict(kernel="k_a@9", launches=2, ms=1.0, bytes=1.0),
+            dict(kernel="k_b", launches=1, ms=3.0, bytes=2.0)]
+    got = bench._by_kernel(rows)
+    assert [r["kernel"] for r in got] == ["k_a", "k_b"]
+    assert got[0]["launches"] == 4 and got[0]["ms"] == 5.0 and got[0]["bytes"] == 9.0

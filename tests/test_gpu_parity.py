@@ -155,13 +155,25 @@ def test_vcycle_step_bit_exact(cmg, name):
     f_np = S.gaussian_noise_rhs(c["dim"], L, sigma=0.1, seed=2)
     f = torch.from_numpy(f_np).cuda()
     U = _random_sections(cfg, L, 7)
-    with _solver(cmg, c) as s:
-        _enter_all(s, L, f)
-        for level, sec in U.items():
-            s.import_section("u", level, sec.w, np.frombuffer(ob.pack(sec.m, sec.w), dtype=np.uint8), sec.e)
-        s.ir_residual(f)
-        s.vcycle_correct()
-        got = {(w, level): _export(s, w, level) for w in ("u", "y", "r") for level in range(1, L + 1)}
+    got = {}
+    for keep in (True, False):
+        with _solver(cmg, c, keep_correction=keep) as s:
+            _enter_all(s, L, f)
+            for level, sec in U.items():
+                s.import_section("u", level, sec.w, np.frombuffer(ob.pack(sec.m, sec.w), dtype=np.uint8), sec.e)
+            s.ir_residual(f)
+            s.vcycle_correct()
+            kinds = ("u", "y", "r") if keep else ("u", "r")
+            got[keep] = {(w, level): _export(s, w, level) for w in kinds for level in range(1, L + 1)}
+            if not keep:  # the correction is not kept: its export is refused
+                with pytest.raises(cmg.CmgError) as ei:
+                    s.export_section("y", L)
+                assert ei.value.status == 2
+    # without the kept correction sections the solution and residuals are the same bits
+    for key, (m, e, bits) in got[False].items():
+        m1, e1, bits1 = got[True][key]
+        assert bits == bits1 and np.array_equal(e, e1) and np.array_equal(m, m1), key
+    got = got[True]
     ops = og.hierarchy(c["dim"], L, 1)
     g = oc.residual_hierarchy(U, og.inject(f_np, L, L), ops, cfg, L)
     trace = {}
@@ -296,3 +308,53 @@ def test_gpu_fmg_discretisation_accuracy_3d(cmg, bits):
     disc = og.norm_h(uh - us, h)
     assert og.norm_h(u - us, h) <= 2.0 * disc
     assert og.norm_h(u - uh, h) <= 0.5 * disc
+
+
+# ------------------------------------------------------ coarsest level 2
+@pytest.mark.parametrize("name", ["3d-rbgs-b12", "3d-L7-b16", "2d-wjacobi-b16", "3d-L7-V01-b12"])
+def test_coarsest_level_two_matches_oracle(cmg, name):
+    """A coarsest level of 3^dim interior nodes solved by the dense L D L^T
+    factorisation: the whole compact FMG (single-workgroup V-cycle, fused
+    and per-operation levels) and the plain FP64 FMG, bit for bit."""
+    c = CFGS[name]
+    cfg = _oracle_cfg(c, coarsest=2)
+    L = c["L"]
+    f_np = S.gaussian_noise_rhs(c["dim"], L, sigma=1e-3, seed=6)
+    with _solver(cmg, c, coarsest=2) as s:
+        u = s.solve(torch.from_numpy(f_np).cuda()[None])[0].cpu().numpy()
+    u_ref, _ = oc.fmg_solve(f_np, cfg)
+    assert np.array_equal(u, u_ref)
+    with _solver(cmg, c, coarsest=2, storage="plain", vcycle_prec="fp64") as s:
+        u = s.solve(torch.from_numpy(f_np).cuda()[None])[0].cpu().numpy()
+    assert np.array_equal(u, op.fmg_solve(f_np, cfg, vcycle_dtype=np.float64))
+
+
+def test_coarsest_level_two_diffusion_matches_oracle(cmg):
+    dim, L = 3, 5
+    kappa = S.lognormal_kappa(dim, L, 0.2, 1)
+    f_np = np.zeros(((1 << L) + 1,) * dim)
+    f_np[(slice(1, -1),) * dim] = 1.0
+    cfg = oc.Config(dim=dim, L=L, coarsest=2, op="diffusion")
+    with cmg.Solver(dim, L, op="diffusion", coarsest=2, kappa=torch.from_numpy(kappa).cuda()) as s:
+        u = s.solve(torch.from_numpy(f_np).cuda()[None])[0].cpu().numpy()
+    u_ref, _ = oc.fmg_solve(f_np, cfg, kappa)
+    assert np.array_equal(u, u_ref)
+
+
+@pytest.mark.parametrize("storage", ["compact", "plain"])
+def test_divergence_reported(cmg, storage):
+    """Weighted Jacobi with omega = 1.99 amplifies the highest grid mode by
+    |1 - 2 omega| ~ 3 per sweep: the IR residual grows from one iteration to
+    the next and the solve ends with CMG_ERR_NOT_CONVERGED (the kernels run
+    normally; only the host reads the monitor).  omega = 0.8 on the same
+    problem converges and reports nothing."""
+    f = torch.from_numpy(S.gaussian_noise_rhs(2, 5, sigma=1.0, seed=8)).cuda()[None]
+    kw = dict(smoother="wjacobi", bfp_block=32, bits=16, storage=storage)
+    with cmg.Solver(2, 5, omega=1.99, **kw) as s:
+        with pytest.raises(cmg.CmgError) as ei:
+            s.solve(f)
+        assert ei.value.status == 6
+        assert "FMG level" in str(ei.value)
+    with cmg.Solver(2, 5, omega=0.8, **kw) as s:
+        _, norms = s.solve(f, record=True)
+    assert all(b < a for a, b in zip(norms[0::2], norms[1::2]))

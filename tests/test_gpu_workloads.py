@@ -6,13 +6,14 @@
   and converges at order >= 1.95 over 33^3 .. 257^3.
 * 3-D variable-coefficient diffusion, 513^3 nodes, log-normal kappa
   (correlation length 0.05, unit variance), 8 seeded smoothed-noise
-  right-hand sides (drawn on the device at this size): the batched solve
-  equals the per-item solves exactly, and against a converged float64
-  solve of the same system (plain storage, float64 V-cycles, 12 extra
-  iterations) the compact FMG's error per right-hand side is at most 1.05
-  times that of the plain float64 FMG with the same iteration counts, i.e.
-  storing the tails in BFP costs no accuracy the float64 multigrid has;
-  the small-grid version of the same batch matches the oracle bit for bit.
+  right-hand sides (drawn on the device at this size), N = 3: the batched
+  solve equals the per-item solves exactly; against a converged float64
+  solve of the same system (plain storage, float64 V-cycles, 30 extra
+  iterations) the compact FMG's error per right-hand side is at most half
+  the Richardson estimate of the discretisation error and below 1e-3, and
+  at most 1.05 times that of the plain float64 FMG with the same iteration
+  counts; the small-grid version of the same batch matches the oracle bit
+  for bit.
 """
 import numpy as np
 import pytest
@@ -68,27 +69,45 @@ def test_diffusion_batch_matches_oracle_small(cmg):
         assert np.array_equal(u[b], ref), b
 
 
+def _coarsen_cells(k):
+    n = k.shape[0] // 2
+    return k.reshape(n, 2, n, 2, n, 2).mean(dim=(1, 3, 5)).contiguous()
+
+
 @pytest.mark.slow
 def test_diffusion3d_513x8_batch(cmg):
     L, seeds = 9, tuple(range(100, 108))
+    N = S.WORKLOADS["diffusion3d_513x8"]["ir_iters"]
     kappa = S.lognormal_kappa_torch(3, L, 0.05, 4, device="cuda")
     f = torch.stack([S.smoothed_noise_rhs_torch(3, L, sd, device="cuda") for sd in seeds])
-    with cmg.Solver(3, L, op="diffusion", kappa=kappa, batch=len(seeds), bits=16) as s:
+    with cmg.Solver(3, L, op="diffusion", kappa=kappa, batch=len(seeds), bits=16, ir_iters=N) as s:
         u = s.solve(f)
-    with cmg.Solver(3, L, op="diffusion", kappa=kappa, batch=1, bits=16) as s:
+    with cmg.Solver(3, L, op="diffusion", kappa=kappa, batch=1, bits=16, ir_iters=N) as s:
         for b in (0, len(seeds) - 1):
             assert torch.equal(s.solve(f[b:b + 1].contiguous())[0], u[b]), b
     plain = dict(storage="plain", vcycle_prec="fp64")
-    with cmg.Solver(3, L, op="diffusion", kappa=kappa, batch=len(seeds), final_iters=12, **plain) as s:
+    with cmg.Solver(3, L, op="diffusion", kappa=kappa, batch=len(seeds), final_iters=30, **plain) as s:
         ref = s.solve(f)
-    with cmg.Solver(3, L, op="diffusion", kappa=kappa, batch=len(seeds), **plain) as s:
+    with cmg.Solver(3, L, op="diffusion", kappa=kappa, batch=len(seeds), ir_iters=N, **plain) as s:
         up = s.solve(f)
+    # discretisation-error scale: Richardson from the same system on 2h
+    # (children-mean kappa, injected right-hand side), at coincident nodes
+    with cmg.Solver(3, L - 1, op="diffusion", kappa=_coarsen_cells(kappa), batch=len(seeds), final_iters=30,
+                    **plain) as s:
+        ref2 = s.solve(f[:, ::2, ::2, ::2].contiguous())
     for b in range(len(seeds)):
         nr = torch.linalg.vector_norm(ref[b])
         ec = float(torch.linalg.vector_norm(u[b] - ref[b]) / nr)
         ep = float(torch.linalg.vector_norm(up[b] - ref[b]) / nr)
-        print(f"rhs {b}: relative L2 error vs converged: compact {ec:.3e}, plain float64 FMG {ep:.3e}", flush=True)
-        assert ec <= 1.05 * ep, (b, ec, ep)
+        c = ref[b][::2, ::2, ::2]
+        disc = float(torch.linalg.vector_norm(c - ref2[b]) / 3.0 / torch.linalg.vector_norm(c))
+        print(f"rhs {b}: relative L2 error vs converged: compact {ec:.3e}, plain float64 FMG {ep:.3e}; "
+              f"Richardson discretisation estimate {disc:.3e}", flush=True)
+        # the paper's acceptance reading: the solver error is at most half
+        # the discretisation error (measured 0.05x at N = 3), and absolutely
+        # below 1e-3 (measured 1.7e-4 .. 3.0e-4)
+        assert ec <= 0.5 * disc and ec <= 1e-3, (b, ec, disc)
+        assert ec <= 1.05 * ep + 1e-6, (b, ec, ep)
 
 
 @pytest.mark.slow
@@ -128,7 +147,8 @@ def test_poisson3d_1025_ir_residual_sampled_blocks(cmg):
     b = 16, B = 64, the fused float64 residual kernel): random compact
     sections are imported on every level, one IR residual runs on the GPU,
     and sampled residual blocks (boundary rows included) equal the
-    node-by-node oracle bit for bit."""
+    node-by-node oracle bit for bit; so do 109 sampled nodes of the final
+    decode (eq. compact-to-standard) of the same sections."""
     from oracle import bfp as ob
     from oracle import pointwise as pw
     L, B = 10, 64
@@ -154,6 +174,17 @@ def test_poisson3d_1025_ir_residual_sampled_blocks(cmg):
             Uc[level] = pw.Codes(codes, exps, B, w)
         s.ir_residual(f)
         gcodes, gexps, gw = s.export_section("r", L)
+        # the final decode (k_decode_full) of the same sections: sampled
+        # nodes of the full node grid, far faces and edges included
+        u = s.decode_solution(L)
+        pts = [(0, 0, 0), (n, n, n), (n, 5, 7), (3, n, 9), (11, 13, n), (1, 1, 1), (n - 1, n - 1, n - 1),
+               (n - 1, 1, n), (2, n - 1, 1)]
+        pts += [tuple(int(v) for v in r) for r in rng.integers(0, n + 1, (100, 3))]
+        idx = np.array(pts, dtype=np.int64)
+        got = u[tuple(torch.from_numpy(idx[:, a]).cuda() for a in range(3))].cpu().numpy()
+        del u
+    want = pw.decode_chain_at(Uc, 1, L, idx)
+    assert np.array_equal(got, want)
     assert ob.container_bits(gw) == 16
     gm = gcodes.view(np.int16).reshape(n, n, n // B, B)
     ge = gexps.reshape(n, n, n // B)
@@ -180,7 +211,8 @@ def test_poisson3d_1025_down_sweep_sampled_blocks(cmg):
     n, m = 1 << L, 1 << (L - 1)
     f = torch.zeros((1,) + ((n + 1),) * 3, dtype=torch.float64, device="cuda")
     rng = np.random.default_rng(31)
-    with cmg.Solver(3, L, smoother="rbgs", bfp_block=B, bits=16, ir_iters=2, vcycle_prec="fp32") as s:
+    with cmg.Solver(3, L, smoother="rbgs", bfp_block=B, bits=16, ir_iters=2, vcycle_prec="fp32",
+                    keep_correction=True) as s:
         for level in range(1, L + 1):
             s.enter_level(level, f)
         w = s.section_info("r", L)["bits"]
@@ -215,3 +247,57 @@ def test_poisson3d_1025_down_sweep_sampled_blocks(cmg):
         mo, eo = pw.restrict_block(G, L, nu, K, J, bxc, B, yw, gw)
         assert int(ge[K, J, bxc]) == eo, (K, J, bxc)
         assert np.array_equal(gm[K, J, bxc].astype(np.int64), mo), (K, J, bxc)
+
+
+@pytest.mark.slow
+def test_poisson3d_1025_up_sweep_sampled_blocks(cmg):
+    """The fused up sweep and correction, the dominant kernel, at full size
+    (1025^3, b = 16, B = 64, V(2,2)) in the configuration bench.py times:
+    random residual, pre-smoothed correction and solution sections are
+    imported on the finest level and a random float32 coarse correction
+    e_{L-1} is given; the up sweep of that level runs alone, and sampled
+    blocks of the post-smoothed correction y'_L and of the corrected u'_L
+    (boundary rows included) equal the node-local oracle bit for bit."""
+    from oracle import bfp as ob
+    from oracle import pointwise as pw
+    L, B, nu = 10, 64, 2
+    n, m = 1 << L, 1 << (L - 1)
+    f = torch.zeros((1,) + ((n + 1),) * 3, dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(41)
+
+    def random_section(w, elo, ehi):
+        lim = (1 << (w - 1)) - 1
+        codes = rng.integers(-lim, lim + 1, size=n ** 3, dtype=np.int16)
+        c3 = codes.reshape(n, n, n)
+        c3[0], c3[:, 0], c3[:, :, 0] = 0, 0, 0              # Dirichlet nodes hold 0
+        exps = rng.integers(elo, ehi, size=n ** 3 // B, dtype=np.int16)
+        return codes, exps
+
+    e_np = np.zeros((m, m, m), dtype=np.float32)
+    e_np[1:, 1:, 1:] = rng.uniform(-1e-6, 1e-6, size=(m - 1,) * 3).astype(np.float32)
+    with cmg.Solver(3, L, smoother="rbgs", bfp_block=B, bits=16, ir_iters=2, vcycle_prec="fp32",
+                    keep_correction=True) as s:
+        for level in range(1, L + 1):
+            s.enter_level(level, f)
+        secs = {}
+        for which, (elo, ehi) in (("r", (-3, 4)), ("ypre", (-24, -19)), ("u", (-10, -4))):
+            w = s.section_info(which, L)["bits"]
+            assert ob.container_bits(w) == 16
+            codes, exps = random_section(w, elo, ehi)
+            s.import_section(which, L, w, codes.view(np.uint8), exps)
+            secs[which] = pw.Codes(codes, exps, B, w)
+        s.up_sweep(L, torch.from_numpy(e_np).cuda())
+        ym, ye, yw = s.export_section("y", L)
+        um, ue, uw = s.export_section("u", L)
+    del f
+    ym = ym.view(np.int16).reshape(n, n, n // B, B)
+    ye = ye.reshape(n, n, n // B)
+    um = um.view(np.int16).reshape(n, n, n // B, B)
+    ue = ue.reshape(n, n, n // B)
+    rows = [(0, 3, 0), (1, 1, 0), (n - 1, n - 1, n // B - 1), (2, n - 1, 3), (n - 1, 1, 5), (n // 2, 0, 7)]
+    rows += [tuple(int(v) for v in r) for r in np.stack([rng.integers(0, n, 44), rng.integers(0, n, 44),
+                                                         rng.integers(0, n // B, 44)], axis=1)]
+    for z, y, bx in rows:
+        my, ey, mu, eu = pw.up_sweep_block(secs["r"], secs["ypre"], secs["u"], e_np, L, nu, z, y, bx, B, yw, uw)
+        assert int(ye[z, y, bx]) == ey and np.array_equal(ym[z, y, bx].astype(np.int64), my), (z, y, bx)
+        assert int(ue[z, y, bx]) == eu and np.array_equal(um[z, y, bx].astype(np.int64), mu), (z, y, bx)

@@ -403,3 +403,59 @@ def test_fold_reading_changes_the_solution_little(bits, tol):
     diff = grid.norm_h(sols["fold"] - sols["fp64"], h) / disc
     print(f"fold vs fp64 s at {bits} bits: |u_fold - u_fp64| / disc = {diff:.3e}")
     assert diff <= tol
+
+
+# ------------------------------------------------ coarsest level 2
+@pytest.mark.parametrize("dim,L", [(2, 6), (3, 5)])
+def test_coarsest_level_two(dim, L):
+    # a dense coarsest solve of 3^dim nodes instead of one: the unquantised
+    # compact FMG still equals the plain FP64 FMG, and the quantised one
+    # meets the acceptance test on the sine problem
+    f = S.sine_rhs(dim, L)
+    cfg = compact.Config(dim=dim, L=L, coarsest=2, quantize=False, vcycle_dtype=np.float64,
+                         smoother="rbgs", omega=1.0)
+    u_c, _ = compact.fmg_solve(f, cfg)
+    u_p = plain.fmg_solve(f, cfg)
+    assert np.abs(u_c - u_p).max() <= 1e-12 * np.abs(u_p).max()
+    us, uh, h = _closed_form(dim, L)
+    disc = grid.norm_h(uh - us, h)
+    cfg = compact.Config(dim=dim, L=L, coarsest=2, bits_u=12, bits_r=12, bits_y=12)
+    u, _ = compact.fmg_solve(f, cfg)
+    assert grid.norm_h(u - us, h) <= 2.0 * disc
+    assert grid.norm_h(u - uh, h) <= 0.5 * disc
+
+
+@pytest.mark.parametrize("L", [6, 7])
+def test_pointwise_up_sweep_equals_whole_array(L):
+    """The node-local up sweep and correction (z = P e, y = S^nu(y'_pre;
+    g - A z), y' = Q(y), u' = Q(u' + y')) equal the whole-array V-cycle's
+    finest level, traced, on sampled blocks of 64^3 and 128^3 grids (random
+    residual and solution sections; boundary rows included)."""
+    nu = 2
+    cfg = compact.Config(dim=3, L=L, bits_u=16, bits_r=16, bits_y=16, nu_pre=nu, nu_post=nu)
+    rng = np.random.default_rng(30 + L)
+    n = 1 << L
+    x = np.zeros((n,) * 3)
+    x[1:, 1:, 1:] = rng.standard_normal((n - 1,) * 3)
+    g = compact.Section.quantize(x, cfg.block, cfg.w_r(L, L))
+    U = {}
+    for lv in range(1, L + 1):
+        m = 1 << lv
+        u = np.zeros((m,) * 3)
+        u[1:, 1:, 1:] = rng.standard_normal((m - 1,) * 3) * 4.0 ** -lv
+        U[lv] = compact.Section.quantize(u, cfg.block, cfg.w_u(lv, L))
+    U0 = dict(U)
+    trace = {}
+    Y = compact.vcycle_correct(U, g, grid.hierarchy(3, L, 1), cfg, L, trace=trace)
+    G, Yp = _section_codes(g), _section_codes(trace["Ypre"][L])
+    Uc = _section_codes(U0[L])
+    E = trace["E"][L - 1]
+    assert E.dtype == np.float32 and E.shape == (n // 2,) * 3
+    rows = [(0, 3), (1, 1), (n - 1, n - 2), (5, n - 1)] + [tuple(r) for r in rng.integers(0, n, (6, 2))]
+    for z, y in rows:
+        for bx in range(n // cfg.block):
+            my, ey, mu, eu = pw.up_sweep_block(G, Yp, Uc, E, L, nu, z, y, bx, cfg.block, cfg.w_y(L, L),
+                                               cfg.w_u(L, L))
+            k = (z * n + y) * n + bx * cfg.block
+            assert np.array_equal(my, Y[L].m[k:k + cfg.block]) and ey == int(Y[L].e[k // cfg.block]), (z, y, bx)
+            assert np.array_equal(mu, U[L].m[k:k + cfg.block]) and eu == int(U[L].e[k // cfg.block]), (z, y, bx)

@@ -201,3 +201,17 @@ def test_kappa_coarsening_mean():
     c = grid.coarsen_kappa(k)
     assert c.shape == (2, 2, 2)
     assert c[1, 0, 1] == np.mean(k[2:4, 0:2, 2:4])
+
+
+def test_ldlt_solve_hand_case_and_library():
+    # hand case: A = [[4, 2], [2, 3]]: d = (4, 2), l_10 = 1/2; b = (2, 1)
+    # gives z = (2, 0), x = (1/2, 0), exactly
+    x = grid.ldlt_solve(np.array([[4.0, 2.0], [2.0, 3.0]]), np.array([2.0, 1.0]))
+    assert x[0] == 0.5 and x[1] == 0.0
+    rng = np.random.default_rng(3)
+    for m in (1, 5, 27):
+        M = rng.standard_normal((m, m))
+        A = M @ M.T + m * np.eye(m)
+        b = rng.standard_normal(m)
+        ref = np.linalg.solve(A, b)
+        assert np.allclose(grid.ldlt_solve(A, b), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
