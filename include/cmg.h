@@ -238,6 +238,17 @@ int64_t cmg_abfp_workspace_bytes(int64_t n);
 cmg_status cmg_abfp_encode(const void* x, int32_t x_is_f64, int64_t n, int32_t bits, void* codes, int64_t* starts,
                            int16_t* exps, int32_t* nblocks, void* workspace, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * encode as cmg_abfp_encode, with the same outputs, but no workspace
+ * argument: its workspace is one static device array per GPU (about 4 MiB,
+ * held until the process ends) for n of at most 2^31 values; larger n fails
+ * with CMG_ERR_INVALID_ARG.  Allocates nothing.  Calls that overlap on one
+ * GPU (other streams or threads) share that array and race; calls in stream
+ * order do not.  Asynchronous on hip_stream. */
+cmg_status cmg_abfp_encode_noalloc(const void* x, int32_t x_is_f64, int64_t n, int32_t bits, void* codes,
+                                   int64_t* starts, int16_t* exps, int32_t* nblocks, void* hip_stream);
+
 /* Decode n values into x (device float64) from an encode's outputs (a
  * negative *nblocks decodes as no block: all zeros); exact for bits <= 53. */
 cmg_status cmg_abfp_decode(const void* codes, const int64_t* starts, const int16_t* exps, const int32_t* nblocks,

@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import CmgError, load  # noqa: F401
 
-__all__ = ["Solver", "bfp_encode", "bfp_decode", "bfp_code_bytes", "abfp_encode", "abfp_decode", "abfp_workspace",
+__all__ = ["Solver", "bfp_encode", "bfp_decode", "bfp_code_bytes", "abfp_encode", "abfp_encode_noalloc", "abfp_decode",
+           "abfp_workspace",
            "CmgError", "load", "options"]
 
 _SMOOTHERS = {"wjacobi": _lib.WJACOBI, "rbgs": _lib.RBGS}
@@ -293,6 +294,18 @@ def abfp_encode(x, bits: int, stream=None, workspace=None):
                                    _lib.ptr(starts), _lib.ptr(exps), _lib.ptr(nblocks), _lib.ptr(workspace),
                                    _lib.stream_ptr(stream)))
     return codes, starts, exps, nblocks
+
+
+def abfp_encode_noalloc(x, bits: int, codes, starts, exps, nblocks, stream=None):
+    """``cmg_abfp_encode_noalloc``: :func:`abfp_encode` into caller-given
+    output tensors, with the library's static workspace (nothing is
+    allocated; at most 2**31 values)."""
+    import torch
+    lib = load()
+    x = x.contiguous()
+    _lib.check(lib.cmg_abfp_encode_noalloc(_lib.ptr(x), 1 if x.dtype == torch.float64 else 0, x.numel(), bits,
+                                           _lib.ptr(codes), _lib.ptr(starts), _lib.ptr(exps), _lib.ptr(nblocks),
+                                           _lib.stream_ptr(stream)))
 
 
 def abfp_decode(codes, starts, exps, nblocks, n: int, bits: int, stream=None):

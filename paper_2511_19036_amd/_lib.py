@@ -76,6 +76,7 @@ SIGNATURES = {
     "cmg_abfp_code_bytes": (_I64, [_I64, _I32]),
     "cmg_abfp_workspace_bytes": (_I64, [_I64]),
     "cmg_abfp_encode": (_ST, [_P, _I32, _I64, _I32, _P, _P, _P, _P, _P, _P]),
+    "cmg_abfp_encode_noalloc": (_ST, [_P, _I32, _I64, _I32, _P, _P, _P, _P, _P]),
     "cmg_abfp_decode": (_ST, [_P, _P, _P, _P, _I64, _I32, _P, _P]),
     "cmg_section_info": (_ST, [_P, _I32, _I32, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I32),
                                C.POINTER(_I64), C.POINTER(_I64)]),

@@ -11,8 +11,17 @@ constexpr int kAbEmin = -1100, kAbEtab = 2200;  // exponent table: -1100 .. 1099
 
 // Workspace of one encode: tile ticket, error flags, the start of the block
 // with each exponent, and one look-back status word per tile.
-inline int64_t abfp_tiles(int64_t n) { return (n + kAbTile - 1) / kAbTile; }
-inline int64_t abfp_workspace_bytes(int64_t n) { return 16 + 8 * kAbEtab + 8 * abfp_tiles(n); }
+constexpr int64_t abfp_tiles(int64_t n) { return (n + kAbTile - 1) / kAbTile; }
+constexpr int64_t abfp_workspace_bytes(int64_t n) { return 16 + 8 * kAbEtab + 8 * abfp_tiles(n); }
+
+// The allocation-free encode (cmg_abfp_encode_noalloc) takes its workspace
+// from one static device array per GPU, sized for inputs of up to
+// kAbNoAllocMax values (about 4 MiB).  abfp_static_workspace() returns the
+// current device's address of that array (nullptr if HIP cannot give it);
+// every call on one device shares it.
+constexpr int64_t kAbNoAllocMax = int64_t{1} << 31;
+constexpr int64_t kAbNoAllocBytes = abfp_workspace_bytes(kAbNoAllocMax);
+void* abfp_static_workspace();
 
 // Codes of the first ceil(n/64)*64 values, block list (kept blocks, at most
 // `w`), *nblocks (-1: non-finite input, -2: look-back gave up).  Async.

@@ -23,6 +23,8 @@
 // Codes are packed per thread (16 values: 16, 24, 32, 64 or 128 bytes), in
 // the containers of the fixed-block codec.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "abfp.h"
@@ -323,6 +325,27 @@ void launch_abfp_decode(const void* codes, const int64_t* starts, const int16_t*
   hipLaunchKernelGGL(k_abfp_decode, dim3(static_cast<unsigned>(abfp_tiles(n))), dim3(kAbNT), 0, st,
                      static_cast<const char*>(codes), starts, exps, nblocks, n, w, cbits, x);
   if (g_timing != nullptr) g_timing->end(st);
+}
+
+// Workspace of the allocation-free encode.  In host code `scratch` is a
+// host-side stand-in for the device array, not a device address: the address
+// on each device comes from hipGetSymbolAddress, taken once per device (with
+// that device current) on its first use and kept.  k_abfp_prep clears what
+// must start at zero on every call.
+static __device__ __align__(256) unsigned char scratch[kAbNoAllocBytes];
+
+void* abfp_static_workspace() {
+  static std::mutex mu;
+  static std::map<int, void*> addr;  // device -> address of `scratch` there
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return nullptr;
+  addr[dev] = ptr;
+  return ptr;
 }
 
 template void launch_abfp_encode<float>(const float*, int64_t, int, int, void*, int64_t*, int16_t*, int32_t*, void*,

@@ -995,6 +995,26 @@ cmg_status cmg_abfp_encode(const void* x, int32_t x_is_f64, int64_t n, int32_t b
   });
 }
 
+cmg_status cmg_abfp_encode_noalloc(const void* x, int32_t x_is_f64, int64_t n, int32_t bits, void* codes,
+                                   int64_t* starts, int16_t* exps, int32_t* nblocks, void* hip_stream) {
+  return guard(nullptr, [&] {
+    need(n >= 0 && n <= kAbNoAllocMax, "n must lie in [0, 2^31]: the static workspace holds no more");
+    need(bits >= 2 && bits <= 53, "bad bits");
+    need(starts != nullptr && exps != nullptr && nblocks != nullptr, "NULL buffer");
+    need(n == 0 || (x != nullptr && codes != nullptr), "NULL buffer");
+    need(reinterpret_cast<uintptr_t>(codes) % 16 == 0, "codes must be 16-byte aligned");
+    void* ws = abfp_static_workspace();
+    if (ws == nullptr) fail(CMG_ERR_HIP, "hipGetSymbolAddress gave no address for the static workspace");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int cb = container_bits(bits);
+    if (x_is_f64)
+      launch_abfp_encode<double>(static_cast<const double*>(x), n, bits, cb, codes, starts, exps, nblocks, ws, st);
+    else
+      launch_abfp_encode<float>(static_cast<const float*>(x), n, bits, cb, codes, starts, exps, nblocks, ws, st);
+    KCK();
+  });
+}
+
 cmg_status cmg_abfp_decode(const void* codes, const int64_t* starts, const int16_t* exps, const int32_t* nblocks,
                            int64_t n, int32_t bits, double* x, void* hip_stream) {
   return guard(nullptr, [&] {

@@ -88,6 +88,13 @@ def test_null_arguments(lib):
     assert isinstance(lib.cmg_last_error(None), bytes)
 
 
+def test_noalloc_encode_rejects_sizes_beyond_its_workspace(lib):
+    # checked before any HIP call: the static workspace holds 2^31 values
+    assert lib.cmg_abfp_encode_noalloc(None, 1, (1 << 31) + 1, 16, None, None, None, None, None) == _lib.INVALID_ARG
+    assert b"2^31" in lib.cmg_last_error(None)
+    assert lib.cmg_abfp_encode_noalloc(None, 1, -1, 16, None, None, None, None, None) == _lib.INVALID_ARG
+
+
 def test_code_bytes(lib):
     assert lib.cmg_bfp_code_bytes(100, 64, 8) == 128
     assert lib.cmg_bfp_code_bytes(100, 32, 12) == 128 * 12 // 8
