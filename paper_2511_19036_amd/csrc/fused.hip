@@ -207,12 +207,14 @@ __device__ __forceinline__ void quantise_rows(const float* ob, const PSec& S, in
   const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const PlanePtr pq = plane_at<CB, LB>(S, po, level);
   int m[RPW], e[RPW];
+  float v[RPW];
 #pragma unroll
   for (int t = 0; t < RPW; ++t) {
     const int rr0 = out_row<NW>(wv, t);
     const int rr = rr0 < TY ? rr0 : out_row<NW>(wv, 0);
-    m[t] = quant_f32<LB>(ob[rr * kTX + lane], S.w, lane, &e[t]);
+    v[t] = ob[rr * kTX + lane];
   }
+  quant_f32_rows<LB, RPW>(v, S.w, lane, m, e);
 #pragma unroll
   for (int t = 0; t < RPW; ++t) {
     const int rr = out_row<NW>(wv, t);
@@ -445,20 +447,69 @@ __device__ __forceinline__ T prolong_node(const T* c0, const T* c1, int ci, bool
   return s;
 }
 
+// Quads (2 x 2 nodes at even local coordinates) of an up-sweep tile of
+// 64 x TY output nodes with halo H, numbered ring by ring: the output tile
+// (ring 0, row by row), then ring r = 1 .. H / 2 (the quads r quads outside
+// it: bottom row, top row, left column, right column).  Ring r holds the
+// nodes at distance 2 r - 1 and 2 r from the output tile.
+template <int H, int TY>
+__device__ __forceinline__ void quad_of(int t, int& qx, int& qy) {
+  constexpr int W0 = kTX / 2, H0 = TY / 2, C = H / 2;  // output quads per row and column; quads of halo
+  if (t < W0 * H0) {
+    qx = C + t % W0;
+    qy = C + t / W0;
+    return;
+  }
+  int before = W0 * H0;
+#pragma unroll
+  for (int r = 1; r <= C; ++r) {
+    const int w = W0 + 2 * r, h = H0 + 2 * r, lo = C - r;
+    const int k = t - before;
+    if (k >= 0 && k < 2 * w + 2 * (h - 2)) {
+      if (k < w) {
+        qx = lo + k;
+        qy = lo;
+      } else if (k < 2 * w) {
+        qx = lo + k - w;
+        qy = lo + h - 1;
+      } else if (k < 2 * w + h - 2) {
+        qx = lo;
+        qy = lo + 1 + (k - 2 * w);
+      } else {
+        qx = lo + w - 1;
+        qy = lo + 1 + (k - 2 * w - (h - 2));
+      }
+    }
+    before += 2 * w + 2 * (h - 2);
+  }
+}
+
+// Quads within `dist` nodes of the output tile (the first ones in the
+// numbering of quad_of): rings 0 .. (dist + 1) / 2.
+template <int H, int TY>
+constexpr int cone_quads(int dist) {
+  const int r = (dist + 1) / 2 < H / 2 ? (dist + 1) / 2 : H / 2;
+  return (kTX / 2 + 2 * r) * (TY / 2 + 2 * r);
+}
+
 template <int S, int TY, int NT, int LB, bool HI, int CB>
 __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ ec, PSec G, PSec Y, PSec Yp, PSec U,
                                                      float* __restrict__ eout, int level, int levelc, float cp,
                                                      float ih2, int TZ) {
   constexpr int H = S;
-  static_assert(H % 2 == 0, "even halo: column 0 of a pair has even x");
-  using T = ColTile<H, TY, NT>;
-  constexpr int K = T::K, EXW = T::EXW, PS = T::PS, PAD = T::PAD, NW = T::NW, RPW = T::RPW;
+  static_assert(H % 2 == 0, "even halo: quads start at even coordinates");
+  constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H, QW = EXW / 2, QH = EXH / 2, NQ = QW * QH;
+  static_assert(NQ <= NT, "one quad per thread");
+  // plane of the extended tile and its stride: a missing quad works on the
+  // two spare rows after the plane
+  constexpr int LPL = EXW * EXH, PS = LPL + 2 * EXW + 2, PAD = EXW + 2;
+  constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;
   constexpr int NB = S + 1;  // y buffers: plane j - 1 - s in flight from step j - s to j - s + S
-  constexpr int NC = 8, CW = EXW / 2 + 2, CH = T::EXH / 2 + 1, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
-  __shared__ float cs[NC * CPL];
+  constexpr int NC = 8, CW = QW + 2, CH = QH + 1, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
+  constexpr int OB = TY * kTX + 2 * kTX;  // output tile plus two spare rows (written by the other quads)
+  __shared__ float cs[NC * CPL + 1];       // plus a spare word (written by threads past the coarse tile)
   __shared__ __align__(8) float lds[2 * PAD + (2 + NB) * PS];  // z of planes j, j - 1; then y buffers
-  static_assert(PAD % 2 == 0 && PS % 2 == 0 && T::LPL % 2 == 0, "column pairs at 8-byte offsets");
-  __shared__ float outb[2][TY * kTX];
+  __shared__ __align__(8) float outb[2][OB];
   const int tid = threadIdx.x;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   int lane = tid & 63;
@@ -469,16 +520,27 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   const int n = 1 << level, nc = 1 << levelc;
   const int CX0 = (X0 - H) >> 1, CY0 = (Y0 - H) >> 1;
 
-  int pos[K], oidx[K], cb[K];
-  uint32_t xy[K][2];
-  unsigned fl[K];
-  col_setup<H, TY, NT>(tid, X0, Y0, level, pos, xy, fl, oidx);
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int q = tid + k * NT;
-    const int ly = q < T::NPAIR ? q / T::PW : 0, lx0 = q < T::NPAIR ? 2 * (q - ly * T::PW) : 0;
-    cb[k] = (((Y0 - H + ly) >> 1) - CY0) * CW + (((X0 - H + lx0) >> 1) - CX0);
+  // The quad of this thread: nodes (gx0 + dx, gy0 + dy), dx, dy in {0, 1},
+  // node d = dx + 2 dy.  gx0 and gy0 are even, so a node's x and y parities
+  // are dx and dy, and its class (x + y) & 1 is dx ^ dy: all compile-time.
+  // Threads take the quads ring by ring: first the output tile, then the
+  // rings of the halo, so that the later stages (whose dependence cone
+  // narrows by one node per stage) skip whole waves.
+  const bool valid = tid < NQ;
+  int qx = 0, qy = 0;
+  if (valid) quad_of<H, TY>(tid, qx, qy);
+  const int gx0 = X0 - H + 2 * qx, gy0 = Y0 - H + 2 * qy;
+  const bool dom = valid && gx0 >= 0 && gx0 < n && gy0 >= 0 && gy0 < n;  // the quad lies in the level
+  int pos = valid ? 2 * qy * EXW + 2 * qx : LPL;  // LDS offset of node 0
+  int ci = qy * CW + qx;                          // coarse node (gx0 / 2, gy0 / 2) in the coarse ring
+  // bits 0-3: node d is an interior node of the level; bit 4: output quad
+  unsigned fq = 0u;
+  if (dom) {
+    fq |= (gx0 >= 1 && gy0 >= 1 ? 1u : 0u) | (gy0 >= 1 ? 2u : 0u) | (gx0 >= 1 ? 4u : 0u) | 8u;
   }
+  if (valid && 2 * qx >= H && 2 * qx < H + kTX && 2 * qy >= H && 2 * qy < H + TY) fq |= 16u;
+  uint32_t xy0 = dom ? ((static_cast<uint32_t>(gy0) << level) | static_cast<uint32_t>(gx0)) : 0u;
+  int oidx = (fq >> 4) & 1u ? (2 * qy - H) * kTX + (2 * qx - H) : TY * kTX;
   auto launder = [&]() {
     opaque(lane);
     opaque_s(wv);
@@ -489,34 +551,28 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     opaque_sec<CB>(Y);
     opaque_sec<CB>(Yp);
     opaque_sec<CB>(U);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      opaque(pos[k]);
-      opaque(oidx[k]);
-      opaque(cb[k]);
-      opaque(fl[k]);
-      opaque(xy[k][0]);
-      opaque(xy[k][1]);
-    }
+    opaque(pos);
+    opaque(ci);
+    opaque(fq);
+    opaque(xy0);
+    opaque(oidx);
   };
 
-  float z[K][2][3];      // column-indexed, planes j-2 .. j
-  float r[K][2][S + 1];  // slot-indexed, planes j-1-S .. j-1
-  float y[K][2][S + 2];  // slot-indexed, planes j-2-S .. j-1
-  RawCode gpre[K], ypre[K], upre[RPW];
+  float z[4][3];      // planes j-2 .. j
+  float r[4][S + 1];  // planes j-1-S .. j-1
+  float y[4][S + 2];  // planes j-2-S .. j-1
+  RawCode gpre[2], ypre[2], upre[RPW];
   float cpf[CPT];
   bool cin[CPT];
 #pragma unroll
-  for (int k = 0; k < K; ++k)
+  for (int d = 0; d < 4; ++d) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int i = 0; i < 3; ++i) z[d][i] = 0.0f;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) z[k][c][i] = 0.0f;
+    for (int i = 0; i < S + 1; ++i) r[d][i] = 0.0f;
 #pragma unroll
-      for (int i = 0; i < S + 1; ++i) r[k][c][i] = 0.0f;
-#pragma unroll
-      for (int i = 0; i < S + 2; ++i) y[k][c][i] = 0.0f;
-    }
+    for (int i = 0; i < S + 2; ++i) y[d][i] = 0.0f;
+  }
   auto cfetch = [&](int cz) {  // coarse tile of plane cz into registers (0 outside the level)
     const bool zin = cz >= 0 && cz < nc;
     const float* src = ec + (static_cast<uint64_t>(zin ? cz : 0) << (2 * levelc));
@@ -538,20 +594,21 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       const int t = tid + k * NT;
-      if (t < CPL) dst[t] = cin[k] ? cpf[k] : 0;
+      (t < CPL ? dst[t] : cs[NC * CPL]) = cin[k] ? cpf[k] : 0;
     }
   };
-  // Codes of plane p for the own column pairs (G and Y have containers of
-  // at most 32 bits: widths of at most 24 with the float32 V-cycle).
+  // Codes of the quad's two rows on plane p (G and Y have containers of at
+  // most 32 bits: widths of at most 24 with the float32 V-cycle).
   // Unconditional: a plane outside the level reads plane 1, and the
   // right-hand side part zeroes its values.
   auto fetch_gy = [&](int p) {
     const int pc = min(max(p, 1), n - 1);
     const PlanePtr gq = plane_at<CB, LB>(G, pc, level), yq = plane_at<CB, LB>(Y, pc, level);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      gpre[k] = pair_at<LB>(gq, xy[k][0], cbits_of<CB>(G));
-      ypre[k] = pair_at<LB>(yq, xy[k][0], cbits_of<CB>(Y));
+    for (int dy = 0; dy < 2; ++dy) {
+      const uint32_t xr = xy0 + (static_cast<uint32_t>(dy) << level);
+      gpre[dy] = pair_at<LB>(gq, xr, cbits_of<CB>(G));
+      ypre[dy] = pair_at<LB>(yq, xr, cbits_of<CB>(Y));
     }
   };
   // Rows of a wave: out_row(wv, t) for t < RPW; a wave with fewer than RPW
@@ -584,22 +641,26 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     if (po < Z0 || po >= Z0 + TZ) return;
     const float* c0 = cs + ((po >> 1) & (NC - 1)) * CPL;
     const float* c1 = cs + (((po >> 1) + 1) & (NC - 1)) * CPL;
+    // the rows are quantised together (their DPP reductions interleave)
+    float yv[RPW];
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) yv[t] = ob[row_of(t) * kTX + lane];
+    quant_f32_rows<LB, RPW>(yv, Yp.w, lane, F.my, F.ey);
+    double vu[RPW];
 #pragma unroll
     for (int t = 0; t < RPW; ++t) {
-      const int rr = row_of(t);
-      const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
-      F.my[t] = quant_f32<LB>(ob[rr * kTX + lane], Yp.w, lane, &F.ey[t]);
+      const uint32_t xyl = ((static_cast<uint32_t>(Y0 + row_of(t)) << level) | static_cast<uint32_t>(X0)) + lane;
       const double dy = ldexp(static_cast<double>(F.my[t]), F.ey[t] - (Yp.w - 1));  // codes 0 in a zero block
-      const double vu = raw_f64<may64<CB, HI>()>(upre[t], xyl, cbits_of<CB>(U), U.w) + dy;
-      F.mu[t] = quant_f64<LB, may64<CB, HI>()>(vu, U.w, lane, &F.eu[t]);
+      vu[t] = raw_f64<may64<CB, HI>()>(upre[t], xyl, cbits_of<CB>(U), U.w) + dy;
       F.ev[t] = static_cast<float>(dy);
     }
+    quant_f64_rows<LB, may64<CB, HI>(), RPW>(vu, U.w, lane, F.mu, F.eu);
     if (eout != nullptr) {
 #pragma unroll
       for (int t = 0; t < RPW; ++t) {
         const int rr = row_of(t);
-        const int ci = ((rr >> 1) + H / 2) * CW + (lane >> 1) + H / 2;
-        F.ev[t] = F.ev[t] + prolong_node<float, PK, CW>(c0, c1, ci, lane & 1, rr & 1);
+        const int cix = ((rr >> 1) + H / 2) * CW + (lane >> 1) + H / 2;
+        F.ev[t] = F.ev[t] + prolong_node<float, PK, CW>(c0, c1, cix, lane & 1, rr & 1);
       }
     }
   };
@@ -617,22 +678,24 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       store_row(uq.c, xyr, lane, F.mu[t], cbits_of<CB>(U));
       if (eout != nullptr) eout[(static_cast<uint64_t>(po) << (2 * level)) + xyr + lane] = F.ev[t];
     }
-    if ((lane & ((1 << LB) - 1)) == 0) {
+    // every lane of a block stores the block's exponent (the same value to
+    // the same address): no branch on the lane
 #pragma unroll
-      for (int t = 0; t < RPW; ++t) {
-        const int rr = out_row<NW>(wv, t);
-        if (rr >= TY) continue;
-        const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
-        if (keep) yq.e[xyl >> LB] = static_cast<int16_t>(F.ey[t]);
-        uq.e[xyl >> LB] = static_cast<int16_t>(F.eu[t]);
-      }
+    for (int t = 0; t < RPW; ++t) {
+      const int rr = out_row<NW>(wv, t);
+      if (rr >= TY) continue;
+      const uint32_t xyl = ((static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0)) + lane;
+      if (keep) yq.e[xyl >> LB] = static_cast<int16_t>(F.ey[t]);
+      uq.e[xyl >> LB] = static_cast<int16_t>(F.eu[t]);
     }
   };
 
   auto step = [&](auto jpc, const int j) {
-    constexpr int JP = decltype(jpc)::value;
-    constexpr int SG = JP;  // slot updated by every stage at this step
+    constexpr int JP = decltype(jpc)::value;  // every stage updates the nodes of class JP at this step
     launder();
+    // y buffer of plane j - 1 - s (0 <= s <= S < NB)
+    const int bj = (j - 1 + 4 * NB) % NB;
+    auto ybuf = [&](int s) { return lds + PAD + (2 + bj - s + (bj < s ? NB : 0)) * PS; };
     {
       Fin F;
       finish_compute(jpc, j - 2 - S, outb[1 - JP], F);
@@ -645,121 +708,126 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const float* c1 = cs + (((j >> 1) + 1) & (NC - 1)) * CPL;
       float* zb = lds + PAD + JP * PS;
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const bool py = (fl[k] >> kOddY) & 1u;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          z[k][c][0] = z[k][c][1];
-          z[k][c][1] = z[k][c][2];
-          z[k][c][2] = prolong_node<float, JP, CW>(c0, c1, cb[k], c == 1, py);
-        }
-        *reinterpret_cast<float2*>(zb + pos[k]) = make_float2(z[k][0][2], z[k][1][2]);
+      for (int d = 0; d < 4; ++d) {
+        z[d][0] = z[d][1];
+        z[d][1] = z[d][2];
+        z[d][2] = prolong_node<float, JP, CW>(c0, c1, ci, (d & 1) != 0, (d & 2) != 0);
       }
+      *reinterpret_cast<float2*>(zb + pos) = make_float2(z[0][2], z[1][2]);
+      *reinterpret_cast<float2*>(zb + pos + EXW) = make_float2(z[2][2], z[3][2]);
     }
     {  // plane j - 1: rhs = g - A z, and y' as stage 0
       const int p = j - 1;
       const bool pin = p >= 1 && p < n;
       const float* zs = lds + PAD + (1 - JP) * PS;
-      float* yb = lds + PAD + (2 + (p + 4 * NB) % NB) * PS;
+      float* yb = ybuf(0);
+      // in-plane neighbours outside the quad: x - 1 / x + 1 of the left /
+      // right column, y - 1 / y + 1 of the lower / upper row
+      const float zxm0 = zs[pos - 1], zxm2 = zs[pos + EXW - 1];
+      const float zxp1 = zs[pos + 2], zxp3 = zs[pos + EXW + 2];
+      const float zym0 = zs[pos - EXW], zym1 = zs[pos - EXW + 1];
+      const float zyp2 = zs[pos + 2 * EXW], zyp3 = zs[pos + 2 * EXW + 1];
+      float rv[4], yv[4];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        float rv[2], yv[2];
+      for (int d = 0; d < 4; ++d) {
+        const int dx = d & 1, dy = d >> 1;
+        const float xm = dx ? z[d ^ 1][1] : (dy ? zxm2 : zxm0);
+        const float xp = dx ? (dy ? zxp3 : zxp1) : z[d ^ 1][1];
+        const float ym = dy ? z[d ^ 2][1] : (dx ? zym1 : zym0);
+        const float yp = dy ? (dx ? zyp3 : zyp2) : z[d ^ 2][1];
+        float a = 6.0f * z[d][1];
+        a = a - xm;
+        a = a - xp;
+        a = a - ym;
+        a = a - yp;
+        a = a - z[d][0];
+        a = a - z[d][2];
+        a = a * ih2;
+        const bool kp = pin && ((fq >> d) & 1u);
+        const uint32_t xr = xy0 + (static_cast<uint32_t>(dy) << level);
+        const float gv = pair_f32(gpre[dy], xr, dx, cbits_of<CB>(G), G.w) - a;
+        const float y0 = pair_f32(ypre[dy], xr, dx, cbits_of<CB>(Y), Y.w);
+        rv[d] = kp ? gv : 0.0f;
+        yv[d] = kp ? y0 : 0.0f;
+      }
+      *reinterpret_cast<float2*>(yb + pos) = make_float2(yv[0], yv[1]);
+      *reinterpret_cast<float2*>(yb + pos + EXW) = make_float2(yv[2], yv[3]);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int pc = pos[k] + c;
-          float a = 6.0f * z[k][c][1];
-          a = a - zs[pc - 1];
-          a = a - zs[pc + 1];
-          a = a - zs[pc - EXW];
-          a = a - zs[pc + EXW];
-          a = a - z[k][c][0];
-          a = a - z[k][c][2];
-          a = a * ih2;
-          const bool keep = pin && ((fl[k] >> (kInnerCol + c)) & 1u);
-          const float gv = pair_f32(gpre[k], xy[k][0], c, cbits_of<CB>(G), G.w) - a;
-          const float y0 = pair_f32(ypre[k], xy[k][0], c, cbits_of<CB>(Y), Y.w);
-          rv[c] = keep ? gv : 0.0f;
-          yv[c] = keep ? y0 : 0.0f;
-        }
-        *reinterpret_cast<float2*>(yb + pos[k]) = make_float2(yv[0], yv[1]);
-        const bool sw = (fl[k] >> kSwap) & 1u;
+      for (int d = 0; d < 4; ++d) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int i = 0; i < S; ++i) r[d][i] = r[d][i + 1];
 #pragma unroll
-          for (int i = 0; i < S; ++i) r[k][c][i] = r[k][c][i + 1];
-#pragma unroll
-          for (int i = 0; i < S + 1; ++i) y[k][c][i] = y[k][c][i + 1];
-        }
-        r[k][0][S] = sw ? rv[1] : rv[0];
-        r[k][1][S] = sw ? rv[0] : rv[1];
-        y[k][0][S + 1] = sw ? yv[1] : yv[0];
-        y[k][1][S + 1] = sw ? yv[0] : yv[1];
+        for (int i = 0; i < S + 1; ++i) y[d][i] = y[d][i + 1];
+        r[d][S] = rv[d];
+        y[d][S + 1] = yv[d];
       }
       fetch_gy(j);
     }
-    // Post-smoothing: stage s on plane j - 1 - s.  The in-plane neighbours
-    // of stage s + 1 are loaded before stage s stores (they are the other
-    // colour of another plane), so the loads overlap the arithmetic.  As in
-    // the down sweep, stages run on every plane of the march.
-    auto active = [&](int s) {
-      const int p = j - 1 - s;
-      return p >= 1 && p < n;
-    };
-    float nb[2][K][4];
-    auto load_stage = [&](int s, float (&d)[K][4]) {
-      const int p = j - 1 - s;
-      const float* yb = lds + PAD + (2 + (p + 4 * NB) % NB) * PS;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const unsigned sw = (fl[k] >> kSwap) & 1u;
-        const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
-        d[k][0] = yb[pa - 1];
-        d[k][1] = yb[pa + 1];
-        d[k][2] = yb[pa - EXW];
-        d[k][3] = yb[pa + EXW];
+    // Post-smoothing: stage s on plane j - 1 - s updates the two nodes of
+    // class JP of the quad (d = 0, 3 or d = 1, 2); of the four in-plane
+    // neighbours of a node two are in the quad (registers) and two in the
+    // neighbouring quads (LDS, written by stage s - 1 at the previous step).
+    // As in the down sweep, stages run on every plane of the march.  Stage s
+    // matters only within S - s nodes of the output tile: waves whose quads
+    // all lie farther out skip it (their values there are never read by a
+    // node that matters).
+    constexpr int DA = JP == 0 ? 0 : 1, DB = JP == 0 ? 3 : 2;  // the two nodes of class JP
+    float nb[2][4];  // outer neighbours of node DA (x, y) and DB (x, y), stage s + 1 loaded ahead
+    auto load_stage = [&](int s, float (&v)[4]) {
+      const float* yb = ybuf(s);
+      if (JP == 0) {  // node 0: x - 1, y - 1; node 3: x + 1, y + 1
+        v[0] = yb[pos - 1];
+        v[1] = yb[pos - EXW];
+        v[2] = yb[pos + EXW + 2];
+        v[3] = yb[pos + 2 * EXW + 1];
+      } else {  // node 1: x + 1, y - 1; node 2: x - 1, y + 1
+        v[0] = yb[pos + 2];
+        v[1] = yb[pos - EXW + 1];
+        v[2] = yb[pos + EXW - 1];
+        v[3] = yb[pos + 2 * EXW];
       }
     };
-    load_stage(1, nb[0]);
+    auto stage_on = [&](int s) { return 64 * wv < cone_quads<H, TY>(S - s); };
+    if (stage_on(1)) load_stage(1, nb[0]);
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
-      if (s < S) load_stage(s + 1, nb[s & 1]);
-      const bool act = active(s);
+      if (!stage_on(s)) continue;
+      if (s < S && stage_on(s + 1)) load_stage(s + 1, nb[s & 1]);
       const int p = j - 1 - s;
+      if (p < 1 || p >= n) continue;  // a plane outside the level keeps its zeros
       const int iy = S + 1 - s;
-      float* yb = lds + PAD + (2 + (p + 4 * NB) % NB) * PS;
+      float* yb = ybuf(s);
+      const float* o = nb[(s - 1) & 1];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const unsigned sw = (fl[k] >> kSwap) & 1u;
-        const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
-        const float yc = y[k][SG][iy];
-        const float* d = nb[(s - 1) & 1][k];
+      for (int h = 0; h < 2; ++h) {
+        const int d = h == 0 ? DA : DB;
+        const int dx = d & 1, dy = d >> 1;
+        const float ox = o[2 * h], oy = o[2 * h + 1];
+        const float xm = dx ? y[d ^ 1][iy] : ox;
+        const float xp = dx ? ox : y[d ^ 1][iy];
+        const float ym = dy ? y[d ^ 2][iy] : oy;
+        const float yp = dy ? oy : y[d ^ 2][iy];
+        const float yc = y[d][iy];
         float a = 6.0f * yc;
-        a = a - d[0];
-        a = a - d[1];
-        a = a - d[2];
-        a = a - d[3];
-        a = a - y[k][SG][iy - 1];
-        a = a - y[k][SG][iy + 1];
+        a = a - xm;
+        a = a - xp;
+        a = a - ym;
+        a = a - yp;
+        a = a - y[d][iy - 1];
+        a = a - y[d][iy + 1];
         a = a * ih2;
-        const float rr = r[k][SG][S - s] - a;
+        const float rr = r[d][S - s] - a;
         const float v = yc + cp * rr;
-        const float yv = (act && ((fl[k] >> (kInnerSlot + SG)) & 1u)) ? v : yc;
-        y[k][SG][iy] = yv;
-        if (s < S) yb[pa] = yv;
+        const float yv = ((fq >> d) & 1u) ? v : yc;
+        y[d][iy] = yv;
+        if (s < S) yb[pos + dy * EXW + dx] = yv;
       }
     }
-    {
-      const int po = j - 1 - S;  // complete
-      if (po >= Z0 && po < Z0 + TZ) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const unsigned sw = (fl[k] >> kSwap) & 1u;
-#pragma unroll
-          for (int sg = 0; sg < 2; ++sg)
-            if ((fl[k] >> (kOutSlot + sg)) & 1u) outb[JP][oidx[k] + static_cast<int>(sg ^ sw)] = y[k][sg][1];
-        }
-      }
-    }
+    // plane j - 1 - S is complete: into the output buffer (read at the next
+    // step when the plane lies in the chunk; quads outside the output tile
+    // write the spare rows)
+    *reinterpret_cast<float2*>(&outb[JP][oidx]) = make_float2(y[0][1], y[1][1]);
+    *reinterpret_cast<float2*>(&outb[JP][oidx + kTX]) = make_float2(y[2][1], y[3][1]);
     if (JP == 0) cstore((j + 2) >> 1);
     __syncthreads();
   };
@@ -1131,8 +1199,8 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         a = a * ih2;
         const bool inside = p >= 1 && X0 + lane >= 1 && Y0 + rr >= 1;
         tv[t] = inside ? fpre[t] - a : 0.0;
-        m[t] = quant_f64<LB, GW64>(tv[t], Gout.w, lane, &e[t]);
       }
+      quant_f64_rows<LB, GW64, RPT>(tv, Gout.w, lane, m, e);
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
         const uint32_t xyr = (static_cast<uint32_t>(Y0 + wv + NW * t) << level) | static_cast<uint32_t>(X0);

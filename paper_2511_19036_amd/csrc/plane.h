@@ -235,6 +235,65 @@ __device__ __forceinline__ int64_t quant_f64(double v, int w, int lane, int* e_o
   return w <= 32 ? static_cast<int64_t>(static_cast<int>(q)) : static_cast<int64_t>(q);
 }
 
+// The same for R rows at once: every reduction step is taken for all rows
+// before the next, so that the rows' independent DPP operations fill each
+// other's wait states instead of no-ops.
+template <int LB, int R>
+__device__ __forceinline__ void block_max_rows(int (&a)[R], int lane) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = max(a[r], dpp_int<0xB1>(a[r]));
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = max(a[r], dpp_int<0x4E>(a[r]));
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = max(a[r], dpp_int<0x141>(a[r]));
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = max(a[r], dpp_int<0x140>(a[r]));
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = max(a[r], __builtin_amdgcn_update_dpp(INT32_MIN, a[r], 0x142, 0xA, 0xF, false));
+  if (LB == 6) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      a[r] = max(a[r], __builtin_amdgcn_update_dpp(INT32_MIN, a[r], 0x143, 0xC, 0xF, false));
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = __builtin_amdgcn_readlane(a[r], 63);
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int h0 = __builtin_amdgcn_readlane(a[r], 31), h1 = __builtin_amdgcn_readlane(a[r], 63);
+    a[r] = lane < 32 ? h0 : h1;
+  }
+}
+
+// quant_f32 / quant_f64 of R rows at once (the same codes and exponents).
+template <int LB, int R>
+__device__ __forceinline__ void quant_f32_rows(const float (&v)[R], int w, int lane, int (&m)[R], int (&e)[R]) {
+  int E[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) E[r] = lane_exp(v[r], exp_lim(v[r], w));
+  block_max_rows<LB, R>(E, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int Eq = E[r] == kNoExp ? 0 : E[r];
+    e[r] = E[r] == kNoExp ? kZeroExp : E[r];
+    m[r] = static_cast<int>(rintf(ldexpf(v[r], w - 1 - Eq)));
+  }
+}
+template <int LB, bool W64, int R>
+__device__ __forceinline__ void quant_f64_rows(const double (&v)[R], int w, int lane, int64_t (&m)[R], int (&e)[R]) {
+  int E[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) E[r] = lane_exp(v[r], exp_lim(v[r], w));
+  block_max_rows<LB, R>(E, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int Eq = E[r] == kNoExp ? 0 : E[r];
+    e[r] = E[r] == kNoExp ? kZeroExp : E[r];
+    const double q = rint(ldexp(v[r], w - 1 - Eq));
+    m[r] = !W64 || w <= 32 ? static_cast<int64_t>(static_cast<int>(q)) : static_cast<int64_t>(q);
+  }
+}
+
 // Store the codes of one row of 64 values (in-plane offset xy0, a multiple
 // of 64) held by the 64 lanes.  In the 12-bit container two values take
 // three bytes: each even lane joins its code with its odd neighbour's (one
