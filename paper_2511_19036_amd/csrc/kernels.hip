@@ -528,6 +528,94 @@ __global__ void __launch_bounds__(kSwNT) k_rbgs_sweep(const T* __restrict__ yin,
   }
 }
 
+// ------------------------------------------------ plain FP64 multigrid
+// The plain path keeps u, r and y per level and no further level arrays;
+// these kernels fuse what it would otherwise stage through one.
+
+// out = (T)(f - A u) on interior nodes (0 elsewhere), float64 arithmetic:
+// f is sampled from the finest node array (injection), u is the padded
+// float64 solution of level g.  The same values as k_inject, k_rhs_minus_A
+// <double> and k_convert<double, T>; the squares of the float64 residual
+// go to the monitor slots, non-finite values to nonfinite.
+template <typename T, bool DIFF>
+__global__ void __launch_bounds__(kThreads) k_residual_full(const double* __restrict__ f, int Lfull,
+                                                            const double* __restrict__ u,
+                                                            const double* __restrict__ kap, Geom g, double inv_h2,
+                                                            T* __restrict__ out, int* nonfinite, double* mon) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  double t = 0.0;
+  if (idx < g.size) {
+    int i, j, k;
+    unflatten(g, idx, i, j, k);
+    if (is_interior(g, i, j, k)) {
+      const int64_t N = (int64_t{1} << Lfull) + 1, st = int64_t{1} << (Lfull - g.level);
+      const int64_t fi = g.dim == 3 ? ((k * st) * N + j * st) * N + i * st : (j * st) * N + i * st;
+      const double au = DIFF ? diffusion_at<double>(u, kap, g, i, j, k, inv_h2, nullptr)
+                             : apply_A<double>(u, nullptr, g, i, j, k, inv_h2);
+      t = f[fi] - au;
+    }
+    out[idx] = static_cast<T>(t);
+    if (!isfinite(t)) atomicOr(nonfinite, 1);
+  }
+  monitor_add(mon, t * t);
+}
+
+// rc = R (r - A y) (full weighting of the residual, formed on the fly at
+// the 3^d fine nodes of each coarse node): the same values as
+// k_rhs_minus_A<T> followed by k_restrict<T>.
+template <typename T, bool DIFF>
+__global__ void __launch_bounds__(kThreads) k_restrict_residual(const T* __restrict__ r, const T* __restrict__ y,
+                                                                const T* __restrict__ kap, Geom gc, Geom gf,
+                                                                T inv_h2, T* __restrict__ rc) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= gc.size) return;
+  int I, J, K;
+  unflatten(gc, idx, I, J, K);
+  if (!is_interior(gc, I, J, K)) {
+    rc[idx] = T(0);
+    return;
+  }
+  T s = T(0);
+  bool first = true;
+  const int z0 = gc.dim == 3 ? -1 : 0, z1 = gc.dim == 3 ? 1 : 0;
+  for (int oz = z0; oz <= z1; ++oz) {
+    const double wz = gc.dim == 3 ? (oz == 0 ? 0.5 : 0.25) : 1.0;
+    for (int oy = -1; oy <= 1; ++oy) {
+      const double wy = oy == 0 ? 0.5 : 0.25;
+      for (int ox = -1; ox <= 1; ++ox) {
+        const double wx = ox == 0 ? 0.5 : 0.25;
+        const int fi = 2 * I + ox, fj = 2 * J + oy, fk = gc.dim == 3 ? 2 * K + oz : 0;
+        const T au = DIFF ? diffusion_at<T>(y, kap, gf, fi, fj, fk, inv_h2, nullptr)
+                          : apply_A<T>(y, nullptr, gf, fi, fj, fk, inv_h2);
+        const T res = r[flat(gf, fi, fj, fk)] - au;  // every fine node here is interior
+        const T t = static_cast<T>(wz * wy * wx) * res;
+        s = first ? t : s + t;
+        first = false;
+      }
+    }
+  }
+  rc[idx] = s;
+}
+
+// y = y + P yc in place (k_prolong and k_add in one pass).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_prolong_add(const T* __restrict__ coarse, Geom gf, Geom gc,
+                                                          T* __restrict__ y) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= gf.size) return;
+  int i, j, k;
+  unflatten(gf, idx, i, j, k);
+  y[idx] = y[idx] + prolong_at(coarse, gc, i, j, k);
+}
+
+// u = u + (double) y (k_convert<T, double> and k_add<double> in one pass).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_add_correction(double* __restrict__ u, const T* __restrict__ y,
+                                                             int64_t n) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx < n) u[idx] = u[idx] + static_cast<double>(y[idx]);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_add(const T* __restrict__ a, const T* __restrict__ b,
                                                   T* __restrict__ out, int64_t n) {
@@ -890,6 +978,39 @@ void launch_coarsen_kappa(const double* fine, const Geom& gc, const Geom& gf, do
 void launch_check_positive(const double* x, int64_t n, int* flags, hipStream_t st) {
   CMG_TLAUNCH("k_check_positive", 8.0 * n, k_check_positive, n, st, x, n, flags);
 }
+template <typename T>
+void launch_residual_full(const double* f, int Lfull, const double* u, const double* kap, const Geom& g,
+                          double inv_h2, T* out, int* nonfinite, double* mon, hipStream_t st) {
+  const double b = 8.0 * g.size * (kap != nullptr ? 3.0 : 2.0) + sizeof(T) * static_cast<double>(g.size);
+  if (kap != nullptr)
+    CMG_TLAUNCH(tname("k_residual_full", TName<T>::s).c_str(), b, (k_residual_full<T, true>), g.size, st, f, Lfull,
+                u, kap, g, inv_h2, out, nonfinite, mon);
+  else
+    CMG_TLAUNCH(tname("k_residual_full", TName<T>::s).c_str(), b, (k_residual_full<T, false>), g.size, st, f, Lfull,
+                u, kap, g, inv_h2, out, nonfinite, mon);
+}
+template <typename T>
+void launch_restrict_residual(const T* r, const T* y, const T* kap, const Geom& gc, const Geom& gf, T inv_h2, T* rc,
+                              hipStream_t st) {
+  const double b = sizeof(T) * (2.0 * gf.size + gc.size) + (kap != nullptr ? sizeof(T) * gf.size : 0.0);
+  if (kap != nullptr)
+    CMG_TLAUNCH(tname("k_restrict_residual", TName<T>::s).c_str(), b, (k_restrict_residual<T, true>), gc.size, st, r,
+                y, kap, gc, gf, inv_h2, rc);
+  else
+    CMG_TLAUNCH(tname("k_restrict_residual", TName<T>::s).c_str(), b, (k_restrict_residual<T, false>), gc.size, st, r,
+                y, kap, gc, gf, inv_h2, rc);
+}
+template <typename T>
+void launch_prolong_add(const T* coarse, const Geom& gf, const Geom& gc, T* y, hipStream_t st) {
+  CMG_TLAUNCH(tname("k_prolong_add", TName<T>::s).c_str(), (2.0 * gf.size + gc.size) * sizeof(T), k_prolong_add<T>,
+              gf.size, st, coarse, gf, gc, y);
+}
+template <typename T>
+void launch_add_correction(double* u, const T* y, int64_t n, hipStream_t st) {
+  CMG_TLAUNCH(tname("k_add_correction", TName<T>::s).c_str(), (16.0 + sizeof(T)) * n, k_add_correction<T>, n, st, u,
+              y, n);
+}
+
 void launch_check_finite(const double* x, int64_t n, int* flags, hipStream_t st) {
   CMG_TLAUNCH("k_check_finite", 8.0 * n, k_check_finite, n, st, x, n, flags);
 }
@@ -931,6 +1052,12 @@ void launch_monitor_check(double* mon, int* flags, int level, double growth, hip
   template bool launch_rbgs_sweep<T>(const T*, const SecRef*, T*, const T*, const T*, const Geom&, T, T, bool,    \
                                      hipStream_t);                                                              \
   template void launch_add<T>(const T*, const T*, T*, int64_t, hipStream_t);                            \
+  template void launch_residual_full<T>(const double*, int, const double*, const double*, const Geom&, double, T*, \
+                                        int*, double*, hipStream_t);                                           \
+  template void launch_restrict_residual<T>(const T*, const T*, const T*, const Geom&, const Geom&, T, T*,       \
+                                            hipStream_t);                                                      \
+  template void launch_prolong_add<T>(const T*, const Geom&, const Geom&, T*, hipStream_t);                   \
+  template void launch_add_correction<T>(double*, const T*, int64_t, hipStream_t);                            \
   template void launch_fill<T>(T*, T, int64_t, hipStream_t);
 CMG_INST_T(float)
 CMG_INST_T(double)

@@ -60,6 +60,17 @@ template <typename T>
 bool launch_rbgs_sweep(const T* yin, const SecRef* ysec, T* yout, const T* rhs, const T* kap, const Geom& g, T inv_h2,
                        T cpois, bool zero, hipStream_t st);
 template <typename T> void launch_add(const T* a, const T* b, T* out, int64_t n, hipStream_t st);
+// Plain FP64 multigrid: out = (T)(f - A u) with f sampled from the finest
+// node array (monitor slots and non-finite flag fed); rc = R (r - A y);
+// y += P yc in place; u += (double) y.
+template <typename T>
+void launch_residual_full(const double* f, int Lfull, const double* u, const double* kap, const Geom& g,
+                          double inv_h2, T* out, int* nonfinite, double* mon, hipStream_t st);
+template <typename T>
+void launch_restrict_residual(const T* r, const T* y, const T* kap, const Geom& gc, const Geom& gf, T inv_h2, T* rc,
+                              hipStream_t st);
+template <typename T> void launch_prolong_add(const T* coarse, const Geom& gf, const Geom& gc, T* y, hipStream_t st);
+template <typename T> void launch_add_correction(double* u, const T* y, int64_t n, hipStream_t st);
 template <typename T> void launch_fill(T* x, T v, int64_t n, hipStream_t st);
 template <typename S, typename D> void launch_convert(const S* a, D* b, int64_t n, hipStream_t st);
 

@@ -96,6 +96,7 @@ struct cmg_ctx_s {
   int Lp = -1;
   int* flags = nullptr;   // [0] non-positive kappa, [1] non-finite value, [2] FMG level that diverged
   double* mon = nullptr;  // IR residual monitor (device.h: slots, smallest and last sum of squares)
+  double* pu[2] = {nullptr, nullptr};  // plain path: float64 FMG solution, levels L, L-2, ... / L-1, L-3, ...
   bool mon_fresh = true;  // the next IR residual is the first one on its FMG level
   bool dead = false;
   bool timing_on = false;
@@ -226,14 +227,23 @@ void setup_levels(cmg_ctx c, const double* kappa) {
       if (v1res || l == lc || (c->chain() && l < L)) D.t64 = static_cast<double*>(c->alloc(n * 8, f64c));
       if (v1res || l == lc) D.f64 = static_cast<double*>(c->alloc(n * 8, f64c));
     } else {
+      // u, r and y per level (the V-cycle runs in place, with fused
+      // residual-restriction and prolongation-add kernels); weighted Jacobi
+      // needs a second y array; the float64 solution of the current FMG
+      // level lives in pu[(L - level) & 1]
       D.yf = c->alloc(n * tsz, work);
-      D.zf = c->alloc(n * tsz, work);
       D.rf = c->alloc(n * tsz, work);
-      D.uh = static_cast<double*>(c->alloc(n * 8, f64c));
-      D.t64 = static_cast<double*>(c->alloc(n * 8, f64c));
-      D.f64 = static_cast<double*>(c->alloc(n * 8, f64c));
+      if (c->o.smoother == CMG_WJACOBI) D.zf = c->alloc(n * tsz, work);
+      if (l == lc) {
+        D.t64 = static_cast<double*>(c->alloc(n * 8, kCoarse64));
+        D.f64 = static_cast<double*>(c->alloc(n * 8, kCoarse64));
+      }
     }
     if (l == lc) D.s64 = static_cast<double*>(c->alloc(n * 8, kCoarse64));
+  }
+  if (!c->compact()) {
+    c->pu[0] = static_cast<double*>(c->alloc(static_cast<size_t>(c->lv[L].g.size) * 8, kFineWork));
+    c->pu[1] = static_cast<double*>(c->alloc(static_cast<size_t>(c->lv[L - 1].g.size) * 8, kCoarse64));
   }
   c->flags = static_cast<int*>(c->alloc(64, kOther));
   c->mon = static_cast<double*>(c->alloc(kMonDoubles * 8, kOther));
@@ -274,7 +284,8 @@ const T* kapT(cmg_ctx c, int l) {
 }
 const double* kap64(cmg_ctx c, int l) { return c->p.op == CMG_DIFFUSION ? c->lv[l].kap64 : nullptr; }
 
-// nu sweeps of the smoother on A y = rhs (level l), in place on y.
+// nu sweeps of the smoother on A y = rhs (level l), in place on y.  Without
+// a scratch array red-black Gauss-Seidel runs one launch per half-sweep.
 template <typename T>
 void smooth(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) {
   LevelData& D = c->lv[l];
@@ -283,7 +294,7 @@ void smooth(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) {
   const int d = c->p.dim;
   if (c->o.smoother == CMG_RBGS) {
     const T cp = static_cast<T>(1.0 / (2.0 * d * ih2));
-    if (nu > 0 && d == 3 && D.g.n >= 64) {  // one launch per sweep, out of place between y and scratch
+    if (nu > 0 && d == 3 && D.g.n >= 64 && scratch != nullptr) {  // one launch per sweep, out of place
       T* a = y;
       T* b = scratch;
       for (int s = 0; s < nu; ++s) {
@@ -328,7 +339,7 @@ void smooth_from_zero(cmg_ctx c, int l, T* y, const T* rhs, T* scratch, int nu) 
   const double ih2 = inv_h2(l);
   const T* kap = kapT<T>(c, l);
   const T cp = static_cast<T>(1.0 / (2.0 * c->p.dim * ih2));
-  if (c->p.dim == 3 && D.g.n >= 64) {  // one launch per sweep, the first from zero; the last writes y
+  if (c->p.dim == 3 && D.g.n >= 64 && scratch != nullptr) {  // one launch per sweep, the first from zero
     T* a = (nu & 1) ? scratch : y;
     T* b = (nu & 1) ? y : scratch;
     for (int s = 0; s < nu; ++s) {
@@ -622,7 +633,9 @@ void compact_fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
 }
 
 // Correction-scheme V(nu1, nu2) cycle (supplement Sec. SM1.1.1) on rf[Lp];
-// result in yf[Lp].
+// result in yf[Lp].  In place on the level arrays r and y: red-black sweeps
+// one half-sweep per launch, the restriction of the residual and the
+// prolongation-add each in one kernel (weighted Jacobi alternates with zf).
 template <typename T>
 void cs_vcycle(cmg_ctx c, int Lp) {
   const int lc = c->lc();
@@ -632,10 +645,9 @@ void cs_vcycle(cmg_ctx c, int Lp) {
     LevelData& C = c->lv[l - 1];
     T* yf = static_cast<T*>(F.yf);
     T* rf = static_cast<T*>(F.rf);
-    T* zf = static_cast<T*>(F.zf);
-    smooth_from_zero<T>(c, l, yf, rf, zf, c->o.nu_pre);
-    launch_rhs_minus_A<T>(rf, yf, kapT<T>(c, l), F.g, static_cast<T>(inv_h2(l)), zf, st);
-    launch_restrict<T>(zf, C.g, F.g, static_cast<T*>(C.rf), st);
+    smooth_from_zero<T>(c, l, yf, rf, static_cast<T*>(F.zf), c->o.nu_pre);
+    launch_restrict_residual<T>(rf, yf, kapT<T>(c, l), C.g, F.g, static_cast<T>(inv_h2(l)), static_cast<T*>(C.rf),
+                                st);
     KCK();
   }
   LevelData& B = c->lv[lc];
@@ -647,33 +659,33 @@ void cs_vcycle(cmg_ctx c, int Lp) {
     LevelData& F = c->lv[l];
     LevelData& C = c->lv[l - 1];
     T* yf = static_cast<T*>(F.yf);
-    T* zf = static_cast<T*>(F.zf);
-    launch_prolong<T>(static_cast<T*>(C.yf), F.g, C.g, zf, st);
-    launch_add<T>(yf, zf, yf, F.g.size, st);
+    launch_prolong_add<T>(static_cast<T*>(C.yf), F.g, C.g, yf, st);
     KCK();
-    smooth<T>(c, l, yf, static_cast<T*>(F.rf), zf, c->o.nu_post);
+    smooth<T>(c, l, yf, static_cast<T*>(F.rf), static_cast<T*>(F.zf), c->o.nu_post);
   }
 }
 
+// Plain FMG (Alg. SM2) on float64 standard vectors: the solution of FMG
+// level l lives in pu[(L - l) & 1], so that the prolongation to the next
+// level reads one buffer and writes the other.
 template <typename T>
 void plain_fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
   const int L = c->p.L, lc = c->lc();
   hipStream_t s = c->st;
+  auto ubuf = [&](int level) { return c->pu[(L - level) & 1]; };
   LevelData& B = c->lv[lc];
   launch_inject(f, L, B.g, B.f64, s);
-  launch_coarse_single(B.f64, kap64(c, lc), B.g, inv_h2(lc), B.uh, s);
+  launch_coarse_single(B.f64, kap64(c, lc), B.g, inv_h2(lc), ubuf(lc), s);
   KCK();
   for (int level = lc + 1; level <= L; ++level) {
     LevelData& F = c->lv[level];
-    launch_prolong<double>(c->lv[level - 1].uh, F.g, c->lv[level - 1].g, F.uh, s);
-    launch_inject(f, L, F.g, F.f64, s);
+    launch_prolong<double>(ubuf(level - 1), F.g, c->lv[level - 1].g, ubuf(level), s);
     KCK();
     const int iters = c->o.ir_iters + (level == L ? c->o.final_iters : 0);
     for (int it = 0; it < iters; ++it) {
-      launch_rhs_minus_A<double>(F.f64, F.uh, kap64(c, level), F.g, inv_h2(level), F.t64, s);
-      launch_check_finite(F.t64, F.g.size, c->flags, s);
       launch_monitor_reset(c->mon, it == 0, s);
-      launch_sumsq(F.t64, F.g.size, c->mon, s);
+      launch_residual_full<T>(f, L, ubuf(level), kap64(c, level), F.g, inv_h2(level), static_cast<T*>(F.rf),
+                              c->flags + 1, c->mon, s);
       launch_monitor_check(c->mon, c->flags, level, kDivergeGrowth, s);
       KCK();
       if (st != nullptr && st->record && st->count < 256) {
@@ -682,14 +694,12 @@ void plain_fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
         HIPCK(hipStreamSynchronize(s));
         st->residual_norm[st->count++] = std::sqrt(h);
       }
-      launch_convert<double, T>(F.t64, static_cast<T*>(F.rf), F.g.size, s);
       cs_vcycle<T>(c, level);
-      launch_convert<T, double>(static_cast<T*>(F.yf), F.t64, F.g.size, s);
-      launch_add<double>(F.uh, F.t64, F.uh, F.g.size, s);
+      launch_add_correction<T>(ubuf(level), static_cast<T*>(F.yf), F.g.size, s);
       KCK();
     }
   }
-  launch_to_full(c->lv[L].uh, c->lv[L].g, u, s);
+  launch_to_full(ubuf(L), c->lv[L].g, u, s);
   KCK();
 }
 
@@ -873,18 +883,22 @@ cmg_status cmg_vcycle(cmg_ctx c, const double* r, double* y) {
         c->Lp = L;
         if (f32) vcycle_correct<float>(c, L); else vcycle_correct<double>(c, L);
         decode_to_full(c, L, y + b * M);
-      } else {
-        launch_inject(r + b * M, L, F.g, F.t64, c->st);
+      } else {  // r - A 0 = r sampled into the level array, then y from zero
+        double* u0 = c->pu[0];
+        launch_fill<double>(u0, 0.0, F.g.size, c->st);
+        launch_monitor_reset(c->mon, true, c->st);
         if (f32) {
-          launch_convert<double, float>(F.t64, static_cast<float*>(F.rf), F.g.size, c->st);
+          launch_residual_full<float>(r + b * M, L, u0, nullptr, F.g, inv_h2(L), static_cast<float*>(F.rf),
+                                      c->flags + 1, c->mon, c->st);
           cs_vcycle<float>(c, L);
-          launch_convert<float, double>(static_cast<float*>(F.yf), F.uh, F.g.size, c->st);
+          launch_add_correction<float>(u0, static_cast<float*>(F.yf), F.g.size, c->st);
         } else {
-          launch_convert<double, double>(F.t64, static_cast<double*>(F.rf), F.g.size, c->st);
+          launch_residual_full<double>(r + b * M, L, u0, nullptr, F.g, inv_h2(L), static_cast<double*>(F.rf),
+                                       c->flags + 1, c->mon, c->st);
           cs_vcycle<double>(c, L);
-          launch_convert<double, double>(static_cast<double*>(F.yf), F.uh, F.g.size, c->st);
+          launch_add_correction<double>(u0, static_cast<double*>(F.yf), F.g.size, c->st);
         }
-        launch_to_full(F.uh, F.g, y + b * M, c->st);
+        launch_to_full(u0, F.g, y + b * M, c->st);
       }
       KCK();
     }
