@@ -104,11 +104,14 @@ def header_symbols() -> list[str]:
     return sorted(set(re.findall(r"^\s*(?:cmg_status|int64_t|const char\*)\s+(cmg_\w+)\s*\(", text, re.M)))
 
 
-def load(path: str = LIB_PATH):
-    """Load ``libcmg.so`` and declare its signatures (raises if absent)."""
+def load(path: str | None = None):
+    """Load ``libcmg.so`` (or the build named by the environment variable
+    ``CMG_LIBRARY``, e.g. the host-sanitized one) and declare its signatures
+    (raises if absent)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("CMG_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
     lib = C.CDLL(path)
