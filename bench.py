@@ -113,6 +113,108 @@ def _by_kernel(rows):
     return sorted(acc.values(), key=lambda r: -r["ms"])
 
 
+def _family(kernel_name):
+    """The library's timing name of a fused level kernel from a profiler
+    name ("void cmg::k_up_smooth<4, 32, 768, 6, false, 16>(...)" ->
+    "k_up_smooth<4>"), with its container template argument; (None, None)
+    for other kernels."""
+    import re
+    m = re.search(r"cmg::(k_up_smooth|k_down_smooth|k_ir_residual|k_resid_restrict|k_decode_full)<([^>]*)>",
+                  kernel_name)
+    if not m:
+        return None, None
+    name, args = m.group(1), [a.strip() for a in m.group(2).split(",")]
+    if name in ("k_up_smooth", "k_down_smooth"):
+        name = f"{name}<{args[0]}>"
+    elif name == "k_decode_full" and args[2] == "true":
+        name = "k_decode_level"
+    return name, int(args[-1])
+
+
+def summarize_counters(d, L, bits, block=64):
+    """Markdown rows of the counter passes in directory d (rocprofv3 csv
+    output of bench.py --pmc-pass: fetch_, write_ and valu_
+    counter_collection.csv): per fused kernel family, HBM bytes per launch
+    over the measured solve (after the calibration copy), FETCH_SIZE and
+    WRITE_SIZE scaled by what they read for the runtime's copy of
+    CALIB_BYTES; and the same for the launches on the finest level (the
+    instantiation with the finest level's container), beside the per-DoF
+    model's bytes; then the VALU/SALU/LDS instruction counts per launch."""
+    import csv
+    import collections
+
+    def load(name):
+        path = os.path.join(d, f"{name}_counter_collection.csv")
+        return list(csv.DictReader(open(path))) if os.path.exists(path) else []
+
+    def measured(rows):
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        calib = max(copies, key=lambda r: float(r["Counter_Value"]))
+        return calib, [r for r in rows if int(r["Dispatch_Id"]) > int(calib["Dispatch_Id"])]
+
+    cbits = 8 if bits <= 8 else 12 if bits <= 12 else 16 if bits <= 16 else 32
+    dofs = ((1 << L) - 1) ** 3
+    out = []
+    per = {}
+    for pas in ("fetch", "write"):
+        rows = load(pas)
+        calib, rows = measured(rows)
+        scale = CALIB_BYTES / (float(calib["Counter_Value"]) * 1024.0)
+        acc = collections.defaultdict(lambda: [0, 0.0])
+        for r in rows:
+            fam, cb = _family(r["Kernel_Name"])
+            if fam is None:
+                continue
+            for key in ([fam] + ([f"{fam}@{L}"] if cb == cbits and fam != "k_decode_level" else [])):
+                acc[key][0] += 1
+                acc[key][1] += float(r["Counter_Value"])
+        per[pas] = (scale, float(calib["Counter_Value"]), acc)
+    fs, fcal, fa = per["fetch"]
+    ws, wcal, wa = per["write"]
+    out.append(f"Calibration: the runtime's device-to-device copy of {CALIB_BYTES} bytes reads FETCH_SIZE = "
+               f"{fcal:.1f} KiB and WRITE_SIZE = {wcal:.1f} KiB, so FETCH_SIZE is scaled by {fs:.4f} and "
+               f"WRITE_SIZE by {ws:.4f} to give bytes.")
+    out.append("")
+    out.append("| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | model bytes | HBM bytes (calibrated) "
+               "| HBM / model |")
+    out.append("|---|---:|---:|---:|---:|---:|---:|")
+    for key in sorted(fa, key=lambda k: ("@" in k, k)):
+        n, fkib = fa[key]
+        wkib = wa[key][1] if key in wa else 0.0
+        fk, wk = fkib / n, wkib / n
+        hbm = fk * 1024.0 * fs + wk * 1024.0 * ws
+        if "@" in key:
+            model = model_bytes_per_dof(key.partition("@")[0], bits, block) * dofs
+            out.append(f"| `{key}` | {n} | {fk:.1f} | {wk:.1f} | {model:.4e} | {hbm:.4e} | {hbm / model:.2f} |")
+        else:
+            out.append(f"| `{key}` | {n} | {fk:.1f} | {wk:.1f} | - | {hbm:.4e} | - |")
+    vrows = load("valu")
+    if vrows:
+        vrows = measured(vrows)[1] if any("copyBuffer" in r["Kernel_Name"] for r in vrows) else vrows
+        ids = sorted({int(r["Dispatch_Id"]) for r in vrows})
+        half = ids[len(ids) // 2]  # the second (measured) solve of the pass
+        acc = collections.defaultdict(lambda: collections.defaultdict(float))
+        cnt = collections.defaultdict(set)
+        for r in vrows:
+            if int(r["Dispatch_Id"]) < half:
+                continue
+            fam, cb = _family(r["Kernel_Name"])
+            if fam is None:
+                continue
+            for key in ([fam] + ([f"{fam}@{L}"] if cb == cbits and fam != "k_decode_level" else [])):
+                acc[key][r["Counter_Name"]] += float(r["Counter_Value"])
+                cnt[key].add(int(r["Dispatch_Id"]))
+        out.append("")
+        out.append("| kernel | launches | SQ_INSTS_VALU | SQ_INSTS_SALU | SQ_INSTS_LDS | SQ_WAVES |")
+        out.append("|---|---:|---:|---:|---:|---:|")
+        for key in sorted(acc, key=lambda k: ("@" in k, k)):
+            n = len(cnt[key])
+            c = acc[key]
+            out.append(f"| `{key}` | {n} | {c['SQ_INSTS_VALU'] / n:.4e} | {c['SQ_INSTS_SALU'] / n:.4e} | "
+                       f"{c['SQ_INSTS_LDS'] / n:.4e} | {c['SQ_WAVES'] / n:.4e} |")
+    return "\n".join(out)
+
+
 def discretisation_check(u, L, dim=3):
     """Errors of u against the closed-form discrete solution of the sine part.
 
@@ -417,7 +519,12 @@ def main():
                     help="for counter runs: one warm-up solve, a calibration copy of 1 GiB, one solve; no JSON")
     ap.add_argument("--only-workloads", action="store_true",
                     help="for kernel traces: time only the other workloads and print their figures as JSON")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="print the markdown tables of the --pmc-pass counter csv files in DIR (no GPU)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.L, args.bits))
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the solver is a single-GPU level sweep); use --gpus 1", file=sys.stderr)
