@@ -1035,31 +1035,36 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
 // also decode one node of the one-node x-y halo.  Every plane of u goes
 // through a ring of three LDS planes, so that a single barrier per step
 // separates the writes of plane j from the reads of plane j - 2.
-template <int TY, int NT, int LB, bool HI, bool GW64, int CB>
+template <int TY, int NT, int XW, int LB, bool HI, bool GW64, int CB>
 __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __restrict__ uc,
                                                     const double* __restrict__ f, int Lfull, int level, int levelc,
                                                     double ih2, PSec Gout, int TZ, int* nonfinite, double* sumsq) {
-  constexpr int NW = NT / 64, RPT = TY / NW;
-  static_assert(TY % NW == 0, "whole rows per wave");
-  constexpr int EXW = kTX + 2, LPL = EXW * (TY + 2);
+  // XW blocks of 64 side by side: wave wv owns block wv % XW of rows
+  // wv / XW + NWR t
+  constexpr int TXW = kTX * XW, NW = NT / 64, NWR = NW / XW, RPT = TY / NWR;
+  static_assert(NW % XW == 0 && TY % NWR == 0, "whole rows per wave");
+  constexpr int EXW = TXW + 2, LPL = EXW * (TY + 2);
   constexpr int NHALO = 2 * EXW + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread");
-  constexpr int NC = 4, CW = kTX / 2 + 3, CH = TY / 2 + 3, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
+  constexpr int NC = 4, CW = TXW / 2 + 3, CH = TY / 2 + 3, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
   __shared__ double us[3 * LPL];
   __shared__ double cs[NC * CPL];
   const int tid = threadIdx.x;
   int lane = tid & 63;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int xl = lane + kTX * (tid / 64 % XW);                          // tile-local x of the lane
+  int wr = __builtin_amdgcn_readfirstlane(tid / 64 / XW);          // first row of the wave
+  int xb = __builtin_amdgcn_readfirstlane(kTX * (tid / 64 % XW));  // tile-local x of its block
   int bx, by, bz;
-  tile_of((1 << level) / kTX, (1 << level) / TY, bx, by, bz);
-  int X0 = bx * kTX, Y0 = by * TY;
+  tile_of((1 << level) / TXW, (1 << level) / TY, bx, by, bz);
+  int X0 = bx * TXW, Y0 = by * TY;
   const int Z0 = bz * TZ;
   const int n = 1 << level, nc = 1 << levelc;
   const int CX0 = (X0 >> 1) - 1, CY0 = (Y0 >> 1) - 1;
   const int64_t N = (static_cast<int64_t>(1) << Lfull) + 1;
   const int fst = 1 << (Lfull - level);
 
-  // halo node of this thread (tile-local hx in -1..64, hy in -1..TY)
+  // halo node of this thread (tile-local hx in -1..TXW, hy in -1..TY)
   int hx = 0, hy = 0;
   if (tid < EXW) {
     hy = -1;
@@ -1071,7 +1076,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
     hx = -1;
     hy = tid - 2 * EXW;
   } else {
-    hx = kTX;
+    hx = TXW;
     hy = tid - 2 * EXW - TY;
   }
   const bool has_h = tid < NHALO;
@@ -1089,7 +1094,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
 #pragma unroll
   for (int t = 0; t < RPT; ++t) u[t][0] = u[t][1] = u[t][2] = 0.0;
   auto xy_own = [&](int t) {
-    return (static_cast<uint32_t>(Y0 + wv + NW * t) << level) | static_cast<uint32_t>(X0 + lane);
+    return (static_cast<uint32_t>(Y0 + wr + NWR * t) << level) | static_cast<uint32_t>(X0 + xl);
   };
   auto cfetch = [&](int cz) {
     const bool zin = cz >= 0 && cz < nc;
@@ -1130,7 +1135,7 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
     const double* fp = f + static_cast<uint64_t>(min(max(p, 0), n - 1)) * fst * N * N;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
-      const int gx = X0 + lane, gy = Y0 + wv + NW * t;
+      const int gx = X0 + xl, gy = Y0 + wr + NWR * t;
       const double v =
           fp[static_cast<uint32_t>(gy * fst) * static_cast<uint32_t>(N) + static_cast<uint32_t>(gx * fst)];
       fpre[t] = v;  // boundary values are read but not used (the residual zeroes them)
@@ -1141,6 +1146,9 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
   auto step = [&](auto jpc, const int j) {
     constexpr int JP = decltype(jpc)::value;
     opaque(lane);
+    opaque(xl);
+    opaque_s(wr);
+    opaque_s(xb);
     opaque(xyh);
     opaque(hpos);
     opaque(hci);
@@ -1159,14 +1167,14 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
       double* ub = us + ((j + 3) % 3) * LPL;
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const int rr = wv + NW * t;
+        const int rr = wr + NWR * t;
         u[t][0] = u[t][1];
         u[t][1] = u[t][2];
-        const int ci = ((rr >> 1) + 1) * CW + (lane >> 1) + 1;
+        const int ci = ((rr >> 1) + 1) * CW + (xl >> 1) + 1;
         const double v = raw_f64<may64<CB, HI>()>(upre[t], xy_own(t), cbits_of<CB>(U), U.w) +
                          prolong_node<double, JP, CW, true>(c0, c1, ci, lane & 1, rr & 1);
         u[t][2] = pin ? v : 0.0;
-        ub[(rr + 1) * EXW + lane + 1] = u[t][2];
+        ub[(rr + 1) * EXW + xl + 1] = u[t][2];
       }
       if (has_h) {
         const double v =
@@ -1187,8 +1195,8 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
       int e[RPT];
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const int rr = wv + NW * t;
-        const int c = (rr + 1) * EXW + lane + 1;
+        const int rr = wr + NWR * t;
+        const int c = (rr + 1) * EXW + xl + 1;
         double a = 6.0 * u[t][1];
         a = a - ua[c - 1];
         a = a - ua[c + 1];
@@ -1197,19 +1205,19 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         a = a - u[t][0];
         a = a - u[t][2];
         a = a * ih2;
-        const bool inside = p >= 1 && X0 + lane >= 1 && Y0 + rr >= 1;
+        const bool inside = p >= 1 && X0 + xl >= 1 && Y0 + rr >= 1;
         tv[t] = inside ? fpre[t] - a : 0.0;
       }
       quant_f64_rows<LB, GW64, RPT>(tv, Gout.w, lane, m, e);
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const uint32_t xyr = (static_cast<uint32_t>(Y0 + wv + NW * t) << level) | static_cast<uint32_t>(X0);
+        const uint32_t xyr = (static_cast<uint32_t>(Y0 + wr + NWR * t) << level) | static_cast<uint32_t>(X0 + xb);
         store_row(gq.c, xyr, lane, m[t], cbits_of<CB>(Gout));
       }
       if ((lane & ((1 << LB) - 1)) == 0) {
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
-          const uint32_t xyr = (static_cast<uint32_t>(Y0 + wv + NW * t) << level) | static_cast<uint32_t>(X0);
+          const uint32_t xyr = (static_cast<uint32_t>(Y0 + wr + NWR * t) << level) | static_cast<uint32_t>(X0 + xb);
           gq.e[(xyr + lane) >> LB] = static_cast<int16_t>(e[t]);
         }
       }
@@ -1520,19 +1528,27 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
                        double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st) {
   if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64) || Gout.B != U.B) return false;
-  const int tiles = (g.n / kTX) * (g.n / kResTY);
-  const dim3 block(kResNT);
+  // tiles of two blocks side by side from 128 nodes per row: half the
+  // partial 128-byte lines at the x-edges of the rows of f and the halos
+  const bool wide = g.n >= 2 * kTX;
+  const int tiles = (g.n / (wide ? 2 * kTX : kTX)) * (g.n / kResTY);
   const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size + sec_b(Gout);
   const PSec pu = psec(U, g), pg = psec(Gout, g);
   const bool hi = U.cbits == 12 || U.cbits == 64, g64 = Gout.cbits == 64;
   const int cb = common_cb({&U, &Gout});
-#define CMG_IR(LB_, HI_, GW_, CB_)                                                                                 \
+#define CMG_IRX(XW_, LB_, HI_, GW_, CB_)                                                                            \
   do {                                                                                                             \
-    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_ir_residual<kResTY, kResNT, LB_, HI_, GW_, CB_>), \
-                                kResNT, g.n, tiles, 1, 2, 4);                                                         \
-    CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, kResNT, LB_, HI_, GW_, CB_>),                         \
-                dim3(tiles * (g.n / tz)), block, st, pu, uc, f, Lfull, g.level, gc.level, ih2, pg, tz, nonfinite,  \
-                sumsq);                                                                                            \
+    constexpr int nt_ = kResNT * (XW_);                                                                            \
+    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_ir_residual<kResTY, nt_, XW_, LB_, HI_, GW_, CB_>), \
+                                nt_, g.n, tiles, 1, 2, 4);                                                         \
+    CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, nt_, XW_, LB_, HI_, GW_, CB_>),                     \
+                dim3(tiles * (g.n / tz)), dim3(nt_), st, pu, uc, f, Lfull, g.level, gc.level, ih2, pg, tz,         \
+                nonfinite, sumsq);                                                                                 \
+  } while (0)
+#define CMG_IR(LB_, HI_, GW_, CB_)                   \
+  do {                                               \
+    if (wide) CMG_IRX(2, LB_, HI_, GW_, CB_);         \
+    else CMG_IRX(1, LB_, HI_, GW_, CB_);              \
   } while (0)
 #define CMG_IRG(LB_, HI_, CB_)          \
   do {                                  \
@@ -1548,6 +1564,7 @@ bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int L
 #undef CMG_IRG
 #undef CMG_IR2
 #undef CMG_IR
+#undef CMG_IRX
   return true;
 }
 
