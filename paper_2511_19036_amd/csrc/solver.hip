@@ -950,8 +950,10 @@ cmg_status cmg_bfp_encode(const void* x, int32_t x_is_f64, int64_t n, int32_t bl
     if (n == 0) return;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     SecRef s{codes, exps, n, block, bits, container_bits(bits)};
+    // the non-finite flag comes from the stream-ordered pool (no device-wide
+    // synchronisation, unlike hipMalloc / hipFree)
     int* flag = nullptr;
-    HIPCK(hipMalloc(&flag, sizeof(int)));
+    HIPCK(hipMallocAsync(reinterpret_cast<void**>(&flag), sizeof(int), st));
     int h = 0;
     try {
       HIPCK(hipMemsetAsync(flag, 0, sizeof(int), st));
@@ -959,12 +961,12 @@ cmg_status cmg_bfp_encode(const void* x, int32_t x_is_f64, int64_t n, int32_t bl
       else launch_encode<float>(static_cast<const float*>(x), n, s, flag, st);
       KCK();
       HIPCK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCK(hipStreamSynchronize(st));
     } catch (...) {
-      (void)hipFree(flag);
+      (void)hipFreeAsync(flag, st);
       throw;
     }
-    HIPCK(hipFree(flag));
+    HIPCK(hipFreeAsync(flag, st));
+    HIPCK(hipStreamSynchronize(st));
     if (h) fail(CMG_ERR_NONFINITE, "codec input holds NaN or Inf");
   });
 }
