@@ -329,10 +329,12 @@ __device__ __forceinline__ void monitor_add(double* mon, double a) {
 // A = L D L^T (unit lower-triangular L, diagonal D; A is symmetric positive
 // definite), and solved by forward substitution, division by D and back
 // substitution, every sum taken in index order.  `e` is scratch for
-// g.size values; g, y and e use the padded level layout.
-constexpr int kDenseMax = 27;
+// g.size values and `work` for kDenseWork values (the matrix, its factor and
+// three vectors; shared memory, so that the kernel needs no private arrays);
+// g, y and e use the padded level layout.
+constexpr int kDenseMax = 27, kDenseWork = (2 * kDenseMax + 3) * kDenseMax;
 __device__ inline void coarse_solve_dense(const double* g_in, const double* kap, const Geom& g, double ih2,
-                                          double* y, double* e) {
+                                          double* y, double* e, double* work) {
   const int kz = g.dim == 3 ? 1 : 0;
   for (int64_t t = 0; t < g.size; ++t) y[t] = 0.0;
   if (g.n == 2) {
@@ -342,20 +344,21 @@ __device__ inline void coarse_solve_dense(const double* g_in, const double* kap,
     return;
   }
   const int w = g.n - 1, m = g.dim == 3 ? w * w * w : w * w;
-  int64_t node[kDenseMax];
-  int ii[kDenseMax], jj[kDenseMax], kk[kDenseMax];
-  for (int t = 0; t < m; ++t) {  // interior nodes in C order, x fastest
-    ii[t] = 1 + t % w;
-    jj[t] = 1 + (t / w) % w;
-    kk[t] = g.dim == 3 ? 1 + t / (w * w) : 0;
-    node[t] = flat(g, ii[t], jj[t], kk[t]);
-  }
-  double A[kDenseMax * kDenseMax], Lf[kDenseMax * kDenseMax], d[kDenseMax], z[kDenseMax], x[kDenseMax];
+  // interior node t in C order, x fastest
+  auto ii = [&](int t) { return 1 + t % w; };
+  auto jj = [&](int t) { return 1 + (t / w) % w; };
+  auto kk = [&](int t) { return g.dim == 3 ? 1 + t / (w * w) : 0; };
+  auto node = [&](int t) { return flat(g, ii(t), jj(t), kk(t)); };
+  double* const A = work;
+  double* const Lf = A + kDenseMax * kDenseMax;
+  double* const d = Lf + kDenseMax * kDenseMax;
+  double* const z = d + kDenseMax;
+  double* const x = z + kDenseMax;
   for (int64_t t = 0; t < g.size; ++t) e[t] = 0.0;
   for (int c = 0; c < m; ++c) {
-    e[node[c]] = 1.0;
-    for (int r = 0; r < m; ++r) A[r * m + c] = apply_A(e, kap, g, ii[r], jj[r], kk[r], ih2);
-    e[node[c]] = 0.0;
+    e[node(c)] = 1.0;
+    for (int r = 0; r < m; ++r) A[r * m + c] = apply_A(e, kap, g, ii(r), jj(r), kk(r), ih2);
+    e[node(c)] = 0.0;
   }
   for (int j = 0; j < m; ++j) {
     double s = A[j * m + j];
@@ -368,7 +371,7 @@ __device__ inline void coarse_solve_dense(const double* g_in, const double* kap,
     }
   }
   for (int i = 0; i < m; ++i) {
-    double s = g_in[node[i]];
+    double s = g_in[node(i)];
     for (int k = 0; k < i; ++k) s = s - Lf[i * m + k] * z[k];
     z[i] = s;
   }
@@ -377,7 +380,7 @@ __device__ inline void coarse_solve_dense(const double* g_in, const double* kap,
     for (int k = i + 1; k < m; ++k) s = s - Lf[k * m + i] * x[k];
     x[i] = s;
   }
-  for (int i = 0; i < m; ++i) y[node[i]] = x[i];
+  for (int i = 0; i < m; ++i) y[node(i)] = x[i];
 }
 
 }  // namespace cmg

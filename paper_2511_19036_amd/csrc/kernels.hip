@@ -672,8 +672,9 @@ __global__ void __launch_bounds__(kThreads) k_to_full(const double* __restrict__
 __global__ void k_coarse_single(const double* __restrict__ gin, const double* __restrict__ kap, Geom g,
                                 double inv_h2, double* __restrict__ y) {
   __shared__ double e[64];
+  __shared__ double work[kDenseWork];
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  coarse_solve_dense(gin, kap, g, inv_h2, y, e);
+  coarse_solve_dense(gin, kap, g, inv_h2, y, e, work);
 }
 
 // ================================================================ kappa
