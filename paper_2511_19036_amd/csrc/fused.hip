@@ -255,7 +255,9 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
   uint32_t xy[K][2];
   unsigned fl[K];
   col_setup<H, TY, NT>(tid, X0, Y0, level, pos, xy, fl, oidx);
+  int gwm1 = G.w - 1;  // opaque, so that a code's scaling exponent is one subtraction
   auto launder = [&]() {
+    opaque_s(gwm1);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       opaque(pos[k]);
@@ -279,7 +281,9 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
       for (int i = 0; i < S + 1; ++i) r[k][c][i] = 0.0f;
     }
   // Codes of plane p.  Unconditional: a plane outside the level reads
-  // plane 1, and its right-hand side is zeroed where it enters.
+  // plane 1, and its right-hand side is zeroed where it enters.  The words
+  // holding the codes are loaded, not the codes themselves (code_at): with
+  // the sign-extending loads this kernel took 80 VGPRs and ran 4% slower.
   auto fetch = [&](int p) {
     const PlanePtr gq = plane_at<CB, LB>(G, min(max(p, 1), n - 1), level);
 #pragma unroll
@@ -297,8 +301,8 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const bool sw = (fl[k] >> kSwap) & 1u;
-      const float g0 = jin ? raw_f32(gpre[k][0], xy[k][0], cbits_of<CB>(G), G.w) : 0.0f;
-      const float g1 = jin ? raw_f32(gpre[k][1], xy[k][1], cbits_of<CB>(G), G.w) : 0.0f;
+      const float g0 = jin ? raw_f32_m1(gpre[k][0], xy[k][0], cbits_of<CB>(G), gwm1) : 0.0f;
+      const float g1 = jin ? raw_f32_m1(gpre[k][1], xy[k][1], cbits_of<CB>(G), gwm1) : 0.0f;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
 #pragma unroll
@@ -541,8 +545,11 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   if (valid && 2 * qx >= H && 2 * qx < H + kTX && 2 * qy >= H && 2 * qy < H + TY) fq |= 16u;
   uint32_t xy0 = dom ? ((static_cast<uint32_t>(gy0) << level) | static_cast<uint32_t>(gx0)) : 0u;
   int oidx = (fq >> 4) & 1u ? (2 * qy - H) * kTX + (2 * qx - H) : TY * kTX;
+  int gwm1 = G.w - 1, ywm1 = Y.w - 1;  // opaque: a code's scaling exponent is one subtraction
   auto launder = [&]() {
     opaque(lane);
+    opaque_s(gwm1);
+    opaque_s(ywm1);
     opaque_s(wv);
     opaque_s(X0);
     opaque_s(Y0);
@@ -607,8 +614,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
 #pragma unroll
     for (int dy = 0; dy < 2; ++dy) {
       const uint32_t xr = xy0 + (static_cast<uint32_t>(dy) << level);
-      gpre[dy] = pair_at<LB>(gq, xr, cbits_of<CB>(G));
-      ypre[dy] = pair_at<LB>(yq, xr, cbits_of<CB>(Y));
+      gpre[dy] = pair_code_at<CB, LB>(gq, xr, cbits_of<CB>(G));
+      ypre[dy] = pair_code_at<CB, LB>(yq, xr, cbits_of<CB>(Y));
     }
   };
   // Rows of a wave: out_row(wv, t) for t < RPW; a wave with fewer than RPW
@@ -625,7 +632,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     const PlanePtr uq = plane_at<CB, LB>(U, min(max(po, Z0), Z0 + TZ - 1), level);
 #pragma unroll
     for (int t = 0; t < RPW; ++t)
-      upre[t] = raw_at<LB, HI>(uq, ((static_cast<uint32_t>(Y0 + row_of(t)) << level) | X0) + lane, cbits_of<CB>(U));
+      upre[t] = code_at<CB, LB, HI>(uq, ((static_cast<uint32_t>(Y0 + row_of(t)) << level) | X0) + lane, cbits_of<CB>(U));
   };
   // Output plane po: quantise y' (Yp), correct u' (float64), e = dec Yp + z.
   // The arithmetic of all rows of the wave is one straight-line block
@@ -651,7 +658,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     for (int t = 0; t < RPW; ++t) {
       const uint32_t xyl = ((static_cast<uint32_t>(Y0 + row_of(t)) << level) | static_cast<uint32_t>(X0)) + lane;
       const double dy = ldexp(static_cast<double>(F.my[t]), F.ey[t] - (Yp.w - 1));  // codes 0 in a zero block
-      vu[t] = raw_f64<may64<CB, HI>()>(upre[t], xyl, cbits_of<CB>(U), U.w) + dy;
+      vu[t] = code_f64<CB, may64<CB, HI>()>(upre[t], xyl, cbits_of<CB>(U), U.w) + dy;
       F.ev[t] = static_cast<float>(dy);
     }
     quant_f64_rows<LB, may64<CB, HI>(), RPW>(vu, U.w, lane, F.mu, F.eu);
@@ -745,8 +752,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
         a = a * ih2;
         const bool kp = pin && ((fq >> d) & 1u);
         const uint32_t xr = xy0 + (static_cast<uint32_t>(dy) << level);
-        const float gv = pair_f32(gpre[dy], xr, dx, cbits_of<CB>(G), G.w) - a;
-        const float y0 = pair_f32(ypre[dy], xr, dx, cbits_of<CB>(Y), Y.w);
+        const float gv = pair_code_f32<CB>(gpre[dy], xr, dx, cbits_of<CB>(G), gwm1) - a;
+        const float y0 = pair_code_f32<CB>(ypre[dy], xr, dx, cbits_of<CB>(Y), ywm1);
         rv[d] = kp ? gv : 0.0f;
         yv[d] = kp ? y0 : 0.0f;
       }
@@ -910,17 +917,20 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
   auto fetch_y = [&](int p) {
     const PlanePtr yq = plane_at<CB, LB>(Y, min(max(p, 0), n - 1), level);
 #pragma unroll
-    for (int k = 0; k < K; ++k) ypre[k] = raw_at<LB, HI>(yq, xy[k], cbits_of<CB>(Y));
+    for (int k = 0; k < K; ++k) ypre[k] = code_at<CB, LB, HI>(yq, xy[k], cbits_of<CB>(Y));
   };
   auto fetch_g = [&](int p) {
     const PlanePtr gq = plane_at<CB, LB>(G, min(max(p, 1), n - 1), level);
 #pragma unroll
-    for (int k = 0; k < K; ++k) gpre[k] = raw_at<LB, HI>(gq, xy[k], cbits_of<CB>(G));
+    for (int k = 0; k < K; ++k) gpre[k] = code_at<CB, LB, HI>(gq, xy[k], cbits_of<CB>(G));
   };
 
+  int ywm1 = Y.w - 1, gwm1 = G.w - 1;
   auto step = [&](auto spc, const int s) {
     constexpr int SP = decltype(spc)::value;  // parity of s and of the plane s - 2 of stage C
     opaque(lane);
+    opaque_s(ywm1);
+    opaque_s(gwm1);
     opaque_s(wv);
     opaque_s(CX0);
     opaque_s(CY0);
@@ -932,7 +942,6 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
       opaque(pos[k]);
       opaque(tpos[k]);
       opaque(xy[k]);
-      opaque(fl[k]);
     }
     {  // A: y' of plane s
       const bool pin = s >= 0 && s < n;
@@ -941,7 +950,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
       for (int k = 0; k < K; ++k) {
         yr[k][0] = yr[k][1];
         yr[k][1] = yr[k][2];
-        const float v = raw_f32(ypre[k], xy[k], cbits_of<CB>(Y), Y.w);
+        const float v = code_f32<CB>(ypre[k], xy[k], cbits_of<CB>(Y), ywm1);
         yr[k][2] = (pin && (fl[k] & 1u)) ? v : 0.0f;
         yb[pos[k]] = yr[k][2];
       }
@@ -962,7 +971,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
         a = a - yr[k][0];
         a = a - yr[k][2];
         a = a * ih2;
-        const float v = raw_f32(gpre[k], xy[k], cbits_of<CB>(G), G.w) - a;
+        const float v = code_f32<CB>(gpre[k], xy[k], cbits_of<CB>(G), gwm1) - a;
         tb[tpos[k]] = (pin && (fl[k] & 4u)) ? v : 0.0f;
       }
     }
@@ -1128,8 +1137,8 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
   auto fetch_u = [&](int p) {
     const PlanePtr uq = plane_at<CB, LB>(U, min(max(p, 0), n - 1), level);
 #pragma unroll
-    for (int t = 0; t < RPT; ++t) upre[t] = raw_at<LB, HI>(uq, xy_own(t), cbits_of<CB>(U));
-    hpre = raw_at<LB, HI>(uq, xyh, cbits_of<CB>(U));
+    for (int t = 0; t < RPT; ++t) upre[t] = code_at<CB, LB, HI>(uq, xy_own(t), cbits_of<CB>(U));
+    hpre = code_at<CB, LB, HI>(uq, xyh, cbits_of<CB>(U));
   };
   auto fetch_f = [&](int p) {  // f at the own columns of plane p
     const double* fp = f + static_cast<uint64_t>(min(max(p, 0), n - 1)) * fst * N * N;
@@ -1171,14 +1180,14 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         u[t][0] = u[t][1];
         u[t][1] = u[t][2];
         const int ci = ((rr >> 1) + 1) * CW + (xl >> 1) + 1;
-        const double v = raw_f64<may64<CB, HI>()>(upre[t], xy_own(t), cbits_of<CB>(U), U.w) +
+        const double v = code_f64<CB, may64<CB, HI>()>(upre[t], xy_own(t), cbits_of<CB>(U), U.w) +
                          prolong_node<double, JP, CW, true>(c0, c1, ci, lane & 1, rr & 1);
         u[t][2] = pin ? v : 0.0;
         ub[(rr + 1) * EXW + xl + 1] = u[t][2];
       }
       if (has_h) {
         const double v =
-            raw_f64<may64<CB, HI>()>(hpre, xyh, cbits_of<CB>(U), U.w) + prolong_node<double, JP, CW, true>(c0, c1, hci, gxh & 1, gyh & 1);
+            code_f64<CB, may64<CB, HI>()>(hpre, xyh, cbits_of<CB>(U), U.w) + prolong_node<double, JP, CW, true>(c0, c1, hci, gxh & 1, gyh & 1);
         ub[hpos] = (pin && hdom) ? v : 0.0;
       }
     }
@@ -1301,7 +1310,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
   };
   auto xy_own = [&]() { return (static_cast<uint32_t>(Y0 + wv) << level) | static_cast<uint32_t>(X0 + lane); };
   auto fetch_u = [&](int k) {  // unconditional: past the last plane it reads that plane again, unused
-    upre = raw_at<LB, HI>(plane_at<CB, LB>(U, min(k, n - 1), level), xy_own(), cbits_of<CB>(U));
+    upre = code_at<CB, LB, HI>(plane_at<CB, LB>(U, min(k, n - 1), level), xy_own(), cbits_of<CB>(U));
   };
   auto step = [&](auto kpc, const int k) {
     constexpr int KP = decltype(kpc)::value;
@@ -1317,7 +1326,7 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     const double* c1 = cs + (((k >> 1) + 1) & (NC - 1)) * CPL;
     const int ci = (wv >> 1) * CW + (lane >> 1);
     const double v =
-        raw_f64<may64<CB, HI>()>(r, xy_own(), cbits_of<CB>(U), U.w) + prolong_node<double, KP, CW, true>(c0, c1, ci, lane & 1, wv & 1);
+        code_f64<CB, may64<CB, HI>()>(r, xy_own(), cbits_of<CB>(U), U.w) + prolong_node<double, KP, CW, true>(c0, c1, ci, lane & 1, wv & 1);
     double* row = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(Y0 + wv)) * N;
     row[X0 + lane] = v;  // (the faces at 2^l of a full array are written by k_far_faces)
     if (KP == 0) cstore((k >> 1) + 1);

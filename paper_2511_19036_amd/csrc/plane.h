@@ -52,6 +52,13 @@ constexpr bool may64() {
   return CB == 0 ? HI : CB == 64;
 }
 
+// Whether a kernel's compile-time container CB holds whole, aligned codes
+// that one load of the container type returns (sign-extended).
+template <int CB>
+constexpr bool direct_cb() {
+  return CB == 8 || CB == 16 || CB == 32;
+}
+
 // Plane p >= 0 of a section.
 __device__ __forceinline__ PlanePtr plane_of(const PSec& s, int p) {
   const uint32_t up = static_cast<uint32_t>(p);
@@ -112,6 +119,37 @@ __device__ __forceinline__ float pair_f32(const RawCode& r, uint32_t xy0, int c,
   return ldexpf(static_cast<float>(m), r.e - (w - 1));
 }
 
+// pair_at for a compile-time container: with direct_cb<CB>() the two codes
+// as one aligned load (CB = 32: lo and hi; 16: the halves of lo; 8: the two
+// low bytes of lo), else pair_at.  Read with pair_code_f32.
+template <int CB, int LB>
+__device__ __forceinline__ RawCode pair_code_at(const PlanePtr& pp, uint32_t xy0, int cbits) {
+  if (!direct_cb<CB>()) return pair_at<LB>(pp, xy0, cbits);
+  const char* p = pp.c + xy0 * static_cast<uint32_t>(CB / 8);  // 32-bit offset, see code_at
+  RawCode r{0u, 0u, pp.e[xy0 >> LB]};
+  if (CB == 32) {
+    uint2 v;
+    __builtin_memcpy(&v, p, 8);
+    r.lo = v.x;
+    r.hi = v.y;
+  } else if (CB == 16) {
+    r.lo = *reinterpret_cast<const uint32_t*>(p);
+  } else {
+    r.lo = *reinterpret_cast<const uint16_t*>(p);
+  }
+  return r;
+}
+// Value c (0 or 1) of a pair read by pair_code_at<CB>, as float (w = wm1 + 1).
+template <int CB>
+__device__ __forceinline__ float pair_code_f32(const RawCode& r, uint32_t xy0, int c, int cbits, int wm1) {
+  if (!direct_cb<CB>()) return pair_f32(r, xy0, c, cbits, wm1 + 1);
+  int m;
+  if (CB == 32) m = static_cast<int>(c != 0 ? r.hi : r.lo);
+  else if (CB == 16) m = c != 0 ? static_cast<int>(r.lo) >> 16 : static_cast<int>(r.lo << 16) >> 16;
+  else m = c != 0 ? static_cast<int>(r.lo << 16) >> 24 : static_cast<int>(r.lo << 24) >> 24;
+  return ldexpf(static_cast<float>(m), r.e - wm1);
+}
+
 // Value of a raw code of width w <= 24 (container at most 32 bits) as float:
 // the code converts exactly and the scaling rounds once, as the conversion
 // of the exact double value to float does.
@@ -120,6 +158,36 @@ __device__ __forceinline__ float raw_f32(const RawCode& r, uint32_t xy, int cbit
   const uint32_t x = __builtin_amdgcn_alignbit(r.hi, r.lo, sh);
   const int m = static_cast<int>(x << (32 - cbits)) >> (32 - cbits);
   return ldexpf(static_cast<float>(m), r.e - (w - 1));
+}
+// The same with wm1 = w - 1 given (a wave-uniform value the caller keeps
+// opaque, so that the scaling exponent is one subtraction).
+__device__ __forceinline__ float raw_f32_m1(const RawCode& r, uint32_t xy, int cbits, int wm1) {
+  const uint32_t sh = (xy * static_cast<uint32_t>(cbits)) & 31u;
+  const uint32_t x = __builtin_amdgcn_alignbit(r.hi, r.lo, sh);
+  const int m = static_cast<int>(x << (32 - cbits)) >> (32 - cbits);
+  return ldexpf(static_cast<float>(m), r.e - wm1);
+}
+
+// raw_at for a compile-time container: with direct_cb<CB>() the code itself
+// (one 8-, 16- or 32-bit load, sign-extended into lo), else raw_at.  Read
+// the result with code_f32.
+template <int CB, int LB, bool HI>
+__device__ __forceinline__ RawCode code_at(const PlanePtr& pp, uint32_t xy, int cbits) {
+  if (!direct_cb<CB>()) return raw_at<LB, HI>(pp, xy, cbits);
+  // in-plane byte offsets stay below 2^32 (a plane holds at most 2^24 values
+  // here), which keeps the address a 32-bit offset from the plane pointer
+  const char* p = pp.c + xy * static_cast<uint32_t>(CB / 8);
+  int c;
+  if (CB == 8) c = *reinterpret_cast<const int8_t*>(p);
+  else if (CB == 16) c = *reinterpret_cast<const int16_t*>(p);
+  else c = *reinterpret_cast<const int32_t*>(p);
+  return RawCode{static_cast<uint32_t>(c), 0u, pp.e[xy >> LB]};
+}
+// Value of a code read by code_at<CB> (width w = wm1 + 1 <= 24), as float.
+template <int CB>
+__device__ __forceinline__ float code_f32(const RawCode& r, uint32_t xy, int cbits, int wm1) {
+  if (!direct_cb<CB>()) return raw_f32_m1(r, xy, cbits, wm1);
+  return ldexpf(static_cast<float>(static_cast<int>(r.lo)), r.e - wm1);
 }
 
 // Exact value of a raw code as double (branch-free: both the 64-bit and the
@@ -139,6 +207,14 @@ __device__ __forceinline__ double raw_f64(const RawCode& r, uint32_t xy, int cbi
     d = static_cast<double>(static_cast<int>(x << (32 - cbits)) >> (32 - cbits));
   }
   return ldexp(d, r.e - (w - 1));
+}
+
+// Exact value of a code read by code_at<CB> as double (raw_f64<C64> when
+// the container is not direct).
+template <int CB, bool C64>
+__device__ __forceinline__ double code_f64(const RawCode& r, uint32_t xy, int cbits, int w) {
+  if (!direct_cb<CB>()) return raw_f64<C64>(r, xy, cbits, w);
+  return ldexp(static_cast<double>(static_cast<int>(r.lo)), r.e - (w - 1));
 }
 
 // Hide a per-lane value from loop-invariant code motion, so that values
