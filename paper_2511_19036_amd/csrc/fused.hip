@@ -22,6 +22,7 @@
 // HI = false the second word is neither loaded nor used).  Container-width
 // flags of the float64 helpers (C64, W64, GW64) likewise remove the 64-bit
 // paths where the launcher knows the container is at most 32 bits.
+#include <cmath>
 #include <cstdint>
 #include <initializer_list>
 #include <map>
@@ -350,8 +351,7 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
           a = a - yb[pa + EXW];
           a = a - y[k][SG][iy - 1];
           a = a - y[k][SG][iy + 1];
-          a = a * ih2;
-          const float rr = rhs - a;
+          const float rr = exact_fma(-a, ih2, rhs);  // rhs - a ih2 (ih2 = 4^l)
           v = yc + cp * rr;
         }
         const float yv = (act && ((fl[k] >> (kInnerSlot + SG)) & 1u)) ? v : yc;
@@ -406,46 +406,48 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
 template <typename T, int PK, int CW, bool LANEP = false>
 __device__ __forceinline__ T prolong_node(const T* c0, const T* c1, int ci, bool px, bool py) {
   const T w = (px ? T(0.5) : T(1)) * (py ? T(0.5) : T(1)) * (PK ? T(0.5) : T(1));
+  // every weight is a power of two or zero: each product and sum is one
+  // exact_fma after the first product
   if (LANEP) {
     const T wx = px ? w : T(0), wy = py ? w : T(0), wxy = (px && py) ? w : T(0);
     T s = w * c0[ci];
-    s = s + wx * c0[ci + 1];
-    s = s + wy * c0[ci + CW];
-    s = s + wxy * c0[ci + CW + 1];
+    s = exact_fma(c0[ci + 1], wx, s);
+    s = exact_fma(c0[ci + CW], wy, s);
+    s = exact_fma(c0[ci + CW + 1], wxy, s);
     if (PK) {
-      s = s + w * c1[ci];
-      s = s + wx * c1[ci + 1];
-      s = s + wy * c1[ci + CW];
-      s = s + wxy * c1[ci + CW + 1];
+      s = exact_fma(c1[ci], w, s);
+      s = exact_fma(c1[ci + 1], wx, s);
+      s = exact_fma(c1[ci + CW], wy, s);
+      s = exact_fma(c1[ci + CW + 1], wxy, s);
     }
     return s;
   }
   T s = w * c0[ci];
   {
-    const T t = w * c0[ci + 1];
-    s = px ? s + t : s;
+    const T t = exact_fma(c0[ci + 1], w, s);
+    s = px ? t : s;
   }
   {
-    const T t = w * c0[ci + CW];
-    s = py ? s + t : s;
+    const T t = exact_fma(c0[ci + CW], w, s);
+    s = py ? t : s;
   }
   {
-    const T t = w * c0[ci + CW + 1];
-    s = (px && py) ? s + t : s;
+    const T t = exact_fma(c0[ci + CW + 1], w, s);
+    s = (px && py) ? t : s;
   }
   if (PK) {
-    s = s + w * c1[ci];
+    s = exact_fma(c1[ci], w, s);
     {
-      const T t = w * c1[ci + 1];
-      s = px ? s + t : s;
+      const T t = exact_fma(c1[ci + 1], w, s);
+      s = px ? t : s;
     }
     {
-      const T t = w * c1[ci + CW];
-      s = py ? s + t : s;
+      const T t = exact_fma(c1[ci + CW], w, s);
+      s = py ? t : s;
     }
     {
-      const T t = w * c1[ci + CW + 1];
-      s = (px && py) ? s + t : s;
+      const T t = exact_fma(c1[ci + CW + 1], w, s);
+      s = (px && py) ? t : s;
     }
   }
   return s;
@@ -749,10 +751,9 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
         a = a - yp;
         a = a - z[d][0];
         a = a - z[d][2];
-        a = a * ih2;
         const bool kp = pin && ((fq >> d) & 1u);
         const uint32_t xr = xy0 + (static_cast<uint32_t>(dy) << level);
-        const float gv = pair_code_f32<CB>(gpre[dy], xr, dx, cbits_of<CB>(G), gwm1) - a;
+        const float gv = exact_fma(-a, ih2, pair_code_f32<CB>(gpre[dy], xr, dx, cbits_of<CB>(G), gwm1));
         const float y0 = pair_code_f32<CB>(ypre[dy], xr, dx, cbits_of<CB>(Y), ywm1);
         rv[d] = kp ? gv : 0.0f;
         yv[d] = kp ? y0 : 0.0f;
@@ -822,8 +823,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
         a = a - yp;
         a = a - y[d][iy - 1];
         a = a - y[d][iy + 1];
-        a = a * ih2;
-        const float rr = r[d][S - s] - a;
+        const float rr = exact_fma(-a, ih2, r[d][S - s]);
         const float v = yc + cp * rr;
         const float yv = ((fq >> d) & 1u) ? v : yc;
         y[d][iy] = yv;
@@ -970,8 +970,7 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
         a = a - ya[c + YW];
         a = a - yr[k][0];
         a = a - yr[k][2];
-        a = a * ih2;
-        const float v = code_f32<CB>(gpre[k], xy[k], cbits_of<CB>(G), gwm1) - a;
+        const float v = exact_fma(-a, ih2, code_f32<CB>(gpre[k], xy[k], cbits_of<CB>(G), gwm1));
         tb[tpos[k]] = (pin && (fl[k] & 4u)) ? v : 0.0f;
       }
     }
@@ -1213,9 +1212,8 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         a = a - ua[c + EXW];
         a = a - u[t][0];
         a = a - u[t][2];
-        a = a * ih2;
         const bool inside = p >= 1 && X0 + xl >= 1 && Y0 + rr >= 1;
-        tv[t] = inside ? fpre[t] - a : 0.0;
+        tv[t] = inside ? exact_fma(-a, ih2, fpre[t]) : 0.0;
       }
       quant_f64_rows<LB, GW64, RPT>(tv, Gout.w, lane, m, e);
 #pragma unroll
@@ -1455,9 +1453,17 @@ static PSec psec(const SecRef& s, const Geom& g) {
   return p;
 }
 
+// The kernels contract the products with h^-2 into exact_fma: h^-2 must be
+// a power of two (4^l on the unit cube), else the per-operation kernels run.
+static bool pow2_scale(double v) {
+  int e;
+  return v > 0.0 && std::frexp(v, &e) == 0.5;
+}
+
 bool fused_down_smooth(const SecRef& G, const SecRef& Y, const Geom& g, int nu, float cp, float ih2,
                        hipStream_t st) {
-  if (g.dim != 3 || g.n < kTX || (nu != 1 && nu != 2) || (G.B != 32 && G.B != 64) || Y.B != G.B) return false;
+  if (g.dim != 3 || g.n < kTX || (nu != 1 && nu != 2) || (G.B != 32 && G.B != 64) || Y.B != G.B || !pow2_scale(ih2))
+    return false;
   const int tiles = (g.n / kTX) * (g.n / kDownTY);
   const dim3 block(kDownNT);
   const double bytes = sec_b(G) + sec_b(Y);
@@ -1485,7 +1491,7 @@ bool fused_down_smooth(const SecRef& G, const SecRef& Y, const Geom& g, int nu, 
 bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const SecRef& Yp, const SecRef& U,
                      float* eout, const Geom& g, const Geom& gc, int nu, float cp, float ih2, hipStream_t st) {
   if (g.dim != 3 || g.n < kTX || (nu != 1 && nu != 2) || (G.B != 32 && G.B != 64) || Y.B != G.B || Yp.B != G.B ||
-      U.B != G.B)
+      U.B != G.B || !pow2_scale(ih2))
     return false;
   const int tiles = (g.n / kTX) * (g.n / kUpTY);
   const dim3 block(kUpNT);
@@ -1514,7 +1520,7 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
 
 bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, const Geom& g, const Geom& gc,
                           float ih2, hipStream_t st) {
-  if (g.dim != 3 || gc.n < kTX || (G.B != 32 && G.B != 64) || Y.B != G.B || Gc.B != G.B) return false;
+  if (g.dim != 3 || gc.n < kTX || (G.B != 32 && G.B != 64) || Y.B != G.B || Gc.B != G.B || !pow2_scale(ih2)) return false;
   const int tiles = (gc.n / kTX) * (gc.n / kRRCTY);
   const dim3 block(kRRNT);
   const double bytes = sec_b(G) + sec_b(Y) + sec_b(Gc);
@@ -1536,7 +1542,7 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
 
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
                        double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st) {
-  if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64) || Gout.B != U.B) return false;
+  if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64) || Gout.B != U.B || !pow2_scale(ih2)) return false;
   // tiles of two blocks side by side from 128 nodes per row: half the
   // partial 128-byte lines at the x-edges of the rows of f and the halos
   const bool wide = g.n >= 2 * kTX;

@@ -217,6 +217,12 @@ __device__ __forceinline__ double code_f64(const RawCode& r, uint32_t xy, int cb
   return ldexp(static_cast<double>(static_cast<int>(r.lo)), r.e - (w - 1));
 }
 
+// a * b + c with one rounding, for products that are exact: b is a power of
+// two (or zero) and a * b stays in the normal range.  Then the result is the
+// separately rounded product and sum, bit for bit, in one instruction.
+__device__ __forceinline__ float exact_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double exact_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Hide a per-lane value from loop-invariant code motion, so that values
 // derived from it are recomputed where they are used instead of occupying
 // registers for the whole z-march.

@@ -394,9 +394,10 @@ void up_level(cmg_ctx c, int l, int Lp) {
   F.U.w = c->wu(l, Lp);
   if (std::is_same<T, float>::value && c->smooth_fused(l)) {
     const float cp = static_cast<float>(1.0 / (2.0 * c->p.dim * ih2));
-    fused_up_smooth(static_cast<const float*>(C.ef), F.G.ref(), F.Y.ref(), F.Yp.ref(), F.U.ref(),
-                    l < Lp ? static_cast<float*>(F.ef) : nullptr, F.g, C.g, c->o.nu_post, cp,
-                    static_cast<float>(ih2), st);
+    if (!fused_up_smooth(static_cast<const float*>(C.ef), F.G.ref(), F.Y.ref(), F.Yp.ref(), F.U.ref(),
+                         l < Lp ? static_cast<float*>(F.ef) : nullptr, F.g, C.g, c->o.nu_post, cp,
+                         static_cast<float>(ih2), st))
+      fail(CMG_ERR_HIP, "fused up-smoothing rejected a level it was selected for");
     KCK();
     return;
   }
@@ -451,7 +452,8 @@ void vcycle_correct(cmg_ctx c, int Lp) {
       KCK();
     }
     if (f32 && c->rr_fused(l)) {
-      fused_resid_restrict(F.G.ref(), F.Y.ref(), C.G.ref(), F.g, C.g, static_cast<float>(ih2), st);
+      if (!fused_resid_restrict(F.G.ref(), F.Y.ref(), C.G.ref(), F.g, C.g, static_cast<float>(ih2), st))
+        fail(CMG_ERR_HIP, "fused residual restriction rejected a level it was selected for");
       KCK();
       continue;
     }
@@ -566,8 +568,9 @@ void ir_residual(cmg_ctx c, int Lp, const double* f, cmg_stats* st, bool watch =
   c->mon_fresh = false;
   if (c->res_fused(Lp)) {
     decode_chain(c, Lp - 1);
-    fused_ir_residual(F.U.ref(), c->lv[Lp - 1].uh, f, c->p.L, F.g, c->lv[Lp - 1].g, inv_h2(Lp), F.G.ref(),
-                      c->flags + 1, c->mon, c->st);
+    if (!fused_ir_residual(F.U.ref(), c->lv[Lp - 1].uh, f, c->p.L, F.g, c->lv[Lp - 1].g, inv_h2(Lp), F.G.ref(),
+                           c->flags + 1, c->mon, c->st))
+      fail(CMG_ERR_HIP, "fused IR residual rejected a level it was selected for");
     KCK();
   } else {
     decode_chain(c, Lp);
