@@ -685,7 +685,9 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const uint32_t xyr = (static_cast<uint32_t>(Y0 + rr) << level) | static_cast<uint32_t>(X0);
       if (keep) store_row(yq.c, xyr, lane, F.my[t], cbits_of<CB>(Yp));
       store_row(uq.c, xyr, lane, F.mu[t], cbits_of<CB>(U));
-      if (eout != nullptr) eout[(static_cast<uint64_t>(po) << (2 * level)) + xyr + lane] = F.ev[t];
+      if (eout != nullptr)  // the plane's base, then a 32-bit offset in it
+        *reinterpret_cast<float*>(reinterpret_cast<char*>(eout + (static_cast<uint64_t>(po) << (2 * level))) +
+                                  4u * (xyr + static_cast<uint32_t>(lane))) = F.ev[t];
     }
     // every lane of a block stores the block's exponent (the same value to
     // the same address): no branch on the lane

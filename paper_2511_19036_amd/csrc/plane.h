@@ -380,12 +380,15 @@ __device__ __forceinline__ void quant_f64_rows(const double (&v)[R], int w, int 
 // of 64) held by the 64 lanes.  In the 12-bit container two values take
 // three bytes: each even lane joins its code with its odd neighbour's (one
 // DPP move) and writes the three bytes as a byte and an aligned short.
+// Byte offsets are formed in 32 bits (a plane holds at most 2^24 values), so
+// that the store addresses the plane pointer plus a 32-bit offset.
 __device__ __forceinline__ void store_row(char* pc, uint32_t xy0, int lane, int64_t m, int cbits) {
+  const uint32_t i = xy0 + static_cast<uint32_t>(lane);
   switch (cbits) {
-    case 8: reinterpret_cast<int8_t*>(pc)[xy0 + lane] = static_cast<int8_t>(m); break;
-    case 16: reinterpret_cast<int16_t*>(pc)[xy0 + lane] = static_cast<int16_t>(m); break;
-    case 32: reinterpret_cast<int32_t*>(pc)[xy0 + lane] = static_cast<int32_t>(m); break;
-    case 64: reinterpret_cast<int64_t*>(pc)[xy0 + lane] = m; break;
+    case 8: *reinterpret_cast<int8_t*>(pc + i) = static_cast<int8_t>(m); break;
+    case 16: *reinterpret_cast<int16_t*>(pc + 2u * i) = static_cast<int16_t>(m); break;
+    case 32: *reinterpret_cast<int32_t*>(pc + 4u * i) = static_cast<int32_t>(m); break;
+    case 64: *reinterpret_cast<int64_t*>(pc + 8u * i) = m; break;
     default: {
       const int c = static_cast<int>(m) & 0xFFF;
       const uint32_t p24 = static_cast<uint32_t>(c) | (static_cast<uint32_t>(dpp_int<0xB1>(c)) << 12);
