@@ -91,12 +91,14 @@ def model_bytes_per_dof(kernel, bits, block):
       up sweep:     g, y' read; u' read and written; coarse y' and FP32 z read
       down sweep:   g read, y' written
       restriction:  g, y' read, coarse g written
-      IR residual:  u' read, coarse FP64 u read, FP64 f read, g written
+      IR residual:  u' and coarse u' read, FP64 u two levels down read (the
+                    coarse solution is rebuilt in the kernel), FP64 f read,
+                    g written
       final decode: u' read, coarse FP64 u read, FP64 u written"""
     beta = bits / 8.0 + 2.0 / block
     name = kernel.partition("<")[0]
     table = {"k_up_smooth": 4 * beta + (beta + 4.0) / 8.0, "k_down_smooth": 2 * beta,
-             "k_resid_restrict": 2 * beta + beta / 8.0, "k_ir_residual": 2 * beta + 1.0 + 8.0,
+             "k_resid_restrict": 2 * beta + beta / 8.0, "k_ir_residual": 2 * beta + beta / 8.0 + 8.0 / 64.0 + 8.0,
              "k_decode_full": beta + 1.0 + 8.0}
     return table[name]
 

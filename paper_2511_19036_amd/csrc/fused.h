@@ -24,13 +24,17 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
 
 // g = Q(f - A(dec u' + P uc)) in float64; f sampled from the level-Lfull grid.
 // sumsq (nullable): the IR residual monitor's slots (device.h), which receive
-// sum t^2 (unordered atomics, one per wave).
+// sum t^2 (unordered atomics, one per wave).  With Uc (u' of level gc) and
+// ucc (the float64 level array one level below gc), the coarse solution is
+// rebuilt as dec Uc + P ucc where it is needed and uc is not read.
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
-                       double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st);
+                       double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st,
+                       const SecRef* Uc = nullptr, const double* ucc = nullptr);
 
-// Full node grid u = dec u'_l + P uc (3-D levels of at least 64^3 nodes).
+// Full node grid u = dec u'_l + P uc (3-D levels of at least 64^3 nodes);
+// Uc and ucc as for fused_ir_residual.
 bool fused_decode_full(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* full,
-                       hipStream_t st);
+                       hipStream_t st, const SecRef* Uc = nullptr, const double* ucc = nullptr);
 
 // One decode-chain step u_l = dec u'_l + P u_{l-1} in the padded layout
 // (3-D levels of at least 64^3 nodes).

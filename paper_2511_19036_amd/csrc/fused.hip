@@ -453,6 +453,83 @@ __device__ __forceinline__ T prolong_node(const T* c0, const T* c1, int ci, bool
   return s;
 }
 
+// One step of the decode chain, u_l = dec u'_l + P u_{l-1} (float64), at a
+// node of level l, for kernels that rebuild the planes of u_l they need
+// instead of reading a stored level array (then u_l is never written to
+// HBM).  The planes of u_{l-1} under the kernel's coarse footprint pass
+// through a ring of three LDS planes (ChainRing, zeros outside the level);
+// chain_value forms a node's value with the operand order of the chain's
+// own kernel: the decoded code plus the interpolation, whose terms are
+// summed in C order (z, y, x) with a zero weight for an absent neighbour.
+struct ChainSrc {
+  PSec U;            // u'_l (run-time container)
+  const double* uc;  // u_{l-1}, level array
+  int level;         // l
+};
+// The LDS ring of u_{l-1} for a coarse footprint of CW x CH nodes of level l
+// at (CX0, CY0) (CX0, CY0 >= -1): its parent footprint is CWP x CHP nodes
+// at (CX0 >> 1, CY0 >> 1).  fetch/store move plane K (stored at slot
+// (K + 3) % 3, K >= -1) through registers so that the loads of one step are
+// consumed at its end.
+template <int CW, int CH, int NT>
+struct ChainRing {
+  static constexpr int CWP = CW / 2 + 2, CHP = CH / 2 + 2, PL = CWP * CHP, PT = (PL + NT - 1) / NT;
+  double v[PT];
+  bool in[PT];
+  __device__ __forceinline__ void fetch(const ChainSrc& c, int CX0, int CY0, int K, int tid) {
+    const int lp = c.level - 1, np = 1 << lp;
+    const bool kin = K >= 0 && K < np;
+    const uint32_t kc = static_cast<uint32_t>(min(max(K, 0), np - 1));
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int t = tid + k * NT;
+      const int py = t / CWP, px = t - py * CWP;
+      const int gx = (CX0 >> 1) + px, gy = (CY0 >> 1) + py;
+      in[k] = kin && t < PL && gx >= 0 && gx < np && gy >= 0 && gy < np;
+      const uint32_t i = min(max(gx, 0), np - 1), j = min(max(gy, 0), np - 1);
+      // the level array of u_{l-1} holds at most 2^27 values: 32-bit byte offsets
+      v[k] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(c.uc) +
+                                              8u * ((kc << (2 * lp)) | (j << lp) | i));
+    }
+  }
+  __device__ __forceinline__ void store(double* ring, int K, int tid) const {
+    double* dst = ring + ((K + 3) % 3) * PL;
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int t = tid + k * NT;
+      if (t < PL) dst[t] = in[k] ? v[k] : 0.0;
+    }
+  }
+  // Node (gx, gy, gz) of level l (inside it, and inside the footprint at
+  // (CX0, CY0)) with code r; the ring holds its parent planes gz >> 1 and
+  // (gz >> 1) + 1.
+  __device__ __forceinline__ static double value(const ChainSrc& c, const RawCode& r, int gx, int gy, int gz,
+                                                 const double* ring, int CX0, int CY0) {
+    const uint32_t xy = (static_cast<uint32_t>(gy) << c.level) | static_cast<uint32_t>(gx);
+    const double d = raw_f64<true>(r, xy, c.U.cbits, c.U.w);
+    const int K = gz >> 1;
+    const double* p0 = ring + (K % 3) * PL;
+    const double* p1 = ring + ((K + 1) % 3) * PL;
+    const int b = ((gy >> 1) - (CY0 >> 1)) * CWP + ((gx >> 1) - (CX0 >> 1));
+    const bool px = gx & 1, py = gy & 1, pz = gz & 1;
+    const double w = (px ? 0.5 : 1.0) * (py ? 0.5 : 1.0) * (pz ? 0.5 : 1.0);
+    const double wx = px ? w : 0.0, wy = py ? w : 0.0, wxy = (px && py) ? w : 0.0;
+    double s = w * p0[b];
+    s = exact_fma(p0[b + 1], wx, s);
+    s = exact_fma(p0[b + CWP], wy, s);
+    s = exact_fma(p0[b + CWP + 1], wxy, s);
+    s = exact_fma(p1[b], pz ? w : 0.0, s);
+    s = exact_fma(p1[b + 1], pz ? wx : 0.0, s);
+    s = exact_fma(p1[b + CWP], pz ? wy : 0.0, s);
+    s = exact_fma(p1[b + CWP + 1], pz ? wxy : 0.0, s);
+    return d + s;
+  }
+};
+template <int LB>
+__device__ __forceinline__ RawCode chain_code(const ChainSrc& c, int gx, int gy, int gz) {
+  const uint32_t xy = (static_cast<uint32_t>(gy) << c.level) | static_cast<uint32_t>(gx);
+  return raw_at<LB, true>(plane_of(c.U, gz), xy, c.U.cbits);
+}
 // Quads (2 x 2 nodes at even local coordinates) of an up-sweep tile of
 // 64 x TY output nodes with halo H, numbered ring by ring: the output tile
 // (ring 0, row by row), then ring r = 1 .. H / 2 (the quads r quads outside
@@ -1045,10 +1122,11 @@ __global__ void __launch_bounds__(NT) k_resid_restrict(PSec G, PSec Y, PSec Gc, 
 // also decode one node of the one-node x-y halo.  Every plane of u goes
 // through a ring of three LDS planes, so that a single barrier per step
 // separates the writes of plane j from the reads of plane j - 2.
-template <int TY, int NT, int XW, int LB, bool HI, bool GW64, int CB>
+template <int TY, int NT, int XW, int LB, bool HI, bool GW64, int CB, bool SKIP>
 __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __restrict__ uc,
                                                     const double* __restrict__ f, int Lfull, int level, int levelc,
-                                                    double ih2, PSec Gout, int TZ, int* nonfinite, double* sumsq) {
+                                                    double ih2, PSec Gout, int TZ, int* nonfinite, double* sumsq,
+                                                    ChainSrc ch) {
   // XW blocks of 64 side by side: wave wv owns block wv % XW of rows
   // wv / XW + NWR t
   constexpr int TXW = kTX * XW, NW = NT / 64, NWR = NW / XW, RPT = TY / NWR;
@@ -1057,8 +1135,10 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
   constexpr int NHALO = 2 * EXW + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread");
   constexpr int NC = 4, CW = TXW / 2 + 3, CH = TY / 2 + 3, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
+  using Ring = ChainRing<CW, CH, NT>;
   __shared__ double us[3 * LPL];
   __shared__ double cs[NC * CPL];
+  __shared__ double ps[SKIP ? 3 * Ring::PL : 1];  // SKIP: planes of u_{Lp-2}
   const int tid = threadIdx.x;
   int lane = tid & 63;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1101,10 +1181,18 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
   double fpre[RPT];
   double cpf[CPT];
   bool cin[CPT];
+  RawCode ccode[SKIP ? CPT : 1];  // SKIP: u_{Lp-1} is rebuilt from u'_{Lp-1} and u_{Lp-2}
+  Ring ring;
 #pragma unroll
   for (int t = 0; t < RPT; ++t) u[t][0] = u[t][1] = u[t][2] = 0.0;
   auto xy_own = [&](int t) {
     return (static_cast<uint32_t>(Y0 + wr + NWR * t) << level) | static_cast<uint32_t>(X0 + xl);
+  };
+  // the node of coarse slot t, clamped into the level
+  auto cnode = [&](int t, int& gx, int& gy) {
+    const int cy = t / CW, cx = t - cy * CW;
+    gx = CX0 + cx;
+    gy = CY0 + cy;
   };
   auto cfetch = [&](int cz) {
     const bool zin = cz >= 0 && cz < nc;
@@ -1112,22 +1200,38 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       const int t = tid + k * NT;
-      const int cy = t / CW, cx = t - cy * CW;
-      const int gx = CX0 + cx, gy = CY0 + cy;
+      int gx, gy;
+      cnode(t, gx, gy);
       const bool in = zin && t < CPL && gx >= 0 && gx < nc && gy >= 0 && gy < nc;
       // every lane loads (a node of the level); the value is selected
-      const double v = src[(static_cast<uint32_t>(min(max(gy, 0), nc - 1)) << levelc) |
-                           static_cast<uint32_t>(min(max(gx, 0), nc - 1))];
-      cpf[k] = v;
+      const int gxc = min(max(gx, 0), nc - 1), gyc = min(max(gy, 0), nc - 1);
+      if (SKIP) {
+        ccode[k] = chain_code<LB>(ch, gxc, gyc, zin ? cz : 0);
+      } else {
+        const double v = src[(static_cast<uint32_t>(gyc) << levelc) | static_cast<uint32_t>(gxc)];
+        cpf[k] = v;
+      }
       cin[k] = in;  // applied where the value is stored: a select here would wait for the load
     }
   };
   auto cstore = [&](int cz) {
     double* dst = cs + (cz & (NC - 1)) * CPL;
+    const bool zin = cz >= 0 && cz < nc;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       const int t = tid + k * NT;
-      if (t < CPL) dst[t] = cin[k] ? cpf[k] : 0;
+      if (t < CPL) {
+        double v;
+        if (SKIP) {
+          int gx, gy;
+          cnode(t, gx, gy);
+          v = Ring::value(ch, ccode[k], min(max(gx, 0), nc - 1), min(max(gy, 0), nc - 1), zin ? cz : 0, ps, CX0,
+                          CY0);
+        } else {
+          v = cpf[k];
+        }
+        dst[t] = cin[k] ? v : 0;
+      }
     }
   };
   // The loads below are unconditional (a plane outside the level reads a
@@ -1169,7 +1273,10 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
     opaque_s(Y0);
     opaque_sec<CB>(U);
     opaque_sec<CB>(Gout);
-    if (JP == 0) cfetch((j + 2) >> 1);  // u(j + 1) needs coarse plane (j + 2) / 2
+    if (JP == 0) {
+      cfetch((j + 2) >> 1);  // u(j + 1) needs coarse plane (j + 2) / 2
+      if (SKIP) ring.fetch(ch, CX0, CY0, (((j + 2) >> 1) >> 1) + 2, tid);  // its parent planes run 2 ahead
+    }
     {  // u of plane j
       const bool pin = j >= 0 && j < n;
       const double* c0 = cs + ((j >> 1) & (NC - 1)) * CPL;
@@ -1193,7 +1300,10 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
       }
     }
     fetch_u(j + 1);
-    if (JP == 0) cstore((j + 2) >> 1);
+    if (JP == 0) {
+      cstore((j + 2) >> 1);
+      if (SKIP) ring.store(ps, (((j + 2) >> 1) >> 1) + 2, tid);
+    }
     __syncthreads();
     const int p = j - 1;
     if (p >= Z0 && p < Z0 + TZ) {  // residual on plane p
@@ -1243,6 +1353,14 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
   };
 
   const int jbeg = Z0 - 1, jend = Z0 + TZ + 1;  // an even number of steps, jbeg odd
+  if (SKIP) {  // the parent planes of the first two coarse planes and of the first step's
+#pragma unroll 1
+    for (int K = (jbeg >> 1) >> 1; K <= ((jbeg >> 1) >> 1) + 2; ++K) {
+      ring.fetch(ch, CX0, CY0, K, tid);
+      ring.store(ps, K, tid);
+    }
+    __syncthreads();
+  }
   cfetch(jbeg >> 1);
   cstore(jbeg >> 1);
   cfetch((jbeg >> 1) + 1);
@@ -1265,13 +1383,17 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
 // written as whole rows.  Tiles at the far x / y edges also write the
 // boundary column / row at node 2^l; the last chunk writes plane 2^l.
 // PAD: write the padded level layout (2^l per axis) instead, as one step of
-// the decode chain u_l = dec u'_l + P u_{l-1}.
-template <int TY, int LB, bool PAD, bool HI, int CB>
+// the decode chain u_l = dec u'_l + P u_{l-1}.  SKIP: u_{l-1} is rebuilt
+// from u'_{l-1} and u_{l-2} (ch) where it is needed; uc is not read.
+template <int TY, int LB, bool PAD, bool HI, int CB, bool SKIP>
 __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* __restrict__ uc, int level,
-                                                         int levelc, int TZ, double* __restrict__ full) {
+                                                         int levelc, int TZ, double* __restrict__ full,
+                                                         ChainSrc ch) {
   constexpr int NT = 64 * TY;
   constexpr int NC = 4, CW = kTX / 2 + 2, CH = TY / 2 + 2, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
+  using Ring = ChainRing<CW, CH, NT>;
   __shared__ double cs[NC * CPL];
+  __shared__ double ps[SKIP ? 3 * Ring::PL : 1];  // SKIP: planes of u_{l-2}
   const int tid = threadIdx.x;
   int lane = tid & 63;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1284,6 +1406,8 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
   const int CX0 = X0 >> 1, CY0 = Y0 >> 1;
   double cpf[CPT];
   bool cin[CPT];
+  RawCode ccode[SKIP ? CPT : 1];
+  Ring ring;
   RawCode upre;
   auto cfetch = [&](int cz) {
     const bool zin = cz >= 0 && cz < nc;
@@ -1295,17 +1419,32 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
       const int gx = CX0 + cx, gy = CY0 + cy;
       const bool in = zin && t < CPL && gx < nc && gy < nc;
       // every lane loads (a node of the level); the value is selected
-      const double v = src[(static_cast<uint32_t>(min(gy, nc - 1)) << levelc) | static_cast<uint32_t>(min(gx, nc - 1))];
-      cpf[k] = v;
+      if (SKIP) {
+        ccode[k] = chain_code<LB>(ch, min(gx, nc - 1), min(gy, nc - 1), zin ? cz : 0);
+      } else {
+        const double v =
+            src[(static_cast<uint32_t>(min(gy, nc - 1)) << levelc) | static_cast<uint32_t>(min(gx, nc - 1))];
+        cpf[k] = v;
+      }
       cin[k] = in;  // applied where the value is stored: a select here would wait for the load
     }
   };
   auto cstore = [&](int cz) {
     double* dst = cs + (cz & (NC - 1)) * CPL;
+    const bool zin = cz >= 0 && cz < nc;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       const int t = tid + k * NT;
-      if (t < CPL) dst[t] = cin[k] ? cpf[k] : 0;
+      if (t < CPL) {
+        double v;
+        if (SKIP) {
+          const int cy = t / CW, cx = t - cy * CW;
+          v = Ring::value(ch, ccode[k], min(CX0 + cx, nc - 1), min(CY0 + cy, nc - 1), zin ? cz : 0, ps, CX0, CY0);
+        } else {
+          v = cpf[k];
+        }
+        dst[t] = cin[k] ? v : 0;
+      }
     }
   };
   auto xy_own = [&]() { return (static_cast<uint32_t>(Y0 + wv) << level) | static_cast<uint32_t>(X0 + lane); };
@@ -1319,7 +1458,10 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
     opaque_s(X0);
     opaque_s(Y0);
     opaque_sec<CB>(U);
-    if (KP == 0) cfetch((k >> 1) + 1);  // plane k + 1 needs coarse plane k / 2 + 1
+    if (KP == 0) {
+      cfetch((k >> 1) + 1);  // plane k + 1 needs coarse plane k / 2 + 1
+      if (SKIP) ring.fetch(ch, CX0, CY0, (((k >> 1) + 1) >> 1) + 2, tid);  // its parent planes run 2 ahead
+    }
     const RawCode r = upre;
     fetch_u(k + 1);
     const double* c0 = cs + ((k >> 1) & (NC - 1)) * CPL;
@@ -1329,9 +1471,20 @@ __global__ void __launch_bounds__(64 * TY) k_decode_full(PSec U, const double* _
         code_f64<CB, may64<CB, HI>()>(r, xy_own(), cbits_of<CB>(U), U.w) + prolong_node<double, KP, CW, true>(c0, c1, ci, lane & 1, wv & 1);
     double* row = full + (static_cast<uint64_t>(k) * N + static_cast<uint64_t>(Y0 + wv)) * N;
     row[X0 + lane] = v;  // (the faces at 2^l of a full array are written by k_far_faces)
-    if (KP == 0) cstore((k >> 1) + 1);
+    if (KP == 0) {
+      cstore((k >> 1) + 1);
+      if (SKIP) ring.store(ps, (((k >> 1) + 1) >> 1) + 2, tid);
+    }
     __syncthreads();
   };
+  if (SKIP) {  // the parent planes of the first coarse plane and of the first step's
+#pragma unroll 1
+    for (int K = (Z0 >> 1) >> 1; K <= ((Z0 >> 1) >> 1) + 2; ++K) {
+      ring.fetch(ch, CX0, CY0, K, tid);
+      ring.store(ps, K, tid);
+    }
+    __syncthreads();
+  }
   cfetch(Z0 >> 1);
   cstore(Z0 >> 1);
   fetch_u(Z0);
@@ -1543,24 +1696,36 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
 }
 
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
-                       double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st) {
+                       double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st,
+                       const SecRef* Uc, const double* ucc) {
   if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64) || Gout.B != U.B || !pow2_scale(ih2)) return false;
+  const bool skip = Uc != nullptr;
+  if (skip && (Uc->B != U.B || gc.level < 4 || ucc == nullptr)) return false;
   // tiles of two blocks side by side from 128 nodes per row: half the
   // partial 128-byte lines at the x-edges of the rows of f and the halos
   const bool wide = g.n >= 2 * kTX;
   const int tiles = (g.n / (wide ? 2 * kTX : kTX)) * (g.n / kResTY);
-  const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * g.size + sec_b(Gout);
+  const double coarse = skip ? sec_b(*Uc) + 8.0 * (gc.size >> 3) : 8.0 * gc.size;
+  const double bytes = sec_b(U) + coarse + 8.0 * g.size + sec_b(Gout);
   const PSec pu = psec(U, g), pg = psec(Gout, g);
+  ChainSrc ch{};
+  if (skip) ch = ChainSrc{psec(*Uc, gc), ucc, gc.level};
   const bool hi = U.cbits == 12 || U.cbits == 64, g64 = Gout.cbits == 64;
   const int cb = common_cb({&U, &Gout});
-#define CMG_IRX(XW_, LB_, HI_, GW_, CB_)                                                                            \
-  do {                                                                                                             \
-    constexpr int nt_ = kResNT * (XW_);                                                                            \
-    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_ir_residual<kResTY, nt_, XW_, LB_, HI_, GW_, CB_>), \
-                                nt_, g.n, tiles, 1, 2, 4);                                                         \
-    CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, nt_, XW_, LB_, HI_, GW_, CB_>),                     \
-                dim3(tiles * (g.n / tz)), dim3(nt_), st, pu, uc, f, Lfull, g.level, gc.level, ih2, pg, tz,         \
-                nonfinite, sumsq);                                                                                 \
+#define CMG_IRS(XW_, LB_, HI_, GW_, CB_, SK_)                                                                    \
+  do {                                                                                                          \
+    constexpr int nt_ = kResNT * (XW_);                                                                         \
+    const int tz = chunk_planes(                                                                                \
+        reinterpret_cast<const void*>(&k_ir_residual<kResTY, nt_, XW_, LB_, HI_, GW_, CB_, SK_>), nt_, g.n,      \
+        tiles, 1, 2, 4);                                                                                        \
+    CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, nt_, XW_, LB_, HI_, GW_, CB_, SK_>),             \
+                dim3(tiles * (g.n / tz)), dim3(nt_), st, pu, uc, f, Lfull, g.level, gc.level, ih2, pg, tz,      \
+                nonfinite, sumsq, ch);                                                                          \
+  } while (0)
+#define CMG_IRX(XW_, LB_, HI_, GW_, CB_)                 \
+  do {                                                   \
+    if (skip) CMG_IRS(XW_, LB_, HI_, GW_, CB_, true);     \
+    else CMG_IRS(XW_, LB_, HI_, GW_, CB_, false);         \
   } while (0)
 #define CMG_IR(LB_, HI_, GW_, CB_)                   \
   do {                                               \
@@ -1582,29 +1747,41 @@ bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int L
 #undef CMG_IR2
 #undef CMG_IR
 #undef CMG_IRX
+#undef CMG_IRS
   return true;
 }
 
 bool fused_decode_full(const SecRef& U, const double* uc, const Geom& g, const Geom& gc, double* full,
-                       hipStream_t st) {
+                       hipStream_t st, const SecRef* Uc, const double* ucc) {
   if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64)) return false;
+  const bool skip = Uc != nullptr;
+  if (skip && (Uc->B != U.B || gc.level < 4 || ucc == nullptr)) return false;
   const int64_t N = g.n + 1;
-  const double bytes = sec_b(U) + 8.0 * gc.size + 8.0 * N * N * N;
+  const double coarse = skip ? sec_b(*Uc) + 8.0 * (gc.size >> 3) : 8.0 * gc.size;
+  const double bytes = sec_b(U) + coarse + 8.0 * N * N * N;
   const PSec pu = psec(U, g);
+  ChainSrc ch{};
+  if (skip) ch = ChainSrc{psec(*Uc, gc), ucc, gc.level};
   const int tiles = (g.n / kTX) * (g.n / kDecTY);
   const dim3 block(64 * kDecTY);
   const bool hi = U.cbits == 12 || U.cbits == 64;
   const int cb = common_cb({&U});
-#define CMG_DEC(LB_, HI_, CB_)                                                                                 \
-  do {                                                                                                        \
-    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_decode_full<kDecTY, LB_, false, HI_, CB_>),  \
-                                64 * kDecTY, g.n, tiles, 1, 2, 1);                                               \
-    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, LB_, false, HI_, CB_>), dim3(tiles * (g.n / tz)), \
-                block, st, pu, uc, g.level, gc.level, tz, full);                                              \
+#define CMG_DECS(LB_, HI_, CB_, SK_)                                                                            \
+  do {                                                                                                         \
+    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_decode_full<kDecTY, LB_, false, HI_, CB_, SK_>), \
+                                64 * kDecTY, g.n, tiles, 1, 2, 1);                                                \
+    CMG_FLAUNCH("k_decode_full", bytes, (k_decode_full<kDecTY, LB_, false, HI_, CB_, SK_>),                     \
+                dim3(tiles * (g.n / tz)), block, st, pu, uc, g.level, gc.level, tz, full, ch);                 \
+  } while (0)
+#define CMG_DEC(LB_, HI_, CB_)                  \
+  do {                                          \
+    if (skip) CMG_DECS(LB_, HI_, CB_, true);     \
+    else CMG_DECS(LB_, HI_, CB_, false);         \
   } while (0)
   if (U.B == 64) CMG_BY_CB(CMG_DEC, hi, cb, 6);
   else CMG_BY_CB(CMG_DEC, hi, cb, 5);
 #undef CMG_DEC
+#undef CMG_DECS
   hipLaunchKernelGGL(k_far_faces, dim3(1024), dim3(256), 0, st, full, g.n);
   return true;
 }
@@ -1620,10 +1797,10 @@ bool fused_decode_level(const SecRef& U, const double* uc, const Geom& g, const 
   const int cb = common_cb({&U});
 #define CMG_DEC(LB_, HI_, CB_)                                                                                  \
   do {                                                                                                         \
-    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_decode_full<kDecTY, LB_, true, HI_, CB_>),    \
+    const int tz = chunk_planes(reinterpret_cast<const void*>(&k_decode_full<kDecTY, LB_, true, HI_, CB_, false>), \
                                 64 * kDecTY, g.n, tiles, 1, 2, 1);                                                \
-    CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, LB_, true, HI_, CB_>), dim3(tiles * (g.n / tz)), \
-                block, st, pu, uc, g.level, gc.level, tz, out);                                                \
+    CMG_FLAUNCH("k_decode_level", bytes, (k_decode_full<kDecTY, LB_, true, HI_, CB_, false>),                     \
+                dim3(tiles * (g.n / tz)), block, st, pu, uc, g.level, gc.level, tz, out, ChainSrc{});          \
   } while (0)
   if (U.B == 64) CMG_BY_CB(CMG_DEC, hi, cb, 6);
   else CMG_BY_CB(CMG_DEC, hi, cb, 5);

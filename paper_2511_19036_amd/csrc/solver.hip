@@ -133,6 +133,11 @@ struct cmg_ctx_s {
   bool smooth_fused(int l) const { return fused3d() && l >= 6; }
   bool rr_fused(int l) const { return fused3d() && l >= 7; }
   bool res_fused(int l) const { return compact() && p.dim == 3 && p.op == CMG_POISSON && l >= 6 && !chain(); }
+  // The fused IR residual and final decode of level l rebuild the decoded
+  // solution of level l - 1 from its section and the level below (the
+  // multi-level sweep of the decode chain), so that u_{l-1} is never stored:
+  // the chain of decoded levels ends at l - 2.
+  bool skip_fused(int l) const { return res_fused(l) && l - 2 >= lc(); }
 };
 
 namespace {
@@ -223,7 +228,8 @@ void setup_levels(cmg_ctx c, const double* kappa) {
       if (v1s) D.zf = c->alloc(n * tsz, work);
       if (l < L || v1s) D.ef = c->alloc(n * tsz, work);
       const bool v1res = !c->res_fused(l);
-      if (l < L || d == 2 || v1res) D.uh = static_cast<double*>(c->alloc(n * 8, f64c));
+      const bool rebuilt = l == L - 1 && c->skip_fused(L);  // u_{L-1} is rebuilt where it is read
+      if ((l < L && !rebuilt) || d == 2 || v1res) D.uh = static_cast<double*>(c->alloc(n * 8, f64c));
       if (v1res || l == lc || (c->chain() && l < L)) D.t64 = static_cast<double*>(c->alloc(n * 8, f64c));
       if (v1res || l == lc) D.f64 = static_cast<double*>(c->alloc(n * 8, f64c));
     } else {
@@ -528,10 +534,25 @@ void decode_chain(cmg_ctx c, int top) {
 }
 
 // Decoded solution of FMG level Lp into a full node array (Lp + 1)^dim.
-void decode_to_full(cmg_ctx c, int Lp, double* u) {
+// Where u_{Lp-1} is not stored (skip_fused), `spare` (a section whose codes
+// are dead, e.g. y' of the finest level at the end of a solve) may hold it:
+// it is decoded there in one pass and the final decode reads it; otherwise
+// the final decode rebuilds it plane by plane.
+void decode_to_full(cmg_ctx c, int Lp, double* u, const Section* spare = nullptr) {
   if (c->p.dim == 3 && Lp > c->lc() && c->lv[Lp].g.n >= 64) {
-    decode_chain(c, Lp - 1);
-    if (!fused_decode_full(c->lv[Lp].U.ref(), c->lv[Lp - 1].uh, c->lv[Lp].g, c->lv[Lp - 1].g, u, c->st))
+    const bool skip = c->skip_fused(Lp);
+    decode_chain(c, skip ? Lp - 2 : Lp - 1);
+    LevelData& C = c->lv[Lp - 1];
+    double* uc = skip ? nullptr : C.uh;
+    if (skip && spare != nullptr && spare->bytes >= 8 * C.g.size) {
+      uc = static_cast<double*>(spare->codes);
+      if (!fused_decode_level(C.U.ref(), c->lv[Lp - 2].uh, C.g, c->lv[Lp - 2].g, uc, c->st))
+        launch_prolong_add_dec(C.U.ref(), c->lv[Lp - 2].uh, C.g, c->lv[Lp - 2].g, uc, c->st);
+    }
+    const bool rebuild = uc == nullptr;
+    const SecRef ucs = C.U.ref();
+    if (!fused_decode_full(c->lv[Lp].U.ref(), uc, c->lv[Lp].g, C.g, u, c->st, rebuild ? &ucs : nullptr,
+                           rebuild ? c->lv[Lp - 2].uh : nullptr))
       fail(CMG_ERR_HIP, "fused decode rejected a level it was selected for");
   } else {
     decode_chain(c, Lp);
@@ -567,9 +588,12 @@ void ir_residual(cmg_ctx c, int Lp, const double* f, cmg_stats* st, bool watch =
   launch_monitor_reset(c->mon, c->mon_fresh, c->st);
   c->mon_fresh = false;
   if (c->res_fused(Lp)) {
-    decode_chain(c, Lp - 1);
-    if (!fused_ir_residual(F.U.ref(), c->lv[Lp - 1].uh, f, c->p.L, F.g, c->lv[Lp - 1].g, inv_h2(Lp), F.G.ref(),
-                           c->flags + 1, c->mon, c->st))
+    const bool skip = c->skip_fused(Lp);
+    decode_chain(c, skip ? Lp - 2 : Lp - 1);
+    const SecRef uc = c->lv[Lp - 1].U.ref();
+    if (!fused_ir_residual(F.U.ref(), skip ? nullptr : c->lv[Lp - 1].uh, f, c->p.L, F.g, c->lv[Lp - 1].g, inv_h2(Lp),
+                           F.G.ref(), c->flags + 1, c->mon, c->st, skip ? &uc : nullptr,
+                           skip ? c->lv[Lp - 2].uh : nullptr))
       fail(CMG_ERR_HIP, "fused IR residual rejected a level it was selected for");
     KCK();
   } else {
@@ -632,7 +656,9 @@ void compact_fmg_one(cmg_ctx c, const double* f, double* u, cmg_stats* st) {
       vcycle_correct<T>(c, level);
     }
   }
-  decode_to_full(c, L, u);
+  // y' of the finest level is dead now (and not exported without
+  // keep_correction): its buffer holds u_{L-1} for the final decode
+  decode_to_full(c, L, u, c->o.keep_correction ? nullptr : &c->lv[L].Y);
 }
 
 // Correction-scheme V(nu1, nu2) cycle (supplement Sec. SM1.1.1) on rf[Lp];

@@ -51,7 +51,7 @@ def test_model_bytes_per_dof_follow_the_per_dof_model():
     # correction (codes and float32 z, 1/8 of the values): 8.879 B/DoF
     beta = 2.0 + 2.0 / 64
     assert abs(bench.model_bytes_per_dof("k_up_smooth<4>", 16, 64) - 8.87890625) < 1e-12
-    assert bench.model_bytes_per_dof("k_ir_residual", 16, 64) == 2 * beta + 9.0
+    assert bench.model_bytes_per_dof("k_ir_residual", 16, 64) == 2 * beta + beta / 8 + 8.0 / 64 + 8.0
     assert bench.model_bytes_per_dof("k_down_smooth<4>", 8, 64) == 2 * (1.0 + 2.0 / 64)
 
 
