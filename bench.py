@@ -130,7 +130,9 @@ def _family(kernel_name):
         name = f"{name}<{args[0]}>"
     elif name == "k_decode_full" and args[2] == "true":
         name = "k_decode_level"
-    return name, int(args[-1])
+    # the container is the last integer argument (the IR residual and the
+    # decode end with a flag: whether they rebuild the coarse solution)
+    return name, int([a for a in args if a not in ("true", "false")][-1])
 
 
 def summarize_counters(d, L, bits, block=64):

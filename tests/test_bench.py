@@ -61,3 +61,14 @@ def test_per_level_rows_are_summed_per_kernel():
     got = bench._by_kernel(rows)
     assert [r["kernel"] for r in got] == ["k_a", "k_b"]
     assert got[0]["launches"] == 4 and got[0]["ms"] == 5.0 and got[0]["bytes"] == 9.0
+
+
+def test_kernel_family_names_and_containers():
+    # the profiler's kernel names map to the library's timing names, with the
+    # container (the last integer template argument)
+    assert bench._family("void cmg::k_up_smooth<4, 32, 768, 6, false, 16>(float const*)") == ("k_up_smooth<4>", 16)
+    assert bench._family("void cmg::k_ir_residual<32, 1024, 2, 6, false, false, 16, true>(cmg::PSec)") == \
+        ("k_ir_residual", 16)
+    assert bench._family("void cmg::k_decode_full<8, 6, true, false, 32, false>(cmg::PSec)") == ("k_decode_level", 32)
+    assert bench._family("void cmg::k_decode_full<8, 6, false, false, 16, false>(cmg::PSec)") == ("k_decode_full", 16)
+    assert bench._family("void at::native::reduce_kernel<512, 1>(x)") == (None, None)
