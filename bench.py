@@ -26,20 +26,29 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 # every 4 cycles (16 lanes per SIMD), 2.4 GHz.
 VALU_PEAK = 256 * 4 / 4 * 2.4e9  # wave instructions per second
 CALIB_BYTES = 1 << 30  # size of the calibration copy of the --pmc-pass mode
+# the diffusion pass uses a size no other copy of that run has (building the
+# coefficients copies 1 GiB arrays)
+CALIB_BYTES_DIFF = 3 << 29
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_digest():
-    """SHA-256 of the fused-kernel sources (fused.hip and the device headers
+FUSED_SOURCES = ("fused.hip", "plane.h", "device.h")
+# every kernel and the schedule that launches them (the diffusion workload
+# runs the per-operation kernels)
+ALL_SOURCES = ("kernels.hip", "coarse.hip", "fused.hip", "plane.h", "device.h", "launch.h", "solver.hip")
+
+
+def kernel_source_digest(names=FUSED_SOURCES):
+    """SHA-256 of kernel sources (by default fused.hip and the device headers
     it includes) with comments and blank lines removed, to tell whether
     stored counter readings still describe the kernels being run."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for name in ("fused.hip", "plane.h", "device.h"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2511_19036_amd", "csrc", name)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -69,6 +78,24 @@ def _stored_column(fname, kernel, col):
     if digest != kernel_source_digest():
         return None
     return per_launch.get(kernel)
+
+
+def stored_diffusion_hbm():
+    """The measured HBM rate of the compact 513^3 diffusion solve (GB/s, from
+    the committed summary of its counter passes), or None when the summary
+    is missing or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_diffusion3d_513x8.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            key, sep, val = line.partition(":")
+            if sep and key in ("measured_gbs", "source_sha256_all"):
+                vals[key] = val.strip()
+    if vals.get("source_sha256_all") != kernel_source_digest(ALL_SOURCES) or "measured_gbs" not in vals:
+        return None
+    return float(vals["measured_gbs"])
 
 
 def stored_traffic(kernel):
@@ -488,6 +515,7 @@ def other_workloads():
         top = s.timing_report()[0]
         s.timing(False)
     gbs = top["bytes"] / (top["ms"] * 1e-3)
+    meas = stored_diffusion_hbm()
     fwd = [_rel(u[b], uref[b]) for b in range(B)]
     adj = [_rel(lam[b], lref[b]) for b in range(B)]
     out["diffusion3d_513x8_b16"] = dict(ms_per_solve=ms, dof_per_s=B * 511 ** 3 / (ms * 1e-3),
@@ -498,11 +526,123 @@ def other_workloads():
                                         dominant_kernel=dict(kernel=top["kernel"], ms_per_solve=top["ms"],
                                                              launches=top["launches"], gbs=gbs / 1e9,
                                                              hbm_frac=gbs / HBM_PEAK),
+                                        measured_hbm=None if meas is None else dict(
+                                            gbs=meas, frac=meas * 1e9 / HBM_PEAK,
+                                            source="profiles/hbm_traffic_diffusion3d_513x8.md",
+                                            note="FETCH_SIZE + WRITE_SIZE (calibrated) over the library's "
+                                                 "kernels of one right-hand side's solve, over their summed "
+                                                 "duration"),
                                         note="errors relative L2 against converged float64 solves of the same "
                                              "system; the right-hand sides vary on the grid scale, so the "
                                              "Richardson estimate (2h: children-mean kappa, injected f) is a "
                                              "scale, not a converged discretisation error")
     return out
+
+
+def pmc_pass_diffusion():
+    """For counter and trace runs of the compact 513^3 x 8 diffusion workload
+    of other_workloads, one right-hand side of it (the batch solves its
+    right-hand sides one after another, each with the same kernels): one
+    warm-up solve, a calibration copy of CALIB_BYTES, one measured solve;
+    no JSON."""
+    import torch
+
+    import synthetic
+    from paper_2511_19036_amd import Solver
+    c5 = synthetic.WORKLOADS["diffusion3d_513x8"]
+    L, seed = c5["L"], c5["rhs_seeds"][0]
+    kap = synthetic.lognormal_kappa_torch(3, L, c5["kappa_corr"], c5["kappa_seed"], device="cuda")
+    f = synthetic.smoothed_noise_rhs_torch(3, L, seed, device="cuda")[None].contiguous()
+    with Solver(3, L, op="diffusion", kappa=kap, batch=1, bits=16, ir_iters=c5["ir_iters"]) as s:
+        u = torch.empty_like(f)
+        s.solve(f, u)
+        torch.cuda.synchronize()
+        log("[bench] diffusion pmc pass: warm-up solve done")
+        a = torch.empty(CALIB_BYTES_DIFF // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # the runtime's copy kernel: CALIB_BYTES_DIFF read and written
+        torch.cuda.synchronize()
+        del a, b
+        s.solve(f, u)
+        torch.cuda.synchronize()
+    log("[bench] diffusion pmc pass done")
+
+
+def summarize_diffusion_counters(d):
+    """Markdown table of the measured HBM traffic of one right-hand side of
+    the compact 513^3 x 8 diffusion workload from directory d: dfetch_ and dwrite_
+    counter_collection.csv (FETCH_SIZE, WRITE_SIZE passes of
+    --pmc-pass-diffusion) and dkt_kernel_trace.csv (a kernel trace of the
+    same command).  Rows after the calibration copy (the measured solve);
+    bytes calibrated against the copy as in summarize_counters; per kernel
+    (template arguments kept, call arguments dropped) and in total, for the
+    library's kernels (the counter passes see only those)."""
+    import csv
+    import collections
+
+    def load(name):
+        return list(csv.DictReader(open(os.path.join(d, name))))
+
+    # the calibration copy: the copy whose WRITE_SIZE is CALIB_BYTES_DIFF;
+    # the passes run the same program, so its dispatch id is theirs too
+    wrows = load("dwrite_counter_collection.csv")
+    calib_row = min((r for r in wrows if "copyBuffer" in r["Kernel_Name"]),
+                    key=lambda r: abs(float(r["Counter_Value"]) * 1024.0 - CALIB_BYTES_DIFF))
+    cid = int(calib_row["Dispatch_Id"])
+
+    def after_copy(rows):
+        copies = [r for r in rows if int(r["Dispatch_Id"]) == cid]
+        return copies, [r for r in rows if int(r["Dispatch_Id"]) > cid and "cmg::" in r["Kernel_Name"]]
+
+    def duration(r):
+        return int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+
+    def short(name):
+        name = name[5:] if name.startswith("void ") else name
+        depth = 0
+        for i, ch in enumerate(name):
+            depth += ch == "<"
+            depth -= ch == ">"
+            if ch == "(" and depth == 0:
+                return name[:i]
+        return name
+
+    scale, calib, acc = {}, {}, collections.defaultdict(lambda: [0, 0.0, 0.0, 0.0])
+    for pas, col in (("dfetch", 1), ("dwrite", 2)):
+        copies, rows = after_copy(load(f"{pas}_counter_collection.csv"))
+        c = float(copies[0]["Counter_Value"])
+        calib[pas], scale[pas] = c, CALIB_BYTES_DIFF / (c * 1024.0)
+        for r in rows:
+            a = acc[short(r["Kernel_Name"])]
+            a[col] += float(r["Counter_Value"]) * 1024.0 * scale[pas]
+            if col == 1:
+                a[0] += 1
+    copies, trace = after_copy(load("dkt_kernel_trace.csv"))
+    assert copies and "copyBuffer" in copies[0]["Kernel_Name"], "the trace is not a run of the same program"
+    for r in trace:
+        acc[short(r["Kernel_Name"])][3] += duration(r) * 1e-9
+    tb = sum(a[1] + a[2] for a in acc.values())
+    tt = sum(a[3] for a in acc.values())
+    out = [f"measured_gbs: {tb / tt / 1e9:.1f}",
+           f"source_sha256_all: {kernel_source_digest(ALL_SOURCES)}",
+           "",
+           f"Calibration: the runtime's copy of {CALIB_BYTES_DIFF} bytes reads FETCH_SIZE = {calib['dfetch']:.1f} KiB "
+           f"and WRITE_SIZE = {calib['dwrite']:.1f} KiB (scales {scale['dfetch']:.4f}, {scale['dwrite']:.4f}).",
+           "",
+           f"Measured solve (one right-hand side): {tb / 1e9:.2f} GB of HBM traffic in {tt * 1e3:.1f} ms of "
+           f"kernel time: "
+           f"{tb / tt / 1e9:.0f} GB/s, {tb / tt / HBM_PEAK:.1%} of {HBM_PEAK / 1e12:.0f} TB/s.",
+           "",
+           "| kernel | launches | HBM GB (calibrated) | kernel ms | GB/s | of peak |",
+           "|---|---:|---:|---:|---:|---:|"]
+    for k, a in sorted(acc.items(), key=lambda kv: -kv[1][3]):
+        if a[3] <= 0 or a[3] < 0.005 * tt:
+            continue
+        gb = (a[1] + a[2]) / 1e9
+        out.append(f"| `{k}` | {a[0]} | {gb:.2f} | {a[3] * 1e3:.1f} | {gb / a[3]:.0f} | "
+                   f"{gb * 1e9 / a[3] / HBM_PEAK:.1%} |")
+    return "\n".join(out)
 
 
 def main():
@@ -525,9 +665,17 @@ def main():
                     help="for kernel traces: time only the other workloads and print their figures as JSON")
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="print the markdown tables of the --pmc-pass counter csv files in DIR (no GPU)")
+    ap.add_argument("--pmc-pass-diffusion", action="store_true",
+                    help="for counter and trace runs: one right-hand side of the 513^3 x 8 diffusion workload, "
+                         "warm-up, copy, one solve")
+    ap.add_argument("--summarize-diffusion", metavar="DIR",
+                    help="print the measured HBM table of the --pmc-pass-diffusion csv files in DIR (no GPU)")
     args = ap.parse_args()
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters, args.L, args.bits))
+        return
+    if args.summarize_diffusion:
+        print(summarize_diffusion_counters(args.summarize_diffusion))
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -535,6 +683,9 @@ def main():
         sys.exit(2)
     if args.only_workloads:
         print(json.dumps(other_workloads()), flush=True)
+        return
+    if args.pmc_pass_diffusion:
+        pmc_pass_diffusion()
         return
 
     import torch

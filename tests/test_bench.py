@@ -72,3 +72,39 @@ def test_kernel_family_names_and_containers():
     assert bench._family("void cmg::k_decode_full<8, 6, true, false, 32, false>(cmg::PSec)") == ("k_decode_level", 32)
     assert bench._family("void cmg::k_decode_full<8, 6, false, false, 16, false>(cmg::PSec)") == ("k_decode_full", 16)
     assert bench._family("void at::native::reduce_kernel<512, 1>(x)") == (None, None)
+
+
+def test_stored_diffusion_hbm_follows_the_kernel_sources(monkeypatch):
+    gbs = bench.stored_diffusion_hbm()
+    if gbs is None:
+        pytest.skip("the stored diffusion counters predate the current kernel sources")
+    assert 100.0 < gbs < 8000.0
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda names=None: "0" * 64)
+    assert bench.stored_diffusion_hbm() is None
+
+
+def test_diffusion_summary_takes_the_solve_after_the_calibration_copy(tmp_path):
+    # dispatch 1: another 1 GiB copy (not the calibration); 2: warm-up solve
+    # kernel; 3: the calibration copy; 4, 6: the measured solve's kernels;
+    # 5: a kernel of another library (not counted)
+    cal = bench.CALIB_BYTES_DIFF
+    fetch = {1: 524288.0, 2: 7.0, 3: cal / 2048.0, 4: 1000.0, 6: 300.0}
+    write = {1: 1048576.0, 2: 7.0, 3: cal / 1024.0, 4: 500.0, 6: 100.0}
+    names = {1: "__amd_rocclr_copyBuffer", 2: "void cmg::k_a<1>(int)", 3: "__amd_rocclr_copyBuffer",
+             4: "void cmg::k_a<1>(int)", 5: "void at::native::other(int)", 6: "void cmg::k_b(float*)"}
+    dur = {1: 100, 2: 5, 3: 200, 4: 1000, 5: 7000, 6: 3000}
+    for pas, vals in (("dfetch", fetch), ("dwrite", write)):
+        with open(tmp_path / f"{pas}_counter_collection.csv", "w") as fh:
+            fh.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+            for i, v in vals.items():
+                fh.write(f'{i},"{names[i]}",X,{v}\n')
+    with open(tmp_path / "dkt_kernel_trace.csv", "w") as fh:
+        fh.write("Dispatch_Id,Kernel_Name,Start_Timestamp,End_Timestamp\n")
+        for i, d in dur.items():
+            fh.write(f'{i},"{names[i]}",{1000 * i},{1000 * i + d}\n')
+    out = bench.summarize_diffusion_counters(str(tmp_path))
+    # fetch is scaled by 2 (the copy reads half its bytes), write by 1
+    total = (1000.0 + 300.0) * 1024.0 * 2.0 + (500.0 + 100.0) * 1024.0
+    gbs = total / ((1000 + 3000) * 1e-9) / 1e9
+    assert out.splitlines()[0] == f"measured_gbs: {gbs:.1f}"
+    assert "`cmg::k_a<1>` | 1 |" in out and "at::native" not in out
