@@ -14,9 +14,11 @@ bool fused_down_smooth(const SecRef& G, const SecRef& Y, const Geom& g, int nu, 
 
 // z = P e_{l-1}; Yp = Q(S^nu(dec Y; g_l - A z)); u'_l = Q(u'_l + dec Yp);
 // eout (nullable) = dec Yp + z.  Y (pre-smoothed) is only read: other
-// workgroups read it at their halos while Yp is written.
+// workgroups read it at their halos while Yp is written.  u_zero: U holds
+// zeros that were never written (its codes are read as 0).
 bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const SecRef& Yp, const SecRef& U,
-                     float* eout, const Geom& g, const Geom& gc, int nu, float cp, float ih2, hipStream_t st);
+                     float* eout, const Geom& g, const Geom& gc, int nu, float cp, float ih2, hipStream_t st,
+                     bool u_zero = false);
 
 // g_{l-1} = Q(R(g_l - A y'_l)).
 bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, const Geom& g, const Geom& gc,
@@ -26,10 +28,11 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
 // sumsq (nullable): the IR residual monitor's slots (device.h), which receive
 // sum t^2 (unordered atomics, one per wave).  With Uc (u' of level gc) and
 // ucc (the float64 level array one level below gc), the coarse solution is
-// rebuilt as dec Uc + P ucc where it is needed and uc is not read.
+// rebuilt as dec Uc + P ucc where it is needed and uc is not read.  u_zero:
+// U holds zeros that were never written (its codes are read as 0).
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
                        double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st,
-                       const SecRef* Uc = nullptr, const double* ucc = nullptr);
+                       const SecRef* Uc = nullptr, const double* ucc = nullptr, bool u_zero = false);
 
 // Full node grid u = dec u'_l + P uc (3-D levels of at least 64^3 nodes);
 // Uc and ucc as for fused_ir_residual.

@@ -578,7 +578,7 @@ constexpr int cone_quads(int dist) {
 template <int S, int TY, int NT, int LB, bool HI, int CB>
 __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ ec, PSec G, PSec Y, PSec Yp, PSec U,
                                                      float* __restrict__ eout, int level, int levelc, float cp,
-                                                     float ih2, int TZ) {
+                                                     float ih2, int TZ, int uz) {
   constexpr int H = S;
   static_assert(H % 2 == 0, "even halo: quads start at even coordinates");
   constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H, QW = EXW / 2, QH = EXH / 2, NQ = QW * QH;
@@ -737,7 +737,9 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     for (int t = 0; t < RPW; ++t) {
       const uint32_t xyl = ((static_cast<uint32_t>(Y0 + row_of(t)) << level) | static_cast<uint32_t>(X0)) + lane;
       const double dy = ldexp(static_cast<double>(F.my[t]), F.ey[t] - (Yp.w - 1));  // codes 0 in a zero block
-      vu[t] = code_f64<CB, may64<CB, HI>()>(upre[t], xyl, cbits_of<CB>(U), U.w) + dy;
+      // uz: u' holds zeros that were never written (its first correction
+      // on this FMG level): the codes read are not used
+      vu[t] = (uz ? 0.0 : code_f64<CB, may64<CB, HI>()>(upre[t], xyl, cbits_of<CB>(U), U.w)) + dy;
       F.ev[t] = static_cast<float>(dy);
     }
     quant_f64_rows<LB, may64<CB, HI>(), RPW>(vu, U.w, lane, F.mu, F.eu);
@@ -1126,7 +1128,7 @@ template <int TY, int NT, int XW, int LB, bool HI, bool GW64, int CB, bool SKIP>
 __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __restrict__ uc,
                                                     const double* __restrict__ f, int Lfull, int level, int levelc,
                                                     double ih2, PSec Gout, int TZ, int* nonfinite, double* sumsq,
-                                                    ChainSrc ch) {
+                                                    ChainSrc ch, int uz) {
   // XW blocks of 64 side by side: wave wv owns block wv % XW of rows
   // wv / XW + NWR t
   constexpr int TXW = kTX * XW, NW = NT / 64, NWR = NW / XW, RPT = TY / NWR;
@@ -1288,14 +1290,17 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
         u[t][0] = u[t][1];
         u[t][1] = u[t][2];
         const int ci = ((rr >> 1) + 1) * CW + (xl >> 1) + 1;
-        const double v = code_f64<CB, may64<CB, HI>()>(upre[t], xy_own(t), cbits_of<CB>(U), U.w) +
+        // uz: u' holds zeros that were never written (the first IR
+        // iteration of an FMG level): the codes read are not used
+        const double v = (uz ? 0.0 : code_f64<CB, may64<CB, HI>()>(upre[t], xy_own(t), cbits_of<CB>(U), U.w)) +
                          prolong_node<double, JP, CW, true>(c0, c1, ci, lane & 1, rr & 1);
         u[t][2] = pin ? v : 0.0;
         ub[(rr + 1) * EXW + xl + 1] = u[t][2];
       }
       if (has_h) {
         const double v =
-            code_f64<CB, may64<CB, HI>()>(hpre, xyh, cbits_of<CB>(U), U.w) + prolong_node<double, JP, CW, true>(c0, c1, hci, gxh & 1, gyh & 1);
+            (uz ? 0.0 : code_f64<CB, may64<CB, HI>()>(hpre, xyh, cbits_of<CB>(U), U.w)) +
+            prolong_node<double, JP, CW, true>(c0, c1, hci, gxh & 1, gyh & 1);
         ub[hpos] = (pin && hdom) ? v : 0.0;
       }
     }
@@ -1644,7 +1649,8 @@ bool fused_down_smooth(const SecRef& G, const SecRef& Y, const Geom& g, int nu, 
 }
 
 bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const SecRef& Yp, const SecRef& U,
-                     float* eout, const Geom& g, const Geom& gc, int nu, float cp, float ih2, hipStream_t st) {
+                     float* eout, const Geom& g, const Geom& gc, int nu, float cp, float ih2, hipStream_t st,
+                     bool u_zero) {
   if (g.dim != 3 || g.n < kTX || (nu != 1 && nu != 2) || (G.B != 32 && G.B != 64) || Y.B != G.B || Yp.B != G.B ||
       U.B != G.B || !pow2_scale(ih2))
     return false;
@@ -1660,7 +1666,8 @@ bool fused_up_smooth(const float* ec, const SecRef& G, const SecRef& Y, const Se
     const int tz = chunk_planes(reinterpret_cast<const void*>(&k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_, CB_>), kUpNT, \
                                 g.n, tiles, 1, 2 * (S_) + 2, 2);                                                 \
     CMG_FLAUNCH("k_up_smooth<" #S_ ">", bytes, (k_up_smooth<S_, kUpTY, kUpNT, LB_, HI_, CB_>),                     \
-                dim3(tiles * (g.n / tz)), block, st, ec, pg, py, pp, pu, eout, g.level, gc.level, cp, ih2, tz);  \
+                dim3(tiles * (g.n / tz)), block, st, ec, pg, py, pp, pu, eout, g.level, gc.level, cp, ih2, tz,   \
+                u_zero ? 1 : 0);                                                                                 \
   } while (0)
   if (nu == 2) {
     if (G.B == 64) CMG_BY_CB(CMG_UP, hi, cb, 4, 6);
@@ -1697,7 +1704,7 @@ bool fused_resid_restrict(const SecRef& G, const SecRef& Y, const SecRef& Gc, co
 
 bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int Lfull, const Geom& g, const Geom& gc,
                        double ih2, const SecRef& Gout, int* nonfinite, double* sumsq, hipStream_t st,
-                       const SecRef* Uc, const double* ucc) {
+                       const SecRef* Uc, const double* ucc, bool u_zero) {
   if (g.dim != 3 || g.n < kTX || (U.B != 32 && U.B != 64) || Gout.B != U.B || !pow2_scale(ih2)) return false;
   const bool skip = Uc != nullptr;
   if (skip && (Uc->B != U.B || gc.level < 4 || ucc == nullptr)) return false;
@@ -1720,7 +1727,7 @@ bool fused_ir_residual(const SecRef& U, const double* uc, const double* f, int L
         tiles, 1, 2, 4);                                                                                        \
     CMG_FLAUNCH("k_ir_residual", bytes, (k_ir_residual<kResTY, nt_, XW_, LB_, HI_, GW_, CB_, SK_>),             \
                 dim3(tiles * (g.n / tz)), dim3(nt_), st, pu, uc, f, Lfull, g.level, gc.level, ih2, pg, tz,      \
-                nonfinite, sumsq, ch);                                                                          \
+                nonfinite, sumsq, ch, u_zero ? 1 : 0);                                                          \
   } while (0)
 #define CMG_IRX(XW_, LB_, HI_, GW_, CB_)                 \
   do {                                                   \

@@ -80,6 +80,10 @@ struct LevelData {
   double* s64 = nullptr;  // float64 scratch (coarse solve)
   double* kap64 = nullptr;
   void* kapT = nullptr;
+  // u' of a new FMG level is zero: where the fused IR residual and up sweep
+  // are its first readers, they read its codes as 0 and the zero fill is
+  // left out until another reader needs it (ensure_u)
+  bool u_zero = false;
 };
 
 double inv_h2(int level) { return std::ldexp(1.0, 2 * level); }
@@ -138,6 +142,9 @@ struct cmg_ctx_s {
   // multi-level sweep of the decode chain), so that u_{l-1} is never stored:
   // the chain of decoded levels ends at l - 2.
   bool skip_fused(int l) const { return res_fused(l) && l - 2 >= lc(); }
+  // u' of a new FMG level l is read first by the fused IR residual and up
+  // sweep, which take it as zero without the fill
+  bool u_lazy(int l) const { return smooth_fused(l) && res_fused(l); }
 };
 
 namespace {
@@ -388,6 +395,14 @@ void smooth_from_section(cmg_ctx c, int l, const SecRef& ys, T* y, const T* rhs,
 // correction): z = P e_{l-1} (e_{l-1} in the ef array of level l - 1),
 // y = S^nu2(y'_l; g_l - A z), y'_l = Q(y), u'_l = Q(dec u'_l + dec y'_l) and,
 // below the FMG level, e_l = dec y'_l + z.
+// Write the zeros of a u' section that the fused kernels took as zero.
+void ensure_u(cmg_ctx c, int l) {
+  LevelData& D = c->lv[l];
+  if (!D.u_zero) return;
+  launch_zero_section(D.U.ref(), c->st);
+  D.u_zero = false;
+}
+
 template <typename T>
 void up_level(cmg_ctx c, int l, int Lp) {
   hipStream_t st = c->st;
@@ -402,11 +417,13 @@ void up_level(cmg_ctx c, int l, int Lp) {
     const float cp = static_cast<float>(1.0 / (2.0 * c->p.dim * ih2));
     if (!fused_up_smooth(static_cast<const float*>(C.ef), F.G.ref(), F.Y.ref(), F.Yp.ref(), F.U.ref(),
                          l < Lp ? static_cast<float*>(F.ef) : nullptr, F.g, C.g, c->o.nu_post, cp,
-                         static_cast<float>(ih2), st))
+                         static_cast<float>(ih2), st, F.u_zero))
       fail(CMG_ERR_HIP, "fused up-smoothing rejected a level it was selected for");
+    F.u_zero = false;  // every code of u' is written now
     KCK();
     return;
   }
+  ensure_u(c, l);
   T* yf = static_cast<T*>(F.yf);
   T* zf = static_cast<T*>(F.zf);
   T* rf = static_cast<T*>(F.rf);
@@ -526,6 +543,7 @@ void vcycle_correct(cmg_ctx c, int Lp) {
 // Decoded solution u_l = dec u'_l + P u_{l-1} for levels lc .. top (float64).
 void decode_chain(cmg_ctx c, int top) {
   const int lc = c->lc();
+  for (int l = lc; l <= top; ++l) ensure_u(c, l);
   launch_decode<double>(c->lv[lc].U.ref(), c->lv[lc].g.size, c->lv[lc].uh, c->st);
   for (int l = lc + 1; l <= top; ++l)
     if (!fused_decode_level(c->lv[l].U.ref(), c->lv[l - 1].uh, c->lv[l].g, c->lv[l - 1].g, c->lv[l].uh, c->st))
@@ -539,6 +557,7 @@ void decode_chain(cmg_ctx c, int top) {
 // it is decoded there in one pass and the final decode reads it; otherwise
 // the final decode rebuilds it plane by plane.
 void decode_to_full(cmg_ctx c, int Lp, double* u, const Section* spare = nullptr) {
+  ensure_u(c, Lp);
   if (c->p.dim == 3 && Lp > c->lc() && c->lv[Lp].g.n >= 64) {
     const bool skip = c->skip_fused(Lp);
     decode_chain(c, skip ? Lp - 2 : Lp - 1);
@@ -593,7 +612,7 @@ void ir_residual(cmg_ctx c, int Lp, const double* f, cmg_stats* st, bool watch =
     const SecRef uc = c->lv[Lp - 1].U.ref();
     if (!fused_ir_residual(F.U.ref(), skip ? nullptr : c->lv[Lp - 1].uh, f, c->p.L, F.g, c->lv[Lp - 1].g, inv_h2(Lp),
                            F.G.ref(), c->flags + 1, c->mon, c->st, skip ? &uc : nullptr,
-                           skip ? c->lv[Lp - 2].uh : nullptr))
+                           skip ? c->lv[Lp - 2].uh : nullptr, F.u_zero))
       fail(CMG_ERR_HIP, "fused IR residual rejected a level it was selected for");
     KCK();
   } else {
@@ -627,16 +646,23 @@ void enter_level(cmg_ctx c, int level, const double* f) {
     launch_coarse_single(D.f64, kap64(c, lc), D.g, inv_h2(lc), D.s64, c->st);
     D.U.w = c->wu(lc, lc);
     launch_encode<double>(D.s64, D.g.size, D.U.ref(), c->flags + 1, c->st);
+    D.u_zero = false;
     KCK();
   } else {
     for (int l = lc; l < level; ++l) {
+      ensure_u(c, l);
       Section& U = c->lv[l].U;
       const int wnew = c->wu(l, level);
       if (wnew > U.w) launch_widen(U.ref(), wnew - U.w, c->st);
       U.w = wnew;
     }
     D.U.w = c->wu(level, level);
-    launch_zero_section(D.U.ref(), c->st);
+    if (c->u_lazy(level)) {
+      D.u_zero = true;
+    } else {
+      D.u_zero = false;
+      launch_zero_section(D.U.ref(), c->st);
+    }
     if (D.f64 != nullptr) launch_inject(f, c->p.L, D.g, D.f64, c->st);
     KCK();
   }
@@ -907,6 +933,7 @@ cmg_status cmg_vcycle(cmg_ctx c, const double* r, double* y) {
         for (int l = lc; l <= L; ++l) {
           c->lv[l].U.w = c->wu(l, L);
           launch_zero_section(c->lv[l].U.ref(), c->st);
+          c->lv[l].u_zero = false;
         }
         KCK();
         c->Lp = L;
@@ -1092,6 +1119,7 @@ cmg_status cmg_export_section(cmg_ctx c, int32_t which, int32_t level, void* cod
   return guard(c, [&] {
     Section& s = section_of(c, which, level);
     need(codes_host != nullptr && exps_host != nullptr, "NULL buffer");
+    if (which == CMG_SECTION_U) ensure_u(c, level);
     HIPCK(hipMemcpyAsync(codes_host, s.codes, static_cast<size_t>(s.bytes), hipMemcpyDeviceToHost, c->st));
     HIPCK(hipMemcpyAsync(exps_host, s.exps, static_cast<size_t>(s.nblk) * 2, hipMemcpyDeviceToHost, c->st));
     HIPCK(hipStreamSynchronize(c->st));
@@ -1110,6 +1138,7 @@ cmg_status cmg_import_section(cmg_ctx c, int32_t which, int32_t level, int32_t b
     HIPCK(hipMemcpyAsync(s.exps, exps_host, static_cast<size_t>(s.nblk) * 2, hipMemcpyHostToDevice, c->st));
     HIPCK(hipStreamSynchronize(c->st));
     s.w = bits;
+    if (which == CMG_SECTION_U) c->lv[level].u_zero = false;
   });
 }
 
