@@ -358,3 +358,32 @@ def test_divergence_reported(cmg, storage):
     with cmg.Solver(2, 5, omega=0.8, **kw) as s:
         _, norms = s.solve(f, record=True)
     assert all(b < a for a, b in zip(norms[0::2], norms[1::2]))
+
+
+def test_new_level_solution_reads_as_zero(cmg):
+    """A new FMG level's u' is zero.  On the fused 3-D levels its zero fill
+    is left to the first reader that needs it: decoding the solution, or
+    exporting the section, right after entering the level gives the oracle's
+    decode of the coarser sections with a zero finest section, and the zero
+    section itself."""
+    c = CFGS["3d-L7-b16"]
+    cfg = _oracle_cfg(c)
+    L = c["L"]
+    f = torch.from_numpy(S.gaussian_noise_rhs(3, L, sigma=0.1, seed=2)).cuda()
+    with _solver(cmg, c) as s:
+        for level in range(1, L + 1):
+            s.enter_level(level, f)
+            if 1 < level < L:  # the coarsest level is solved on entry
+                s.ir_residual(f)
+                s.vcycle_correct()
+        u_dec = s.decode_solution(L).cpu().numpy()
+        secs = {level: _export(s, "u", level) for level in range(1, L + 1)}
+    m, e, bits = secs[L]
+    assert bits == cfg.w_u(L, L) and not np.any(m)
+    U = {level: oc.Section(3, level, cfg.block, w, m=mm.astype(np.int64), e=ee.astype(np.int64))
+         for level, (mm, ee, w) in secs.items()}
+    ref = oc.decode_chain(U, 1, L)
+    n = 1 << L
+    assert np.any(ref)
+    assert np.array_equal(u_dec[:n, :n, :n], ref)
+    assert not np.any(u_dec[n]) and not np.any(u_dec[:, n]) and not np.any(u_dec[:, :, n])
