@@ -242,11 +242,13 @@ void setup_levels(cmg_ctx c, const double* kappa) {
     } else {
       // u, r and y per level (the V-cycle runs in place, with fused
       // residual-restriction and prolongation-add kernels); weighted Jacobi
-      // needs a second y array; the float64 solution of the current FMG
-      // level lives in pu[(L - level) & 1]
+      // needs a second y array, and so do the one-launch red-black sweeps
+      // of 3-D levels from 64^3 (out of place: a workgroup's halo must not
+      // see its neighbours' new values); the float64 solution of the
+      // current FMG level lives in pu[(L - level) & 1]
       D.yf = c->alloc(n * tsz, work);
       D.rf = c->alloc(n * tsz, work);
-      if (c->o.smoother == CMG_WJACOBI) D.zf = c->alloc(n * tsz, work);
+      if (c->o.smoother == CMG_WJACOBI || (d == 3 && D.g.n >= 64)) D.zf = c->alloc(n * tsz, work);
       if (l == lc) {
         D.t64 = static_cast<double*>(c->alloc(n * 8, kCoarse64));
         D.f64 = static_cast<double*>(c->alloc(n * 8, kCoarse64));
@@ -701,8 +703,13 @@ void cs_vcycle(cmg_ctx c, int Lp) {
     T* yf = static_cast<T*>(F.yf);
     T* rf = static_cast<T*>(F.rf);
     smooth_from_zero<T>(c, l, yf, rf, static_cast<T*>(F.zf), c->o.nu_pre);
-    launch_restrict_residual<T>(rf, yf, kapT<T>(c, l), C.g, F.g, static_cast<T>(inv_h2(l)), static_cast<T*>(C.rf),
-                                st);
+    if (F.zf != nullptr) {  // residual into the free sweep scratch, then restricted: two coalesced passes
+      launch_rhs_minus_A<T>(rf, yf, kapT<T>(c, l), F.g, static_cast<T>(inv_h2(l)), static_cast<T*>(F.zf), st);
+      launch_restrict<T>(static_cast<const T*>(F.zf), C.g, F.g, static_cast<T*>(C.rf), st);
+    } else {
+      launch_restrict_residual<T>(rf, yf, kapT<T>(c, l), C.g, F.g, static_cast<T>(inv_h2(l)), static_cast<T*>(C.rf),
+                                  st);
+    }
     KCK();
   }
   LevelData& B = c->lv[lc];
