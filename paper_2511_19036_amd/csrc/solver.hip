@@ -393,10 +393,6 @@ void smooth_from_section(cmg_ctx c, int l, const SecRef& ys, T* y, const T* rhs,
   smooth<T>(c, l, y, rhs, scratch, nu);
 }
 
-// Up sweep and correction of level l (Alg. 1, coarse to fine; Alg. 3 apply
-// correction): z = P e_{l-1} (e_{l-1} in the ef array of level l - 1),
-// y = S^nu2(y'_l; g_l - A z), y'_l = Q(y), u'_l = Q(dec u'_l + dec y'_l) and,
-// below the FMG level, e_l = dec y'_l + z.
 // Write the zeros of a u' section that the fused kernels took as zero.
 void ensure_u(cmg_ctx c, int l) {
   LevelData& D = c->lv[l];
@@ -405,6 +401,10 @@ void ensure_u(cmg_ctx c, int l) {
   D.u_zero = false;
 }
 
+// Up sweep and correction of level l (Alg. 1, coarse to fine; Alg. 3 apply
+// correction): z = P e_{l-1} (e_{l-1} in the ef array of level l - 1),
+// y = S^nu2(y'_l; g_l - A z), y'_l = Q(y), u'_l = Q(dec u'_l + dec y'_l) and,
+// below the FMG level, e_l = dec y'_l + z.
 template <typename T>
 void up_level(cmg_ctx c, int l, int Lp) {
   hipStream_t st = c->st;
