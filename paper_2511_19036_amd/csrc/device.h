@@ -100,73 +100,92 @@ __device__ __forceinline__ double raw_value(const SecRef& s, int64_t i, const Ra
 }
 
 // Wave-wide max over groups of `width` lanes (width 32 or 64).
-__device__ __forceinline__ double group_max(double a, int width) {
-  for (int off = width >> 1; off > 0; off >>= 1) a = fmax(a, __shfl_xor(a, off, 64));
-  return a;
+// ------------------------------------------------------- block exponents
+// Block quantisation uses this fact: with E(a) the exponent that a block
+// whose maximum magnitude is a receives (the frexp exponent of a, plus one
+// when a rounds up to 2^(w-1) at w bits), E is non-decreasing in a, so the
+// block exponent equals the largest E over the block's values.  Each lane
+// computes its own E and the block takes an integer maximum over its lanes
+// (DPP row reductions and readlane), which gives the same exponent and codes
+// as rounding the block maximum itself.
+constexpr int kNoExp = INT32_MIN;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+// Max over the lanes of each block of B = 2^LB lanes.  All 64 lanes active.
+// Four DPP steps leave every lane with the maximum of its row of 16; a
+// row_bcast:15 step folds row 0 into row 1 and row 2 into row 3, and for
+// B = 64 a row_bcast:31 step folds lane 31 into rows 2 and 3.  The block
+// maximum is then read from the block's last lane: for B = 64 the result is
+// wave-uniform (a scalar register).
+template <int LB>
+__device__ __forceinline__ int block_max_int(int a, int lane) {
+  a = max(a, dpp_int<0xB1>(a));   // quad_perm 1,0,3,2
+  a = max(a, dpp_int<0x4E>(a));   // quad_perm 2,3,0,1
+  a = max(a, dpp_int<0x141>(a));  // row_half_mirror
+  a = max(a, dpp_int<0x140>(a));  // row_mirror
+  a = max(a, __builtin_amdgcn_update_dpp(INT32_MIN, a, 0x142, 0xA, 0xF, false));  // row_bcast:15, rows 1 and 3
+  if (LB == 6) {
+    a = max(a, __builtin_amdgcn_update_dpp(INT32_MIN, a, 0x143, 0xC, 0xF, false));  // row_bcast:31, rows 2 and 3
+    return __builtin_amdgcn_readlane(a, 63);
+  }
+  const int h0 = __builtin_amdgcn_readlane(a, 31), h1 = __builtin_amdgcn_readlane(a, 63);
+  return lane < 32 ? h0 : h1;
+}
+
+// Per-lane exponent E(|v|) at width w (kNoExp for 0).  With frexp |v| =
+// m 2^e (1/2 <= m < 1), the scaled value m 2^(w-1) rounds to 2^(w-1) at w
+// bits exactly when m >= 1 - 2^-w (its tie rounds to the even 2^(w-1)), so
+// E = e + [m >= lim] with lim = 1 - 2^-w, which is exact in the value's
+// type for the widths used (w <= 24 in float, w <= 53 in double).
+__device__ __forceinline__ float exp_lim(float, int w) { return __int_as_float(0x3F800000 - (1 << (24 - w))); }
+__device__ __forceinline__ double exp_lim(double, int w) {
+  return __longlong_as_double(0x3FF0000000000000LL - (1LL << (53 - w)));
+}
+__device__ __forceinline__ int lane_exp(float v, float lim) {
+  const float a = fabsf(v);
+  const int up = __builtin_amdgcn_frexp_mantf(a) >= lim ? 1 : 0;
+  return a == 0.0f ? kNoExp : __builtin_amdgcn_frexp_expf(a) + up;
+}
+__device__ __forceinline__ int lane_exp(double v, double lim) {
+  const double a = fabs(v);
+  const int up = __builtin_amdgcn_frexp_mant(a) >= lim ? 1 : 0;
+  return a == 0.0 ? kNoExp : __builtin_amdgcn_frexp_exp(a) + up;
+}
+// The exponent of this lane's block of B (32 or 64) lanes.
+template <typename T>
+__device__ __forceinline__ int block_exp(T v, int B, int w, int lane) {
+  const int le = lane_exp(v, exp_lim(v, w));
+  return B == 64 ? block_max_int<6>(le, lane) : block_max_int<5>(le, lane);
 }
 
 // Quantise the value v held by this lane into its block (the lanes of one
-// group of B lanes form one block).  Returns the code; *e_out the exponent.
+// group of B lanes form one block; every lane of the wave active).  Returns
+// the code; *e_out the exponent (kZeroExp for an all-zero block).
 __device__ __forceinline__ int64_t quantise_lane(double v, int B, int w, int* e_out) {
-  const double a = group_max(fabs(v), B);
-  if (a == 0.0) {
+  const int E = block_exp(v, B, w, static_cast<int>(threadIdx.x & 63));
+  if (E == kNoExp) {
     *e_out = kZeroExp;
     return 0;
   }
-  int e;
-  (void)frexp(a, &e);                  // 2^(e-1) <= a < 2^e
-  int q = e - (w - 1);
-  if (rint(ldexp(a, -q)) == ldexp(1.0, w - 1)) {  // the max rounds up to 2^(w-1)
-    ++e;
-    ++q;
-  }
-  *e_out = e;
-  return static_cast<int64_t>(rint(ldexp(v, -q)));
-}
-
-// --------------------------------------------------- wave reductions (DPP)
-// Max over each 16-lane row by quad permutes and row mirrors, then over the
-// rows of one block (B = 64: all four rows; B = 32: rows 0-1 and 2-3) with
-// readlane.  Every lane of the wave must be active.
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-__device__ __forceinline__ float dpp_maxf(float a) {
-  a = fmaxf(a, __int_as_float(dpp_i<0xB1>(__float_as_int(a))));   // quad_perm 1,0,3,2
-  a = fmaxf(a, __int_as_float(dpp_i<0x4E>(__float_as_int(a))));   // quad_perm 2,3,0,1
-  a = fmaxf(a, __int_as_float(dpp_i<0x141>(__float_as_int(a))));  // row_half_mirror
-  a = fmaxf(a, __int_as_float(dpp_i<0x140>(__float_as_int(a))));  // row_mirror
-  return a;
-}
-__device__ __forceinline__ float block_maxf(float a, int B, int lane) {
-  a = dpp_maxf(a);
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 48));
-  if (B == 64) return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
-  return lane < 32 ? fmaxf(r0, r1) : fmaxf(r2, r3);
+  *e_out = E;
+  return static_cast<int64_t>(rint(ldexp(v, w - 1 - E)));
 }
 
 // Quantise a float32 value; identical codes to quantise_lane for w <= 24:
 // a float scaled by a power of two stays exact, and results in the float
 // subnormal range lie far below 1/2 and round to zero either way.
 __device__ __forceinline__ int32_t quantise_lane_f32(float v, int B, int w, int lane, int* e_out) {
-  const float a = block_maxf(fabsf(v), B, lane);
-  if (a == 0.0f) {
+  const int E = block_exp(v, B, w, lane);
+  if (E == kNoExp) {
     *e_out = kZeroExp;
     return 0;
   }
-  int e;
-  (void)frexpf(a, &e);
-  int q = e - (w - 1);
-  if (rintf(ldexpf(a, -q)) == ldexpf(1.0f, w - 1)) {
-    ++e;
-    ++q;
-  }
-  *e_out = e;
-  return static_cast<int32_t>(rintf(ldexpf(v, -q)));
+  *e_out = E;
+  return static_cast<int32_t>(rintf(ldexpf(v, w - 1 - E)));
 }
 
 // Store the 64 codes held by the 64 lanes of a wave at values base..base+63.

@@ -41,7 +41,10 @@ __global__ void __launch_bounds__(kThreads) k_encode(const T* x, int64_t n, SecR
   // the decoded value of the new code, as k_decode gives it (plus add)
   const double dv = e == kZeroExp ? 0.0 : ldexp(static_cast<double>(m), e - (s.w - 1));
   if (out != nullptr && i < n) {
-    const T d = static_cast<T>(dv);
+    // a float result of width <= 24 rounds once either way (see decode_value_f32)
+    const T d = (std::is_same<T, float>::value && s.w <= 24)
+                    ? static_cast<T>(e == kZeroExp ? 0.0f : ldexpf(static_cast<float>(m), e - (s.w - 1)))
+                    : static_cast<T>(dv);
     out[i] = add != nullptr ? d + add[i] : d;
   }
   // u <- Q(dec u + dec s), as k_correct computes it (u has the blocks of s)
@@ -54,10 +57,20 @@ __global__ void __launch_bounds__(kThreads) k_encode(const T* x, int64_t n, SecR
   }
 }
 
+// Value i of a section as float with width <= 24: the code converts exactly
+// and the scaling rounds once, as the conversion of decode_value's exact
+// double does (a zero block's codes are 0, so its sentinel exponent
+// scales 0 to 0).
+__device__ __forceinline__ float decode_value_f32(const SecRef& s, int64_t i) {
+  return ldexpf(static_cast<float>(load_code(s, i)), s.exps[blk(s, i)] - (s.w - 1));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_decode(SecRef s, int64_t n, T* __restrict__ x) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  if (i < n) x[i] = static_cast<T>(decode_value(s, i));
+  if (i >= n) return;
+  if (std::is_same<T, float>::value && s.w <= 24) x[i] = static_cast<T>(decode_value_f32(s, i));
+  else x[i] = static_cast<T>(decode_value(s, i));
 }
 
 // Append k zero bits to every code (exponents unchanged).
@@ -283,6 +296,45 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const T* __restrict__ coar
   int i, j, k;
   unflatten(gf, idx, i, j, k);
   fine[idx] = prolong_at(coarse, gc, i, j, k);
+}
+
+// k_prolong on a 3-D level of at most 2^30 nodes: prolong_at's terms and
+// order (z, y, x; a product by the weight, then the sum), with 32-bit
+// indices; every coarse neighbour is loaded (clamped into the level) and
+// the terms are chosen by selects, so that no load sits under a branch.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_prolong3(const T* __restrict__ coarse, int lf, T* __restrict__ fine) {
+  const uint32_t idx = blockIdx.x * kThreads + threadIdx.x;
+  const int nf = 1 << lf, lc = lf - 1, nc = nf >> 1;
+  if (idx >= (1u << (3 * lf))) return;
+  const int i = idx & (nf - 1), j = (idx >> lf) & (nf - 1), k = idx >> (2 * lf);
+  const int ti = i >> 1, tj = j >> 1, tk = k >> 1;
+  const bool px = i & 1, py = j & 1, pz = k & 1;
+  const T w = static_cast<T>((px ? 0.5 : 1.0) * (py ? 0.5 : 1.0) * (pz ? 0.5 : 1.0));
+  // coarse value at (ti + ox, tj + oy, tk + oz); the far boundary node nc is 0
+  auto at = [&](int ox, int oy, int oz) {
+    const int a = ti + ox, b = tj + oy, c = tk + oz;
+    const uint32_t q = (static_cast<uint32_t>(min(c, nc - 1)) << (2 * lc)) |
+                       (static_cast<uint32_t>(min(b, nc - 1)) << lc) | static_cast<uint32_t>(min(a, nc - 1));
+    const T v = coarse[q];
+    return (a < nc && b < nc && c < nc) ? v : T(0);
+  };
+  T s = w * at(0, 0, 0);
+  T t = s + w * at(1, 0, 0);
+  s = px ? t : s;
+  t = s + w * at(0, 1, 0);
+  s = py ? t : s;
+  t = s + w * at(1, 1, 0);
+  s = (px && py) ? t : s;
+  t = s + w * at(0, 0, 1);
+  s = pz ? t : s;
+  t = s + w * at(1, 0, 1);
+  s = (pz && px) ? t : s;
+  t = s + w * at(0, 1, 1);
+  s = (pz && py) ? t : s;
+  t = s + w * at(1, 1, 1);
+  s = (pz && px && py) ? t : s;
+  fine[idx] = s;
 }
 
 // out = dec(section) + P coarse, float64 (one step of the decode chain).
@@ -864,8 +916,12 @@ void launch_res_encode(const double* f, const double* u, const double* kap, cons
 }
 template <typename T>
 void launch_prolong(const T* coarse, const Geom& gf, const Geom& gc, T* fine, hipStream_t st) {
-  CMG_TLAUNCH(tname("k_prolong", TName<T>::s).c_str(), (gf.size + gc.size) * sizeof(T), k_prolong<T>, gf.size, st,
-              coarse, gf, gc, fine);
+  if (gf.dim == 3 && gf.level <= 10)
+    CMG_TLAUNCH(tname("k_prolong", TName<T>::s).c_str(), (gf.size + gc.size) * sizeof(T), k_prolong3<T>, gf.size, st,
+                coarse, gf.level, fine);
+  else
+    CMG_TLAUNCH(tname("k_prolong", TName<T>::s).c_str(), (gf.size + gc.size) * sizeof(T), k_prolong<T>, gf.size, st,
+                coarse, gf, gc, fine);
 }
 void launch_prolong_add_dec(const SecRef& s, const double* coarse, const Geom& gf, const Geom& gc, double* out,
                             hipStream_t st) {

@@ -248,53 +248,7 @@ __device__ __forceinline__ void opaque_sec(PSec& s) {
 }
 
 // ------------------------------------------------------- block exponents
-constexpr int kNoExp = INT32_MIN;
-
-template <int CTRL>
-__device__ __forceinline__ int dpp_int(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-
-// Max over the lanes of each block of B = 2^LB lanes.  All 64 lanes active.
-// Four DPP steps leave every lane with the maximum of its row of 16; a
-// row_bcast:15 step folds row 0 into row 1 and row 2 into row 3, and for
-// B = 64 a row_bcast:31 step folds lane 31 into rows 2 and 3.  The block
-// maximum is then read from the block's last lane: for B = 64 the result is
-// wave-uniform (a scalar register).
-template <int LB>
-__device__ __forceinline__ int block_max_int(int a, int lane) {
-  a = max(a, dpp_int<0xB1>(a));   // quad_perm 1,0,3,2
-  a = max(a, dpp_int<0x4E>(a));   // quad_perm 2,3,0,1
-  a = max(a, dpp_int<0x141>(a));  // row_half_mirror
-  a = max(a, dpp_int<0x140>(a));  // row_mirror
-  a = max(a, __builtin_amdgcn_update_dpp(INT32_MIN, a, 0x142, 0xA, 0xF, false));  // row_bcast:15, rows 1 and 3
-  if (LB == 6) {
-    a = max(a, __builtin_amdgcn_update_dpp(INT32_MIN, a, 0x143, 0xC, 0xF, false));  // row_bcast:31, rows 2 and 3
-    return __builtin_amdgcn_readlane(a, 63);
-  }
-  const int h0 = __builtin_amdgcn_readlane(a, 31), h1 = __builtin_amdgcn_readlane(a, 63);
-  return lane < 32 ? h0 : h1;
-}
-
-// Per-lane exponent E(|v|) at width w (kNoExp for 0).  With frexp |v| =
-// m 2^e (1/2 <= m < 1), the scaled value m 2^(w-1) rounds to 2^(w-1) at w
-// bits exactly when m >= 1 - 2^-w (its tie rounds to the even 2^(w-1)), so
-// E = e + [m >= lim] with lim = 1 - 2^-w, which is exact in the value's
-// type for the widths used (w <= 24 in float, w <= 53 in double).
-__device__ __forceinline__ float exp_lim(float, int w) { return __int_as_float(0x3F800000 - (1 << (24 - w))); }
-__device__ __forceinline__ double exp_lim(double, int w) {
-  return __longlong_as_double(0x3FF0000000000000LL - (1LL << (53 - w)));
-}
-__device__ __forceinline__ int lane_exp(float v, float lim) {
-  const float a = fabsf(v);
-  const int up = __builtin_amdgcn_frexp_mantf(a) >= lim ? 1 : 0;
-  return a == 0.0f ? kNoExp : __builtin_amdgcn_frexp_expf(a) + up;
-}
-__device__ __forceinline__ int lane_exp(double v, double lim) {
-  const double a = fabs(v);
-  const int up = __builtin_amdgcn_frexp_mant(a) >= lim ? 1 : 0;
-  return a == 0.0 ? kNoExp : __builtin_amdgcn_frexp_exp(a) + up;
-}
+// (dpp_int, block_max_int, exp_lim, lane_exp and kNoExp: device.h)
 
 // Quantise the value of each lane into its block (w <= 24): returns the code,
 // *e_out the block exponent (kZeroExp for an all-zero block).
