@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kCoarseNT) k_coarse_vcycle(CoarseArgs a) {
       if (u != nullptr) {  // u' <- Q(dec u' + dec y')
         const double vu = (i < limit) ? decode_value(*u, i) + d : 0.0;
         int eu;
-        const int64_t mu = quantise_lane(vu, u->B, u->w, &eu);
+        const int64_t mu = quantise_lane(vu, u->B, corr_width(*u), &eu);
         store_codes_wave(*u, base, lane, mu, limit);
         if ((lane & (u->B - 1)) == 0 && i < limit) u->exps[blk(*u, i)] = static_cast<int16_t>(eu);
       }

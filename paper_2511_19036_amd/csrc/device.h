@@ -25,9 +25,14 @@ struct SecRef {
   int16_t* exps;    // one exponent per block
   int64_t n;        // values (padded level size)
   int32_t B;        // block length, 32 or 64
-  int32_t w;        // current logical width (bits, sign included)
+  int32_t w;        // width of the stored codes (bits, sign included): decoding uses it
   int32_t cbits;    // container: 8, 12, 16, 32 or 64
+  // Width a correction (u <- Q(dec u + dec y)) quantises the new codes to;
+  // 0: w.  Widening a section to a new FMG level's width changes no value,
+  // so it is left to the section's first correction on that level.
+  int32_t wq = 0;
 };
+__host__ __device__ __forceinline__ int corr_width(const SecRef& s) { return s.wq > 0 ? s.wq : s.w; }
 
 // ------------------------------------------------------------------ codes
 // Block index of value i (B is 32 or 64: a shift, never a division).

@@ -742,7 +742,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       vu[t] = (uz ? 0.0 : code_f64<CB, may64<CB, HI>()>(upre[t], xyl, cbits_of<CB>(U), U.w)) + dy;
       F.ev[t] = static_cast<float>(dy);
     }
-    quant_f64_rows<LB, may64<CB, HI>(), RPW>(vu, U.w, lane, F.mu, F.eu);
+    quant_f64_rows<LB, may64<CB, HI>(), RPW>(vu, U.wq, lane, F.mu, F.eu);
     if (eout != nullptr) {
 #pragma unroll
       for (int t = 0; t < RPW; ++t) {
@@ -1610,6 +1610,7 @@ static PSec psec(const SecRef& s, const Geom& g) {
   p.plane_blks = static_cast<uint32_t>(pv / s.B);
   p.cbits = s.cbits;
   p.w = s.w;
+  p.wq = corr_width(s);
   return p;
 }
 

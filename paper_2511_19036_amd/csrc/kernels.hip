@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(kThreads) k_encode(const T* x, int64_t n, SecR
   if (correct) {
     const double vu = (i < limit) ? decode_value(u, i) + dv : 0.0;
     int eu;
-    const int64_t mu = quantise_lane(vu, u.B, u.w, &eu);
+    const int64_t mu = quantise_lane(vu, u.B, corr_width(u), &eu);
     store_codes_wave(u, base, lane, mu, limit);
     if ((lane & (u.B - 1)) == 0 && i < limit) u.exps[blk(u, i)] = static_cast<int16_t>(eu);
   }
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(kThreads) k_correct(SecRef u, SecRef y) {
   const int64_t i = base + lane;
   const double v = (i < limit) ? decode_value(u, i) + decode_value(y, i) : 0.0;
   int e;
-  const int64_t m = quantise_lane(v, u.B, u.w, &e);
+  const int64_t m = quantise_lane(v, u.B, corr_width(u), &e);
   store_codes_wave(u, base, lane, m, limit);
   if ((lane & (u.B - 1)) == 0 && i < limit) u.exps[blk(u, i)] = static_cast<int16_t>(e);
 }

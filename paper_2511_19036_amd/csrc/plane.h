@@ -28,7 +28,8 @@ struct PSec {
   uint32_t plane_bytes;  // 4^l * cbits / 8
   uint32_t plane_blks;   // 4^l / B
   int32_t cbits;         // 8, 12, 16, 32 or 64
-  int32_t w;             // logical width, sign included
+  int32_t w;             // width of the stored codes, sign included
+  int32_t wq;            // width of a correction's new codes (SecRef::wq, resolved)
 };
 
 struct PlanePtr {

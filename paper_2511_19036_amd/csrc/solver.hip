@@ -60,8 +60,19 @@ struct Section {
   void* codes = nullptr;
   int16_t* exps = nullptr;
   int64_t n = 0, nblk = 0, bytes = 0;
-  int B = 64, w = 2, cbits = 8;
+  // w: width of the stored codes (what decoding uses); wt: the section's
+  // width on the current FMG level (u' only: raised on entering a level,
+  // reached by the codes at the section's next correction, or by widening
+  // them when they are exported)
+  int B = 64, w = 2, wt = 2, cbits = 8;
   SecRef ref() const { return SecRef{codes, exps, n, B, w, cbits}; }
+  // for a correction u <- Q(dec u + dec y): new codes of width wt
+  SecRef ref_corr() const {
+    SecRef r = ref();
+    r.wq = wt;
+    return r;
+  }
+  void set_w(int bits) { w = wt = bits; }
 };
 
 struct LevelData {
@@ -197,7 +208,7 @@ void alloc_section(cmg_ctx c, Section& s, const Geom& g, int wmax) {
   s.B = c->o.bfp_block;
   s.nblk = n_blocks(s.n, s.B);
   s.cbits = container_bits(wmax);
-  s.w = wmax;
+  s.set_w(wmax);
   s.bytes = code_bytes(s.n, s.B, wmax);
   // 16 bytes of padding: the fused kernels read codes as 8-byte windows
   s.codes = c->alloc(static_cast<size_t>(s.bytes) + 16, kSections);
@@ -414,14 +425,15 @@ void up_level(cmg_ctx c, int l, int Lp) {
   const double ih2 = inv_h2(l);
   F.Y.w = c->wy(l, Lp);
   F.Yp.w = c->wy(l, Lp);
-  F.U.w = c->wu(l, Lp);
+  F.U.wt = c->wu(l, Lp);  // the correction writes codes of this width
   if (std::is_same<T, float>::value && c->smooth_fused(l)) {
     const float cp = static_cast<float>(1.0 / (2.0 * c->p.dim * ih2));
-    if (!fused_up_smooth(static_cast<const float*>(C.ef), F.G.ref(), F.Y.ref(), F.Yp.ref(), F.U.ref(),
+    if (!fused_up_smooth(static_cast<const float*>(C.ef), F.G.ref(), F.Y.ref(), F.Yp.ref(), F.U.ref_corr(),
                          l < Lp ? static_cast<float*>(F.ef) : nullptr, F.g, C.g, c->o.nu_post, cp,
                          static_cast<float>(ih2), st, F.u_zero))
       fail(CMG_ERR_HIP, "fused up-smoothing rejected a level it was selected for");
-    F.u_zero = false;  // every code of u' is written now
+    F.u_zero = false;  // every code of u' is written now, at width wt
+    F.U.w = F.U.wt;
     KCK();
     return;
   }
@@ -433,8 +445,9 @@ void up_level(cmg_ctx c, int l, int Lp) {
   launch_dec_minus_A<T>(F.G.ref(), zf, kapT<T>(c, l), F.g, static_cast<T>(ih2), rf, st);  // dec g - A z
   smooth_from_section<T>(c, l, F.Y.ref(), yf, rf, static_cast<T*>(F.ef), c->o.nu_post);
   // y' = Q(y); u' = Q(dec u' + dec y'); below the top level e_l = dec y' + z
-  const SecRef u = F.U.ref();
+  const SecRef u = F.U.ref_corr();
   launch_encode_dec<T>(yf, F.g.size, F.Yp.ref(), nf, l < Lp ? static_cast<T*>(F.ef) : nullptr, zf, &u, st);
+  F.U.w = F.U.wt;
   KCK();
 }
 
@@ -503,13 +516,13 @@ void vcycle_correct(cmg_ctx c, int Lp) {
       LevelData& D = c->lv[l];
       D.Y.w = c->wy(l, Lp);
       D.Yp.w = c->wy(l, Lp);
-      D.U.w = c->wu(l, Lp);
+      D.U.wt = c->wu(l, Lp);
       if (l < Lc) D.G.w = c->wr(l, Lp);
       CoarseLevel& q = a.lv[l];
       q.G = D.G.ref();
       q.Y = D.Y.ref();
       q.Yp = D.Yp.ref();
-      q.U = D.U.ref();
+      q.U = D.U.ref_corr();
       q.ef = D.ef;
       a.off[l] = l == lc ? 0 : a.off[l - 1] + 5 * static_cast<int>(c->lv[l - 1].g.size);
       q.kap = kapT<T>(c, l);
@@ -528,14 +541,16 @@ void vcycle_correct(cmg_ctx c, int Lp) {
     a.chain = c->chain() ? 1 : 0;
     a.nonfinite = nf;
     launch_coarse_vcycle<T>(a, st);
+    for (int l = lc; l <= Lc; ++l) c->lv[l].U.w = c->lv[l].U.wt;  // corrected at width wt
     KCK();
   } else {
     launch_decode<double>(B.G.ref(), B.g.size, B.t64, st);
     launch_coarse_single(B.t64, kap64(c, lc), B.g, inv_h2(lc), B.s64, st);
     B.Yp.w = c->wy(lc, Lp);
     launch_encode<double>(B.s64, B.g.size, B.Yp.ref(), nf, st);
-    B.U.w = c->wu(lc, Lp);
-    launch_correct(B.U.ref(), B.Yp.ref(), st);
+    B.U.wt = c->wu(lc, Lp);
+    launch_correct(B.U.ref_corr(), B.Yp.ref(), st);
+    B.U.w = B.U.wt;
     launch_decode<T>(B.Yp.ref(), B.g.size, static_cast<T*>(B.ef), st);
     KCK();
   }
@@ -646,19 +661,18 @@ void enter_level(cmg_ctx c, int level, const double* f) {
   if (level == lc) {
     launch_inject(f, c->p.L, D.g, D.f64, c->st);
     launch_coarse_single(D.f64, kap64(c, lc), D.g, inv_h2(lc), D.s64, c->st);
-    D.U.w = c->wu(lc, lc);
+    D.U.set_w(c->wu(lc, lc));
     launch_encode<double>(D.s64, D.g.size, D.U.ref(), c->flags + 1, c->st);
     D.u_zero = false;
     KCK();
   } else {
+    // the coarser u' sections take the new level's widths (Table 1) at their
+    // first correction on it: widening only appends zero bits to the codes
     for (int l = lc; l < level; ++l) {
       ensure_u(c, l);
-      Section& U = c->lv[l].U;
-      const int wnew = c->wu(l, level);
-      if (wnew > U.w) launch_widen(U.ref(), wnew - U.w, c->st);
-      U.w = wnew;
+      c->lv[l].U.wt = c->wu(l, level);
     }
-    D.U.w = c->wu(level, level);
+    D.U.set_w(c->wu(level, level));
     if (c->u_lazy(level)) {
       D.u_zero = true;
     } else {
@@ -938,7 +952,7 @@ cmg_status cmg_vcycle(cmg_ctx c, const double* r, double* y) {
           launch_encode_full(r + b * M, L, F.g, F.G.ref(), c->flags + 1, c->st);
         }
         for (int l = lc; l <= L; ++l) {
-          c->lv[l].U.w = c->wu(l, L);
+          c->lv[l].U.set_w(c->wu(l, L));
           launch_zero_section(c->lv[l].U.ref(), c->st);
           c->lv[l].u_zero = false;
         }
@@ -1114,7 +1128,7 @@ cmg_status cmg_section_info(cmg_ctx c, int32_t which, int32_t level, int64_t* n_
   return guard(c, [&] {
     Section& s = section_of(c, which, level);
     if (n_values) *n_values = s.n;
-    if (bits) *bits = s.w;
+    if (bits) *bits = which == CMG_SECTION_U && s.wt > s.w ? s.wt : s.w;  // u': its width on this FMG level
     if (cbits) *cbits = s.cbits;
     if (bytes) *bytes = s.bytes;
     if (nblk) *nblk = s.nblk;
@@ -1126,7 +1140,13 @@ cmg_status cmg_export_section(cmg_ctx c, int32_t which, int32_t level, void* cod
   return guard(c, [&] {
     Section& s = section_of(c, which, level);
     need(codes_host != nullptr && exps_host != nullptr, "NULL buffer");
-    if (which == CMG_SECTION_U) ensure_u(c, level);
+    if (which == CMG_SECTION_U) {
+      ensure_u(c, level);
+      if (s.wt > s.w) {  // codes of the section's width on this FMG level
+        launch_widen(s.ref(), s.wt - s.w, c->st);
+        s.w = s.wt;
+      }
+    }
     HIPCK(hipMemcpyAsync(codes_host, s.codes, static_cast<size_t>(s.bytes), hipMemcpyDeviceToHost, c->st));
     HIPCK(hipMemcpyAsync(exps_host, s.exps, static_cast<size_t>(s.nblk) * 2, hipMemcpyDeviceToHost, c->st));
     HIPCK(hipStreamSynchronize(c->st));
@@ -1144,7 +1164,7 @@ cmg_status cmg_import_section(cmg_ctx c, int32_t which, int32_t level, int32_t b
     HIPCK(hipMemcpyAsync(s.codes, codes_host, static_cast<size_t>(s.bytes), hipMemcpyHostToDevice, c->st));
     HIPCK(hipMemcpyAsync(s.exps, exps_host, static_cast<size_t>(s.nblk) * 2, hipMemcpyHostToDevice, c->st));
     HIPCK(hipStreamSynchronize(c->st));
-    s.w = bits;
+    s.set_w(bits);
     if (which == CMG_SECTION_U) c->lv[level].u_zero = false;
   });
 }

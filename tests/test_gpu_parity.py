@@ -362,10 +362,11 @@ def test_divergence_reported(cmg, storage):
 
 def test_new_level_solution_reads_as_zero(cmg):
     """A new FMG level's u' is zero.  On the fused 3-D levels its zero fill
-    is left to the first reader that needs it: decoding the solution, or
-    exporting the section, right after entering the level gives the oracle's
-    decode of the coarser sections with a zero finest section, and the zero
-    section itself."""
+    is left to the first reader that needs it, and the coarser sections
+    take the level's widths at their first correction: decoding the
+    solution, or exporting the sections, right after entering the level
+    gives the oracle's decode of the coarser sections with a zero finest
+    section, the zero section itself and the widened coarser ones."""
     c = CFGS["3d-L7-b16"]
     cfg = _oracle_cfg(c)
     L = c["L"]
@@ -380,6 +381,9 @@ def test_new_level_solution_reads_as_zero(cmg):
         secs = {level: _export(s, "u", level) for level in range(1, L + 1)}
     m, e, bits = secs[L]
     assert bits == cfg.w_u(L, L) and not np.any(m)
+    # the coarser sections come out at this level's widths (Table 1), their
+    # codes widened on export: the same values
+    assert all(w == cfg.w_u(level, L) for level, (_, _, w) in secs.items())
     U = {level: oc.Section(3, level, cfg.block, w, m=mm.astype(np.int64), e=ee.astype(np.int64))
          for level, (mm, ee, w) in secs.items()}
     ref = oc.decode_chain(U, 1, L)
