@@ -588,11 +588,16 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   constexpr int LPL = EXW * EXH, PS = LPL + 2 * EXW + 2, PAD = EXW + 2;
   constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;
   constexpr int NB = S + 1;  // y buffers: plane j - 1 - s in flight from step j - s to j - s + S
-  constexpr int NC = 8, CW = QW + 2, CH = QH + 1, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
+  // coarse planes: step j reads planes j >> 1 and (j >> 1) + 1 (an odd
+  // plane) or only j >> 1 (an even one, which then stores plane (j >> 1) + 1)
+  constexpr int NC = 2, CW = QW + 2, CH = QH + 1, CPL = CW * CH, CPT = (CPL + NT - 1) / NT;
   constexpr int OB = TY * kTX + 2 * kTX;  // output tile plus two spare rows (written by the other quads)
-  __shared__ float cs[NC * CPL + 1];       // plus a spare word (written by threads past the coarse tile)
+  constexpr int NZ = S + 1;               // z of the output tile: planes j - 2 - S .. j - 2
+  __shared__ float cs[NC * CPL + 1];      // plus a spare word (written by threads past the coarse tile)
   __shared__ __align__(8) float lds[2 * PAD + (2 + NB) * PS];  // z of planes j, j - 1; then y buffers
   __shared__ __align__(8) float outb[2][OB];
+  __shared__ __align__(8) float zo[NZ * OB];
+  auto zslot = [&](int p) { return zo + ((p + 8 * NZ) % NZ) * OB; };  // p >= -S - 2
   const int tid = threadIdx.x;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   int lane = tid & 63;
@@ -722,11 +727,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     int64_t mu[RPW];
     float ev[RPW];
   };
-  auto finish_compute = [&](auto pkc, int po, const float* ob, Fin& F) {
-    constexpr int PK = decltype(pkc)::value;
+  auto finish_compute = [&](int po, const float* ob, Fin& F) {
     if (po < Z0 || po >= Z0 + TZ) return;
-    const float* c0 = cs + ((po >> 1) & (NC - 1)) * CPL;
-    const float* c1 = cs + (((po >> 1) + 1) & (NC - 1)) * CPL;
     // the rows are quantised together (their DPP reductions interleave)
     float yv[RPW];
 #pragma unroll
@@ -743,13 +745,10 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       F.ev[t] = static_cast<float>(dy);
     }
     quant_f64_rows<LB, may64<CB, HI>(), RPW>(vu, U.wq, lane, F.mu, F.eu);
-    if (eout != nullptr) {
+    if (eout != nullptr) {  // z of the plane, kept since its own step
+      const float* zb = zslot(po);
 #pragma unroll
-      for (int t = 0; t < RPW; ++t) {
-        const int rr = row_of(t);
-        const int cix = ((rr >> 1) + H / 2) * CW + (lane >> 1) + H / 2;
-        F.ev[t] = F.ev[t] + prolong_node<float, PK, CW>(c0, c1, cix, lane & 1, rr & 1);
-      }
+      for (int t = 0; t < RPW; ++t) F.ev[t] = F.ev[t] + zb[row_of(t) * kTX + lane];
     }
   };
   // Yp is stored only when the caller keeps it (no buffers otherwise).
@@ -788,7 +787,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     auto ybuf = [&](int s) { return lds + PAD + (2 + bj - s + (bj < s ? NB : 0)) * PS; };
     {
       Fin F;
-      finish_compute(jpc, j - 2 - S, outb[1 - JP], F);
+      finish_compute(j - 2 - S, outb[1 - JP], F);
       fetch_u(j - 1 - S);
       if (JP == 1) cfetch((j + 3) >> 1);  // stored at the next step: z(j + 2) needs coarse plane (j + 3) / 2
       finish_store(j - 2 - S, F);
@@ -805,6 +804,11 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       }
       *reinterpret_cast<float2*>(zb + pos) = make_float2(z[0][2], z[1][2]);
       *reinterpret_cast<float2*>(zb + pos + EXW) = make_float2(z[2][2], z[3][2]);
+      // z of plane j - 2 on the output tile (the other quads write the spare
+      // rows), read when the plane is finished
+      float* zt = zslot(j - 2);
+      *reinterpret_cast<float2*>(&zt[oidx]) = make_float2(z[0][0], z[1][0]);
+      *reinterpret_cast<float2*>(&zt[oidx + kTX]) = make_float2(z[2][0], z[3][0]);
     }
     {  // plane j - 1: rhs = g - A z, and y' as stage 0
       const int p = j - 1;
