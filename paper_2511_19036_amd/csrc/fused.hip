@@ -583,9 +583,12 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   static_assert(H % 2 == 0, "even halo: quads start at even coordinates");
   constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H, QW = EXW / 2, QH = EXH / 2, NQ = QW * QH;
   static_assert(NQ <= NT, "one quad per thread");
-  // plane of the extended tile and its stride: a missing quad works on the
-  // two spare rows after the plane
-  constexpr int LPL = EXW * EXH, PS = LPL + 2 * EXW + 2, PAD = EXW + 2;
+  // LDS row stride RS: the halo's column quads sit in consecutive lanes two
+  // rows apart, 2 RS words, which spreads them over 16 banks (over 4 with
+  // RS = EXW).  Plane of the extended tile and its stride: a missing quad
+  // works on the two spare rows after the plane.
+  constexpr int RS = EXW + 2;
+  constexpr int LPL = RS * EXH, PS = LPL + 2 * RS + 2, PAD = RS + 2;
   constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;
   constexpr int NB = S + 1;  // y buffers: plane j - 1 - s in flight from step j - s to j - s + S
   // coarse planes: step j reads planes j >> 1 and (j >> 1) + 1 (an odd
@@ -619,7 +622,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   if (valid) quad_of<H, TY>(tid, qx, qy);
   const int gx0 = X0 - H + 2 * qx, gy0 = Y0 - H + 2 * qy;
   const bool dom = valid && gx0 >= 0 && gx0 < n && gy0 >= 0 && gy0 < n;  // the quad lies in the level
-  int pos = valid ? 2 * qy * EXW + 2 * qx : LPL;  // LDS offset of node 0
+  int pos = valid ? 2 * qy * RS + 2 * qx : LPL;  // LDS offset of node 0
   int ci = qy * CW + qx;                          // coarse node (gx0 / 2, gy0 / 2) in the coarse ring
   // bits 0-3: node d is an interior node of the level; bit 4: output quad
   unsigned fq = 0u;
@@ -803,7 +806,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
         z[d][2] = prolong_node<float, JP, CW>(c0, c1, ci, (d & 1) != 0, (d & 2) != 0);
       }
       *reinterpret_cast<float2*>(zb + pos) = make_float2(z[0][2], z[1][2]);
-      *reinterpret_cast<float2*>(zb + pos + EXW) = make_float2(z[2][2], z[3][2]);
+      *reinterpret_cast<float2*>(zb + pos + RS) = make_float2(z[2][2], z[3][2]);
       // z of plane j - 2 on the output tile (the other quads write the spare
       // rows), read when the plane is finished
       float* zt = zslot(j - 2);
@@ -817,10 +820,10 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       float* yb = ybuf(0);
       // in-plane neighbours outside the quad: x - 1 / x + 1 of the left /
       // right column, y - 1 / y + 1 of the lower / upper row
-      const float zxm0 = zs[pos - 1], zxm2 = zs[pos + EXW - 1];
-      const float zxp1 = zs[pos + 2], zxp3 = zs[pos + EXW + 2];
-      const float zym0 = zs[pos - EXW], zym1 = zs[pos - EXW + 1];
-      const float zyp2 = zs[pos + 2 * EXW], zyp3 = zs[pos + 2 * EXW + 1];
+      const float zxm0 = zs[pos - 1], zxm2 = zs[pos + RS - 1];
+      const float zxp1 = zs[pos + 2], zxp3 = zs[pos + RS + 2];
+      const float zym0 = zs[pos - RS], zym1 = zs[pos - RS + 1];
+      const float zyp2 = zs[pos + 2 * RS], zyp3 = zs[pos + 2 * RS + 1];
       float rv[4], yv[4];
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
@@ -844,7 +847,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
         yv[d] = kp ? y0 : 0.0f;
       }
       *reinterpret_cast<float2*>(yb + pos) = make_float2(yv[0], yv[1]);
-      *reinterpret_cast<float2*>(yb + pos + EXW) = make_float2(yv[2], yv[3]);
+      *reinterpret_cast<float2*>(yb + pos + RS) = make_float2(yv[2], yv[3]);
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
 #pragma unroll
@@ -870,14 +873,14 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       const float* yb = ybuf(s);
       if (JP == 0) {  // node 0: x - 1, y - 1; node 3: x + 1, y + 1
         v[0] = yb[pos - 1];
-        v[1] = yb[pos - EXW];
-        v[2] = yb[pos + EXW + 2];
-        v[3] = yb[pos + 2 * EXW + 1];
+        v[1] = yb[pos - RS];
+        v[2] = yb[pos + RS + 2];
+        v[3] = yb[pos + 2 * RS + 1];
       } else {  // node 1: x + 1, y - 1; node 2: x - 1, y + 1
         v[0] = yb[pos + 2];
-        v[1] = yb[pos - EXW + 1];
-        v[2] = yb[pos + EXW - 1];
-        v[3] = yb[pos + 2 * EXW];
+        v[1] = yb[pos - RS + 1];
+        v[2] = yb[pos + RS - 1];
+        v[3] = yb[pos + 2 * RS];
       }
     };
     auto stage_on = [&](int s) { return 64 * wv < cone_quads<H, TY>(S - s); };
@@ -912,7 +915,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
         const float v = yc + cp * rr;
         const float yv = ((fq >> d) & 1u) ? v : yc;
         y[d][iy] = yv;
-        if (s < S) yb[pos + dy * EXW + dx] = yv;
+        if (s < S) yb[pos + dy * RS + dx] = yv;
       }
     }
     // plane j - 1 - S is complete: into the output buffer (read at the next
