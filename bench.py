@@ -246,6 +246,56 @@ def summarize_counters(d, L, bits, block=64):
     return "\n".join(out)
 
 
+STALL_COUNTERS = (("sa", ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+                           "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS")),
+                  ("sb", ("SQ_ACTIVE_INST_SCA", "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_MISC",
+                          "SQ_INSTS_SALU", "SQ_INSTS_VALU")))
+
+
+def summarize_stalls(d, L, bits):
+    """Markdown rows of the two SQ counter passes in directory d (rocprofv3
+    csv output of bench.py --pmc-pass, passes sa_ and sb_ with the counters
+    of STALL_COUNTERS): for the fused kernels on the finest level (the
+    instantiation with the finest level's container), over the launches of
+    the second (measured) solve, where the waves' cycles go as fractions of
+    SQ_WAVE_CYCLES (summed over waves): issuing an instruction (active),
+    waiting on a memory, LDS or barrier counter (wait_any), waiting for an
+    issue slot (wait_inst), and the VALU, scalar and LDS instructions and
+    the LDS bank-conflict cycles among them."""
+    import csv
+    import collections
+    cbits = 8 if bits <= 8 else 12 if bits <= 12 else 16 if bits <= 16 else 32
+    acc = collections.defaultdict(lambda: collections.defaultdict(float))
+    launches = collections.defaultdict(set)
+    for pas, _ in STALL_COUNTERS:
+        path = os.path.join(d, f"{pas}_counter_collection.csv")
+        if not os.path.exists(path):
+            continue
+        rows = list(csv.DictReader(open(path)))
+        ids = sorted({int(r["Dispatch_Id"]) for r in rows})
+        half = ids[len(ids) // 2]  # the second (measured) solve of the pass
+        for r in rows:
+            fam, cb = _family(r["Kernel_Name"])
+            if fam is None or int(r["Dispatch_Id"]) < half or cb != cbits or fam == "k_decode_level":
+                continue
+            key = f"{fam}@{L}"
+            acc[key][r["Counter_Name"]] += float(r["Counter_Value"])
+            if pas == "sa":
+                launches[key].add(int(r["Dispatch_Id"]))
+    out = ["| kernel | launches | wave cycles per launch | active | wait_any | wait_inst | VALU | scalar | LDS "
+           "| LDS bank conflict |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for key in sorted(acc):
+        c = acc[key]
+        n = max(len(launches[key]), 1)
+        wc = c.get("SQ_WAVE_CYCLES", 0.0) or 1.0
+        frac = [c.get(name, 0.0) / wc for name in ("SQ_ACTIVE_INST_ANY", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+                                                    "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_SCA",
+                                                    "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT")]
+        out.append(f"| `{key}` | {n} | {c.get('SQ_WAVE_CYCLES', 0.0) / n:.4e} | "
+                   + " | ".join(f"{x:.3f}" for x in frac) + " |")
+    return "\n".join(out)
+
+
 def discretisation_check(u, L, dim=3):
     """Errors of u against the closed-form discrete solution of the sine part.
 
@@ -665,6 +715,9 @@ def main():
                     help="for kernel traces: time only the other workloads and print their figures as JSON")
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="print the markdown tables of the --pmc-pass counter csv files in DIR (no GPU)")
+    ap.add_argument("--summarize-stalls", metavar="DIR",
+                    help="print the markdown table of the SQ stall counter csv files (passes sa_, sb_) in DIR "
+                         "(no GPU)")
     ap.add_argument("--pmc-pass-diffusion", action="store_true",
                     help="for counter and trace runs: one right-hand side of the 513^3 x 8 diffusion workload, "
                          "warm-up, copy, one solve")
@@ -673,6 +726,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters, args.L, args.bits))
+        return
+    if args.summarize_stalls:
+        print(summarize_stalls(args.summarize_stalls, args.L, args.bits))
         return
     if args.summarize_diffusion:
         print(summarize_diffusion_counters(args.summarize_diffusion))

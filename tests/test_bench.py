@@ -108,3 +108,22 @@ def test_diffusion_summary_takes_the_solve_after_the_calibration_copy(tmp_path):
     gbs = total / ((1000 + 3000) * 1e-9) / 1e9
     assert out.splitlines()[0] == f"measured_gbs: {gbs:.1f}"
     assert "`cmg::k_a<1>` | 1 |" in out and "at::native" not in out
+
+
+def test_stall_summary_takes_the_finest_level_of_the_measured_solve(tmp_path):
+    # dispatches 1-2: warm-up solve; 3-4: measured solve; the 32-bit
+    # container (a coarser level) and other libraries' kernels are left out
+    up16 = "void cmg::k_up_smooth<4, 32, 768, 6, false, 16>(float const*)"
+    up32 = "void cmg::k_up_smooth<4, 32, 768, 6, false, 32>(float const*)"
+    sa = {"SQ_WAVE_CYCLES": 1000.0, "SQ_ACTIVE_INST_ANY": 400.0, "SQ_WAIT_ANY": 350.0, "SQ_WAIT_INST_ANY": 250.0,
+          "SQ_ACTIVE_INST_VALU": 200.0, "SQ_ACTIVE_INST_LDS": 30.0}
+    sb = {"SQ_ACTIVE_INST_SCA": 150.0, "SQ_LDS_BANK_CONFLICT": 60.0}
+    for pas, vals in (("sa", sa), ("sb", sb)):
+        with open(tmp_path / f"{pas}_counter_collection.csv", "w") as fh:
+            fh.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+            for i, name in ((1, up16), (2, up32), (3, up16), (4, up32), (5, "void at::native::k(int)")):
+                for c, v in vals.items():
+                    fh.write(f'{i},"{name}",{c},{v * (1 if i < 3 else 2)}\n')
+    out = bench.summarize_stalls(str(tmp_path), 10, 16).splitlines()
+    assert len(out) == 3 and out[2].startswith("| `k_up_smooth<4>@10` | 1 | 2.0000e+03 |")
+    assert out[2].endswith("| 0.400 | 0.350 | 0.250 | 0.200 | 0.150 | 0.030 | 0.060 |")
