@@ -612,8 +612,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   __shared__ float cs[NC * CPL + 1];      // plus a spare word (written by threads past the coarse tile)
   __shared__ __align__(8) float lds[2 * PAD + (2 + NB) * PS];  // z of planes j, j - 1; then y buffers
   __shared__ __align__(8) float outb[2][OB];
-  __shared__ __align__(8) float zo[NZ * OB];
-  auto zslot = [&](int p) { return zo + ((p + 8 * NZ) % NZ) * OB; };  // p >= -S - 2
+  __shared__ __align__(8) float zo[NZ * OB];  // plane p at slot (p - 1) mod NZ, the y buffer index of p + S
   const int tid = threadIdx.x;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   int lane = tid & 63;
@@ -743,7 +742,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     int64_t mu[RPW];
     float ev[RPW];
   };
-  auto finish_compute = [&](int po, const float* ob, Fin& F) {
+  auto finish_compute = [&](int po, const float* ob, const float* zb, Fin& F) {
     if (po < Z0 || po >= Z0 + TZ) return;
     // the rows are quantised together (their DPP reductions interleave)
     float yv[RPW];
@@ -762,7 +761,6 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     }
     quant_f64_rows<LB, may64<CB, HI>(), RPW>(vu, U.wq, lane, F.mu, F.eu);
     if (eout != nullptr) {  // z of the plane, kept since its own step
-      const float* zb = zslot(po);
 #pragma unroll
       for (int t = 0; t < RPW; ++t) F.ev[t] = F.ev[t] + zb[row_of(t) * kTX + lane];
     }
@@ -795,15 +793,18 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
     }
   };
 
-  auto step = [&](auto jpc, const int j) {
+  // bj: the y buffer index of plane j - 1, (j - 1) mod NB, carried by the loop
+  auto step = [&](auto jpc, const int j, const int bj) {
     constexpr int JP = decltype(jpc)::value;  // every stage updates the nodes of class JP at this step
     launder();
     // y buffer of plane j - 1 - s (0 <= s <= S < NB)
-    const int bj = (j - 1 + 4 * NB) % NB;
     auto ybuf = [&](int s) { return lds + PAD + (2 + bj - s + (bj < s ? NB : 0)) * PS; };
+    // z ring (NZ = NB): plane j - 2 - S = j - 1 - NB at slot bj, plane j - 2 at slot bj - 1
+    float* const zfin = zo + bj * OB;
+    float* const znew = zo + (bj == 0 ? NB - 1 : bj - 1) * OB;
     {
       Fin F;
-      finish_compute(j - 2 - S, outb[1 - JP], F);
+      finish_compute(j - 2 - S, outb[1 - JP], zfin, F);
       fetch_u(j - 1 - S);
       if (JP == 1) cfetch((j + 3) >> 1);  // stored at the next step: z(j + 2) needs coarse plane (j + 3) / 2
       finish_store(j - 2 - S, F);
@@ -822,9 +823,8 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
       *reinterpret_cast<float2*>(zb + pos + RS) = make_float2(z[2][2], z[3][2]);
       // z of plane j - 2 on the output tile (the other quads write the spare
       // rows), read when the plane is finished
-      float* zt = zslot(j - 2);
-      *reinterpret_cast<float2*>(&zt[oidx]) = make_float2(z[0][0], z[1][0]);
-      *reinterpret_cast<float2*>(&zt[oidx + kTX]) = make_float2(z[2][0], z[3][0]);
+      *reinterpret_cast<float2*>(&znew[oidx]) = make_float2(z[0][0], z[1][0]);
+      *reinterpret_cast<float2*>(&znew[oidx + kTX]) = make_float2(z[2][0], z[3][0]);
     }
     {  // plane j - 1: rhs = g - A z, and y' as stage 0
       const int p = j - 1;
@@ -946,10 +946,13 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   cfetch((jbeg + 2) >> 1);
   fetch_gy(jbeg - 1);
   __syncthreads();
+  int bj = (jbeg - 1 + 4 * NB) % NB;
 #pragma unroll 1
   for (int j = jbeg; j < jend; j += 2) {
-    step(std::integral_constant<int, 0>(), j);
-    step(std::integral_constant<int, 1>(), j + 1);
+    step(std::integral_constant<int, 0>(), j, bj);
+    bj = bj == NB - 1 ? 0 : bj + 1;
+    step(std::integral_constant<int, 1>(), j + 1, bj);
+    bj = bj == NB - 1 ? 0 : bj + 1;
   }
 }
 
