@@ -118,9 +118,8 @@ struct CoarseFetch {
 // ======================================================= register columns
 // Scheme of the down-smoothing kernel.  A workgroup owns an x-y tile of
 // 64 x TY output nodes plus a halo of H nodes and marches along z through a
-// chunk of TZ planes.  Each thread owns two pairs of adjacent x-columns of
-// the extended tile (one in a row of each parity) and keeps, per column, a
-// ring of y and right-hand-side
+// chunk of TZ planes.  Each thread owns K pairs of adjacent x-columns of
+// the extended tile and keeps, per column, a ring of y and right-hand-side
 // values of consecutive planes in registers.  The half-sweeps are pipeline
 // stages with a lag of one plane.  Stage s updates colour (s + 1) & 1 of its
 // plane (red first), so at any one step all stages update the columns of a
@@ -131,31 +130,20 @@ struct CoarseFetch {
 // way has one buffer: a stage reads the colour that its predecessor wrote at
 // the previous step and writes the other colour, so one barrier per step
 // suffices.  Nodes near the tile edge outside the dependence cone of the
-// output nodes may take inexact values (their LDS reads wrap into the other
-// half of their row, or into the neighbouring plane) but no node inside the
-// cone reads them.
+// output nodes may take inexact values (their LDS reads wrap into the
+// neighbouring row or plane) but no node inside the cone reads them.
 // Dirichlet boundary nodes and nodes outside the level stay zero.
 
-// Pair geometry of a register-column tile.  Pair (px, ly) holds the nodes
-// lx = 2 px and 2 px + 1 of row ly of the extended tile; slot k of a thread
-// takes the rows of parity k (thread tid: pair tid of those rows, row-major).
-// In LDS a row keeps its even-x nodes, then its odd-x nodes (PW each), so
-// that the consecutive pairs of a wave's lanes touch consecutive words, and a
-// node's x neighbours lie at offsets fixed by its x parity.
+// Pair geometry of a register-column tile.
 template <int H, int TY, int NT>
 struct ColTile {
   static constexpr int EXW = kTX + 2 * H, EXH = TY + 2 * H;
-  static constexpr int PW = EXW / 2, NPC = PW * (EXH / 2), K = 2;
-  static_assert(EXH % 2 == 0 && NPC <= NT, "one pair of each row parity per thread");
-  // Row stride: a wave's lanes run along a row and on into the next row of
-  // their parity, 2 RS - (PW - 1) words on; with that step 2 (mod 64) the 64
-  // lanes fall on distinct banks but one.
-  static constexpr int rs(int r) { return r >= EXW ? r : rs(r + 32); }
-  static constexpr int RS = rs((PW + 2) / 2);
-  // plane, its stride (a spare row, for the pairs past NPC), margin: every
-  // neighbour read stays inside the LDS array
-  static constexpr int LPL = RS * EXH, PS = LPL + RS, PAD = RS + PW + 2;
-  static constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;  // output rows per wave
+  static constexpr int PW = EXW / 2, NPAIR = PW * EXH, K = (NPAIR + NT - 1) / NT;
+  // plane, its stride (two spare words), margin: the neighbour reads of a
+  // missing pair (whose slot is past NPAIR and which works on the spare
+  // words) stay inside the LDS array
+  static constexpr int LPL = EXW * EXH, PS = LPL + 2, PAD = EXW + 2;
+  static constexpr int NW = NT / 64, RPW = (TY + NW - 1) / NW;          // output rows per wave
 };
 
 // Output row t of wave wv when TY rows are shared by NW waves.  Waves are
@@ -171,25 +159,23 @@ __device__ __forceinline__ int out_row(int wv, int t) {
 // Per-pair flags.
 constexpr unsigned kInnerSlot = 0u;  // bits 0, 1: the node of slot s is inside the level's interior
 constexpr unsigned kOutSlot = 2u;    // bits 2, 3: the node of slot s is an output node
+constexpr unsigned kSwap = 4u;       // bit 4: column 0 holds slot 1
 
-// pos[k]: LDS offset of the even-x node of the pair (the odd one is PW
-// further); a missing pair works on the spare row.  X0 and Y0 are even, so
-// the pair's swap bit (gx0 + gy) & 1 is its row parity k.
 template <int H, int TY, int NT>
 __device__ __forceinline__ void col_setup(int tid, int X0, int Y0, int level, int* pos, uint32_t (*xy)[2],
                                           unsigned* fl, int* oidx) {
   using T = ColTile<H, TY, NT>;
   const int n = 1 << level;
-  const bool valid = tid < T::NPC;
-  const int ry = valid ? tid / T::PW : 0, px = valid ? tid - ry * T::PW : 0;
 #pragma unroll
   for (int k = 0; k < T::K; ++k) {
-    const int ly = 2 * ry + k, lx0 = 2 * px;
+    const int q = tid + k * NT;
+    const bool valid = q < T::NPAIR;
+    const int ly = valid ? q / T::PW : 0, lx0 = valid ? 2 * (q - ly * T::PW) : 0;
     const int gx0 = X0 - H + lx0, gy = Y0 - H + ly;
-    pos[k] = valid ? ly * T::RS + px : T::LPL;
+    pos[k] = valid ? ly * T::EXW + lx0 : T::LPL;  // a missing pair writes the spare words
     oidx[k] = (ly - H) * kTX + (lx0 - H);
-    const unsigned sw = static_cast<unsigned>(gx0 + gy) & 1u;  // the slot of column 1
-    unsigned f = 0u;
+    const unsigned sw = static_cast<unsigned>(gx0 + gy) & 1u;
+    unsigned f = sw << kSwap;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int gx = gx0 + c, lx = lx0 + c;
@@ -249,7 +235,7 @@ template <int S, int TY, int NT, int LB, bool HI, int CB>
 __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level, float cp, float ih2, int TZ) {
   constexpr int H = S - 1;
   using T = ColTile<H, TY, NT>;
-  constexpr int K = T::K, PW = T::PW, RS = T::RS, PS = T::PS, PAD = T::PAD;
+  constexpr int K = T::K, EXW = T::EXW, PS = T::PS, PAD = T::PAD;
   constexpr int NB = S;  // plane j - s is in flight from step j - s + 1 to j - s + S
   __shared__ float lds[2 * PAD + NB * PS];
   __shared__ float outb[2][TY * kTX];
@@ -263,12 +249,6 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
   uint32_t xy[K][2];
   unsigned fl[K];
   col_setup<H, TY, NT>(tid, X0, Y0, level, pos, xy, fl, oidx);
-  // the interior flags as lane masks (scalar registers), taken once
-  bool inner[K][2];
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) inner[k][c] = (fl[k] >> (kInnerSlot + c)) & 1u;
   int gwm1 = G.w - 1;  // opaque, so that a code's scaling exponent is one subtraction
   auto launder = [&]() {
     opaque_s(gwm1);
@@ -314,7 +294,7 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
     const bool jin = j >= 1 && j < n;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const bool sw = k != 0;  // the swap bit of a pair is its row parity
+      const bool sw = (fl[k] >> kSwap) & 1u;
       const float g0 = jin ? raw_f32_m1(gpre[k][0], xy[k][0], cbits_of<CB>(G), gwm1) : 0.0f;
       const float g1 = jin ? raw_f32_m1(gpre[k][1], xy[k][1], cbits_of<CB>(G), gwm1) : 0.0f;
 #pragma unroll
@@ -344,13 +324,13 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
       const int p = j - s;
-      const bool act = p >= 1 && p < n;  // the plane lies in the level
+      const bool act = p >= 1 && p < n;
       const int iy = S + 1 - s;
       float* yb = lds + PAD + ((p + 4 * NB) % NB) * PS;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int bx = SG ^ k;  // x parity of the node of slot SG
-        const int pa = pos[k] + bx * PW;
+        const unsigned sw = (fl[k] >> kSwap) & 1u;
+        const int pa = pos[k] + static_cast<int>(static_cast<unsigned>(SG) ^ sw);
         const float yc = y[k][SG][iy];
         const float rhs = r[k][SG][S - s];
         float v;
@@ -358,17 +338,16 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
           v = cp * rhs;
         } else {
           float a = 6.0f * yc;
-          a = a - yb[bx ? pa - PW : pa + PW - 1];      // x - 1
-          a = a - yb[bx ? pa - PW + 1 : pa + PW];      // x + 1
-          a = a - yb[pa - RS];
-          a = a - yb[pa + RS];
+          a = a - yb[pa - 1];
+          a = a - yb[pa + 1];
+          a = a - yb[pa - EXW];
+          a = a - yb[pa + EXW];
           a = a - y[k][SG][iy - 1];
           a = a - y[k][SG][iy + 1];
           const float rr = exact_fma(-a, ih2, rhs);  // rhs - a ih2 (ih2 = 4^l)
           v = yc + cp * rr;
         }
-        opaque(v);  // computed unconditionally: a select, not a branch per stage
-        const float yv = (act && inner[k][SG]) ? v : yc;
+        const float yv = (act && ((fl[k] >> (kInnerSlot + SG)) & 1u)) ? v : yc;
         y[k][SG][iy] = yv;
         if (s < S) yb[pa] = yv;
       }
@@ -378,9 +357,10 @@ __global__ void __launch_bounds__(NT, 6) k_down_smooth(PSec G, PSec Y, int level
       if (po >= Z0 && po < Z0 + TZ) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
+          const unsigned sw = (fl[k] >> kSwap) & 1u;
 #pragma unroll
           for (int sg = 0; sg < 2; ++sg)
-            if ((fl[k] >> (kOutSlot + sg)) & 1u) outb[JP][oidx[k] + (sg ^ k)] = y[k][sg][1];
+            if ((fl[k] >> (kOutSlot + sg)) & 1u) outb[JP][oidx[k] + static_cast<int>(sg ^ sw)] = y[k][sg][1];
         }
       }
     }
