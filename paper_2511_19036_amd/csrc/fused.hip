@@ -446,6 +446,30 @@ __device__ __forceinline__ T prolong_node(const T* c0, const T* c1, int ci, bool
   return s;
 }
 
+// The same with the y parity PY a compile-time constant and the x parity
+// px varying over the lanes: the absent x neighbours are added with a zero
+// weight, the absent y neighbours are left out (the same sums: see above).
+template <typename T, int PK, int PY, int CW>
+__device__ __forceinline__ T prolong_node_x(const T* c0, const T* c1, int ci, bool px) {
+  const T w = (px ? T(0.5) : T(1)) * (PY ? T(0.5) : T(1)) * (PK ? T(0.5) : T(1));
+  const T wx = px ? w : T(0);
+  T s = w * c0[ci];
+  s = exact_fma(c0[ci + 1], wx, s);
+  if (PY) {
+    s = exact_fma(c0[ci + CW], w, s);
+    s = exact_fma(c0[ci + CW + 1], wx, s);
+  }
+  if (PK) {
+    s = exact_fma(c1[ci], w, s);
+    s = exact_fma(c1[ci + 1], wx, s);
+    if (PY) {
+      s = exact_fma(c1[ci + CW], w, s);
+      s = exact_fma(c1[ci + CW + 1], wx, s);
+    }
+  }
+  return s;
+}
+
 // One step of the decode chain, u_l = dec u'_l + P u_{l-1} (float64), at a
 // node of level l, for kernels that rebuild the planes of u_l they need
 // instead of reading a stored level array (then u_l is never written to
@@ -1287,19 +1311,27 @@ __global__ void __launch_bounds__(NT) k_ir_residual(PSec U, const double* __rest
       const double* c0 = cs + ((j >> 1) & (NC - 1)) * CPL;
       const double* c1 = cs + (((j >> 1) + 1) & (NC - 1)) * CPL;
       double* ub = us + ((j + 3) % 3) * LPL;
+      // the rows of a wave are NWR (even) apart: their y parity is the
+      // wave's, a compile-time constant in each branch
+      auto own = [&](auto pyc) {
+        constexpr int PY = decltype(pyc)::value;
 #pragma unroll
-      for (int t = 0; t < RPT; ++t) {
-        const int rr = wr + NWR * t;
-        u[t][0] = u[t][1];
-        u[t][1] = u[t][2];
-        const int ci = ((rr >> 1) + 1) * CW + (xl >> 1) + 1;
-        // uz: u' holds zeros that were never written (the first IR
-        // iteration of an FMG level): the codes read are not used
-        const double v = (uz ? 0.0 : code_f64<CB, may64<CB, HI>()>(upre[t], xy_own(t), cbits_of<CB>(U), U.w)) +
-                         prolong_node<double, JP, CW, true>(c0, c1, ci, lane & 1, rr & 1);
-        u[t][2] = pin ? v : 0.0;
-        ub[(rr + 1) * EXW + xl + 1] = u[t][2];
-      }
+        for (int t = 0; t < RPT; ++t) {
+          const int rr = wr + NWR * t;
+          u[t][0] = u[t][1];
+          u[t][1] = u[t][2];
+          const int ci = ((rr >> 1) + 1) * CW + (xl >> 1) + 1;
+          // uz: u' holds zeros that were never written (the first IR
+          // iteration of an FMG level): the codes read are not used
+          const double v = (uz ? 0.0 : code_f64<CB, may64<CB, HI>()>(upre[t], xy_own(t), cbits_of<CB>(U), U.w)) +
+                           prolong_node_x<double, JP, PY, CW>(c0, c1, ci, lane & 1);
+          u[t][2] = pin ? v : 0.0;
+          ub[(rr + 1) * EXW + xl + 1] = u[t][2];
+        }
+      };
+      static_assert(NWR % 2 == 0, "rows of one parity per wave");
+      if (wr & 1) own(std::integral_constant<int, 1>());
+      else own(std::integral_constant<int, 0>());
       if (has_h) {
         const double v =
             (uz ? 0.0 : code_f64<CB, may64<CB, HI>()>(hpre, xyh, cbits_of<CB>(U), U.w)) +
