@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(NT, 2) k_up_smooth(const float* __restrict__ e
   __shared__ float cs[NC * CPL + 1];      // plus a spare word (written by threads past the coarse tile)
   __shared__ __align__(8) float lds[2 * PAD + (2 + NB) * PS];  // z of planes j, j - 1; then y buffers
   __shared__ __align__(8) float outb[2][OB];
-  __shared__ __align__(8) float zo[NZ * OB];  // plane p at slot (p - 1) mod NZ, the y buffer index of p + S
+  __shared__ __align__(8) float zo[NZ * OB];  // plane p at slot p mod NZ (NZ = NB: its y buffer index)
   const int tid = threadIdx.x;
   int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   int lane = tid & 63;
